@@ -1,0 +1,530 @@
+"""CPU FP64 oracle for the HPS discretization of the Helmholtz impedance problem
+and its homogenized block-Jacobi preconditioned GMRES solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module; only the tests, the smoke check and the benchmark's CPU-baseline leg do.
+It shares no code with the HIP library: it builds its own Chebyshev tables, its
+own node ordering and its own global sparse matrix, and it inverts the
+homogenized leaf matrices with dense LU (no fast diagonalization, no Schur
+complement), so an agreement with the GPU path is an agreement between two
+independent routes.
+
+Everything is complex128 / float64.  Paper references are to Lucero Lorca,
+Beams, Beecroft and Gillman, "An iterative solver for the HPS discretization
+applied to three dimensional Helmholtz problems" (arXiv 2112.02211).
+
+Readings of silent or garbled passages (each listed in the design notes):
+  * n_c (written p here) is the number of Chebyshev nodes per leaf direction,
+    q = p - 2 face nodes per face edge (Sec. 2.1, the 1176/2744 sizes of Sec. 4).
+  * Chebyshev-Lobatto nodes xi_j = -cos(pi j/(p-1)), ascending; the 1D second
+    derivative is D.D (Sec. 2.1 cites the classical construction).
+  * interior nodes are ordered x fastest, then y, then z; nodes of a face are
+    ordered in its two tangential axes, lower axis fastest; faces 1..6 are
+    -x,+x,-y,+y,-z,+z (Sec. 2.1, eq. (flux)).
+  * Algorithm 1 subtracts C v (eq. (leafmat)); Algorithm 2 applies the
+    neighbour's outgoing impedance operator to the *input* vector (eq.
+    (outgoingimpedance) and the two-leaf system eq. (2x2)).
+  * Algorithm 4's boundary output carries the opposite sign of its printed g_b:
+    J^{-1} is the exact inverse of the homogenized leaf matrix (eq. (block_pc)).
+  * lambda^tau = (max + min)/2 of diag(C_ii) (Sec. 4.1); for complex b the real
+    and imaginary midranges are taken separately.  If the homogenized interior
+    operator is within 1e-3 |lambda| of singular, lambda is replaced by
+    lambda (1 + 0.01 i) (the paper is silent on this case).
+  * E_h sums |u_h - u|^2 over all N nodes (Sec. 6 metric definitions).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from numpy.polynomial import chebyshev as npcheb
+
+# ----------------------------------------------------------------------------
+# 1D tables (Sec. 2.1)
+# ----------------------------------------------------------------------------
+
+
+def cheb_nodes(p: int) -> np.ndarray:
+    """Chebyshev-Lobatto nodes on [-1, 1], ascending."""
+    j = np.arange(p)
+    return -np.cos(np.pi * j / (p - 1))
+
+
+def diff_matrix(p: int) -> np.ndarray:
+    """Spectral differentiation matrix on the reference nodes.
+
+    Defined as the derivative of the degree p-1 interpolant: D = T' T^{-1}
+    where T[i, k] = T_k(xi_i) and T'[i, k] = T_k'(xi_i) (Chebyshev basis).
+    """
+    xi = cheb_nodes(p)
+    T = npcheb.chebvander(xi, p - 1)
+    Tp = np.zeros_like(T)
+    for k in range(p):
+        c = np.zeros(p)
+        c[k] = 1.0
+        Tp[:, k] = npcheb.chebval(xi, npcheb.chebder(c))
+    return np.linalg.solve(T.T, Tp.T).T
+
+
+# ----------------------------------------------------------------------------
+# discretization (Sec. 2, Sec. 3.1)
+# ----------------------------------------------------------------------------
+
+# face f (1..6): axis, endpoint grid index (0 or p-1), outward sign
+FACES = [(0, 0, -1.0), (0, 1, 1.0), (1, 0, -1.0), (1, 1, 1.0), (2, 0, -1.0), (2, 1, 1.0)]
+PARTNER = [1, 0, 3, 2, 5, 4]  # face on the other side of a shared interface (0-based)
+
+
+@dataclass
+class Disc:
+    n_elem: tuple
+    p: int
+    kappa: float
+    eta: float
+    lo: np.ndarray
+    h: float
+
+    @property
+    def n1(self):
+        return self.p - 2
+
+    @property
+    def ni(self):
+        return self.n1 ** 3
+
+    @property
+    def nb(self):
+        return 6 * self.n1 ** 2
+
+    @property
+    def n(self):
+        return self.ni + self.nb
+
+    @property
+    def nl(self):
+        return int(np.prod(self.n_elem))
+
+    @property
+    def N(self):
+        return self.nl * self.n
+
+
+def make_disc(n_elem, p, kappa, eta, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Disc:
+    lo = np.asarray(lo, dtype=float)
+    hi = np.asarray(hi, dtype=float)
+    hs = (hi - lo) / np.asarray(n_elem, dtype=float)
+    if not np.allclose(hs, hs[0], rtol=1e-14, atol=0):
+        raise ValueError("leaves must be cubes")
+    return Disc(tuple(int(e) for e in n_elem), int(p), float(kappa), float(eta), lo, float(hs[0]))
+
+
+def leaf_grid_index(d: Disc) -> np.ndarray:
+    """Local index of every grid node (i, j, k), or -1 for removed corner/edge nodes.
+
+    Returns G with G[i, j, k] = local index (Sec. 2.1 ordering).
+    """
+    p, n1 = d.p, d.n1
+    G = -np.ones((p, p, p), dtype=np.int64)
+    idx = 0
+    for k in range(1, p - 1):
+        for j in range(1, p - 1):
+            for i in range(1, p - 1):
+                G[i, j, k] = idx
+                idx += 1
+    for f, (ax, end, _) in enumerate(FACES):
+        e = 0 if end == 0 else p - 1
+        t1, t2 = [a for a in range(3) if a != ax]
+        for b in range(1, p - 1):        # slower tangential axis
+            for a in range(1, p - 1):    # faster (lower) tangential axis
+                ijk = [0, 0, 0]
+                ijk[ax] = e
+                ijk[t1] = a
+                ijk[t2] = b
+                G[tuple(ijk)] = idx
+                idx += 1
+    assert idx == d.n
+    return G
+
+
+def leaf_nodes_ref(d: Disc) -> np.ndarray:
+    """(n, 3) grid indices (i, j, k) of the local nodes in local order."""
+    G = leaf_grid_index(d)
+    out = np.zeros((d.n, 3), dtype=np.int64)
+    for ijk in np.argwhere(G >= 0):
+        out[G[tuple(ijk)]] = ijk
+    return out
+
+
+def elem_coords(d: Disc, tau: int):
+    E1, E2, _ = d.n_elem
+    return tau % E1, (tau // E1) % E2, tau // (E1 * E2)
+
+
+def neighbour(d: Disc, tau: int, f: int) -> int:
+    """Leaf across face f (0-based) of leaf tau, or -1 on the domain boundary."""
+    c = list(elem_coords(d, tau))
+    ax, end, _ = FACES[f]
+    c[ax] += 1 if end == 1 else -1
+    if c[ax] < 0 or c[ax] >= d.n_elem[ax]:
+        return -1
+    E1, E2, _ = d.n_elem
+    return c[0] + E1 * (c[1] + E2 * c[2])
+
+
+def node_coords(d: Disc) -> np.ndarray:
+    """(N, 3) physical coordinates of every unknown, leaves numbered x fastest."""
+    xi = cheb_nodes(d.p)
+    ref = leaf_nodes_ref(d)
+    loc = d.h * (xi[ref] + 1.0) / 2.0          # (n, 3) offsets inside a leaf
+    out = np.zeros((d.N, 3))
+    for tau in range(d.nl):
+        org = d.lo + d.h * np.asarray(elem_coords(d, tau), dtype=float)
+        out[tau * d.n:(tau + 1) * d.n] = org[None, :] + loc
+    return out
+
+
+def phys_tables(d: Disc):
+    """D and D^2 scaled to a leaf of side h."""
+    D = diff_matrix(d.p) * (2.0 / d.h)
+    return D, D @ D
+
+
+def local_ops(d: Disc):
+    """Sparse pattern pieces of one leaf, shared by all leaves (C excluded).
+
+    Returns (L, Nf) as dense real arrays:
+      L  (ni, n): rows of -(D_x^2 + D_y^2 + D_z^2) at interior nodes,
+      Nf (nb, n): rows of the outward normal derivative at face nodes (eq. (flux)).
+    """
+    D, D2 = phys_tables(d)
+    G = leaf_grid_index(d)
+    ref = leaf_nodes_ref(d)
+    p = d.p
+    L = np.zeros((d.ni, d.n))
+    Nf = np.zeros((d.nb, d.n))
+    for m in range(d.n):
+        ijk = ref[m]
+        if m < d.ni:
+            for ax in range(3):
+                for qq in range(p):
+                    nb_ijk = ijk.copy()
+                    nb_ijk[ax] = qq
+                    col = G[tuple(nb_ijk)]
+                    L[m, col] -= D2[ijk[ax], qq]
+        else:
+            f = (m - d.ni) // (d.n1 ** 2)
+            ax, end, sgn = FACES[f]
+            for qq in range(p):
+                nb_ijk = ijk.copy()
+                nb_ijk[ax] = qq
+                col = G[tuple(nb_ijk)]
+                Nf[m - d.ni, col] += sgn * D[ijk[ax], qq]
+    return L, Nf
+
+
+def leaf_matrices(d: Disc, Cdiag: np.ndarray, ops=None):
+    """Dense leaf system A^tau (eq. (leaf)) and outgoing operator G^tau (eq. (G)).
+
+    Cdiag: (ni,) values kappa^2 (1 - b) at the interior nodes.
+    """
+    L, Nf = ops if ops is not None else local_ops(d)
+    A = np.zeros((d.n, d.n), dtype=np.complex128)
+    A[:d.ni, :] = L
+    A[np.arange(d.ni), np.arange(d.ni)] -= Cdiag
+    Ib = np.zeros((d.nb, d.n))
+    Ib[np.arange(d.nb), d.ni + np.arange(d.nb)] = 1.0
+    F = Nf + 1j * d.eta * Ib
+    Gm = Nf - 1j * d.eta * Ib
+    A[d.ni:, :] = F
+    return A, Gm
+
+
+def c_values(d: Disc, b_nodes: np.ndarray) -> np.ndarray:
+    """C = kappa^2 (1 - b) at every node; (N,) complex."""
+    return d.kappa ** 2 * (1.0 - np.asarray(b_nodes, dtype=np.complex128))
+
+
+def assemble_global(d: Disc, b_nodes: np.ndarray) -> sp.csr_matrix:
+    """Global sparse A (Sec. 3.1, eq. (2x2) and eq. (outgoingimpedance)).
+
+    Leaf block rows: A^tau on the diagonal.  The face-j rows of leaf tau
+    additionally receive G^{tau'}(I_{j'}, :) applied to the unknowns of the
+    neighbour tau' across face j, where j' is the partner face.
+    """
+    L, Nf = local_ops(d)
+    C = c_values(d, b_nodes)
+    n, ni, nb, n1 = d.n, d.ni, d.nb, d.n1
+    # constant part of A^tau (without C), as COO
+    base = np.zeros((n, n), dtype=np.complex128)
+    base[:ni, :] = L
+    base[ni:, :] = Nf
+    base[ni + np.arange(nb), ni + np.arange(nb)] += 1j * d.eta
+    br, bc = np.nonzero(base)
+    bv = base[br, bc]
+    Gm = Nf.astype(np.complex128).copy()
+    Gm[np.arange(nb), ni + np.arange(nb)] -= 1j * d.eta
+    rows, cols, vals = [], [], []
+    for tau in range(d.nl):
+        off = tau * n
+        rows.append(br + off)
+        cols.append(bc + off)
+        vals.append(bv)
+        rows.append(off + np.arange(ni))
+        cols.append(off + np.arange(ni))
+        vals.append(-C[off:off + ni])
+        for f in range(6):
+            nbr = neighbour(d, tau, f)
+            if nbr < 0:
+                continue
+            fp = PARTNER[f]
+            blk = Gm[fp * n1 * n1:(fp + 1) * n1 * n1, :]   # G^{tau'}(I_{j'}, :)
+            gr, gc = np.nonzero(blk)
+            rows.append(off + ni + f * n1 * n1 + gr)
+            cols.append(nbr * n + gc)
+            vals.append(blk[gr, gc])
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(d.N, d.N)).tocsr()
+    A.sum_duplicates()
+    return A
+
+
+def boundary_face_mask(d: Disc) -> np.ndarray:
+    """(N,) bool: True at face nodes lying on the boundary of the domain."""
+    m = np.zeros(d.N, dtype=bool)
+    n1 = d.n1
+    for tau in range(d.nl):
+        for f in range(6):
+            if neighbour(d, tau, f) < 0:
+                s = tau * d.n + d.ni + f * n1 * n1
+                m[s:s + n1 * n1] = True
+    return m
+
+
+def interior_mask(d: Disc) -> np.ndarray:
+    m = np.zeros(d.N, dtype=bool)
+    for tau in range(d.nl):
+        m[tau * d.n:tau * d.n + d.ni] = True
+    return m
+
+
+def assemble_rhs(d: Disc, s_nodes: np.ndarray, t_nodes: np.ndarray) -> np.ndarray:
+    """b: s at interior rows, t at boundary face rows, 0 at interface rows (Sec. 3.1)."""
+    b = np.zeros(d.N, dtype=np.complex128)
+    im = interior_mask(d)
+    bm = boundary_face_mask(d)
+    b[im] = np.asarray(s_nodes)[im]
+    b[bm] = np.asarray(t_nodes)[bm]
+    return b
+
+
+def apply_elementwise(d: Disc, b_nodes: np.ndarray, x: np.ndarray,
+                      elems: Optional[Sequence[int]] = None) -> dict:
+    """A x restricted to the rows of the listed leaves, from dense leaf matrices.
+
+    A second route to A x (Algorithm 2 read as block rows): for each leaf,
+    A^tau x^tau plus, on every interior face j, G^{tau'}(I_{j'}, :) x^{tau'}.
+    Returns {tau: (n,) complex}.
+    """
+    ops = local_ops(d)
+    C = c_values(d, b_nodes)
+    n, ni, n1 = d.n, d.ni, d.n1
+    out = {}
+    for tau in (range(d.nl) if elems is None else elems):
+        A, _ = leaf_matrices(d, C[tau * n:tau * n + ni], ops)
+        w = A @ x[tau * n:(tau + 1) * n]
+        for f in range(6):
+            nbr = neighbour(d, tau, f)
+            if nbr < 0:
+                continue
+            fp = PARTNER[f]
+            _, Gn = leaf_matrices(d, C[nbr * n:nbr * n + ni], ops)
+            w[ni + f * n1 * n1: ni + (f + 1) * n1 * n1] += \
+                Gn[fp * n1 * n1:(fp + 1) * n1 * n1, :] @ x[nbr * n:(nbr + 1) * n]
+        out[tau] = w
+    return out
+
+
+# ----------------------------------------------------------------------------
+# homogenized block-Jacobi preconditioner (Sec. 4, eq. (block_pc))
+# ----------------------------------------------------------------------------
+
+def l1_eigenvalues(d: Disc) -> np.ndarray:
+    """Eigenvalues of L_1, the interior block of the 1D second derivative."""
+    _, D2 = phys_tables(d)
+    return np.linalg.eigvals(D2[1:-1, 1:-1])
+
+
+def homog_lambda(d: Disc, C_int: np.ndarray, eigs: Optional[np.ndarray] = None):
+    """lambda^tau = (max + min)/2 of diag(C_ii) (Sec. 4.1), with the resonance guard.
+
+    Returns (lambda, shifted_flag).
+    """
+    C_int = np.asarray(C_int, dtype=np.complex128)
+    lam = 0.5 * (C_int.real.max() + C_int.real.min()) + \
+        0.5j * (C_int.imag.max() + C_int.imag.min())
+    if eigs is None:
+        eigs = l1_eigenvalues(d)
+    e = np.real(eigs)
+    ed = e[:, None, None] + e[None, :, None] + e[None, None, :]
+    if np.min(np.abs(-ed - lam)) < 1e-3 * abs(lam):
+        return lam * (1.0 + 0.01j), True
+    return lam, False
+
+
+def homog_leaf_matrix(d: Disc, C_int: np.ndarray, ops=None):
+    """The homogenized leaf matrix: eq. (leaf) with C_ii replaced by lambda^tau I."""
+    lam, shifted = homog_lambda(d, C_int)
+    A, Gm = leaf_matrices(d, np.full(d.ni, lam), ops)
+    return A, Gm, lam, shifted
+
+
+class Precond:
+    """J^{-1}: block diagonal, each block the inverse of the homogenized leaf matrix.
+
+    Factorizes each needed leaf with dense LU on first use.
+    """
+
+    def __init__(self, d: Disc, b_nodes: np.ndarray):
+        self.d = d
+        self.C = c_values(d, b_nodes)
+        self.ops = local_ops(d)
+        self.lu = {}
+        self.lams = {}
+
+    def _factor(self, tau):
+        if tau not in self.lu:
+            d = self.d
+            A, _, lam, _ = homog_leaf_matrix(d, self.C[tau * d.n:tau * d.n + d.ni], self.ops)
+            self.lu[tau] = sla.lu_factor(A)
+            self.lams[tau] = lam
+        return self.lu[tau]
+
+    def apply_elems(self, x: np.ndarray, elems: Sequence[int]) -> dict:
+        d = self.d
+        return {tau: sla.lu_solve(self._factor(tau), x[tau * d.n:(tau + 1) * d.n])
+                for tau in elems}
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        d = self.d
+        y = np.zeros_like(x, dtype=np.complex128)
+        for tau, w in self.apply_elems(x, range(d.nl)).items():
+            y[tau * d.n:(tau + 1) * d.n] = w
+        return y
+
+
+# ----------------------------------------------------------------------------
+# solvers
+# ----------------------------------------------------------------------------
+
+def gmres_left(matvec, precond, b, tol=1e-10, restart=30, maxit=10000, x0=None):
+    """Restarted GMRES on J^{-1} A x = J^{-1} b, modified Gram-Schmidt, x0 = 0.
+
+    Stops when ||J^{-1}(b - A x)|| <= tol ||J^{-1} b|| (the paper's PCRR,
+    Sec. 6).  Returns (x, iterations, history of relative preconditioned residuals).
+    """
+    N = b.shape[0]
+    x = np.zeros(N, dtype=np.complex128) if x0 is None else x0.astype(np.complex128).copy()
+    pb = precond(b)
+    nb = np.linalg.norm(pb)
+    if nb == 0.0:
+        return x, 0, [0.0]
+    hist = []
+    its = 0
+    while True:
+        r = precond(b - matvec(x))
+        beta = np.linalg.norm(r)
+        hist.append(beta / nb)
+        if beta <= tol * nb or its >= maxit:
+            break
+        V = np.zeros((restart + 1, N), dtype=np.complex128)
+        H = np.zeros((restart + 1, restart), dtype=np.complex128)
+        V[0] = r / beta
+        g = np.zeros(restart + 1, dtype=np.complex128)
+        g[0] = beta
+        k_used = 0
+        y = np.zeros(0, dtype=np.complex128)
+        for j in range(restart):
+            w = precond(matvec(V[j]))
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            its += 1
+            k_used = j + 1
+            if H[j + 1, j] != 0:
+                V[j + 1] = w / H[j + 1, j]
+            # minimiser of ||g - H y|| for the current Hessenberg block
+            y, *_ = np.linalg.lstsq(H[:j + 2, :j + 1], g[:j + 2], rcond=None)
+            res = np.linalg.norm(g[:j + 2] - H[:j + 2, :j + 1] @ y)
+            if res <= tol * nb or H[j + 1, j] == 0 or its >= maxit:
+                break
+        x = x + V[:k_used].T @ y
+    return x, its, hist
+
+
+@dataclass
+class OracleProblem:
+    """The discrete problem for one Problem spec: disc, b at nodes, A, rhs."""
+    d: Disc
+    xyz: np.ndarray
+    b_nodes: np.ndarray
+    A: Optional[sp.csr_matrix]
+    rhs: np.ndarray
+
+
+def build(prob, with_matrix: bool = True, rhs_index: int = 0) -> OracleProblem:
+    """Discretize a problems.Problem with the oracle's own tables."""
+    from paper_2112_02211_amd import problems as P  # seeded input data only
+    d = make_disc(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi)
+    xyz = node_coords(d)
+    if prob.plane_dir is not None:
+        b_nodes = np.zeros(d.N, dtype=np.complex128)
+        s = np.zeros(d.N, dtype=np.complex128)
+        t = P.plane_wave_impedance(prob, xyz)
+    else:
+        b_nodes = P.bump_field(prob, xyz)
+        s = P.gaussian_source(prob, xyz, rhs_index)
+        t = np.zeros(d.N, dtype=np.complex128)
+    rhs = assemble_rhs(d, s, t)
+    A = assemble_global(d, b_nodes) if with_matrix else None
+    return OracleProblem(d, xyz, b_nodes, A, rhs)
+
+
+def solve_direct(op: OracleProblem, rhs: Optional[np.ndarray] = None) -> np.ndarray:
+    """u = A^{-1} b by a direct solve (dense LU up to 8000 unknowns, sparse LU above)."""
+    b = op.rhs if rhs is None else rhs
+    if op.d.N <= 8000:
+        return sla.solve(op.A.toarray(), b)
+    return spla.spsolve(op.A.tocsc(), b)
+
+
+def solve_gmres(op: OracleProblem, tol=1e-12, restart=50, maxit=20000):
+    """u from the oracle's own MGS-GMRES with the oracle's J^{-1}."""
+    M = Precond(op.d, op.b_nodes)
+    return gmres_left(lambda v: op.A @ v, M.apply, op.rhs, tol=tol, restart=restart, maxit=maxit)
+
+
+def rel_err(u_h: np.ndarray, u: np.ndarray) -> float:
+    """E_h of Sec. 6: sqrt(sum |u_h - u|^2) / sqrt(sum |u|^2) over all N nodes."""
+    return float(np.linalg.norm(u_h - u) / np.linalg.norm(u))
+
+
+def iti_map(d: Disc, C_int: np.ndarray, homogenized: bool = True) -> np.ndarray:
+    """Impedance-to-impedance map of one leaf from a dense leaf solve.
+
+    For incoming impedance data f on the leaf faces and zero source, solve the
+    (homogenized) leaf system for u and return the map f -> g = G u (Sec. 2.2).
+    """
+    if homogenized:
+        A, Gm, _, _ = homog_leaf_matrix(d, C_int)
+    else:
+        A, Gm = leaf_matrices(d, C_int)
+    rhs = np.zeros((d.n, d.nb), dtype=np.complex128)
+    rhs[d.ni:, :] = np.eye(d.nb)
+    U = np.linalg.solve(A, rhs)
+    return Gm @ U

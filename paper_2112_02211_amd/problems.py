@@ -1,0 +1,277 @@
+"""Seeded synthetic problem generators shared by the HIP path and the oracle.
+
+This module holds problem *data* only: the parameters of the Helmholtz
+boundary value problem (Sec. 1, eq. (diffhelm)) and pure functions of
+physical coordinates (medium b(x), source s(x), boundary impedance data
+t(x), closed-form solutions).  It contains none of the HPS method's
+arithmetic: no Chebyshev nodes, no differentiation matrices, no leaf or
+global operators.  Node coordinates always come from the caller (the
+library's own node table on the GPU side, the oracle's own on the CPU
+side), so each side evaluates the problem data independently.
+
+Random numbers are drawn with numpy's PCG64 (``default_rng(seed)``) in a
+fixed order: bump centres (k, 3), then bump amplitudes (k,), then source
+points (r, 3).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+BUMP_WIDTH = 0.08      # exp(-|x-c|^2 / w^2); 1/0.08^2 = 156, the paper's e^{-160 r^2} scale
+SOURCE_WIDTH = 0.03    # Gaussian point source width
+
+
+@dataclass
+class Problem:
+    """One Helmholtz impedance problem on an axis-aligned box of cubic leaves."""
+    name: str
+    n_elem: tuple                  # leaves per axis (E1, E2, E3)
+    p: int                         # Chebyshev nodes per leaf direction (the paper's n_c)
+    kappa: float
+    eta: float
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    bump_centres: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    bump_amps: np.ndarray = field(default_factory=lambda: np.zeros((0,), dtype=complex))
+    bump_width: float = BUMP_WIDTH
+    source_points: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    source_width: float = SOURCE_WIDTH
+    plane_dir: Optional[np.ndarray] = None   # if set: b=0, s=0, t from exp(i kappa d.x)
+    restart: int = 30
+    tol: float = 1e-10
+
+    @property
+    def q(self) -> int:
+        return self.p - 2
+
+    @property
+    def n_leaves(self) -> int:
+        return int(np.prod(self.n_elem))
+
+    @property
+    def n_per_leaf(self) -> int:
+        n1 = self.p - 2
+        return n1 ** 3 + 6 * n1 * n1
+
+    @property
+    def n_unknowns(self) -> int:
+        return self.n_leaves * self.n_per_leaf
+
+    @property
+    def nrhs(self) -> int:
+        return max(1, len(self.source_points))
+
+
+# ----------------------------------------------------------------------------
+# pure functions of coordinates
+# ----------------------------------------------------------------------------
+
+def bump_field(prob: Problem, xyz: np.ndarray) -> np.ndarray:
+    """b(x) = sum_k a_k exp(-|x - c_k|^2 / w^2) at points xyz (M, 3); complex."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    out = np.zeros(xyz.shape[0], dtype=np.complex128)
+    for c, a in zip(prob.bump_centres, prob.bump_amps):
+        r2 = np.sum((xyz - c[None, :]) ** 2, axis=1)
+        out += a * np.exp(-r2 / prob.bump_width ** 2)
+    return out
+
+
+def gaussian_source(prob: Problem, xyz: np.ndarray, which: int = 0) -> np.ndarray:
+    """s(x) = exp(-|x - x_s|^2 / w_s^2) for source point ``which``; complex."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    if len(prob.source_points) == 0:
+        return np.zeros(xyz.shape[0], dtype=np.complex128)
+    c = prob.source_points[which]
+    r2 = np.sum((xyz - c[None, :]) ** 2, axis=1)
+    return np.exp(-r2 / prob.source_width ** 2).astype(np.complex128)
+
+
+def boundary_normals(prob: Problem, xyz: np.ndarray, rtol: float = 1e-12) -> np.ndarray:
+    """Outward unit normal of the box at points lying on its boundary, else 0.
+
+    A point on an edge or corner would be ambiguous; the HPS node sets used
+    here never contain such points, and the function raises if one appears.
+    """
+    xyz = np.asarray(xyz, dtype=np.float64)
+    lo = np.asarray(prob.lo, dtype=np.float64)
+    hi = np.asarray(prob.hi, dtype=np.float64)
+    scale = rtol * max(1.0, float(np.max(np.abs(hi - lo))))
+    nrm = np.zeros_like(xyz)
+    on_lo = np.abs(xyz - lo[None, :]) <= scale
+    on_hi = np.abs(xyz - hi[None, :]) <= scale
+    nrm[on_lo] = -1.0
+    nrm[on_hi] = 1.0
+    if np.any(np.sum(on_lo | on_hi, axis=1) > 1):
+        raise ValueError("point on an edge or corner of the box")
+    return nrm
+
+
+def plane_wave(prob: Problem, xyz: np.ndarray) -> np.ndarray:
+    """u(x) = exp(i kappa d.x), an exact solution of the b=0, s=0 problem."""
+    d = np.asarray(prob.plane_dir, dtype=np.float64)
+    return np.exp(1j * prob.kappa * (np.asarray(xyz) @ d))
+
+
+def plane_wave_impedance(prob: Problem, xyz: np.ndarray) -> np.ndarray:
+    """t = du/dn + i eta u of the plane wave at boundary points (0 elsewhere)."""
+    d = np.asarray(prob.plane_dir, dtype=np.float64)
+    nrm = boundary_normals(prob, xyz)
+    u = plane_wave(prob, xyz)
+    on = np.any(nrm != 0.0, axis=1)
+    t = (1j * prob.kappa * (nrm @ d) + 1j * prob.eta) * u
+    return np.where(on, t, 0.0)
+
+
+# ---- a polynomial field with analytic derivatives (for reproduction checks) --
+
+@dataclass
+class PolyField:
+    """u(x,y,z) = sum_{a,b,c} coef[a,b,c] x^a y^b z^c (complex coefficients)."""
+    coef: np.ndarray  # (dx+1, dy+1, dz+1) complex
+
+    def _eval(self, xyz: np.ndarray, dx: int = 0, dy: int = 0, dz: int = 0) -> np.ndarray:
+        x, y, z = (np.asarray(xyz, dtype=np.float64)[:, i] for i in range(3))
+        out = np.zeros(x.shape, dtype=np.complex128)
+        A, B, Cc = self.coef.shape
+        for a in range(A):
+            fa = _dpow(x, a, dx)
+            if fa is None:
+                continue
+            for b in range(B):
+                fb = _dpow(y, b, dy)
+                if fb is None:
+                    continue
+                for c in range(Cc):
+                    fc = _dpow(z, c, dz)
+                    if fc is None:
+                        continue
+                    out += self.coef[a, b, c] * fa * fb * fc
+        return out
+
+    def value(self, xyz):
+        return self._eval(xyz)
+
+    def grad(self, xyz):
+        return np.stack([self._eval(xyz, 1, 0, 0), self._eval(xyz, 0, 1, 0),
+                         self._eval(xyz, 0, 0, 1)], axis=1)
+
+    def laplacian(self, xyz):
+        return self._eval(xyz, 2, 0, 0) + self._eval(xyz, 0, 2, 0) + self._eval(xyz, 0, 0, 2)
+
+
+def _dpow(x: np.ndarray, a: int, d: int):
+    """d-th derivative of x**a, or None if identically zero."""
+    if d > a:
+        return None
+    k = 1.0
+    for j in range(d):
+        k *= (a - j)
+    return k * x ** (a - d)
+
+
+def random_poly(seed: int, degree: int) -> PolyField:
+    """Random complex polynomial of degree <= ``degree`` in each variable."""
+    rng = np.random.default_rng(seed)
+    shp = (degree + 1,) * 3
+    coef = rng.uniform(-1, 1, shp) + 1j * rng.uniform(-1, 1, shp)
+    # damp high-order terms so values stay O(1) on the unit cube
+    idx = np.indices(shp).sum(axis=0)
+    coef = coef / (1.0 + idx) ** 2
+    return PolyField(coef)
+
+
+def poly_rhs(prob: Problem, poly: PolyField, b_at: np.ndarray, xyz: np.ndarray):
+    """Data (s, t) for which ``poly`` solves the BVP of eq. (diffhelm).
+
+    s = -Lap u - kappa^2 (1 - b) u at every point, t = du/dn + i eta u at
+    boundary points (0 elsewhere).  ``b_at`` is b at the same points.
+    """
+    u = poly.value(xyz)
+    s = -poly.laplacian(xyz) - prob.kappa ** 2 * (1.0 - b_at) * u
+    nrm = boundary_normals(prob, xyz)
+    on = np.any(nrm != 0.0, axis=1)
+    dudn = np.sum(poly.grad(xyz) * nrm, axis=1)
+    t = np.where(on, dudn + 1j * prob.eta * u, 0.0)
+    return s, t
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+
+def _cube_leaf_box(n_elem) -> tuple:
+    """Upper corner of the box [0, E/max(E)] whose leaves are cubes of side 1/max(E)."""
+    m = float(max(n_elem))
+    return tuple(float(e) / m for e in n_elem)
+
+
+def _bumps_and_sources(rng, k: int, r: int):
+    centres = rng.uniform(0.2, 0.8, (k, 3))
+    amps = rng.uniform(-0.5, 0.5, k).astype(np.complex128)
+    pts = rng.uniform(0.2, 0.8, (r, 3))
+    return centres, amps, pts
+
+
+def plane_wave_problem(n_elem=(2, 2, 2), p=8, kappa=10.0, restart=30, tol=1e-10) -> Problem:
+    """b=0, s=0, t chosen so exp(i kappa d.x), d=(1,2,2)/3, is the exact solution."""
+    return Problem(name="plane_wave", n_elem=tuple(n_elem), p=p, kappa=kappa, eta=kappa,
+                   hi=_cube_leaf_box(n_elem), plane_dir=np.array([1.0, 2.0, 2.0]) / 3.0, restart=restart, tol=tol)
+
+
+def bump_problem(name, n_elem, p, kappa, n_bumps, n_sources, seed, restart, tol) -> Problem:
+    """Gaussian-bump medium with Gaussian point sources and t=0."""
+    rng = np.random.default_rng(seed)
+    c, a, pts = _bumps_and_sources(rng, n_bumps, n_sources)
+    return Problem(name=name, n_elem=tuple(n_elem), p=p, kappa=kappa, eta=kappa,
+                   hi=_cube_leaf_box(n_elem), bump_centres=c, bump_amps=a,
+                   source_points=pts, restart=restart, tol=tol)
+
+
+def workload(name: str) -> Problem:
+    """The named synthetic workloads (plane wave, bump media, batched sources)."""
+    if name == "plane_2x2x2_p8":
+        return plane_wave_problem((2, 2, 2), 8, 10.0, restart=30, tol=1e-10)
+    if name == "bumps_8x8x8_p10":
+        return bump_problem(name, (8, 8, 8), 10, 40.0, 6, 1, seed=2, restart=50, tol=1e-8)
+    if name == "bumps_16x16x16_p12":
+        return bump_problem(name, (16, 16, 16), 12, 80.0, 20, 1, seed=3, restart=50, tol=1e-8)
+    if name == "bumps_16x16x16_p10_64rhs":
+        return bump_problem(name, (16, 16, 16), 10, 60.0, 6, 64, seed=4, restart=30, tol=1e-8)
+    raise KeyError(name)
+
+
+@dataclass
+class Request:
+    """One solve request of the serving stream."""
+    rid: int
+    arrival: float       # seconds after stream start
+    prob: Problem
+
+
+def request_stream(n_requests: int = 512, rate: float = 20.0, seed: int = 5,
+                   meshes=(4, 8, 12, 16), orders=(8, 10)) -> List[Request]:
+    """Poisson stream of solve requests with mixed meshes, orders and media.
+
+    Each request draws: E1 from ``meshes``, p from ``orders``, points per
+    wavelength ppw ~ U[8, 12] with kappa = 2 pi E1 p / ppw, a bump count
+    in {5..20}, bump centres/amplitudes, and one Gaussian source.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        e1 = int(rng.choice(meshes))
+        p = int(rng.choice(orders))
+        ppw = rng.uniform(8.0, 12.0)
+        kappa = 2.0 * math.pi * e1 * p / ppw
+        k = int(rng.integers(5, 21))
+        c, a, pts = _bumps_and_sources(rng, k, 1)
+        prob = Problem(name=f"req{rid}", n_elem=(e1, e1, e1), p=p, kappa=kappa, eta=kappa,
+                       bump_centres=c, bump_amps=a, source_points=pts, restart=50, tol=1e-8)
+        out.append(Request(rid, t, prob))
+    return out
