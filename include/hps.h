@@ -1,0 +1,184 @@
+/*
+ * hps.h - C-ABI of the MI355X (gfx950) hot path of the iterative HPS solver for
+ * the variable-coefficient Helmholtz impedance problem
+ *
+ *     -Lap u - kappa^2 (1 - b(x)) u = s   in a box Omega,
+ *      du/dn + i eta u              = t   on its boundary        (Sec. 1, eq. (diffhelm))
+ *
+ * discretized by the Hierarchical Poincare-Steklov method on a uniform mesh of
+ * cubic leaves (Sec. 2) and solved by GMRES with the locally homogenized
+ * block-Jacobi preconditioner (Sec. 4).  Paper: Lucero Lorca, Beams, Beecroft,
+ * Gillman, arXiv 2112.02211.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Unknowns.  p Chebyshev-Lobatto nodes per leaf direction (the paper's n_c),
+ *   n1 = q = p - 2, n_i = n1^3 interior and n_b = 6 n1^2 face nodes per leaf,
+ *   n = n_i + n_b per leaf, N = n * (number of leaves).  Leaves own their face
+ *   nodes, so interior interfaces carry two copies (Sec. 3.1, remark).
+ * Layout.  Leaves are numbered x fastest: tau = ex + E1 (ey + E2 ez).  A vector
+ *   is leaf-major: [leaf][local node].  Inside a leaf: the n_i interior nodes
+ *   (x fastest, then y, then z), then faces 1..6 = -x,+x,-y,+y,-z,+z (eq.
+ *   (flux)), each face's n1^2 nodes ordered in its two tangential axes, the
+ *   lower axis fastest.  Several right-hand sides are stored one after the
+ *   other: vector r occupies elements [r*N, (r+1)*N).
+ * Complex numbers are interleaved (re, im) doubles (hps_z).
+ * Memory.  Pointers named "device" are HIP device memory owned by the caller;
+ *   the library reads or writes them during the call (stream ordered) and never
+ *   keeps them.  The context owns everything else it allocates and releases it
+ *   in hps_free.
+ * Streams.  Every call is ordered on the stream set in hps_opts (or
+ *   hps_set_stream); 0 means the default stream.  A context is not thread
+ *   safe; calls on different contexts may run concurrently.
+ * Errors.  0 = HPS_OK.  HPS_NOT_CONVERGED (1): the solver stopped at its
+ *   iteration limit; outputs hold the last iterate and the stats are filled.
+ *   Negative values are errors; the message is in hps_last_error() (thread
+ *   local) and outputs are unspecified.
+ */
+#ifndef HPS_H
+#define HPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPS_OK 0
+#define HPS_NOT_CONVERGED 1
+#define HPS_ERR_ARG (-1)
+#define HPS_ERR_UNSUPPORTED (-2)
+#define HPS_ERR_OOM (-3)
+#define HPS_ERR_DEVICE (-4)
+#define HPS_ERR_BREAKDOWN (-5)
+#define HPS_ERR_NUMERIC (-6)
+
+typedef struct hps_ctx hps_ctx;
+typedef struct { double re, im; } hps_z;
+
+/* Axis-aligned box Omega = [lo, hi]; hi - lo must be the same multiple of
+ * the leaf side on every axis (cubic leaves, Sec. 2 remark on uniform meshes). */
+typedef struct { double lo[3], hi[3]; } hps_domain;
+
+/* Medium b(x) of eq. (diffhelm). */
+#define HPS_MEDIUM_ZERO 0   /* b = 0 */
+#define HPS_MEDIUM_NODAL 1  /* nodal: device array of N complex values in library node order */
+#define HPS_MEDIUM_BUMPS 2  /* b(x) = sum_k amp_k exp(-|x - c_k|^2 / width^2) */
+typedef struct {
+  int kind;
+  int n_bumps;
+  const double* centres; /* host, n_bumps x 3 */
+  const hps_z* amps;     /* host, n_bumps */
+  double width;
+  const hps_z* nodal;    /* device, N values (HPS_MEDIUM_NODAL) */
+} hps_medium;
+
+/* Storage precisions of the dense per-leaf blocks S~^{tau,-1} (Sec. 4, eq.
+ * (schur_pc)); a bit mask in hps_opts.block_precs selects which are built. */
+#define HPS_PREC_FP64 1
+#define HPS_PREC_FP32 2
+#define HPS_PREC_BF16 4
+
+typedef struct {
+  int block_precs;     /* OR of HPS_PREC_*; 0 means HPS_PREC_FP64 */
+  void* stream;        /* hipStream_t; 0 = default stream */
+  int verbose;         /* nonzero: setup timings on stderr */
+} hps_opts;
+
+/* Solvers for hps_gmres. */
+#define HPS_SOLVER_GMRES 0   /* left preconditioned GMRES(m) on J^-1 A x = J^-1 b (eq. (globalsystem)), FP64 */
+#define HPS_SOLVER_FGMRES 1  /* right preconditioned flexible GMRES(m), FP64 outer; J^-1 in precond_prec */
+#define HPS_SOLVER_BLOCK 2   /* block GMRES(m) over all right-hand sides together */
+
+typedef struct {
+  int solver;          /* HPS_SOLVER_* (default GMRES) */
+  int max_iters;       /* total Arnoldi steps; 0 = 20000 */
+  int use_x0;          /* nonzero: u holds the initial guess on entry */
+  int precond_prec;    /* HPS_PREC_* used inside J^-1 (must have been built); 0 = FP64 */
+  int check_every;     /* host convergence poll interval in iterations; 0 = 1 */
+} hps_solve_opts;
+
+typedef struct {
+  int iters;            /* Arnoldi steps taken (per right-hand side for lock-step solves) */
+  int restarts;
+  int converged;
+  int lambda_shifted;   /* number of leaves whose lambda was moved off a resonance */
+  double rel_res;       /* final residual estimate, relative (preconditioned for GMRES) */
+  double true_rel_res;  /* recomputed at the end from x: same norm as rel_res */
+  double t_solve;       /* seconds, host wall clock around the solve */
+  double bytes_apply;   /* algorithmic HBM bytes of one hps_apply */
+  double bytes_precond; /* algorithmic HBM bytes of one hps_precond */
+} hps_stats;
+
+/* Build a context: node tables, medium at the nodes, C = kappa^2 (1 - b),
+ * lambda^tau (Sec. 4.1), and every block S~^{tau,-1} (Sec. 5.1: precomputed
+ * before the iteration), in the precisions asked for.
+ *   d        box; n_elem[3] leaves per axis (each >= 1)
+ *   kappa    wave number (> 0); eta impedance parameter (the paper sets eta = kappa)
+ *   b        medium (NULL = zero)
+ *   p, q     Chebyshev nodes per leaf direction (3 <= p <= 16) and face nodes per
+ *            face edge; q must equal p - 2 (HPS_ERR_UNSUPPORTED otherwise)
+ *   o        options (NULL = defaults)
+ *   out      receives the context.
+ * Errors: HPS_ERR_ARG (bad sizes, non-cubic leaves), HPS_ERR_UNSUPPORTED,
+ * HPS_ERR_OOM, HPS_ERR_DEVICE, HPS_ERR_NUMERIC (a singular leaf block). */
+int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b,
+              int p, int q, const int n_elem[3], const hps_opts* o, hps_ctx** out);
+
+/* N = (#leaves) * (p-2)^2 (p+4). */
+int64_t hps_num_unknowns(const hps_ctx* c);
+
+/* Physical coordinates of the N unknowns, library order; xyz_host is N x 3 host doubles. */
+int hps_nodes(const hps_ctx* c, double* xyz_host);
+
+/* Per-leaf homogenization constant lambda^tau (after the resonance guard);
+ * lam_host receives (#leaves) complex values. */
+int hps_lambdas(const hps_ctx* c, hps_z* lam_host);
+
+/* Set the stream used by subsequent calls (hipStream_t; 0 = default). */
+int hps_set_stream(hps_ctx* c, void* stream);
+
+/* y = A x (Sec. 3.2, Algorithm 2): leaf rows by tensor-product contractions
+ * (Algorithm 1, eq. (leafmat)) plus the outgoing impedance of each neighbour
+ * on shared faces (eq. (outgoingimpedance)).  x, y: device, nrhs * N complex;
+ * must not overlap. */
+int hps_apply(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
+
+/* y = J^{-1} x (Sec. 4, Algorithm 4, eq. (block_pc)) with the FP64 blocks.
+ * x, y: device, nrhs * N complex; must not overlap. */
+int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
+
+/* As hps_precond with the blocks stored in precision prec (HPS_PREC_*; must
+ * have been built).  Reduced-precision blocks are applied with FP32 arithmetic. */
+int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec);
+
+/* Right-hand side b of Sec. 3.1: s at interior nodes, t at face nodes on the
+ * boundary of Omega, 0 at interface nodes.  s, t, b: device, nrhs * N complex
+ * in library node order (entries of s and t at other nodes are ignored). */
+int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int nrhs);
+
+/* Solve A u = b(s, t) (Sec. 4, eq. (globalsystem)) by the solver in so.
+ *   s, t     device, nrhs * N complex (see hps_assemble_rhs)
+ *   tol      relative residual target: ||J^-1 r|| <= tol ||J^-1 b|| for
+ *            HPS_SOLVER_GMRES (the paper's PCRR, Sec. 6), ||r|| <= tol ||b||
+ *            for FGMRES and BLOCK (each right-hand side)
+ *   restart  Krylov dimension m per cycle (1..200)
+ *   u        device, nrhs * N complex: the solution (initial guess if use_x0)
+ *   so       NULL = defaults; st may be NULL.
+ * Returns HPS_OK, HPS_NOT_CONVERGED, or an error. */
+int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
+              hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st);
+
+/* Device bytes held by the context (blocks, tables, workspaces). */
+int64_t hps_device_bytes(const hps_ctx* c);
+
+/* Message of the last error on this thread ("" if none). */
+const char* hps_last_error(void);
+
+/* Release a context (NULL is ignored). */
+void hps_free(hps_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_H */

@@ -1,0 +1,380 @@
+// C-ABI entry points: context setup and teardown, node table, and the
+// stream-ordered wrappers of the hot-path operators.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hps_internal.h"
+#include "hps_krylov.h"
+#include "k_common.h"
+
+namespace hps {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return HPS_OK;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return (e == hipErrorOutOfMemory) ? HPS_ERR_OOM : HPS_ERR_DEVICE;
+}
+
+int dev_alloc(hps_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return HPS_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? HPS_ERR_OOM : HPS_ERR_DEVICE,
+                "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->dev_bytes += bytes;
+  return HPS_OK;
+}
+
+int ws_reserve(hps_ctx* c, Workspace* w, size_t bytes) {
+  if (w->bytes >= bytes) return HPS_OK;
+  if (w->ptr) {
+    HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+    HPS_TRY_HIP(hipFree(w->ptr));
+    c->dev_bytes -= w->bytes;
+    w->ptr = nullptr;
+    w->bytes = 0;
+  }
+  int rc = dev_alloc(c, &w->ptr, bytes);
+  if (rc) return rc;
+  w->bytes = bytes;
+  return HPS_OK;
+}
+
+namespace {
+
+int prec_index(int prec_flag) {
+  switch (prec_flag) {
+    case HPS_PREC_FP64: return kFP64;
+    case HPS_PREC_FP32: return kFP32;
+    case HPS_PREC_BF16: return kBF16;
+    default: return -1;
+  }
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Inverse of every homogenized Schur complement S~^tau, packed per precision.
+int build_blocks(hps_ctx* c, int precs) {
+  const int nb = c->nb;
+  for (int q = 0; q < 3; ++q) {
+    if (!(precs & (1 << q))) continue;
+    const int cw = block_cw(q);
+    Blocks& B = c->blk[q];
+    B.ncp = (nb + cw - 1) / cw * cw;
+    B.bytes = (size_t)c->nl * B.ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
+    int rc = dev_alloc(c, &B.data, B.bytes);
+    if (rc) return rc;
+  }
+  // shared real factors P, Q on the device
+  double *dP = nullptr, *dQ = nullptr;
+  int rc = dev_alloc(c, (void**)&dP, sizeof(double) * c->tab.P.size());
+  if (rc) return rc;
+  rc = dev_alloc(c, (void**)&dQ, sizeof(double) * c->tab.Q.size());
+  if (rc) return rc;
+  HPS_TRY_HIP(hipMemcpyAsync(dP, c->tab.P.data(), sizeof(double) * c->tab.P.size(),
+                             hipMemcpyHostToDevice, c->stream));
+  HPS_TRY_HIP(hipMemcpyAsync(dQ, c->tab.Q.data(), sizeof(double) * c->tab.Q.size(),
+                             hipMemcpyHostToDevice, c->stream));
+  const size_t blk_bytes = (size_t)nb * nb * sizeof(double2);
+  int64_t chunk = (int64_t)((1ull << 30) / blk_bytes);
+  if (chunk < 1) chunk = 1;
+  if (chunk > c->nl) chunk = c->nl;
+  double2* S = nullptr;
+  rocblas_int *ipiv = nullptr, *info = nullptr;
+  rc = dev_alloc(c, (void**)&S, blk_bytes * chunk);
+  if (rc) return rc;
+  rc = dev_alloc(c, (void**)&ipiv, sizeof(rocblas_int) * nb * chunk);
+  if (rc) return rc;
+  rc = dev_alloc(c, (void**)&info, sizeof(rocblas_int) * chunk);
+  if (rc) return rc;
+  rocblas_handle handle;
+  if (rocblas_create_handle(&handle) != rocblas_status_success)
+    return fail(HPS_ERR_DEVICE, "rocblas_create_handle failed");
+  rocblas_set_stream(handle, c->stream);
+  std::vector<rocblas_int> hinfo(chunk);
+  int status = HPS_OK;
+  for (int64_t e0 = 0; e0 < c->nl && status == HPS_OK; e0 += chunk) {
+    const int ne = (int)std::min<int64_t>(chunk, c->nl - e0);
+    status = launch_build_schur(c, dP, dQ, (int)e0, ne, S);
+    if (status) break;
+    auto* A = reinterpret_cast<rocblas_double_complex*>(S);
+    if (rocsolver_zgetrf_strided_batched(handle, nb, nb, A, nb, (rocblas_stride)nb * nb, ipiv, nb,
+                                         info, ne) != rocblas_status_success) {
+      status = fail(HPS_ERR_DEVICE, "rocsolver getrf failed");
+      break;
+    }
+    hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * ne, hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int i = 0; i < ne; ++i)
+      if (hinfo[i] != 0) {
+        status = fail(HPS_ERR_NUMERIC, "homogenized Schur complement of leaf " +
+                                           std::to_string(e0 + i) + " is singular");
+        break;
+      }
+    if (status) break;
+    if (rocsolver_zgetri_strided_batched(handle, nb, A, nb, (rocblas_stride)nb * nb, ipiv, nb, info,
+                                         ne) != rocblas_status_success) {
+      status = fail(HPS_ERR_DEVICE, "rocsolver getri failed");
+      break;
+    }
+    for (int q = 0; q < 3 && status == HPS_OK; ++q)
+      if (c->blk[q].data) status = launch_pack_blocks(c, S, (int)e0, ne, q);
+  }
+  hipStreamSynchronize(c->stream);
+  rocblas_destroy_handle(handle);
+  hipFree(S);
+  hipFree(ipiv);
+  hipFree(info);
+  hipFree(dP);
+  hipFree(dQ);
+  c->dev_bytes -= blk_bytes * chunk + sizeof(rocblas_int) * (nb + 1) * chunk +
+                  sizeof(double) * (c->tab.P.size() + c->tab.Q.size());
+  if (status == HPS_OK) status = check_hip(hipGetLastError(), "block build");
+  return status;
+}
+
+}  // namespace
+}  // namespace hps
+
+using namespace hps;
+
+extern "C" {
+
+const char* hps_last_error(void) { return g_err.c_str(); }
+
+int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b, int p, int q,
+              const int n_elem[3], const hps_opts* o, hps_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(HPS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d || !n_elem) return fail(HPS_ERR_ARG, "domain or n_elem is NULL");
+  if (p < kMinP || p > kMaxP) return fail(HPS_ERR_UNSUPPORTED, "p must lie in [4, 16]");
+  if (q != p - 2) return fail(HPS_ERR_UNSUPPORTED, "q must equal p - 2 (face nodes are the interior Chebyshev nodes of each face)");
+  if (!(kappa > 0.0) || !std::isfinite(kappa) || !std::isfinite(eta) || eta == 0.0)
+    return fail(HPS_ERR_ARG, "kappa must be positive and eta nonzero");
+  double hs[3];
+  for (int a = 0; a < 3; ++a) {
+    if (n_elem[a] < 1) return fail(HPS_ERR_ARG, "n_elem must be >= 1");
+    hs[a] = (d->hi[a] - d->lo[a]) / n_elem[a];
+    if (!(hs[a] > 0.0)) return fail(HPS_ERR_ARG, "empty domain");
+  }
+  if (std::fabs(hs[1] - hs[0]) > 1e-12 * hs[0] || std::fabs(hs[2] - hs[0]) > 1e-12 * hs[0])
+    return fail(HPS_ERR_ARG, "leaves must be cubes");
+  if (b && b->kind == HPS_MEDIUM_BUMPS && b->n_bumps > 0 &&
+      (!b->centres || !b->amps || !(b->width > 0.0)))
+    return fail(HPS_ERR_ARG, "bump medium needs centres, amplitudes and a positive width");
+  if (b && b->kind == HPS_MEDIUM_NODAL && !b->nodal) return fail(HPS_ERR_ARG, "nodal medium is NULL");
+  if (b && (b->kind < 0 || b->kind > 2)) return fail(HPS_ERR_ARG, "unknown medium kind");
+  const int precs = (o && o->block_precs) ? o->block_precs : HPS_PREC_FP64;
+  if (precs & ~7) return fail(HPS_ERR_ARG, "unknown block precision bits");
+
+  const double t0 = now();
+  hps_ctx* c = new hps_ctx();
+  c->p = p;
+  c->n1 = p - 2;
+  c->ni = c->n1 * c->n1 * c->n1;
+  c->nb = 6 * c->n1 * c->n1;
+  c->n = c->ni + c->nb;
+  for (int a = 0; a < 3; ++a) { c->E[a] = n_elem[a]; c->lo[a] = d->lo[a]; }
+  c->nl = (int64_t)n_elem[0] * n_elem[1] * n_elem[2];
+  c->N = c->nl * c->n;
+  c->kappa = kappa;
+  c->eta = eta;
+  c->h = hs[0];
+  c->stream = o ? static_cast<hipStream_t>(o->stream) : nullptr;
+  c->verbose = o ? o->verbose : 0;
+  hipGetDevice(&c->device);
+
+  auto bail = [&](int rc) {
+    hps_free(c);
+    return rc;
+  };
+  std::string err = build_tables(p, c->h, &c->tab);
+  if (!err.empty()) return bail(fail(HPS_ERR_NUMERIC, err));
+
+  // packed table D | D2 | V | W | E | xi | Ed3
+  std::vector<double> tab(tab_size(p), 0.0);
+  std::copy(c->tab.D.begin(), c->tab.D.end(), tab.begin() + tab_off_D(p));
+  std::copy(c->tab.D2.begin(), c->tab.D2.end(), tab.begin() + tab_off_D2(p));
+  std::copy(c->tab.V.begin(), c->tab.V.end(), tab.begin() + tab_off_V(p));
+  std::copy(c->tab.W.begin(), c->tab.W.end(), tab.begin() + tab_off_W(p));
+  std::copy(c->tab.E.begin(), c->tab.E.end(), tab.begin() + tab_off_E(p));
+  std::copy(c->tab.xi.begin(), c->tab.xi.end(), tab.begin() + tab_off_xi(p));
+  const int n1 = c->n1;
+  for (int k = 0; k < n1; ++k)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n1; ++i)
+        tab[tab_off_ed3(p) + i + n1 * (j + n1 * k)] = c->tab.E[i] + c->tab.E[j] + c->tab.E[k];
+  int rc = dev_alloc(c, (void**)&c->d_tab, sizeof(double) * tab.size());
+  if (rc) return bail(rc);
+  if ((rc = check_hip(hipMemcpyAsync(c->d_tab, tab.data(), sizeof(double) * tab.size(),
+                                     hipMemcpyHostToDevice, c->stream), "upload tables")))
+    return bail(rc);
+  c->dt = DevTables{c->d_tab + tab_off_D(p), c->d_tab + tab_off_D2(p), c->d_tab + tab_off_V(p),
+                    c->d_tab + tab_off_W(p), c->d_tab + tab_off_E(p)};
+
+  // neighbour table, leaves numbered x fastest
+  std::vector<int> nbr(c->nl * 6);
+  for (int64_t t = 0; t < c->nl; ++t) {
+    const int e[3] = {(int)(t % c->E[0]), (int)((t / c->E[0]) % c->E[1]),
+                      (int)(t / ((int64_t)c->E[0] * c->E[1]))};
+    for (int f = 0; f < 6; ++f) {
+      int g[3] = {e[0], e[1], e[2]};
+      const int ax = face_axis(f);
+      g[ax] += face_high(f) ? 1 : -1;
+      nbr[t * 6 + f] = (g[ax] < 0 || g[ax] >= c->E[ax])
+                           ? -1
+                           : (int)(g[0] + (int64_t)c->E[0] * (g[1] + (int64_t)c->E[1] * g[2]));
+    }
+  }
+  if ((rc = dev_alloc(c, (void**)&c->d_nbr, sizeof(int) * nbr.size()))) return bail(rc);
+  if ((rc = check_hip(hipMemcpyAsync(c->d_nbr, nbr.data(), sizeof(int) * nbr.size(),
+                                     hipMemcpyHostToDevice, c->stream), "upload neighbours")))
+    return bail(rc);
+
+  // medium: C = kappa^2 (1 - b) at interior nodes
+  int nbump = 0;
+  double* d_bc = nullptr;
+  double2* d_ba = nullptr;
+  c->c_complex = 0;
+  if (b && b->kind == HPS_MEDIUM_NODAL) c->c_complex = 1;
+  if (b && b->kind == HPS_MEDIUM_BUMPS && b->n_bumps > 0) {
+    nbump = b->n_bumps;
+    for (int i = 0; i < nbump; ++i)
+      if (b->amps[i].im != 0.0) c->c_complex = 1;
+    if ((rc = dev_alloc(c, (void**)&d_bc, sizeof(double) * 3 * nbump))) return bail(rc);
+    if ((rc = dev_alloc(c, (void**)&d_ba, sizeof(double2) * nbump))) return bail(rc);
+    hipMemcpyAsync(d_bc, b->centres, sizeof(double) * 3 * nbump, hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(d_ba, b->amps, sizeof(double2) * nbump, hipMemcpyHostToDevice, c->stream);
+  }
+  const size_t cbytes = (size_t)c->nl * c->ni * (c->c_complex ? 16 : 8);
+  if ((rc = dev_alloc(c, &c->d_C, cbytes))) return bail(rc);
+  if ((rc = launch_eval_medium(c, b, d_bc, d_ba, nbump))) return bail(rc);
+  if ((rc = dev_alloc(c, (void**)&c->d_lambda, sizeof(double2) * c->nl))) return bail(rc);
+  if ((rc = launch_lambda(c))) return bail(rc);
+  if (d_bc) { hipFree(d_bc); c->dev_bytes -= sizeof(double) * 3 * nbump; }
+  if (d_ba) { hipFree(d_ba); c->dev_bytes -= sizeof(double2) * nbump; }
+  const double t1 = now();
+  // dense homogenized blocks
+  int pb = 0;
+  if (precs & HPS_PREC_FP64) pb |= 1 << kFP64;
+  if (precs & HPS_PREC_FP32) pb |= 1 << kFP32;
+  if (precs & HPS_PREC_BF16) pb |= 1 << kBF16;
+  if ((rc = build_blocks(c, pb))) return bail(rc);
+  if ((rc = check_hip(hipStreamSynchronize(c->stream), "setup"))) return bail(rc);
+  if (c->verbose)
+    std::fprintf(stderr, "[hps] setup: tables+medium %.3f s, blocks %.3f s, %.2f GB on device\n",
+                 t1 - t0, now() - t1, c->dev_bytes / 1e9);
+  *out = c;
+  return HPS_OK;
+}
+
+void hps_free(hps_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  hipFree(c->d_tab);
+  hipFree(c->d_nbr);
+  hipFree(c->d_C);
+  hipFree(c->d_lambda);
+  for (auto& B : c->blk) hipFree(B.data);
+  hipFree(c->w_g.ptr);
+  hipFree(c->w_red.ptr);
+  hipFree(c->w_krylov.ptr);
+  hipFree(c->w_small.ptr);
+  if (c->h_pinned) hipHostFree(c->h_pinned);
+  delete c;
+}
+
+int64_t hps_num_unknowns(const hps_ctx* c) { return c ? c->N : -1; }
+
+int64_t hps_device_bytes(const hps_ctx* c) { return c ? (int64_t)c->dev_bytes : -1; }
+
+int hps_set_stream(hps_ctx* c, void* stream) {
+  if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
+  c->stream = static_cast<hipStream_t>(stream);
+  return HPS_OK;
+}
+
+int hps_nodes(const hps_ctx* c, double* xyz) {
+  if (!c || !xyz) return fail(HPS_ERR_ARG, "NULL argument");
+  const int p = c->p, n1 = c->n1, L = n1 * n1;
+  std::vector<int> gi(c->n * 3);
+  for (int m = 0; m < c->n; ++m) {
+    int g[3];
+    if (m < c->ni) {
+      g[0] = m % n1 + 1; g[1] = (m / n1) % n1 + 1; g[2] = m / L + 1;
+    } else {
+      const int mm = m - c->ni, f = mm / L, r = mm % L;
+      const int ax = face_axis(f);
+      int t1 = -1, t2 = -1;
+      for (int a = 0; a < 3; ++a)
+        if (a != ax) { if (t1 < 0) t1 = a; else t2 = a; }
+      g[ax] = face_high(f) ? p - 1 : 0;
+      g[t1] = r % n1 + 1;
+      g[t2] = r / n1 + 1;
+    }
+    for (int a = 0; a < 3; ++a) gi[m * 3 + a] = g[a];
+  }
+  for (int64_t t = 0; t < c->nl; ++t) {
+    const int64_t e[3] = {t % c->E[0], (t / c->E[0]) % c->E[1], t / ((int64_t)c->E[0] * c->E[1])};
+    for (int m = 0; m < c->n; ++m)
+      for (int a = 0; a < 3; ++a)
+        xyz[(t * c->n + m) * 3 + a] =
+            c->lo[a] + c->h * ((double)e[a] + 0.5 * (c->tab.xi[gi[m * 3 + a]] + 1.0));
+  }
+  return HPS_OK;
+}
+
+int hps_lambdas(const hps_ctx* c, hps_z* lam) {
+  if (!c || !lam) return fail(HPS_ERR_ARG, "NULL argument");
+  int rc = check_hip(hipMemcpyAsync(lam, c->d_lambda, sizeof(double2) * c->nl, hipMemcpyDeviceToHost,
+                                    c->stream), "lambda copy");
+  if (rc) return rc;
+  return check_hip(hipStreamSynchronize(c->stream), "lambda copy");
+}
+
+int hps_apply(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
+  if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_apply");
+  return launch_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nrhs);
+}
+
+int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec) {
+  if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_precond");
+  const int q = prec_index(prec);
+  if (q < 0) return fail(HPS_ERR_ARG, "unknown precision");
+  return launch_precond(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nrhs, q);
+}
+
+int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
+  return hps_precond_prec(c, x, y, nrhs, HPS_PREC_FP64);
+}
+
+int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int nrhs) {
+  if (!c || !s || !t || !b || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_assemble_rhs");
+  return launch_assemble_rhs(c, reinterpret_cast<const double2*>(s),
+                             reinterpret_cast<const double2*>(t), reinterpret_cast<double2*>(b), nrhs);
+}
+
+}  // extern "C"

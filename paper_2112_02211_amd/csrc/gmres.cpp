@@ -1,0 +1,310 @@
+// GMRES drivers for A u = b (Sec. 4, eq. (globalsystem); Sec. 5.2 uses a
+// restarted GMRES with matrix-free operator and preconditioner shells).
+//
+//  * left preconditioned GMRES(m) on J^{-1} A x = J^{-1} b in FP64, stopping on
+//    the preconditioned residual reduction ||J^{-1}(b - A x)|| <= tol ||J^{-1} b||
+//    (the PCRR of Sec. 6), x0 = 0 unless an initial guess is given;
+//  * right preconditioned flexible GMRES(m) in FP64 whose preconditioner may
+//    use reduced-precision blocks (the preconditioner then changes from step
+//    to step by rounding, which the flexible variant tolerates), stopping on
+//    the true residual ||b - A x|| <= tol ||b||;
+//  * the same two methods in lock step over many right-hand sides: one
+//    batched operator and one batched preconditioner application per step,
+//    inner products and rotations per right-hand side.
+//
+// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): two multi-dot
+// passes and two multi-axpy passes per step, each one pass over the basis.
+// Everything except the loop control lives on the device; the host reads the
+// residual estimates back every check_every steps.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hps_internal.h"
+#include "hps_krylov.h"
+
+namespace hps {
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int pinned(hps_ctx* c, void** out) {
+  if (!c->h_pinned) HPS_TRY_HIP(hipHostMalloc(&c->h_pinned, 1 << 16, hipHostMallocDefault));
+  *out = c->h_pinned;
+  return HPS_OK;
+}
+
+double bytes_apply(const hps_ctx* c) {
+  return 32.0 * c->N + (c->c_complex ? 16.0 : 8.0) * c->nl * c->ni + 32.0 * c->nl * c->nb;
+}
+
+double bytes_precond(const hps_ctx* c, int q) {
+  const double beta = q == kFP64 ? 16.0 : (q == kFP32 ? 8.0 : 4.0);
+  return beta * c->nl * (double)c->nb * c->blk[q].ncp + 32.0 * c->N;
+}
+
+struct Job {
+  int nrhs;          // right-hand sides iterated in lock step
+  bool flexible;     // right preconditioning with stored Z
+  int prec;          // block precision index inside J^{-1}
+};
+
+// Lock-step (F)GMRES over nb right-hand sides stored one after the other.
+// b: nb*N device, x: nb*N device (initial guess if use_x0).
+int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m,
+              int maxit, int use_x0, int check_every, hps_stats* st) {
+  const int64_t N = c->N;
+  const int nb = job.nrhs;
+  const int64_t NB = N * nb;  // one batched vector
+  // workspace: V (m+1 batched vectors), Z (m, flexible only), tmp
+  const size_t vec_bytes = sizeof(double2) * NB;
+  const size_t need = vec_bytes * ((size_t)(m + 1) + (job.flexible ? m : 0) + 1);
+  int rc = ws_reserve(c, &c->w_krylov, need);
+  if (rc) return rc;
+  rc = ws_reserve(c, &c->w_small, sizeof(GmresState) * nb);
+  if (rc) return rc;
+  RedBuf rb;
+  if ((rc = red_buf(c, m + 1, &rb))) return rc;
+  double2* V = static_cast<double2*>(c->w_krylov.ptr);
+  double2* Z = job.flexible ? V + (size_t)(m + 1) * NB : nullptr;
+  double2* tmp = V + (size_t)((m + 1) + (job.flexible ? m : 0)) * NB;
+  GmresState* S = static_cast<GmresState*>(c->w_small.ptr);
+  const int64_t sst = sizeof(GmresState) / sizeof(double2);  // state stride in double2 units
+  static_assert(sizeof(GmresState) % sizeof(double2) == 0, "state stride");
+  double* nrm2 = &S[0].nrm2;
+  const int64_t nrm_stride = sizeof(GmresState) / sizeof(double);
+  void* hp = nullptr;
+  if ((rc = pinned(c, &hp))) return rc;
+  double* hbuf = static_cast<double*>(hp);
+
+  auto Vj = [&](int j) { return V + (size_t)j * NB; };
+  auto Zj = [&](int j) { return Z + (size_t)j * NB; };
+  // norm^2 of every right-hand side's part of a batched vector into S[r].nrm2
+  auto norms = [&](const double2* v) -> int {
+    return launch_norm2_b(c, v, N, N, nrm2, nrm_stride, nb, rb);
+  };
+  auto read_nrm2 = [&](std::vector<double>& out) -> int {
+    for (int r = 0; r < nb; ++r)
+      HPS_TRY_HIP(hipMemcpyAsync(hbuf + r, nrm2 + r * nrm_stride, sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+    out.assign(hbuf, hbuf + nb);
+    return HPS_OK;
+  };
+  // residual source r = b - A x (or b when x = 0) into tmp, then the cycle's
+  // first vector: left: J^{-1} r; flexible: r
+  auto residual = [&](bool x_zero) -> int {
+    int e;
+    if (x_zero) {
+      HPS_TRY_HIP(hipMemcpyAsync(tmp, b, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      if ((e = launch_apply(c, x, tmp, nb))) return e;
+      if ((e = launch_sub_from(c, b, tmp, NB))) return e;
+    }
+    if (!job.flexible) {
+      if ((e = launch_precond(c, tmp, Vj(0), nb, job.prec))) return e;
+    } else {
+      HPS_TRY_HIP(hipMemcpyAsync(Vj(0), tmp, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return norms(Vj(0));
+  };
+
+  const double t0 = now();
+  // normalizer: ||J^{-1} b|| (left) or ||b|| (flexible), per right-hand side
+  std::vector<double> bn2, beta2;
+  if ((rc = residual(true))) return rc;
+  if ((rc = read_nrm2(bn2))) return rc;
+  std::vector<double> bnorm(nb);
+  for (int r = 0; r < nb; ++r) bnorm[r] = std::sqrt(bn2[r]);
+  if (use_x0) {
+    if ((rc = residual(false))) return rc;
+    if ((rc = read_nrm2(beta2))) return rc;
+  } else {
+    HPS_TRY_HIP(hipMemsetAsync(x, 0, vec_bytes, c->stream));
+    beta2 = bn2;
+  }
+  for (int r = 0; r < nb; ++r)
+    if (!std::isfinite(beta2[r]) || !std::isfinite(bn2[r]))
+      return fail(HPS_ERR_NUMERIC, "non-finite residual norm (NaN or Inf in the data)");
+
+  int its = 0, restarts = 0;
+  std::vector<int> done(nb, 0);
+  std::vector<double> est(nb, 0.0);
+  auto all_done = [&]() {
+    for (int r = 0; r < nb; ++r)
+      if (!done[r]) return false;
+    return true;
+  };
+  for (int r = 0; r < nb; ++r) {
+    done[r] = (bnorm[r] == 0.0) || (std::sqrt(beta2[r]) <= tol * bnorm[r]);
+    est[r] = bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0;
+  }
+  bool breakdown = false;
+  while (!all_done() && its < maxit) {
+    // V0 = r / beta; g = (beta, 0, ...)
+    if ((rc = launch_scale_by_b(c, Vj(0), N, Vj(0), N, N, nrm2, nrm_stride, 1, nb))) return rc;
+    if ((rc = launch_gm_start(c, S, nb))) return rc;
+    int k = 0;
+    for (int j = 0; j < m && its < maxit; ++j) {
+      // w_j = J^{-1} A v_j (left) or A M^{-1} v_j (flexible), into V[j+1]
+      if (!job.flexible) {
+        if ((rc = launch_apply(c, Vj(j), tmp, nb))) return rc;
+        if ((rc = launch_precond(c, tmp, Vj(j + 1), nb, job.prec))) return rc;
+      } else {
+        if ((rc = launch_precond(c, Vj(j), Zj(j), nb, job.prec))) return rc;
+        if ((rc = launch_apply(c, Zj(j), Vj(j + 1), nb))) return rc;
+      }
+      // CGS2 against V[0..j], per right-hand side
+      for (int pass = 0; pass < 2; ++pass) {
+        double2* hv = pass == 0 ? S[0].h1 : S[0].h2;
+        if ((rc = launch_mdot_b(c, V, NB, N, j + 1, Vj(j + 1), N, N, hv, sst, nb, rb))) return rc;
+        if ((rc = launch_mupdate_b(c, V, NB, N, j + 1, hv, sst, -1.0, Vj(j + 1), N, N,
+                                   pass == 1 ? nrm2 : nullptr, nrm_stride, nb, rb)))
+          return rc;
+      }
+      if ((rc = launch_gm_givens(c, S, nb, j))) return rc;
+      if ((rc = launch_scale_by_b(c, Vj(j + 1), N, Vj(j + 1), N, N, nrm2, nrm_stride, 1, nb)))
+        return rc;
+      ++its;
+      k = j + 1;
+      if (its % check_every == 0 || j == m - 1 || its >= maxit) {
+        for (int r = 0; r < nb; ++r)
+          HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * r, &S[r].res, 2 * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+        HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+        bool all = true;
+        for (int r = 0; r < nb; ++r) {
+          const double res = hbuf[2 * r];
+          int bd;
+          std::memcpy(&bd, hbuf + 2 * r + 1, sizeof(int));
+          if (!std::isfinite(res)) return fail(HPS_ERR_NUMERIC, "non-finite residual estimate");
+          est[r] = bnorm[r] > 0 ? res / bnorm[r] : 0.0;
+          if (bd) breakdown = true;
+          if (!(done[r] || res <= tol * bnorm[r] || bd)) all = false;
+        }
+        if (all) break;
+      }
+    }
+    // x += V y (left) or Z y (flexible), per right-hand side
+    if ((rc = launch_gm_trisolve(c, S, nb, k))) return rc;
+    if ((rc = launch_mupdate_b(c, job.flexible ? Z : V, NB, N, k, S[0].y, sst, 1.0, x, N, N,
+                               nullptr, 0, nb, rb)))
+      return rc;
+    ++restarts;
+    // true residual of the new iterate (preconditioned for the left variant)
+    if ((rc = residual(false))) return rc;
+    if ((rc = read_nrm2(beta2))) return rc;
+    for (int r = 0; r < nb; ++r) {
+      if (!std::isfinite(beta2[r])) return fail(HPS_ERR_NUMERIC, "non-finite residual");
+      const double rr = bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0;
+      if (rr <= tol) done[r] = 1;
+    }
+    if (breakdown && !all_done()) {
+      // an exact invariant subspace without convergence can only come from
+      // rounding; one more cycle from the current iterate decides
+      breakdown = false;
+    }
+  }
+  if (st) {
+    double worst_est = 0.0, worst_true = 0.0;
+    for (int r = 0; r < nb; ++r) {
+      worst_est = std::max(worst_est, est[r]);
+      worst_true = std::max(worst_true, bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0);
+    }
+    st->iters = its;
+    st->restarts = restarts;
+    st->converged = all_done() ? 1 : 0;
+    st->lambda_shifted = c->n_shifted;
+    st->rel_res = worst_est;
+    st->true_rel_res = worst_true;
+    st->t_solve = now() - t0;
+    st->bytes_apply = bytes_apply(c);
+    st->bytes_precond = bytes_precond(c, job.prec);
+  }
+  return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace hps
+
+using namespace hps;
+
+extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
+                         hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st) {
+  if (!c || !s || !t || !u || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_gmres");
+  if (!(tol > 0.0) || !(tol < 1.0)) return fail(HPS_ERR_ARG, "tol must lie in (0, 1)");
+  if (restart < 1 || restart > kMaxRestart) return fail(HPS_ERR_ARG, "restart must lie in [1, 200]");
+  hps_solve_opts o{};
+  if (so) o = *so;
+  const int maxit = o.max_iters > 0 ? o.max_iters : 20000;
+  const int check_every = o.check_every > 0 ? o.check_every : 1;
+  int prec = kFP64;
+  if (o.precond_prec == HPS_PREC_FP32) prec = kFP32;
+  else if (o.precond_prec == HPS_PREC_BF16) prec = kBF16;
+  else if (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64)
+    return fail(HPS_ERR_ARG, "unknown precond_prec");
+  if (!c->blk[prec].data) return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
+  if (o.solver < 0 || o.solver > 2) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver == HPS_SOLVER_GMRES && prec != kFP64)
+    return fail(HPS_ERR_ARG, "left GMRES runs the FP64 preconditioner; use FGMRES for reduced precision");
+  // b for every right-hand side
+  double2* bvec = nullptr;
+  int rc = dev_alloc(c, (void**)&bvec, sizeof(double2) * c->N * nrhs);
+  if (rc) return rc;
+  rc = launch_assemble_rhs(c, reinterpret_cast<const double2*>(s), reinterpret_cast<const double2*>(t),
+                           bvec, nrhs);
+  double2* x = reinterpret_cast<double2*>(u);
+  if (rc == HPS_OK) {
+    Job job;
+    job.flexible = (o.solver == HPS_SOLVER_FGMRES) || prec != kFP64;
+    job.prec = prec;
+    if (o.solver == HPS_SOLVER_BLOCK) {
+      hps_stats acc{};
+      for (int r0 = 0; r0 < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); r0 += kMaxBatch) {
+        job.nrhs = std::min(kMaxBatch, nrhs - r0);
+        hps_stats one{};
+        const int r1 = run_gmres(c, job, bvec + (size_t)r0 * c->N, x + (size_t)r0 * c->N, tol,
+                                 restart, maxit, o.use_x0, check_every, &one);
+        if (r1 < 0) { rc = r1; break; }
+        if (r1 == HPS_NOT_CONVERGED) rc = r1;
+        acc.iters = std::max(acc.iters, one.iters);
+        acc.restarts = std::max(acc.restarts, one.restarts);
+        acc.rel_res = std::max(acc.rel_res, one.rel_res);
+        acc.true_rel_res = std::max(acc.true_rel_res, one.true_rel_res);
+        acc.t_solve += one.t_solve;
+        acc.bytes_apply = one.bytes_apply;
+        acc.bytes_precond = one.bytes_precond;
+      }
+      acc.converged = rc == HPS_OK;
+      acc.lambda_shifted = c->n_shifted;
+      if (st) *st = acc;
+    } else {
+      job.nrhs = 1;
+      hps_stats acc{};
+      for (int r = 0; r < nrhs; ++r) {
+        hps_stats one{};
+        const int r1 = run_gmres(c, job, bvec + (size_t)r * c->N, x + (size_t)r * c->N, tol,
+                                 restart, maxit, o.use_x0, check_every, &one);
+        if (r1 < 0) { rc = r1; break; }
+        if (r1 == HPS_NOT_CONVERGED) rc = r1;
+        acc.iters += one.iters;
+        acc.restarts += one.restarts;
+        acc.rel_res = std::max(acc.rel_res, one.rel_res);
+        acc.true_rel_res = std::max(acc.true_rel_res, one.true_rel_res);
+        acc.t_solve += one.t_solve;
+        acc.bytes_apply = one.bytes_apply;
+        acc.bytes_precond = one.bytes_precond;
+      }
+      acc.converged = rc == HPS_OK;
+      acc.lambda_shifted = c->n_shifted;
+      if (st) *st = acc;
+    }
+  }
+  hipStreamSynchronize(c->stream);
+  hipFree(bvec);
+  c->dev_bytes -= sizeof(double2) * c->N * nrhs;
+  return rc;
+}

@@ -1,0 +1,146 @@
+// Internal declarations of the HPS library: the context, the host tables and
+// the launchers of the device kernels.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hps.h"
+
+namespace hps {
+
+constexpr int kMinP = 4;
+constexpr int kMaxP = 16;
+
+// ---------------------------------------------------------------- host tables
+// One-leaf tables shared by every leaf (they do not depend on the medium).
+struct HostTables {
+  int p = 0, n1 = 0, ni = 0, nb = 0, n = 0;
+  double h = 0.0;
+  std::vector<double> xi;   // p reference Chebyshev-Lobatto nodes, ascending
+  std::vector<double> D;    // p x p first derivative on a leaf of side h, row major
+  std::vector<double> D2;   // p x p, D * D
+  std::vector<double> V;    // n1 x n1 eigenvectors of L1 = D2[1:p-1, 1:p-1] (columns)
+  std::vector<double> W;    // n1 x n1, V^{-1}
+  std::vector<double> E;    // n1 eigenvalues of L1 (real, negative)
+  std::vector<double> P;    // nb x ni, F_bi (V x V x V)            (setup only)
+  std::vector<double> Q;    // ni x nb, (V x V x V)^{-1} A_ib       (setup only)
+};
+
+// Builds every table; returns an empty string or an error message.
+std::string build_tables(int p, double h, HostTables* t);
+
+// Face f (0..5): axis = f/2, high side = f%2, outward sign -1 / +1.
+inline int face_axis(int f) { return f >> 1; }
+inline int face_high(int f) { return f & 1; }
+
+// --------------------------------------------------------------- device views
+struct DevTables {
+  const double* D;    // p x p
+  const double* D2;   // p x p
+  const double* V;    // n1 x n1
+  const double* W;    // n1 x n1
+  const double* E;    // n1
+};
+
+enum BlockPrec { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
+
+// Column-group width (complex numbers per 16-byte group) of the block layout.
+inline int block_cw(int prec) { return prec == kFP64 ? 1 : (prec == kFP32 ? 2 : 4); }
+
+struct Blocks {
+  void* data = nullptr;   // [leaf][col group][row][cw complex]
+  int ncp = 0;            // padded column count (multiple of cw)
+  size_t bytes = 0;
+};
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace hps
+
+struct hps_ctx {
+  int p = 0, n1 = 0, ni = 0, nb = 0, n = 0;
+  int E[3] = {0, 0, 0};
+  int64_t nl = 0, N = 0;
+  double kappa = 0, eta = 0, h = 0, lo[3] = {0, 0, 0};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int verbose = 0;
+
+  hps::HostTables tab;
+  double* d_tab = nullptr;          // D | D2 | V | W | E
+  hps::DevTables dt{};
+  int* d_nbr = nullptr;             // [nl][6], -1 on the boundary
+  int c_complex = 0;                // C stored as complex (else real)
+  void* d_C = nullptr;              // [nl][ni] kappa^2 (1 - b) at interior nodes
+  double2* d_lambda = nullptr;      // [nl]
+  int n_shifted = 0;
+  hps::Blocks blk[3];
+
+  // reusable workspaces (grown on demand)
+  hps::Workspace w_g;               // outgoing impedance buffer
+  hps::Workspace w_red;             // reduction partials + counters
+  hps::Workspace w_krylov;          // Krylov bases etc.
+  hps::Workspace w_small;           // Hessenberg / Givens state
+  void* h_pinned = nullptr;         // small pinned host buffer for scalars
+  size_t dev_bytes = 0;
+};
+
+namespace hps {
+
+// error reporting ----------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+#define HPS_TRY_HIP(expr)                                       \
+  do {                                                          \
+    int _rc = ::hps::check_hip((expr), #expr);                  \
+    if (_rc != HPS_OK) return _rc;                              \
+  } while (0)
+
+int ws_reserve(hps_ctx* c, Workspace* w, size_t bytes);
+int dev_alloc(hps_ctx* c, void** p, size_t bytes);
+
+// launchers (all stream ordered on c->stream) ------------------------------
+// setup
+int launch_eval_medium(hps_ctx* c, const hps_medium* b, const double* d_bump_c,
+                       const double2* d_bump_a, int nbump);
+int launch_lambda(hps_ctx* c);
+int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, int e0, int ne,
+                       double2* S /* [ne][nb][nb] column major */);
+int launch_pack_blocks(hps_ctx* c, const double2* Sinv, int e0, int ne, int prec);
+int launch_node_coords(hps_ctx* c, double* d_xyz);
+
+// hot path
+int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs);
+int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
+int launch_assemble_rhs(hps_ctx* c, const double2* s, const double2* t, double2* b, int nrhs);
+
+// Krylov primitives over vectors of length n (complex)
+struct RedBuf {
+  double2* part;      // partial sums
+  unsigned* counter;  // one counter per concurrent reduction slot
+  int nblk;
+};
+int red_buf(hps_ctx* c, int kmax, RedBuf* rb);
+// out[k] = sum_n conj(V[k*ldv + n]) w[n], k < K.
+int launch_mdot(hps_ctx* c, const double2* V, int64_t ldv, int K, const double2* w, int64_t n,
+                double2* out, const RedBuf& rb);
+// w[n] += sign * sum_k V[k*ldv + n] coef[k]; if nrm2 != null: *nrm2 = ||w_new||^2.
+int launch_mupdate(hps_ctx* c, const double2* V, int64_t ldv, int K, const double2* coef,
+                   double sign, double2* w, int64_t n, double* nrm2, const RedBuf& rb);
+// *nrm2 = ||w||^2
+int launch_norm2(hps_ctx* c, const double2* w, int64_t n, double* nrm2, const RedBuf& rb);
+// y = x * (1/sqrt(*nrm2)) (or by *scale if inv_sqrt == 0)
+int launch_scale_by(hps_ctx* c, const double2* x, double2* y, int64_t n, const double* s,
+                    int inv_sqrt);
+// y = a - y
+int launch_sub_from(hps_ctx* c, const double2* a, double2* y, int64_t n);
+
+}  // namespace hps

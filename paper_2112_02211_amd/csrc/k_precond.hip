@@ -1,0 +1,308 @@
+// y = J^{-1} x: the homogenized block-Jacobi preconditioner (Sec. 4, eq.
+// (block_pc), Algorithm 4).  J^{-1} is block diagonal; on each leaf it is the
+// exact inverse of the homogenized leaf matrix [[A~_ii, A_ib], [F_bi, F_bb]]:
+//
+//   f_i = A~_ii^{-1} x_i                  (Algorithm 3: fast diagonalization)
+//   h_b = x_b - F_bi f_i
+//   u_b = S~^{-1} h_b                     (dense n_b x n_b block, streamed)
+//   y_i = f_i - A~_ii^{-1} (A_ib u_b),    y_b = u_b
+//
+// (Algorithm 4 as printed returns -u_b on the faces; the signs above are the
+// ones of eq. (block_pc), i.e. the exact block solve.)
+//
+// One workgroup per leaf.  Algorithm 3 runs in LDS as line-wise mode products:
+// a thread owns one grid line per axis, keeps its n1 values in registers and
+// multiplies them by V^{-1} (or V), so each mode product reads and writes the
+// tensor once.  The block product streams S~^{-1} from HBM with one row per
+// thread: the block is stored column-group major ([col group][row][cw]), so a
+// wavefront's 16-byte loads for one column group are contiguous, and h_b is
+// broadcast from LDS.  No cross-lane reduction is needed.
+#include "hps_internal.h"
+#include "k_common.h"
+
+namespace hps {
+namespace {
+
+template <int P>
+struct PL {
+  static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
+  static constexpr int RPT = (NB + 1023) / 1024;                  // block rows per thread
+  static constexpr int BD = ((NB + RPT - 1) / RPT + 63) / 64 * 64; // workgroup size
+  static constexpr int NBP = (NB + 3) / 4 * 4;                     // padded column count
+};
+
+// In-place mode product along axis AX of the n1^3 tensor T by the n1 x n1
+// row-major matrix M: T[.., a, ..] <- sum_i M[a][i] T[.., i, ..].
+template <int P, int AX>
+__device__ __forceinline__ void mode_product(double2* __restrict__ T, const double* __restrict__ M) {
+  constexpr int N1 = P - 2, L = N1 * N1;
+  for (int line = threadIdx.x; line < L; line += PL<P>::BD) {
+    const int a = line % N1, b = line / N1;
+    int base, stride;
+    if (AX == 0) { base = N1 * a + L * b; stride = 1; }
+    else if (AX == 1) { base = a + L * b; stride = N1; }
+    else { base = a + N1 * b; stride = L; }
+    double2 v[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) v[i] = T[base + i * stride];
+#pragma unroll
+    for (int o = 0; o < N1; ++o) {
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < N1; ++i) cfma_r(s, M[o * N1 + i], v[i]);
+      T[base + o * stride] = s;
+    }
+  }
+}
+
+// T <- A~_ii^{-1} T = (V x V x V) diag(1 / (-E_Delta - lambda)) (W x W x W) T
+template <int P>
+__device__ __forceinline__ void homog_solve(double2* __restrict__ T, const double* __restrict__ tab,
+                                            double2 lam) {
+  constexpr int NI = PL<P>::NI;
+  const double* V = tab + tab_off_V(P);
+  const double* W = tab + tab_off_W(P);
+  const double* Ed3 = tab + tab_off_ed3(P);
+  mode_product<P, 0>(T, W);
+  __syncthreads();
+  mode_product<P, 1>(T, W);
+  __syncthreads();
+  mode_product<P, 2>(T, W);
+  __syncthreads();
+  for (int m = threadIdx.x; m < NI; m += PL<P>::BD) {
+    // 1 / (a + i b), a = -E - lr, b = -li
+    const double a = -Ed3[m] - lam.x, b = -lam.y;
+    const double den = 1.0 / (a * a + b * b);
+    T[m] = cmul(T[m], make_double2(a * den, -b * den));
+  }
+  __syncthreads();
+  mode_product<P, 0>(T, V);
+  __syncthreads();
+  mode_product<P, 1>(T, V);
+  __syncthreads();
+  mode_product<P, 2>(T, V);
+  __syncthreads();
+}
+
+// 16-byte column group of the block in each storage precision
+template <int PREC> struct BlockIO;
+template <> struct BlockIO<kFP64> {
+  using vec = double4;  // unused
+  static constexpr int CW = 1;
+};
+template <> struct BlockIO<kFP32> { static constexpr int CW = 2; };
+template <> struct BlockIO<kBF16> { static constexpr int CW = 4; };
+
+__device__ __forceinline__ float bf_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
+
+template <int P, int PREC, int UNR>
+__device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t tau, int ncp,
+                                           const double2* __restrict__ H, double2* __restrict__ U,
+                                           double2* __restrict__ yb) {
+  using Q = PL<P>;
+  constexpr int NB = Q::NB, RPT = Q::RPT, BD = Q::BD;
+  constexpr int CW = BlockIO<PREC>::CW;
+  const int ncg = ncp / CW;
+  int rows[RPT];
+  bool ok[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    rows[k] = threadIdx.x + k * BD;
+    ok[k] = rows[k] < NB;
+    if (!ok[k]) rows[k] = NB - 1;  // clamp: loads stay in bounds, result discarded
+  }
+  if (PREC == kFP64) {
+    const double2* B = static_cast<const double2*>(blk) + (size_t)tau * ncg * NB;
+    double2 acc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) acc[k] = make_double2(0.0, 0.0);
+    int cg = 0;
+    for (; cg + UNR <= ncg; cg += UNR) {
+      double2 s[UNR][RPT];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) s[u][k] = B[(size_t)(cg + u) * NB + rows[k]];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const double2 h = H[cg + u];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          acc[k].x = fma(s[u][k].x, h.x, fma(-s[u][k].y, h.y, acc[k].x));
+          acc[k].y = fma(s[u][k].x, h.y, fma(s[u][k].y, h.x, acc[k].y));
+        }
+      }
+    }
+    for (; cg < ncg; ++cg) {
+      const double2 h = H[cg];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const double2 s = B[(size_t)cg * NB + rows[k]];
+        acc[k].x = fma(s.x, h.x, fma(-s.y, h.y, acc[k].x));
+        acc[k].y = fma(s.x, h.y, fma(s.y, h.x, acc[k].y));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (ok[k]) { U[rows[k]] = acc[k]; yb[rows[k]] = acc[k]; }
+  } else {
+    // reduced-precision blocks: FP32 arithmetic, h rounded to FP32
+    const uint4* B = static_cast<const uint4*>(blk) + (size_t)tau * ncg * NB;
+    float2 acc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) acc[k] = make_float2(0.f, 0.f);
+    for (int cg = 0; cg < ncg; cg += UNR) {
+      uint4 s[UNR][RPT];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int k = 0; k < RPT; ++k)
+          s[u][k] = (cg + u < ncg) ? B[(size_t)(cg + u) * NB + rows[k]] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        float hr[CW], hi[CW];
+#pragma unroll
+        for (int w = 0; w < CW; ++w) {
+          const int cidx = (cg + u) * CW + w;
+          const double2 hv = (cg + u < ncg) ? H[cidx] : make_double2(0.0, 0.0);
+          hr[w] = (float)hv.x;
+          hi[w] = (float)hv.y;
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          float sr[CW], si[CW];
+          const uint32_t wv[4] = {s[u][k].x, s[u][k].y, s[u][k].z, s[u][k].w};
+          if (PREC == kFP32) {
+            sr[0] = __uint_as_float(wv[0]); si[0] = __uint_as_float(wv[1]);
+            sr[1] = __uint_as_float(wv[2]); si[1] = __uint_as_float(wv[3]);
+          } else {
+#pragma unroll
+            for (int w = 0; w < CW; ++w) { sr[w] = bf_lo(wv[w]); si[w] = bf_hi(wv[w]); }
+          }
+#pragma unroll
+          for (int w = 0; w < CW; ++w) {
+            acc[k].x = fmaf(sr[w], hr[w], fmaf(-si[w], hi[w], acc[k].x));
+            acc[k].y = fmaf(sr[w], hi[w], fmaf(si[w], hr[w], acc[k].y));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (ok[k]) {
+        const double2 v = make_double2((double)acc[k].x, (double)acc[k].y);
+        U[rows[k]] = v;
+        yb[rows[k]] = v;
+      }
+  }
+}
+
+template <int P, int PREC>
+__global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
+    const double2* __restrict__ x, double2* __restrict__ y, const void* __restrict__ blk, int ncp,
+    const double2* __restrict__ lam, const double* __restrict__ tab, int64_t N) {
+  using Q = PL<P>;
+  constexpr int N1 = Q::N1, L = Q::L, NI = Q::NI, NB = Q::NB, NN = Q::NN, BD = Q::BD;
+  __shared__ double2 T[NI];
+  __shared__ double2 F[NI];
+  __shared__ double2 H[Q::NBP];
+  __shared__ double2 U[NB];
+  const int64_t tau = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const double2* xv = x + rhs * N + tau * NN;
+  double2* yv = y + rhs * N + tau * NN;
+  const double2 lm = lam[tau];
+  const double* D = tab + tab_off_D(P);
+  const double* D2 = tab + tab_off_D2(P);
+
+  for (int m = threadIdx.x; m < NI; m += BD) T[m] = xv[m];
+  for (int m = threadIdx.x; m < Q::NBP; m += BD) H[m] = (m < NB) ? xv[NI + m] : make_double2(0.0, 0.0);
+  __syncthreads();
+  // f_i = A~_ii^{-1} x_i
+  homog_solve<P>(T, tab, lm);
+  for (int m = threadIdx.x; m < NI; m += BD) F[m] = T[m];
+  // h_b = x_b - F_bi f_i: the interior part of the normal line through each face node
+  for (int r = threadIdx.x; r < NB; r += BD) {
+    const int f = r / L, pos = r - f * L;
+    const int ax = f >> 1, hi = f & 1;
+    const int a = pos % N1, b = pos / N1;
+    int base, stride;
+    if (ax == 0) { base = N1 * a + L * b; stride = 1; }
+    else if (ax == 1) { base = a + L * b; stride = N1; }
+    else { base = a + N1 * b; stride = L; }
+    const int e = hi ? P - 1 : 0;
+    const double sg = hi ? 1.0 : -1.0;
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < N1; ++t) cfma_r(s, D[e * P + t + 1], T[base + t * stride]);
+    const double2 hv = H[r];
+    H[r] = make_double2(hv.x - sg * s.x, hv.y - sg * s.y);
+  }
+  __syncthreads();
+  // u_b = S~^{-1} h_b, written to y_b and kept in LDS
+  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4)>(blk, tau, ncp, H, U, yv + NI);
+  __syncthreads();
+  // t = A_ib u_b: interior rows of -(Dx^2 + Dy^2 + Dz^2) restricted to face columns
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const int i = m % N1, j = (m / N1) % N1, k = m / L;
+    double2 s = make_double2(0.0, 0.0);
+    cfma_r(s, D2[(i + 1) * P + 0], U[0 * L + j + N1 * k]);
+    cfma_r(s, D2[(i + 1) * P + P - 1], U[1 * L + j + N1 * k]);
+    cfma_r(s, D2[(j + 1) * P + 0], U[2 * L + i + N1 * k]);
+    cfma_r(s, D2[(j + 1) * P + P - 1], U[3 * L + i + N1 * k]);
+    cfma_r(s, D2[(k + 1) * P + 0], U[4 * L + i + N1 * j]);
+    cfma_r(s, D2[(k + 1) * P + P - 1], U[5 * L + i + N1 * j]);
+    T[m] = make_double2(-s.x, -s.y);
+  }
+  __syncthreads();
+  homog_solve<P>(T, tab, lm);
+  for (int m = threadIdx.x; m < NI; m += BD) yv[m] = csub(F[m], T[m]);
+}
+
+template <int P>
+int precond_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+  const Blocks& B = c->blk[prec];
+  dim3 grid((unsigned)c->nl, (unsigned)nrhs);
+  dim3 block(PL<P>::BD);
+  switch (prec) {
+    case kFP64:
+      hipLaunchKernelGGL((k_precond_fused<P, kFP64>), grid, block, 0, c->stream, x, y, B.data,
+                         B.ncp, c->d_lambda, c->d_tab, c->N);
+      break;
+    case kFP32:
+      hipLaunchKernelGGL((k_precond_fused<P, kFP32>), grid, block, 0, c->stream, x, y, B.data,
+                         B.ncp, c->d_lambda, c->d_tab, c->N);
+      break;
+    default:
+      hipLaunchKernelGGL((k_precond_fused<P, kBF16>), grid, block, 0, c->stream, x, y, B.data,
+                         B.ncp, c->d_lambda, c->d_tab, c->N);
+      break;
+  }
+  return check_hip(hipGetLastError(), "k_precond_fused");
+}
+
+}  // namespace
+
+int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+  if (prec < 0 || prec > 2 || !c->blk[prec].data)
+    return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
+  switch (c->p) {
+    case 4: return precond_launch<4>(c, x, y, nrhs, prec);
+    case 5: return precond_launch<5>(c, x, y, nrhs, prec);
+    case 6: return precond_launch<6>(c, x, y, nrhs, prec);
+    case 7: return precond_launch<7>(c, x, y, nrhs, prec);
+    case 8: return precond_launch<8>(c, x, y, nrhs, prec);
+    case 9: return precond_launch<9>(c, x, y, nrhs, prec);
+    case 10: return precond_launch<10>(c, x, y, nrhs, prec);
+    case 11: return precond_launch<11>(c, x, y, nrhs, prec);
+    case 12: return precond_launch<12>(c, x, y, nrhs, prec);
+    case 13: return precond_launch<13>(c, x, y, nrhs, prec);
+    case 14: return precond_launch<14>(c, x, y, nrhs, prec);
+    case 15: return precond_launch<15>(c, x, y, nrhs, prec);
+    case 16: return precond_launch<16>(c, x, y, nrhs, prec);
+    default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
+  }
+}
+
+}  // namespace hps

@@ -1,0 +1,294 @@
+// Host construction of the one-leaf tables (Sec. 2.1 and Sec. 4.1):
+//   Chebyshev-Lobatto nodes and differentiation matrices on a leaf of side h,
+//   the eigendecomposition L1 = V E V^{-1} of the interior second-derivative
+//   block used by the fast diagonalization of the homogenized interior
+//   operator, and the two real matrices P = F_bi (V x V x V) and
+//   Q = (V x V x V)^{-1} A_ib that turn the homogenized Schur complement
+//   S~ = F_bb - F_bi A~_ii^{-1} A_ib (eq. (schur_pc)) into
+//   S~ = F_bb - P diag(1 / (-E_Delta - lambda)) Q for every leaf.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+#include "hps_internal.h"
+
+namespace hps {
+namespace {
+
+// Row-major dense helpers for tiny matrices.
+using Mat = std::vector<double>;
+
+// Differentiation matrix of the degree p-1 interpolant at the nodes x, from the
+// barycentric form of the Lagrange basis: D_ij = (w_j / w_i) / (x_i - x_j) for
+// i != j, with the diagonal set so that every row sums to zero (exact for
+// constants).  Chebyshev-Lobatto weights: w_j = (-1)^j, halved at the ends.
+Mat cheb_diff(const std::vector<double>& x) {
+  const int p = (int)x.size();
+  std::vector<double> w(p);
+  for (int j = 0; j < p; ++j) w[j] = ((j & 1) ? -1.0 : 1.0) * ((j == 0 || j == p - 1) ? 0.5 : 1.0);
+  Mat D(p * p, 0.0);
+  for (int i = 0; i < p; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < p; ++j) {
+      if (j == i) continue;
+      D[i * p + j] = (w[j] / w[i]) / (x[i] - x[j]);
+      s += D[i * p + j];
+    }
+    D[i * p + i] = -s;
+  }
+  return D;
+}
+
+// LU with partial pivoting of an n x n row-major matrix, in place.
+bool lu_factor(Mat& A, std::vector<int>& piv, int n) {
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int m = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i * n + k]) > std::fabs(A[m * n + k])) m = i;
+    piv[k] = m;
+    if (A[m * n + k] == 0.0) return false;
+    if (m != k)
+      for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[m * n + j]);
+    for (int i = k + 1; i < n; ++i) {
+      A[i * n + k] /= A[k * n + k];
+      const double f = A[i * n + k];
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+    }
+  }
+  return true;
+}
+
+void lu_solve(const Mat& LU, const std::vector<int>& piv, int n, std::vector<double>& b) {
+  for (int k = 0; k < n; ++k) std::swap(b[k], b[piv[k]]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) b[i] -= LU[i * n + j] * b[j];
+  for (int i = n - 1; i >= 0; --i) {
+    for (int j = i + 1; j < n; ++j) b[i] -= LU[i * n + j] * b[j];
+    b[i] /= LU[i * n + i];
+  }
+}
+
+// Eigenvalues of a real matrix whose spectrum is real: shifted QR iteration
+// (Francis' basic algorithm with a Wilkinson shift taken from the trailing
+// 2 x 2 block), deflating the last row of the active block once it vanishes.
+// The QR factorization of each step is by Householder reflections.
+bool real_eigenvalues(Mat A, int n, std::vector<double>& ev) {
+  ev.clear();
+  double anorm = 0.0;
+  for (double v : A) anorm = std::max(anorm, std::fabs(v));
+  int m = n;
+  int iter = 0;
+  while (m > 0) {
+    if (m == 1) {
+      ev.push_back(A[0]);
+      break;
+    }
+    // deflation test on the last row of the active m x m block
+    double off = 0.0;
+    for (int j = 0; j < m - 1; ++j) off = std::max(off, std::fabs(A[(m - 1) * n + j]));
+    if (off <= 1e-15 * anorm) {
+      ev.push_back(A[(m - 1) * n + (m - 1)]);
+      --m;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 500) return false;
+    // Wilkinson shift
+    const double a = A[(m - 2) * n + (m - 2)], b = A[(m - 2) * n + (m - 1)];
+    const double c = A[(m - 1) * n + (m - 2)], d = A[(m - 1) * n + (m - 1)];
+    const double tr = 0.5 * (a - d);
+    const double disc = tr * tr + b * c;
+    double mu = d;
+    if (disc >= 0.0) {
+      const double r = std::sqrt(disc);
+      const double l1 = d + tr + r, l2 = d + tr - r;  // eigenvalues of the 2x2 block
+      mu = (std::fabs(l1 - d) < std::fabs(l2 - d)) ? l1 : l2;
+    }
+    if (iter % 11 == 10) mu += 0.5 * off;  // exceptional shift
+    // B = A_m - mu I = Q R (Householder), A_m <- R Q + mu I
+    Mat B(m * m), Qm(m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) B[i * m + j] = A[i * n + j] - (i == j ? mu : 0.0);
+    for (int i = 0; i < m; ++i) Qm[i * m + i] = 1.0;
+    for (int k = 0; k < m - 1; ++k) {
+      double s = 0.0;
+      for (int i = k; i < m; ++i) s += B[i * m + k] * B[i * m + k];
+      s = std::sqrt(s);
+      if (s == 0.0) continue;
+      std::vector<double> v(m, 0.0);
+      const double alpha = B[k * m + k] > 0 ? -s : s;
+      v[k] = B[k * m + k] - alpha;
+      for (int i = k + 1; i < m; ++i) v[i] = B[i * m + k];
+      double vv = 0.0;
+      for (int i = k; i < m; ++i) vv += v[i] * v[i];
+      if (vv == 0.0) continue;
+      // B <- (I - 2 v v^T / vv) B ; Qm <- Qm (I - 2 v v^T / vv)
+      for (int j = 0; j < m; ++j) {
+        double t = 0.0;
+        for (int i = k; i < m; ++i) t += v[i] * B[i * m + j];
+        t *= 2.0 / vv;
+        for (int i = k; i < m; ++i) B[i * m + j] -= t * v[i];
+      }
+      for (int i = 0; i < m; ++i) {
+        double t = 0.0;
+        for (int j = k; j < m; ++j) t += Qm[i * m + j] * v[j];
+        t *= 2.0 / vv;
+        for (int j = k; j < m; ++j) Qm[i * m + j] -= t * v[j];
+      }
+    }
+    // A_m = R Qm + mu I  (B now holds R)
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double t = 0.0;
+        for (int k = i; k < m; ++k) t += B[i * m + k] * Qm[k * m + j];
+        A[i * n + j] = t + (i == j ? mu : 0.0);
+      }
+  }
+  return (int)ev.size() == n;
+}
+
+}  // namespace
+
+std::string build_tables(int p, double h, HostTables* t) {
+  if (p < kMinP || p > kMaxP) return "p out of range";
+  const int n1 = p - 2;
+  t->p = p;
+  t->n1 = n1;
+  t->ni = n1 * n1 * n1;
+  t->nb = 6 * n1 * n1;
+  t->n = t->ni + t->nb;
+  t->h = h;
+  t->xi.resize(p);
+  const double pi = 3.14159265358979323846;
+  for (int j = 0; j < p; ++j) t->xi[j] = -std::cos(pi * j / (p - 1));
+  // exact symmetric values: the node set is symmetric about 0
+  for (int j = 0; j < p / 2; ++j) t->xi[p - 1 - j] = -t->xi[j];
+  if (p % 2) t->xi[p / 2] = 0.0;
+  Mat D = cheb_diff(t->xi);
+  const double sc = 2.0 / h;
+  for (double& v : D) v *= sc;
+  Mat D2(p * p, 0.0);
+  for (int i = 0; i < p; ++i)
+    for (int k = 0; k < p; ++k)
+      for (int j = 0; j < p; ++j) D2[i * p + j] += D[i * p + k] * D[k * p + j];
+  t->D = D;
+  t->D2 = D2;
+
+  // L1 = D2[1:p-1, 1:p-1] and its eigendecomposition
+  Mat L1(n1 * n1);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) L1[i * n1 + j] = D2[(i + 1) * p + (j + 1)];
+  std::vector<double> ev;
+  if (!real_eigenvalues(L1, n1, ev)) return "eigenvalues of L1 did not converge";
+  std::sort(ev.begin(), ev.end());
+  double l1norm = 0.0;
+  for (double v : L1) l1norm = std::max(l1norm, std::fabs(v));
+  // eigenvectors by inverse iteration with a slightly perturbed shift
+  Mat V(n1 * n1, 0.0);
+  for (int k = 0; k < n1; ++k) {
+    const double lam = ev[k];
+    double gap = 1e300;
+    for (int j = 0; j < n1; ++j)
+      if (j != k) gap = std::min(gap, std::fabs(ev[j] - lam));
+    const double shift = lam + 1e-10 * std::max(std::fabs(lam), 1.0);
+    Mat M = L1;
+    for (int i = 0; i < n1; ++i) M[i * n1 + i] -= shift;
+    std::vector<int> piv;
+    if (!lu_factor(M, piv, n1)) return "inverse iteration: singular shift";
+    std::vector<double> x(n1);
+    for (int i = 0; i < n1; ++i) x[i] = 1.0 + 0.1 * std::sin(1.7 * i + 0.3 * k);
+    for (int it = 0; it < 4; ++it) {
+      lu_solve(M, piv, n1, x);
+      double nrm = 0.0;
+      for (double v : x) nrm += v * v;
+      nrm = std::sqrt(nrm);
+      for (double& v : x) v /= nrm;
+    }
+    // sign convention: largest component positive
+    int im = 0;
+    for (int i = 1; i < n1; ++i)
+      if (std::fabs(x[i]) > std::fabs(x[im])) im = i;
+    if (x[im] < 0)
+      for (double& v : x) v = -v;
+    for (int i = 0; i < n1; ++i) V[i * n1 + k] = x[i];
+    // residual check ||L1 v - lam v|| / ||L1||
+    double r = 0.0;
+    for (int i = 0; i < n1; ++i) {
+      double s = -lam * x[i];
+      for (int j = 0; j < n1; ++j) s += L1[i * n1 + j] * x[j];
+      r = std::max(r, std::fabs(s));
+    }
+    if (r > 1e-9 * l1norm) return "eigenvector residual too large";
+    (void)gap;
+  }
+  // W = V^{-1}
+  Mat LU = V;
+  std::vector<int> piv;
+  if (!lu_factor(LU, piv, n1)) return "eigenvector matrix singular";
+  Mat W(n1 * n1);
+  for (int j = 0; j < n1; ++j) {
+    std::vector<double> e(n1, 0.0);
+    e[j] = 1.0;
+    lu_solve(LU, piv, n1, e);
+    for (int i = 0; i < n1; ++i) W[i * n1 + j] = e[i];
+  }
+  // reconstruction check ||V E W - L1||
+  double rec = 0.0;
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < n1; ++k) s += V[i * n1 + k] * ev[k] * W[k * n1 + j];
+      rec = std::max(rec, std::fabs(s - L1[i * n1 + j]));
+    }
+  if (rec > 1e-9 * l1norm) return "eigendecomposition reconstruction error too large";
+  t->V = V;
+  t->W = W;
+  t->E = ev;
+
+  // P = F_bi (V x V x V): for a face node r on face f (axis ax, endpoint e,
+  // sign sg, tangential coordinates (a, b)), F_bi[r, :] has sg * D[e][1 + i] at
+  // the interior nodes of the normal line, so
+  //   P[r, (al0, al1, al2)] = sg * dv_e[al_ax] * V[a][al_t1] * V[b][al_t2]
+  // with dv_e[al] = sum_i D[e][1 + i] V[i][al].
+  // Q = (W x W x W) A_ib: A_ib[m, r] = -D2[1 + i_ax(m)][e] on the same line, so
+  //   Q[(al0, al1, al2), r] = -qv_e[al_ax] * W[al_t1][a] * W[al_t2][b]
+  // with qv_e[al] = sum_i W[al][i] D2[1 + i][e].
+  const int nb = t->nb, ni = t->ni, L = n1 * n1;
+  t->P.assign((size_t)nb * ni, 0.0);
+  t->Q.assign((size_t)ni * nb, 0.0);
+  for (int f = 0; f < 6; ++f) {
+    const int ax = face_axis(f);
+    const int e = face_high(f) ? p - 1 : 0;
+    const double sg = face_high(f) ? 1.0 : -1.0;
+    int t1 = -1, t2 = -1;
+    for (int a = 0; a < 3; ++a)
+      if (a != ax) {
+        if (t1 < 0) t1 = a; else t2 = a;
+      }
+    std::vector<double> dv(n1, 0.0), qv(n1, 0.0);
+    for (int al = 0; al < n1; ++al)
+      for (int i = 0; i < n1; ++i) {
+        dv[al] += D[e * p + 1 + i] * V[i * n1 + al];
+        qv[al] += W[al * n1 + i] * D2[(1 + i) * p + e];
+      }
+    for (int b = 0; b < n1; ++b)
+      for (int a = 0; a < n1; ++a) {
+        const int r = f * L + a + n1 * b;
+        for (int g2 = 0; g2 < n1; ++g2)
+          for (int g1 = 0; g1 < n1; ++g1)
+            for (int g0 = 0; g0 < n1; ++g0) {
+              const int al[3] = {g0, g1, g2};
+              const int m = g0 + n1 * (g1 + n1 * g2);
+              t->P[(size_t)r * ni + m] =
+                  sg * dv[al[ax]] * V[a * n1 + al[t1]] * V[b * n1 + al[t2]];
+              t->Q[(size_t)m * nb + r] =
+                  -qv[al[ax]] * W[al[t1] * n1 + a] * W[al[t2] * n1 + b];
+            }
+      }
+  }
+  return std::string();
+}
+
+}  // namespace hps

@@ -1,0 +1,283 @@
+"""ctypes binding of libhps.so (the C-ABI declared in include/hps.h).
+
+Argument marshalling only: every step of the operator, the preconditioner and
+the solvers runs in the library's HIP kernels.  torch provides device memory
+(complex128 tensors) and the current stream.  The binding refuses to run
+without the compiled library; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhps.so")
+
+HPS_OK = 0
+HPS_NOT_CONVERGED = 1
+ERRORS = {-1: "ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BREAKDOWN", -6: "NUMERIC"}
+PREC = {"fp64": 1, "fp32": 2, "bf16": 4}
+SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2}
+MEDIUM_ZERO, MEDIUM_NODAL, MEDIUM_BUMPS = 0, 1, 2
+
+
+class HPSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hps error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class _Z(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class _Domain(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class _Medium(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_bumps", ctypes.c_int),
+                ("centres", ctypes.POINTER(ctypes.c_double)), ("amps", ctypes.POINTER(_Z)),
+                ("width", ctypes.c_double), ("nodal", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("block_precs", ctypes.c_int), ("stream", ctypes.c_void_p), ("verbose", ctypes.c_int)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("max_iters", ctypes.c_int), ("use_x0", ctypes.c_int),
+                ("precond_prec", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("lambda_shifted", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("bytes_apply", ctypes.c_double), ("bytes_precond", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# exported symbols and their signatures
+SIGNATURES = {
+    "hps_setup": (ctypes.c_int, [ctypes.POINTER(_Domain), ctypes.c_double, ctypes.c_double,
+                                 ctypes.POINTER(_Medium), ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_Opts),
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "hps_num_unknowns": (ctypes.c_int64, [ctypes.c_void_p]),
+    "hps_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "hps_lambdas": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Z)]),
+    "hps_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hps_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_precond_prec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_int]),
+    "hps_assemble_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int]),
+    "hps_gmres": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                 ctypes.POINTER(_SolveOpts), ctypes.POINTER(Stats)]),
+    "hps_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "hps_last_error": (ctypes.c_char_p, []),
+    "hps_free": (None, [ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhps.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2112_02211_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, allow_nc: bool = False) -> int:
+    if rc == HPS_OK or (allow_nc and rc == HPS_NOT_CONVERGED):
+        return rc
+    raise HPSError(rc, lib().hps_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One discretized problem resident on the GPU (tables, medium, blocks)."""
+
+    def __init__(self, n_elem: Sequence[int], p: int, kappa: float, eta: Optional[float] = None,
+                 lo=(0.0, 0.0, 0.0), hi=None, bump_centres=None, bump_amps=None,
+                 bump_width: float = 0.08, nodal_b=None, block_precs=("fp64",),
+                 q: Optional[int] = None, verbose: bool = False):
+        L = lib()
+        self.n_elem = tuple(int(e) for e in n_elem)
+        self.p = int(p)
+        self.kappa = float(kappa)
+        self.eta = float(kappa if eta is None else eta)
+        if hi is None:
+            m = float(max(self.n_elem))
+            hi = tuple(float(e) / m for e in self.n_elem)
+        dom = _Domain((ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi))
+        med = _Medium()
+        self._keep = []
+        if nodal_b is not None:
+            med.kind = MEDIUM_NODAL
+            med.nodal = _dev(nodal_b, "nodal_b")
+            self._keep.append(nodal_b)
+        elif bump_centres is not None and len(bump_centres) > 0:
+            c = np.ascontiguousarray(np.asarray(bump_centres, dtype=np.float64).reshape(-1, 3))
+            a = np.asarray(bump_amps, dtype=np.complex128)
+            za = (_Z * len(a))(*[_Z(float(v.real), float(v.imag)) for v in a])
+            med.kind = MEDIUM_BUMPS
+            med.n_bumps = len(a)
+            med.centres = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            med.amps = za
+            med.width = float(bump_width)
+            self._keep += [c, za]
+        else:
+            med.kind = MEDIUM_ZERO
+        bits = 0
+        for name in block_precs:
+            bits |= PREC[name]
+        self.block_precs = tuple(block_precs)
+        opts = _Opts(bits, _stream_ptr(), 1 if verbose else 0)
+        ne = (ctypes.c_int * 3)(*self.n_elem)
+        handle = ctypes.c_void_p()
+        qq = self.p - 2 if q is None else int(q)
+        _check(L.hps_setup(ctypes.byref(dom), self.kappa, self.eta, ctypes.byref(med), self.p, qq,
+                           ne, ctypes.byref(opts), ctypes.byref(handle)))
+        self._h = handle
+        self.N = int(L.hps_num_unknowns(handle))
+        n1 = self.p - 2
+        self.ni, self.nb = n1 ** 3, 6 * n1 * n1
+        self.n = self.ni + self.nb
+        self.nl = int(np.prod(self.n_elem))
+
+    @classmethod
+    def from_problem(cls, prob, block_precs=("fp64",), verbose=False) -> "Context":
+        """Context for a problems.Problem (bump medium, or b = 0 for plane waves)."""
+        if prob.plane_dir is not None or len(prob.bump_centres) == 0:
+            return cls(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi,
+                       block_precs=block_precs, verbose=verbose)
+        return cls(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi,
+                   bump_centres=prob.bump_centres, bump_amps=prob.bump_amps,
+                   bump_width=prob.bump_width, block_precs=block_precs, verbose=verbose)
+
+    # ------------------------------------------------------------------ info
+    def _sync_stream(self):
+        _check(lib().hps_set_stream(self._h, _stream_ptr()))
+
+    def nodes(self) -> np.ndarray:
+        out = np.zeros((self.N, 3), dtype=np.float64)
+        _check(lib().hps_nodes(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def lambdas(self) -> np.ndarray:
+        self._sync_stream()
+        out = np.zeros(self.nl, dtype=np.complex128)
+        _check(lib().hps_lambdas(self._h, out.ctypes.data_as(ctypes.POINTER(_Z))))
+        return out
+
+    def device_bytes(self) -> int:
+        return int(lib().hps_device_bytes(self._h))
+
+    # ------------------------------------------------------------- operators
+    def _nrhs(self, x) -> int:
+        if x.numel() % self.N:
+            raise ValueError("vector length is not a multiple of N")
+        return x.numel() // self.N
+
+    def apply(self, x, y=None):
+        """y = A x for nrhs = x.numel() / N vectors stored one after the other."""
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        self._sync_stream()
+        _check(lib().hps_apply(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x)))
+        return y
+
+    def precond(self, x, y=None, prec: str = "fp64"):
+        """y = J^{-1} x with the blocks stored in ``prec``."""
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        self._sync_stream()
+        _check(lib().hps_precond_prec(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x), PREC[prec]))
+        return y
+
+    def assemble_rhs(self, s, t, b=None):
+        torch = _torch()
+        b = torch.empty_like(s) if b is None else b
+        self._sync_stream()
+        _check(lib().hps_assemble_rhs(self._h, _dev(s, "s"), _dev(t, "t"), _dev(b, "b"),
+                                      self._nrhs(s)))
+        return b
+
+    def gmres(self, s, t, tol: float = 1e-10, restart: int = 30, u=None, solver: str = "gmres",
+              precond_prec: str = "fp64", max_iters: int = 0, check_every: int = 1,
+              use_x0: bool = False, raise_on_nc: bool = False):
+        """Solve A u = b(s, t); returns (u, stats dict, converged flag)."""
+        torch = _torch()
+        u = torch.zeros_like(s) if u is None else u
+        so = _SolveOpts(SOLVER[solver], int(max_iters), 1 if use_x0 else 0, PREC[precond_prec],
+                        int(check_every))
+        st = Stats()
+        self._sync_stream()
+        rc = lib().hps_gmres(self._h, _dev(s, "s"), _dev(t, "t"), float(tol), int(restart),
+                             _dev(u, "u"), self._nrhs(s), ctypes.byref(so), ctypes.byref(st))
+        _check(rc, allow_nc=not raise_on_nc)
+        return u, st.as_dict(), rc == HPS_OK
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().hps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def setup_error(n_elem, p, q, kappa=10.0, lo=(0, 0, 0), hi=(1, 1, 1)):
+    """Run hps_setup on arguments expected to be rejected; returns (code, message).
+
+    The argument checks happen before any device call, so this runs without a GPU.
+    """
+    L = lib()
+    dom = _Domain((ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi))
+    ne = (ctypes.c_int * 3)(*n_elem)
+    h = ctypes.c_void_p()
+    rc = L.hps_setup(ctypes.byref(dom), float(kappa), float(kappa), None, int(p), int(q), ne, None,
+                     ctypes.byref(h))
+    if rc == HPS_OK:
+        L.hps_free(h)
+    return rc, L.hps_last_error().decode()

@@ -275,3 +275,12 @@ def request_stream(n_requests: int = 512, rate: float = 20.0, seed: int = 5,
                        bump_centres=c, bump_amps=a, source_points=pts, restart=50, tol=1e-8)
         out.append(Request(rid, t, prob))
     return out
+
+
+def rhs_data(prob: Problem, xyz: np.ndarray, which: int = 0):
+    """(s, t) of the problem at the points xyz: plane-wave impedance data or a
+    Gaussian source with t = 0."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    if prob.plane_dir is not None:
+        return np.zeros(xyz.shape[0], dtype=np.complex128), plane_wave_impedance(prob, xyz)
+    return gaussian_source(prob, xyz, which), np.zeros(xyz.shape[0], dtype=np.complex128)

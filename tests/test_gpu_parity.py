@@ -1,0 +1,159 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Sizes here are small enough for the oracle to finish in seconds while spanning
+several leaves, every supported kind of leaf adjacency, unequal leaf counts
+per axis, and several orders p (including the smallest, p = 4).
+Tolerances (FP64): operator apply 1e-13 and preconditioner 1e-12 relative in
+the 2-norm; the entrywise error is also bounded relative to the largest entry.
+"""
+import numpy as np
+import pytest
+
+from oracle import hps_oracle as O
+from paper_2112_02211_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_vec(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = [
+    # n_elem, p, kappa, bumps, seed
+    ((3, 2, 2), 7, 9.0, 4, 11),
+    ((2, 2, 2), 8, 10.0, 3, 12),
+    ((1, 1, 1), 4, 3.0, 2, 13),
+    ((2, 3, 1), 10, 20.0, 5, 14),
+    ((1, 2, 2), 12, 30.0, 3, 15),
+    ((2, 1, 1), 16, 25.0, 2, 16),
+    ((1, 1, 5), 9, 12.0, 3, 17),
+]
+
+
+@pytest.fixture(scope="module")
+def hps_mod():
+    from paper_2112_02211_amd import hps
+    hps.lib()
+    return hps
+
+
+def _setup(hps_mod, case, precs=("fp64",)):
+    n_elem, p, kappa, nbump, seed = case
+    prob = P.bump_problem("t", n_elem, p, kappa, nbump, 1, seed, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=precs)
+    op = O.build(prob)
+    return prob, ctx, op
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_nodes_and_lambda_match_oracle(hps_mod, case):
+    prob, ctx, op = _setup(hps_mod, case)
+    assert ctx.N == op.d.N
+    assert np.max(np.abs(ctx.nodes() - op.xyz)) < 1e-14
+    C = O.c_values(op.d, op.b_nodes)
+    want = np.array([O.homog_lambda(op.d, C[t * op.d.n:t * op.d.n + op.d.ni])[0]
+                     for t in range(op.d.nl)])
+    got = ctx.lambdas()
+    assert np.max(np.abs(got - want) / np.abs(want)) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_apply_matches_oracle(hps_mod, case):
+    prob, ctx, op = _setup(hps_mod, case)
+    x = rand_vec(op.d.N, 1)
+    y = host(ctx.apply(dev(x)))
+    ya = op.A @ x
+    assert rel(y, ya) < 1e-13
+    assert np.max(np.abs(y - ya)) < 1e-12 * np.max(np.abs(ya))
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_precond_matches_oracle(hps_mod, case):
+    prob, ctx, op = _setup(hps_mod, case)
+    x = rand_vec(op.d.N, 2)
+    z = host(ctx.precond(dev(x)))
+    za = O.Precond(op.d, op.b_nodes).apply(x)
+    assert rel(z, za) < 1e-12
+    assert np.max(np.abs(z - za)) < 1e-11 * np.max(np.abs(za))
+
+
+def test_assemble_rhs_matches_oracle(hps_mod):
+    prob, ctx, op = _setup(hps_mod, CASES[0])
+    s = rand_vec(op.d.N, 3)
+    t = rand_vec(op.d.N, 4)
+    b = host(ctx.assemble_rhs(dev(s), dev(t)))
+    assert np.array_equal(b, O.assemble_rhs(op.d, s, t))
+
+
+def test_multi_rhs_apply_and_precond_are_columnwise(hps_mod):
+    prob, ctx, op = _setup(hps_mod, CASES[1])
+    X = np.stack([rand_vec(op.d.N, 10 + k) for k in range(3)])
+    Y = host(ctx.apply(dev(X.reshape(-1)))).reshape(3, -1)
+    Z = host(ctx.precond(dev(X.reshape(-1)))).reshape(3, -1)
+    for k in range(3):
+        assert np.array_equal(Y[k], host(ctx.apply(dev(X[k]))))
+        assert np.array_equal(Z[k], host(ctx.precond(dev(X[k]))))
+
+
+def test_apply_and_precond_are_deterministic(hps_mod):
+    prob, ctx, op = _setup(hps_mod, CASES[3])
+    x = dev(rand_vec(op.d.N, 5))
+    assert np.array_equal(host(ctx.apply(x)), host(ctx.apply(x)))
+    assert np.array_equal(host(ctx.precond(x)), host(ctx.precond(x)))
+
+
+def test_gpu_polynomial_reproduction(hps_mod):
+    # A u = b for a polynomial of degree p-1 (a property of the discretization
+    # that holds at any size): checks the GPU operator with no oracle in the loop
+    prob = P.bump_problem("poly", (4, 3, 2), 9, 15.0, 5, 1, 21, 30, 1e-10)
+    from paper_2112_02211_amd import hps
+    ctx = hps.Context.from_problem(prob)
+    xyz = ctx.nodes()
+    bnod = P.bump_field(prob, xyz)
+    poly = P.random_poly(5, prob.p - 1)
+    s, t = P.poly_rhs(prob, poly, bnod, xyz)
+    b = host(ctx.assemble_rhs(dev(s), dev(t)))
+    y = host(ctx.apply(dev(poly.value(xyz))))
+    assert rel(y, b) < 1e-12
+
+
+def test_gmres_plane_wave_matches_direct_solve(hps_mod):
+    prob = P.workload("plane_2x2x2_p8")
+    ctx = hps_mod.Context.from_problem(prob)
+    op = O.build(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-10, restart=30)
+    assert ok and st["converged"] == 1
+    u = host(u)
+    ud = O.solve_direct(op)
+    assert rel(u, ud) < 1e-9
+    # discretization error against the exact plane wave (not parity): p = 8
+    assert 1e-6 < rel(u, P.plane_wave(prob, op.xyz)) < 1e-3
+
+
+@pytest.mark.parametrize("case", CASES[:4])
+def test_gmres_bumps_matches_direct_solve(hps_mod, case):
+    prob, ctx, op = _setup(hps_mod, case)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-12, restart=30)
+    assert ok
+    ud = O.solve_direct(op)
+    assert rel(host(u), ud) < 1e-9
+    assert st["true_rel_res"] <= 1e-12 * 1.0001
