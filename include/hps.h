@@ -169,6 +169,16 @@ int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int n
 int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
               hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st);
 
+/* Kernel timing with HIP events recorded on the context's stream around every
+ * operator launch (sweep + exchange) and every preconditioner launch, by the
+ * solvers and by hps_apply / hps_precond.  enable = 0 switches it off. */
+int hps_set_timing(hps_ctx* c, int enable);
+
+/* Totals since the last reset: out[0] = operator milliseconds, out[1] =
+ * operator launches, out[2] = preconditioner milliseconds, out[3] =
+ * preconditioner launches.  Synchronizes the stream.  reset != 0 clears them. */
+int hps_kernel_times(hps_ctx* c, double out[4], int reset);
+
 /* Device bytes held by the context (blocks, tables, workspaces). */
 int64_t hps_device_bytes(const hps_ctx* c);
 

@@ -60,6 +60,50 @@ int ws_reserve(hps_ctx* c, Workspace* w, size_t bytes) {
   return HPS_OK;
 }
 
+int timing_begin(hps_ctx* c, hipEvent_t* ev) {
+  *ev = nullptr;
+  if (!c->timing) return HPS_OK;
+  if (c->ev_free.empty()) {
+    hipEvent_t e;
+    HPS_TRY_HIP(hipEventCreate(&e));
+    c->ev_free.push_back(e);
+  }
+  *ev = c->ev_free.back();
+  c->ev_free.pop_back();
+  return check_hip(hipEventRecord(*ev, c->stream), "hipEventRecord");
+}
+
+int timing_end(hps_ctx* c, int kind, hipEvent_t ev0) {
+  if (!c->timing || !ev0) return HPS_OK;
+  if (c->ev_free.empty()) {
+    hipEvent_t e;
+    HPS_TRY_HIP(hipEventCreate(&e));
+    c->ev_free.push_back(e);
+  }
+  hipEvent_t ev1 = c->ev_free.back();
+  c->ev_free.pop_back();
+  HPS_TRY_HIP(hipEventRecord(ev1, c->stream));
+  c->ev_pending[kind].emplace_back(ev0, ev1);
+  if (c->ev_pending[kind].size() >= 4096) return timing_collect(c);
+  return HPS_OK;
+}
+
+int timing_collect(hps_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    for (auto& pr : c->ev_pending[k]) {
+      HPS_TRY_HIP(hipEventSynchronize(pr.second));
+      float ms = 0.f;
+      HPS_TRY_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      c->t_ms[k] += ms;
+      c->t_cnt[k] += 1.0;
+      c->ev_free.push_back(pr.first);
+      c->ev_free.push_back(pr.second);
+    }
+    c->ev_pending[k].clear();
+  }
+  return HPS_OK;
+}
+
 namespace {
 
 int prec_index(int prec_flag) {
@@ -291,9 +335,32 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   return HPS_OK;
 }
 
+int hps_set_timing(hps_ctx* c, int enable) {
+  if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
+  c->timing = enable ? 1 : 0;
+  return HPS_OK;
+}
+
+int hps_kernel_times(hps_ctx* c, double out[4], int reset) {
+  if (!c || !out) return fail(HPS_ERR_ARG, "NULL argument");
+  int rc = timing_collect(c);
+  if (rc) return rc;
+  out[0] = c->t_ms[0];
+  out[1] = c->t_cnt[0];
+  out[2] = c->t_ms[1];
+  out[3] = c->t_cnt[1];
+  if (reset) c->t_ms[0] = c->t_ms[1] = c->t_cnt[0] = c->t_cnt[1] = 0.0;
+  return HPS_OK;
+}
+
 void hps_free(hps_ctx* c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
+  for (auto& v : c->ev_pending)
+    for (auto& pr : v) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+  for (auto e : c->ev_free) hipEventDestroy(e);
+  for (auto e : c->ev_solver)
+    if (e) hipEventDestroy(e);
   hipFree(c->d_tab);
   hipFree(c->d_nbr);
   hipFree(c->d_C);

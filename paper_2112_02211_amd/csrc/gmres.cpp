@@ -46,6 +46,14 @@ double bytes_precond(const hps_ctx* c, int q) {
   return beta * c->nl * (double)c->nb * c->blk[q].ncp + 32.0 * c->N;
 }
 
+int solver_events(hps_ctx* c, hipEvent_t* evs) {
+  for (int i = 0; i < 2; ++i) {
+    if (!c->ev_solver[i]) HPS_TRY_HIP(hipEventCreateWithFlags(&c->ev_solver[i], hipEventDisableTiming));
+    evs[i] = c->ev_solver[i];
+  }
+  return HPS_OK;
+}
+
 struct Job {
   int nrhs;          // right-hand sides iterated in lock step
   bool flexible;     // right preconditioning with stored Z
@@ -67,7 +75,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
   rc = ws_reserve(c, &c->w_small, sizeof(GmresState) * nb);
   if (rc) return rc;
   RedBuf rb;
-  if ((rc = red_buf(c, m + 1, &rb))) return rc;
+  if ((rc = red_buf(c, m + 1, nb, &rb))) return rc;
   double2* V = static_cast<double2*>(c->w_krylov.ptr);
   double2* Z = job.flexible ? V + (size_t)(m + 1) * NB : nullptr;
   double2* tmp = V + (size_t)((m + 1) + (job.flexible ? m : 0)) * NB;
@@ -79,6 +87,8 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
   void* hp = nullptr;
   if ((rc = pinned(c, &hp))) return rc;
   double* hbuf = static_cast<double*>(hp);
+  hipEvent_t evs[2];
+  if ((rc = solver_events(c, evs))) return rc;
 
   auto Vj = [&](int j) { return V + (size_t)j * NB; };
   auto Zj = [&](int j) { return Z + (size_t)j * NB; };
@@ -148,6 +158,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     if ((rc = launch_scale_by_b(c, Vj(0), N, Vj(0), N, N, nrm2, nrm_stride, 1, nb))) return rc;
     if ((rc = launch_gm_start(c, S, nb))) return rc;
     int k = 0;
+    int pending = -1;
     for (int j = 0; j < m && its < maxit; ++j) {
       // w_j = J^{-1} A v_j (left) or A M^{-1} v_j (flexible), into V[j+1]
       if (!job.flexible) {
@@ -157,36 +168,62 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
         if ((rc = launch_precond(c, Vj(j), Zj(j), nb, job.prec))) return rc;
         if ((rc = launch_apply(c, Zj(j), Vj(j + 1), nb))) return rc;
       }
-      // CGS2 against V[0..j], per right-hand side
-      for (int pass = 0; pass < 2; ++pass) {
-        double2* hv = pass == 0 ? S[0].h1 : S[0].h2;
-        if ((rc = launch_mdot_b(c, V, NB, N, j + 1, Vj(j + 1), N, N, hv, sst, nb, rb))) return rc;
-        if ((rc = launch_mupdate_b(c, V, NB, N, j + 1, hv, sst, -1.0, Vj(j + 1), N, N,
-                                   pass == 1 ? nrm2 : nullptr, nrm_stride, nb, rb)))
-          return rc;
-      }
+      // CGS2 against V[0..j], per right-hand side, in three passes over the
+      // basis: h1 = V^H w;  w -= V h1 and h2 = V^H w (fused);  w -= V h2 with
+      // ||w||^2.  The Hessenberg column is h1 + h2.
+      if ((rc = launch_cgs_pass(c, false, V, NB, N, j + 1, nullptr, 0, Vj(j + 1), N, N, S[0].h1,
+                                sst, nb, rb)))
+        return rc;
+      if ((rc = launch_cgs_pass(c, true, V, NB, N, j + 1, S[0].h1, sst, Vj(j + 1), N, N, S[0].h2,
+                                sst, nb, rb)))
+        return rc;
+      if ((rc = launch_mupdate_b(c, V, NB, N, j + 1, S[0].h2, sst, -1.0, Vj(j + 1), N, N, nrm2,
+                                 nrm_stride, nb, rb)))
+        return rc;
       if ((rc = launch_gm_givens(c, S, nb, j))) return rc;
       if ((rc = launch_scale_by_b(c, Vj(j + 1), N, Vj(j + 1), N, N, nrm2, nrm_stride, 1, nb)))
         return rc;
       ++its;
       k = j + 1;
-      if (its % check_every == 0 || j == m - 1 || its >= maxit) {
+      // The residual estimate of step j is copied to pinned memory behind an
+      // event; the host looks at it only after step j+1 has been queued, so the
+      // device never waits for the host.
+      const bool last = (j == m - 1) || its >= maxit;
+      const bool want = (its % check_every == 0) || last;
+      if (want) {
+        const int slot = j & 1;
         for (int r = 0; r < nb; ++r)
-          HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * r, &S[r].res, 2 * sizeof(double),
+          HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * (slot * nb + r), &S[r].res, 2 * sizeof(double),
                                      hipMemcpyDeviceToHost, c->stream));
-        HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+        HPS_TRY_HIP(hipEventRecord(evs[slot], c->stream));
+      }
+      auto converged_at = [&](int step) -> int {
+        const int slot = step & 1;
+        HPS_TRY_HIP(hipEventSynchronize(evs[slot]));
         bool all = true;
         for (int r = 0; r < nb; ++r) {
-          const double res = hbuf[2 * r];
+          const double res = hbuf[2 * (slot * nb + r)];
           int bd;
-          std::memcpy(&bd, hbuf + 2 * r + 1, sizeof(int));
+          std::memcpy(&bd, hbuf + 2 * (slot * nb + r) + 1, sizeof(int));
           if (!std::isfinite(res)) return fail(HPS_ERR_NUMERIC, "non-finite residual estimate");
           est[r] = bnorm[r] > 0 ? res / bnorm[r] : 0.0;
           if (bd) breakdown = true;
           if (!(done[r] || res <= tol * bnorm[r] || bd)) all = false;
         }
-        if (all) break;
+        return all ? 1 : 0;
+      };
+      if (pending >= 0) {
+        const int cv = converged_at(pending);
+        pending = -1;
+        if (cv < 0) return cv;
+        if (cv) break;  // step j is already queued; its column is used as well
       }
+      if (last) {
+        const int cv = converged_at(j);
+        if (cv < 0) return cv;
+        break;
+      }
+      if (want) pending = j;
     }
     // x += V y (left) or Z y (flexible), per right-hand side
     if ((rc = launch_gm_trisolve(c, S, nb, k))) return rc;

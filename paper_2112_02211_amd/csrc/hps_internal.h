@@ -90,6 +90,14 @@ struct hps_ctx {
   hps::Workspace w_small;           // Hessenberg / Givens state
   void* h_pinned = nullptr;         // small pinned host buffer for scalars
   size_t dev_bytes = 0;
+
+  // optional kernel timing: event pairs per launch kind (0 operator, 1 preconditioner)
+  hipEvent_t ev_solver[2] = {nullptr, nullptr};
+  int timing = 0;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2];
+  double t_ms[2] = {0.0, 0.0};
+  double t_cnt[2] = {0.0, 0.0};
 };
 
 namespace hps {
@@ -117,6 +125,11 @@ int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, int e0, i
 int launch_pack_blocks(hps_ctx* c, const double2* Sinv, int e0, int ne, int prec);
 int launch_node_coords(hps_ctx* c, double* d_xyz);
 
+// kernel timing around a launch (no-op unless c->timing)
+int timing_begin(hps_ctx* c, hipEvent_t* ev);
+int timing_end(hps_ctx* c, int kind, hipEvent_t ev0);
+int timing_collect(hps_ctx* c);
+
 // hot path
 int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs);
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
@@ -127,8 +140,9 @@ struct RedBuf {
   double2* part;      // partial sums
   unsigned* counter;  // one counter per concurrent reduction slot
   int nblk;
+  int nbatch;         // batches the partial buffer holds
 };
-int red_buf(hps_ctx* c, int kmax, RedBuf* rb);
+int red_buf(hps_ctx* c, int kmax, int nbatch, RedBuf* rb);
 // out[k] = sum_n conj(V[k*ldv + n]) w[n], k < K.
 int launch_mdot(hps_ctx* c, const double2* V, int64_t ldv, int K, const double2* w, int64_t n,
                 double2* out, const RedBuf& rb);

@@ -176,6 +176,8 @@ int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs) {
   int rc = ws_reserve(c, &c->w_g, gbytes);
   if (rc) return rc;
   double2* g = static_cast<double2*>(c->w_g.ptr);
+  hipEvent_t ev0;
+  if ((rc = timing_begin(c, &ev0))) return rc;
   switch (c->p) {
     case 4: rc = sweep_launch<4>(c, x, y, g, nrhs); break;
     case 5: rc = sweep_launch<5>(c, x, y, g, nrhs); break;
@@ -198,7 +200,8 @@ int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs) {
   hipLaunchKernelGGL(k_apply_exchange, dim3((unsigned)((total + threads - 1) / threads), nrhs),
                      dim3(threads), 0, c->stream, y, g, c->d_nbr, c->ni, c->nb, c->n1 * c->n1, c->nl,
                      c->N);
-  return check_hip(hipGetLastError(), "k_apply_exchange");
+  if ((rc = check_hip(hipGetLastError(), "k_apply_exchange"))) return rc;
+  return timing_end(c, 0, ev0);
 }
 
 }  // namespace hps

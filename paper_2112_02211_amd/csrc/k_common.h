@@ -36,6 +36,18 @@ __device__ __forceinline__ void cfma_r(double2& acc, double s, double2 a) {
   acc.y = fma(s, a.y, acc.y);
 }
 
+// 16-byte non-temporal loads (streamed data that is not reused soon)
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+  const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld_nt(const uint4* p) {
+  const nt_u4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -26,9 +26,11 @@ namespace {
 template <int P>
 struct PL {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
-  static constexpr int RPT = (NB + 1023) / 1024;                  // block rows per thread
-  static constexpr int BD = ((NB + RPT - 1) / RPT + 63) / 64 * 64; // workgroup size
-  static constexpr int NBP = (NB + 3) / 4 * 4;                     // padded column count
+  static constexpr int KS = 2;                                         // column halves per row
+  static constexpr int SLOTS = KS * NB;                                // (row, half) work items
+  static constexpr int RPT = (SLOTS + 1023) / 1024;                    // work items per thread
+  static constexpr int BD = ((SLOTS + RPT - 1) / RPT + 63) / 64 * 64;  // workgroup size
+  static constexpr int NBP = (NB + 3) / 4 * 4;                         // padded column count
 };
 
 // In-place mode product along axis AX of the n1^3 tensor T by the n1 x n1
@@ -86,115 +88,107 @@ __device__ __forceinline__ void homog_solve(double2* __restrict__ T, const doubl
 
 // 16-byte column group of the block in each storage precision
 template <int PREC> struct BlockIO;
-template <> struct BlockIO<kFP64> {
-  using vec = double4;  // unused
-  static constexpr int CW = 1;
-};
+template <> struct BlockIO<kFP64> { static constexpr int CW = 1; };
 template <> struct BlockIO<kFP32> { static constexpr int CW = 2; };
 template <> struct BlockIO<kBF16> { static constexpr int CW = 4; };
 
 __device__ __forceinline__ float bf_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
+// u_b = S~^{-1} h_b for one leaf.  Work item (row r, half q) accumulates the
+// columns of half q of row r; the two halves are combined through LDS.  The
+// block is read once, with non-temporal 16-byte loads (it is not reused before
+// the next preconditioner call, which reads every other block first).
 template <int P, int PREC, int UNR>
 __device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t tau, int ncp,
-                                           const double2* __restrict__ H, double2* __restrict__ U,
-                                           double2* __restrict__ yb) {
+                                           const double2* __restrict__ H, double2* __restrict__ Up,
+                                           double2* __restrict__ U, double2* __restrict__ yb) {
   using Q = PL<P>;
-  constexpr int NB = Q::NB, RPT = Q::RPT, BD = Q::BD;
+  constexpr int NB = Q::NB, RPT = Q::RPT, BD = Q::BD, KS = Q::KS;
   constexpr int CW = BlockIO<PREC>::CW;
   const int ncg = ncp / CW;
-  int rows[RPT];
+  const int per = (ncg + KS - 1) / KS;
+  int rows[RPT], cg0[RPT], cg1[RPT];
   bool ok[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    rows[k] = threadIdx.x + k * BD;
-    ok[k] = rows[k] < NB;
-    if (!ok[k]) rows[k] = NB - 1;  // clamp: loads stay in bounds, result discarded
+    const int slot = threadIdx.x + k * BD;
+    ok[k] = slot < Q::SLOTS;
+    const int sl = ok[k] ? slot : 0;
+    rows[k] = sl % NB;
+    const int q = sl / NB;
+    cg0[k] = q * per;
+    cg1[k] = ok[k] ? min(ncg, (q + 1) * per) : cg0[k];
   }
   if (PREC == kFP64) {
     const double2* B = static_cast<const double2*>(blk) + (size_t)tau * ncg * NB;
-    double2 acc[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) acc[k] = make_double2(0.0, 0.0);
-    int cg = 0;
-    for (; cg + UNR <= ncg; cg += UNR) {
-      double2 s[UNR][RPT];
+    for (int k = 0; k < RPT; ++k) {
+      double2 acc = make_double2(0.0, 0.0);
+      const double2* Br = B + rows[k];
+      int cg = cg0[k];
+      for (; cg + UNR <= cg1[k]; cg += UNR) {
+        double2 sv[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
+        for (int u = 0; u < UNR; ++u) sv[u] = ld_nt(Br + (size_t)(cg + u) * NB);
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) s[u][k] = B[(size_t)(cg + u) * NB + rows[k]];
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const double2 h = H[cg + u];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          acc[k].x = fma(s[u][k].x, h.x, fma(-s[u][k].y, h.y, acc[k].x));
-          acc[k].y = fma(s[u][k].x, h.y, fma(s[u][k].y, h.x, acc[k].y));
+        for (int u = 0; u < UNR; ++u) {
+          const double2 h = H[cg + u];
+          acc.x = fma(sv[u].x, h.x, fma(-sv[u].y, h.y, acc.x));
+          acc.y = fma(sv[u].x, h.y, fma(sv[u].y, h.x, acc.y));
         }
       }
-    }
-    for (; cg < ncg; ++cg) {
-      const double2 h = H[cg];
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const double2 s = B[(size_t)cg * NB + rows[k]];
-        acc[k].x = fma(s.x, h.x, fma(-s.y, h.y, acc[k].x));
-        acc[k].y = fma(s.x, h.y, fma(s.y, h.x, acc[k].y));
+      for (; cg < cg1[k]; ++cg) {
+        const double2 h = H[cg];
+        const double2 sv = ld_nt(Br + (size_t)cg * NB);
+        acc.x = fma(sv.x, h.x, fma(-sv.y, h.y, acc.x));
+        acc.y = fma(sv.x, h.y, fma(sv.y, h.x, acc.y));
       }
+      if (ok[k]) Up[threadIdx.x + k * BD] = acc;
     }
-#pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (ok[k]) { U[rows[k]] = acc[k]; yb[rows[k]] = acc[k]; }
   } else {
     // reduced-precision blocks: FP32 arithmetic, h rounded to FP32
     const uint4* B = static_cast<const uint4*>(blk) + (size_t)tau * ncg * NB;
-    float2 acc[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) acc[k] = make_float2(0.f, 0.f);
-    for (int cg = 0; cg < ncg; cg += UNR) {
-      uint4 s[UNR][RPT];
+    for (int k = 0; k < RPT; ++k) {
+      float2 acc = make_float2(0.f, 0.f);
+      const uint4* Br = B + rows[k];
+      for (int cg = cg0[k]; cg < cg1[k]; cg += UNR) {
+        uint4 sv[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
+        for (int u = 0; u < UNR; ++u)
+          sv[u] = (cg + u < cg1[k]) ? ld_nt(Br + (size_t)(cg + u) * NB)
+                                    : make_uint4(0, 0, 0, 0);
 #pragma unroll
-        for (int k = 0; k < RPT; ++k)
-          s[u][k] = (cg + u < ncg) ? B[(size_t)(cg + u) * NB + rows[k]] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        float hr[CW], hi[CW];
-#pragma unroll
-        for (int w = 0; w < CW; ++w) {
-          const int cidx = (cg + u) * CW + w;
-          const double2 hv = (cg + u < ncg) ? H[cidx] : make_double2(0.0, 0.0);
-          hr[w] = (float)hv.x;
-          hi[w] = (float)hv.y;
-        }
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          float sr[CW], si[CW];
-          const uint32_t wv[4] = {s[u][k].x, s[u][k].y, s[u][k].z, s[u][k].w};
-          if (PREC == kFP32) {
-            sr[0] = __uint_as_float(wv[0]); si[0] = __uint_as_float(wv[1]);
-            sr[1] = __uint_as_float(wv[2]); si[1] = __uint_as_float(wv[3]);
-          } else {
-#pragma unroll
-            for (int w = 0; w < CW; ++w) { sr[w] = bf_lo(wv[w]); si[w] = bf_hi(wv[w]); }
-          }
+        for (int u = 0; u < UNR; ++u) {
+          const uint32_t wv[4] = {sv[u].x, sv[u].y, sv[u].z, sv[u].w};
 #pragma unroll
           for (int w = 0; w < CW; ++w) {
-            acc[k].x = fmaf(sr[w], hr[w], fmaf(-si[w], hi[w], acc[k].x));
-            acc[k].y = fmaf(sr[w], hi[w], fmaf(si[w], hr[w], acc[k].y));
+            const double2 hv = (cg + u < cg1[k]) ? H[(cg + u) * CW + w] : make_double2(0.0, 0.0);
+            const float hr = (float)hv.x, hi = (float)hv.y;
+            float sr, si;
+            if (PREC == kFP32) {
+              sr = __uint_as_float(wv[2 * w]);
+              si = __uint_as_float(wv[2 * w + 1]);
+            } else {
+              sr = bf_lo(wv[w]);
+              si = bf_hi(wv[w]);
+            }
+            acc.x = fmaf(sr, hr, fmaf(-si, hi, acc.x));
+            acc.y = fmaf(sr, hi, fmaf(si, hr, acc.y));
           }
         }
       }
+      if (ok[k]) Up[threadIdx.x + k * BD] = make_double2((double)acc.x, (double)acc.y);
     }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < NB; r += BD) {
+    double2 v = Up[r];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (ok[k]) {
-        const double2 v = make_double2((double)acc[k].x, (double)acc[k].y);
-        U[rows[k]] = v;
-        yb[rows[k]] = v;
-      }
+    for (int q = 1; q < KS; ++q) v = cadd(v, Up[q * NB + r]);
+    U[r] = v;
+    yb[r] = v;
   }
 }
 
@@ -208,6 +202,7 @@ __global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
   __shared__ double2 F[NI];
   __shared__ double2 H[Q::NBP];
   __shared__ double2 U[NB];
+  __shared__ double2 Up[Q::SLOTS];
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
   const double2* xv = x + rhs * N + tau * NN;
@@ -241,7 +236,7 @@ __global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
   }
   __syncthreads();
   // u_b = S~^{-1} h_b, written to y_b and kept in LDS
-  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4)>(blk, tau, ncp, H, U, yv + NI);
+  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4)>(blk, tau, ncp, H, Up, U, yv + NI);
   __syncthreads();
   // t = A_ib u_b: interior rows of -(Dx^2 + Dy^2 + Dz^2) restricted to face columns
   for (int m = threadIdx.x; m < NI; m += BD) {
@@ -284,9 +279,7 @@ int precond_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
 
 }  // namespace
 
-int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
-  if (prec < 0 || prec > 2 || !c->blk[prec].data)
-    return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
+static int precond_dispatch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
   switch (c->p) {
     case 4: return precond_launch<4>(c, x, y, nrhs, prec);
     case 5: return precond_launch<5>(c, x, y, nrhs, prec);
@@ -303,6 +296,16 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
     case 16: return precond_launch<16>(c, x, y, nrhs, prec);
     default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
   }
+}
+
+int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+  if (prec < 0 || prec > 2 || !c->blk[prec].data)
+    return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
+  hipEvent_t ev0;
+  int rc = timing_begin(c, &ev0);
+  if (rc) return rc;
+  if ((rc = precond_dispatch(c, x, y, nrhs, prec))) return rc;
+  return timing_end(c, 1, ev0);
 }
 
 }  // namespace hps

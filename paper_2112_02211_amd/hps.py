@@ -83,6 +83,8 @@ SIGNATURES = {
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                  ctypes.POINTER(_SolveOpts), ctypes.POINTER(Stats)]),
     "hps_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "hps_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hps_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     "hps_last_error": (ctypes.c_char_p, []),
     "hps_free": (None, [ctypes.c_void_p]),
 }
@@ -206,6 +208,17 @@ class Context:
         out = np.zeros(self.nl, dtype=np.complex128)
         _check(lib().hps_lambdas(self._h, out.ctypes.data_as(ctypes.POINTER(_Z))))
         return out
+
+    def set_timing(self, enable: bool = True):
+        self._sync_stream()
+        _check(lib().hps_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self, reset: bool = False) -> dict:
+        """Event-timed operator / preconditioner launches since the last reset."""
+        out = (ctypes.c_double * 4)()
+        _check(lib().hps_kernel_times(self._h, out, 1 if reset else 0))
+        return {"apply_ms": out[0], "apply_launches": int(out[1]),
+                "precond_ms": out[2], "precond_launches": int(out[3])}
 
     def device_bytes(self) -> int:
         return int(lib().hps_device_bytes(self._h))
