@@ -370,6 +370,7 @@ void hps_free(hps_ctx* c) {
   hipFree(c->w_red.ptr);
   hipFree(c->w_krylov.ptr);
   hipFree(c->w_small.ptr);
+  hipFree(c->w_batch.ptr);
   if (c->h_pinned) hipHostFree(c->h_pinned);
   delete c;
 }

@@ -88,6 +88,7 @@ struct hps_ctx {
   hps::Workspace w_red;             // reduction partials + counters
   hps::Workspace w_krylov;          // Krylov bases etc.
   hps::Workspace w_small;           // Hessenberg / Givens state
+  hps::Workspace w_batch;           // many-rhs preconditioner: H and U panels
   void* h_pinned = nullptr;         // small pinned host buffer for scalars
   size_t dev_bytes = 0;
 
@@ -133,6 +134,9 @@ int timing_collect(hps_ctx* c);
 // hot path
 int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs);
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
+// many right-hand sides: block product as a GEMM on the matrix cores
+int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
+constexpr int kBatchedMinRhs = 4;   // from this many right-hand sides on, J^-1 uses the GEMM path
 int launch_assemble_rhs(hps_ctx* c, const double2* s, const double2* t, double2* b, int nrhs);
 
 // Krylov primitives over vectors of length n (complex)

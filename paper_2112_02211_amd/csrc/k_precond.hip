@@ -19,6 +19,7 @@
 // broadcast from LDS.  No cross-lane reduction is needed.
 #include "hps_internal.h"
 #include "k_common.h"
+#include "k_leaf.h"
 
 namespace hps {
 namespace {
@@ -32,59 +33,6 @@ struct PL {
   static constexpr int BD = ((SLOTS + RPT - 1) / RPT + 63) / 64 * 64;  // workgroup size
   static constexpr int NBP = (NB + 3) / 4 * 4;                         // padded column count
 };
-
-// In-place mode product along axis AX of the n1^3 tensor T by the n1 x n1
-// row-major matrix M: T[.., a, ..] <- sum_i M[a][i] T[.., i, ..].
-template <int P, int AX>
-__device__ __forceinline__ void mode_product(double2* __restrict__ T, const double* __restrict__ M) {
-  constexpr int N1 = P - 2, L = N1 * N1;
-  for (int line = threadIdx.x; line < L; line += PL<P>::BD) {
-    const int a = line % N1, b = line / N1;
-    int base, stride;
-    if (AX == 0) { base = N1 * a + L * b; stride = 1; }
-    else if (AX == 1) { base = a + L * b; stride = N1; }
-    else { base = a + N1 * b; stride = L; }
-    double2 v[N1];
-#pragma unroll
-    for (int i = 0; i < N1; ++i) v[i] = T[base + i * stride];
-#pragma unroll
-    for (int o = 0; o < N1; ++o) {
-      double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < N1; ++i) cfma_r(s, M[o * N1 + i], v[i]);
-      T[base + o * stride] = s;
-    }
-  }
-}
-
-// T <- A~_ii^{-1} T = (V x V x V) diag(1 / (-E_Delta - lambda)) (W x W x W) T
-template <int P>
-__device__ __forceinline__ void homog_solve(double2* __restrict__ T, const double* __restrict__ tab,
-                                            double2 lam) {
-  constexpr int NI = PL<P>::NI;
-  const double* V = tab + tab_off_V(P);
-  const double* W = tab + tab_off_W(P);
-  const double* Ed3 = tab + tab_off_ed3(P);
-  mode_product<P, 0>(T, W);
-  __syncthreads();
-  mode_product<P, 1>(T, W);
-  __syncthreads();
-  mode_product<P, 2>(T, W);
-  __syncthreads();
-  for (int m = threadIdx.x; m < NI; m += PL<P>::BD) {
-    // 1 / (a + i b), a = -E - lr, b = -li
-    const double a = -Ed3[m] - lam.x, b = -lam.y;
-    const double den = 1.0 / (a * a + b * b);
-    T[m] = cmul(T[m], make_double2(a * den, -b * den));
-  }
-  __syncthreads();
-  mode_product<P, 0>(T, V);
-  __syncthreads();
-  mode_product<P, 1>(T, V);
-  __syncthreads();
-  mode_product<P, 2>(T, V);
-  __syncthreads();
-}
 
 // 16-byte column group of the block in each storage precision
 template <int PREC> struct BlockIO;
@@ -215,43 +163,18 @@ __global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
   for (int m = threadIdx.x; m < Q::NBP; m += BD) H[m] = (m < NB) ? xv[NI + m] : make_double2(0.0, 0.0);
   __syncthreads();
   // f_i = A~_ii^{-1} x_i
-  homog_solve<P>(T, tab, lm);
+  homog_solve<P, BD>(T, tab, lm);
   for (int m = threadIdx.x; m < NI; m += BD) F[m] = T[m];
-  // h_b = x_b - F_bi f_i: the interior part of the normal line through each face node
-  for (int r = threadIdx.x; r < NB; r += BD) {
-    const int f = r / L, pos = r - f * L;
-    const int ax = f >> 1, hi = f & 1;
-    const int a = pos % N1, b = pos / N1;
-    int base, stride;
-    if (ax == 0) { base = N1 * a + L * b; stride = 1; }
-    else if (ax == 1) { base = a + L * b; stride = N1; }
-    else { base = a + N1 * b; stride = L; }
-    const int e = hi ? P - 1 : 0;
-    const double sg = hi ? 1.0 : -1.0;
-    double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int t = 0; t < N1; ++t) cfma_r(s, D[e * P + t + 1], T[base + t * stride]);
-    const double2 hv = H[r];
-    H[r] = make_double2(hv.x - sg * s.x, hv.y - sg * s.y);
-  }
+  // h_b = x_b - F_bi f_i
+  face_update<P, BD>(T, H, D);
   __syncthreads();
   // u_b = S~^{-1} h_b, written to y_b and kept in LDS
   block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4)>(blk, tau, ncp, H, Up, U, yv + NI);
   __syncthreads();
-  // t = A_ib u_b: interior rows of -(Dx^2 + Dy^2 + Dz^2) restricted to face columns
-  for (int m = threadIdx.x; m < NI; m += BD) {
-    const int i = m % N1, j = (m / N1) % N1, k = m / L;
-    double2 s = make_double2(0.0, 0.0);
-    cfma_r(s, D2[(i + 1) * P + 0], U[0 * L + j + N1 * k]);
-    cfma_r(s, D2[(i + 1) * P + P - 1], U[1 * L + j + N1 * k]);
-    cfma_r(s, D2[(j + 1) * P + 0], U[2 * L + i + N1 * k]);
-    cfma_r(s, D2[(j + 1) * P + P - 1], U[3 * L + i + N1 * k]);
-    cfma_r(s, D2[(k + 1) * P + 0], U[4 * L + i + N1 * j]);
-    cfma_r(s, D2[(k + 1) * P + P - 1], U[5 * L + i + N1 * j]);
-    T[m] = make_double2(-s.x, -s.y);
-  }
+  // t = A_ib u_b
+  interior_from_faces<P, BD>(U, T, D2);
   __syncthreads();
-  homog_solve<P>(T, tab, lm);
+  homog_solve<P, BD>(T, tab, lm);
   for (int m = threadIdx.x; m < NI; m += BD) yv[m] = csub(F[m], T[m]);
 }
 
@@ -304,7 +227,9 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
   hipEvent_t ev0;
   int rc = timing_begin(c, &ev0);
   if (rc) return rc;
-  if ((rc = precond_dispatch(c, x, y, nrhs, prec))) return rc;
+  if (nrhs >= kBatchedMinRhs) rc = launch_precond_batched(c, x, y, nrhs, prec);
+  else rc = precond_dispatch(c, x, y, nrhs, prec);
+  if (rc) return rc;
   return timing_end(c, 1, ev0);
 }
 

@@ -1,0 +1,309 @@
+// J^{-1} applied to many right-hand sides at once (the batching pattern on top
+// of Sec. 4, eq. (block_pc) and Algorithm 4).  With k right-hand sides the
+// dense block product of every leaf, u_b = S~^{-1} h_b, becomes a complex GEMM
+// (n_b x n_b) * (n_b x k): the block is streamed from HBM once for all k
+// columns and the product runs on the matrix cores.  Three kernels:
+//
+//   pre   per (leaf, rhs): f_i = A~_ii^{-1} x_i (Algorithm 3), y_i = f_i,
+//         h_b = x_b - F_bi f_i written to H[leaf][rhs][n_b] in the GEMM precision
+//   gemm  per (leaf, 128-row panel, 64-column panel): U = S~^{-1} H on MFMA
+//   post  per (leaf, rhs): y_b = u_b, y_i = f_i - A~_ii^{-1} (A_ib u_b)
+//
+// The complex product is split into real matrix-core products:
+//   Re U = Re S Re H - Im S Im H,   Im U = Re S Im H + Im S Re H.
+// Precisions: FP64 blocks on v_mfma_f64_16x16x4 (FP64 accumulate), FP32 blocks
+// on v_mfma_f32_16x16x4 and BF16 blocks on v_mfma_f32_16x16x16_bf16 (FP32
+// accumulate); H is rounded to the block precision.
+#include "hps_internal.h"
+#include "k_common.h"
+#include "k_leaf.h"
+
+#include <type_traits>
+
+namespace hps {
+namespace {
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+typedef short ms4 __attribute__((ext_vector_type(4)));
+
+constexpr int PB = 256;  // threads of the pre / post kernels
+
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// ------------------------------------------------------------------ pre / post
+template <int P, int PREC>
+__global__ __launch_bounds__(PB) void k_precond_pre(const double2* __restrict__ x,
+                                                    double2* __restrict__ y, void* __restrict__ Hb,
+                                                    const double2* __restrict__ lam,
+                                                    const double* __restrict__ tab, int64_t N,
+                                                    int nrhs) {
+  constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
+  __shared__ double2 T[NI];
+  __shared__ double2 H[NB];
+  const int64_t tau = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const double2* xv = x + rhs * N + tau * NN;
+  double2* yv = y + rhs * N + tau * NN;
+  for (int m = threadIdx.x; m < NI; m += PB) T[m] = xv[m];
+  for (int m = threadIdx.x; m < NB; m += PB) H[m] = xv[NI + m];
+  __syncthreads();
+  homog_solve<P, PB>(T, tab, lam[tau]);
+  for (int m = threadIdx.x; m < NI; m += PB) yv[m] = T[m];
+  face_update<P, PB>(T, H, tab + tab_off_D(P));
+  __syncthreads();
+  const int64_t hoff = (tau * nrhs + rhs) * NB;
+  for (int r = threadIdx.x; r < NB; r += PB) {
+    const double2 h = H[r];
+    if (PREC == kFP64) {
+      static_cast<double2*>(Hb)[hoff + r] = h;
+    } else if (PREC == kFP32) {
+      static_cast<float2*>(Hb)[hoff + r] = make_float2((float)h.x, (float)h.y);
+    } else {
+      static_cast<uint32_t*>(Hb)[hoff + r] = bf16_rne((float)h.x) | (bf16_rne((float)h.y) << 16);
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(PB) void k_precond_post(double2* __restrict__ y,
+                                                     const double2* __restrict__ Ub,
+                                                     const double2* __restrict__ lam,
+                                                     const double* __restrict__ tab, int64_t N,
+                                                     int nrhs) {
+  constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
+  __shared__ double2 T[NI];
+  __shared__ double2 U[NB];
+  const int64_t tau = blockIdx.x;
+  const int rhs = blockIdx.y;
+  double2* yv = y + rhs * N + tau * NN;
+  const double2* uv = Ub + (tau * nrhs + rhs) * NB;
+  for (int r = threadIdx.x; r < NB; r += PB) {
+    const double2 u = uv[r];
+    U[r] = u;
+    yv[NI + r] = u;
+  }
+  __syncthreads();
+  interior_from_faces<P, PB>(U, T, tab + tab_off_D2(P));
+  __syncthreads();
+  homog_solve<P, PB>(T, tab, lam[tau]);
+  for (int m = threadIdx.x; m < NI; m += PB) yv[m] = csub(yv[m], T[m]);
+}
+
+// ------------------------------------------------------------------------ GEMM
+// Workgroup: 8 wavefronts; wavefront w owns rows r0 + 16 w .. +16 of a 128-row
+// panel and all 64 columns of a column panel (4 tiles of 16).  MFMA operand
+// lanes: row (or column) = lane % 16, k-slot group g = lane / 16.  Accumulator
+// register r of a lane holds column lane % 16 and row 4 g + r for the FP32 and
+// BF16 instructions but row g + 4 r for v_mfma_f64_16x16x4 (layouts checked
+// on the device with an in-bounds probe of the builtins).  One 16-byte load of the
+// block per lane supplies CW consecutive inner indices of its row; the k-slots
+// of each MFMA are mapped to inner indices so that A and B agree:
+//   FP64 (CW = 1): slot g      <-> inner kb + g
+//   FP32 (CW = 2): slot g, s   <-> inner kb + 2 g + s  (two MFMA steps)
+//   BF16 (CW = 4): slot (g, e) <-> inner kb + 4 g + e  (one step, 4 values per lane)
+// H for the column panel is staged in LDS, KT inner indices at a time.
+constexpr int GW = 8;             // wavefronts per workgroup
+constexpr int GROWS = 16 * GW;    // rows per workgroup
+constexpr int GCOLS = 64;         // right-hand sides per workgroup
+constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
+
+template <int PREC> struct GemmTraits;
+template <> struct GemmTraits<kFP64> { using H = double2; static constexpr int CW = 1, KT = 32; };
+template <> struct GemmTraits<kFP32> { using H = float2; static constexpr int CW = 2, KT = 64; };
+template <> struct GemmTraits<kBF16> { using H = uint32_t; static constexpr int CW = 4, KT = 64; };
+
+template <int PREC>
+__global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__ blk, int ncp,
+                                                        const void* __restrict__ Hb,
+                                                        double2* __restrict__ Ub, int NB,
+                                                        int nrhs) {
+  using TR = GemmTraits<PREC>;
+  using HT = typename TR::H;
+  constexpr int CW = TR::CW, KT = TR::KT, CH = 4 * CW;  // inner indices per MFMA chunk
+  __shared__ HT Bs[KT][GCOLS];
+  const int64_t tau = blockIdx.x;
+  const int r0 = blockIdx.y * GROWS;
+  const int c0 = blockIdx.z * GCOLS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int row = r0 + wv * 16 + li;
+  const int rowc = row < NB ? row : NB - 1;  // clamp: loads in bounds, results discarded
+  const int ncg = ncp / CW;
+  const uint4* B = static_cast<const uint4*>(blk) + (size_t)tau * ncg * NB;
+  const HT* Hl = static_cast<const HT*>(Hb) + (size_t)tau * nrhs * NB;
+
+  using Acc = typename std::conditional<PREC == kFP64, md4, mf4>::type;
+  Acc are[GCT], aim[GCT];
+#pragma unroll
+  for (int t = 0; t < GCT; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { are[t][r] = 0; aim[t][r] = 0; }
+  }
+
+  for (int kt = 0; kt < NB; kt += KT) {
+    __syncthreads();
+    // stage H[c0 .. c0+63][kt .. kt+KT-1] as Bs[inner][col]
+    for (int idx = threadIdx.x; idx < KT * GCOLS; idx += 64 * GW) {
+      const int col = idx / KT, kin = idx - col * KT;
+      const int cc = c0 + col, kk = kt + kin;
+      HT v;
+      if (cc < nrhs && kk < NB) v = Hl[(size_t)cc * NB + kk];
+      else v = HT{};
+      Bs[kin][col] = v;
+    }
+    __syncthreads();
+    // block fragments of this stage, all issued before use
+    constexpr int NCH = KT / CH;
+    uint4 a16[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int cg = (kt + c * CH) / CW + g;
+      a16[c] = (cg < ncg) ? ld_nt(B + (size_t)cg * NB + rowc) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int kin0 = c * CH + CW * g;  // first inner index (within the stage) of this lane
+      if constexpr (PREC == kFP64) {
+        const double ar = __hiloint2double(a16[c].y, a16[c].x);
+        const double ai = __hiloint2double(a16[c].w, a16[c].z);
+#pragma unroll
+        for (int t = 0; t < GCT; ++t) {
+          const double2 bv = reinterpret_cast<const double2&>(Bs[kin0][t * 16 + li]);
+          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv.x, are[t], 0, 0, 0);
+          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, -bv.y, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv.y, aim[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bv.x, aim[t], 0, 0, 0);
+        }
+      } else if constexpr (PREC == kFP32) {
+        const float a_r[2] = {__uint_as_float(a16[c].x), __uint_as_float(a16[c].z)};
+        const float a_i[2] = {__uint_as_float(a16[c].y), __uint_as_float(a16[c].w)};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+          for (int t = 0; t < GCT; ++t) {
+            const float2 bv = reinterpret_cast<const float2&>(Bs[kin0 + s][t * 16 + li]);
+            are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r[s], bv.x, are[t], 0, 0, 0);
+            are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i[s], -bv.y, are[t], 0, 0, 0);
+            aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r[s], bv.y, aim[t], 0, 0, 0);
+            aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i[s], bv.x, aim[t], 0, 0, 0);
+          }
+        }
+      } else {
+        // four (re, im) bf16 pairs -> four re and four im values per lane
+        const uint32_t w4[4] = {a16[c].x, a16[c].y, a16[c].z, a16[c].w};
+        ms4 a_r, a_i;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a_r[e] = (short)(w4[e] & 0xFFFFu);
+          a_i[e] = (short)(w4[e] >> 16);
+        }
+#pragma unroll
+        for (int t = 0; t < GCT; ++t) {
+          ms4 b_r, b_i, b_ni;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t hv = reinterpret_cast<const uint32_t&>(Bs[kin0 + e][t * 16 + li]);
+            b_r[e] = (short)(hv & 0xFFFFu);
+            b_i[e] = (short)(hv >> 16);
+            b_ni[e] = (short)((hv >> 16) ^ 0x8000u);
+          }
+          are[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_r, b_r, are[t], 0, 0, 0);
+          are[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_i, b_ni, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_r, b_i, aim[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_i, b_r, aim[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // accumulator lane layout: column c0 + 16 t + li; row r0 + 16 wv + (4 g + r)
+  // (FP32, BF16) or r0 + 16 wv + (g + 4 r) (FP64)
+#pragma unroll
+  for (int t = 0; t < GCT; ++t) {
+    const int col = c0 + t * 16 + li;
+    if (col >= nrhs) continue;
+    double2* uo = Ub + ((size_t)tau * nrhs + col) * NB;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = r0 + wv * 16 + (PREC == kFP64 ? g + 4 * r : 4 * g + r);
+      if (rr < NB) uo[rr] = make_double2((double)are[t][r], (double)aim[t][r]);
+    }
+  }
+}
+
+template <int P>
+int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec, void* Hb,
+                   double2* Ub) {
+  dim3 g2((unsigned)c->nl, (unsigned)nrhs);
+  switch (prec) {
+    case kFP64:
+      hipLaunchKernelGGL((k_precond_pre<P, kFP64>), g2, dim3(PB), 0, c->stream, x, y, Hb,
+                         c->d_lambda, c->d_tab, c->N, nrhs);
+      break;
+    case kFP32:
+      hipLaunchKernelGGL((k_precond_pre<P, kFP32>), g2, dim3(PB), 0, c->stream, x, y, Hb,
+                         c->d_lambda, c->d_tab, c->N, nrhs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_precond_pre<P, kBF16>), g2, dim3(PB), 0, c->stream, x, y, Hb,
+                         c->d_lambda, c->d_tab, c->N, nrhs);
+      break;
+  }
+  int rc = check_hip(hipGetLastError(), "k_precond_pre");
+  if (rc) return rc;
+  const Blocks& Bk = c->blk[prec];
+  dim3 g3((unsigned)c->nl, (unsigned)((c->nb + GROWS - 1) / GROWS), (unsigned)((nrhs + GCOLS - 1) / GCOLS));
+  switch (prec) {
+    case kFP64:
+      hipLaunchKernelGGL((k_block_gemm<kFP64>), g3, dim3(64 * GW), 0, c->stream, Bk.data, Bk.ncp, Hb,
+                         Ub, c->nb, nrhs);
+      break;
+    case kFP32:
+      hipLaunchKernelGGL((k_block_gemm<kFP32>), g3, dim3(64 * GW), 0, c->stream, Bk.data, Bk.ncp, Hb,
+                         Ub, c->nb, nrhs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_block_gemm<kBF16>), g3, dim3(64 * GW), 0, c->stream, Bk.data, Bk.ncp, Hb,
+                         Ub, c->nb, nrhs);
+      break;
+  }
+  if ((rc = check_hip(hipGetLastError(), "k_block_gemm"))) return rc;
+  hipLaunchKernelGGL((k_precond_post<P>), g2, dim3(PB), 0, c->stream, y, Ub, c->d_lambda, c->d_tab,
+                     c->N, nrhs);
+  return check_hip(hipGetLastError(), "k_precond_post");
+}
+
+}  // namespace
+
+int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+  const size_t hel = prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4);
+  const size_t hbytes = (size_t)c->nl * nrhs * c->nb * hel;
+  const size_t ubytes = (size_t)c->nl * nrhs * c->nb * sizeof(double2);
+  const size_t hpad = (hbytes + 255) / 256 * 256;
+  int rc = ws_reserve(c, &c->w_batch, hpad + ubytes);
+  if (rc) return rc;
+  void* Hb = c->w_batch.ptr;
+  double2* Ub = reinterpret_cast<double2*>(static_cast<char*>(c->w_batch.ptr) + hpad);
+  switch (c->p) {
+    case 4: return batched_launch<4>(c, x, y, nrhs, prec, Hb, Ub);
+    case 5: return batched_launch<5>(c, x, y, nrhs, prec, Hb, Ub);
+    case 6: return batched_launch<6>(c, x, y, nrhs, prec, Hb, Ub);
+    case 7: return batched_launch<7>(c, x, y, nrhs, prec, Hb, Ub);
+    case 8: return batched_launch<8>(c, x, y, nrhs, prec, Hb, Ub);
+    case 9: return batched_launch<9>(c, x, y, nrhs, prec, Hb, Ub);
+    case 10: return batched_launch<10>(c, x, y, nrhs, prec, Hb, Ub);
+    case 11: return batched_launch<11>(c, x, y, nrhs, prec, Hb, Ub);
+    case 12: return batched_launch<12>(c, x, y, nrhs, prec, Hb, Ub);
+    case 13: return batched_launch<13>(c, x, y, nrhs, prec, Hb, Ub);
+    case 14: return batched_launch<14>(c, x, y, nrhs, prec, Hb, Ub);
+    case 15: return batched_launch<15>(c, x, y, nrhs, prec, Hb, Ub);
+    case 16: return batched_launch<16>(c, x, y, nrhs, prec, Hb, Ub);
+    default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
+  }
+}
+
+}  // namespace hps
