@@ -176,8 +176,10 @@ int hps_set_timing(hps_ctx* c, int enable);
 
 /* Totals since the last reset: out[0] = operator milliseconds, out[1] =
  * operator launches, out[2] = preconditioner milliseconds, out[3] =
- * preconditioner launches.  Synchronizes the stream.  reset != 0 clears them. */
-int hps_kernel_times(hps_ctx* c, double out[4], int reset);
+ * preconditioner launches, out[4] = milliseconds of the many-right-hand-side
+ * block GEMM kernel alone, out[5] = its launches.  Synchronizes the stream.
+ * reset != 0 clears them. */
+int hps_kernel_times(hps_ctx* c, double out[6], int reset);
 
 /* Device bytes held by the context (blocks, tables, workspaces). */
 int64_t hps_device_bytes(const hps_ctx* c);

@@ -75,6 +75,7 @@ int timing_begin(hps_ctx* c, hipEvent_t* ev) {
 
 int timing_end(hps_ctx* c, int kind, hipEvent_t ev0) {
   if (!c->timing || !ev0) return HPS_OK;
+  if (kind < 0 || kind >= kTimingKinds) return fail(HPS_ERR_ARG, "timing kind out of range");
   if (c->ev_free.empty()) {
     hipEvent_t e;
     HPS_TRY_HIP(hipEventCreate(&e));
@@ -89,19 +90,26 @@ int timing_end(hps_ctx* c, int kind, hipEvent_t ev0) {
 }
 
 int timing_collect(hps_ctx* c) {
-  for (int k = 0; k < 2; ++k) {
+  static_assert(sizeof(c->ev_pending) / sizeof(c->ev_pending[0]) == kTimingKinds, "timing kinds");
+  int rc = HPS_OK;
+  for (int k = 0; k < kTimingKinds; ++k) {
     for (auto& pr : c->ev_pending[k]) {
-      HPS_TRY_HIP(hipEventSynchronize(pr.second));
-      float ms = 0.f;
-      HPS_TRY_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-      c->t_ms[k] += ms;
-      c->t_cnt[k] += 1.0;
+      if (rc == HPS_OK) {
+        float ms = 0.f;
+        rc = check_hip(hipEventSynchronize(pr.second), "hipEventSynchronize");
+        if (rc == HPS_OK) rc = check_hip(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+        if (rc == HPS_OK) {
+          c->t_ms[k] += ms;
+          c->t_cnt[k] += 1.0;
+        }
+      }
+      // every event goes back to the pool exactly once, also after an error
       c->ev_free.push_back(pr.first);
       c->ev_free.push_back(pr.second);
     }
     c->ev_pending[k].clear();
   }
-  return HPS_OK;
+  return rc;
 }
 
 namespace {
@@ -341,15 +349,15 @@ int hps_set_timing(hps_ctx* c, int enable) {
   return HPS_OK;
 }
 
-int hps_kernel_times(hps_ctx* c, double out[4], int reset) {
+int hps_kernel_times(hps_ctx* c, double out[6], int reset) {
   if (!c || !out) return fail(HPS_ERR_ARG, "NULL argument");
   int rc = timing_collect(c);
   if (rc) return rc;
-  out[0] = c->t_ms[0];
-  out[1] = c->t_cnt[0];
-  out[2] = c->t_ms[1];
-  out[3] = c->t_cnt[1];
-  if (reset) c->t_ms[0] = c->t_ms[1] = c->t_cnt[0] = c->t_cnt[1] = 0.0;
+  for (int k = 0; k < kTimingKinds; ++k) {
+    out[2 * k] = c->t_ms[k];
+    out[2 * k + 1] = c->t_cnt[k];
+    if (reset) c->t_ms[k] = c->t_cnt[k] = 0.0;
+  }
   return HPS_OK;
 }
 

@@ -72,7 +72,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
   const size_t need = vec_bytes * ((size_t)(m + 1) + (job.flexible ? m : 0) + 1);
   int rc = ws_reserve(c, &c->w_krylov, need);
   if (rc) return rc;
-  rc = ws_reserve(c, &c->w_small, sizeof(GmresState) * nb);
+  rc = ws_reserve(c, &c->w_small, sizeof(GmresState) * nb + 4 * sizeof(double) * nb);
   if (rc) return rc;
   RedBuf rb;
   if ((rc = red_buf(c, m + 1, nb, &rb))) return rc;
@@ -80,6 +80,8 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
   double2* Z = job.flexible ? V + (size_t)(m + 1) * NB : nullptr;
   double2* tmp = V + (size_t)((m + 1) + (job.flexible ? m : 0)) * NB;
   GmresState* S = static_cast<GmresState*>(c->w_small.ptr);
+  // two slots of (residual estimate, breakdown) per right-hand side
+  double* d_res = reinterpret_cast<double*>(S + nb);
   const int64_t sst = sizeof(GmresState) / sizeof(double2);  // state stride in double2 units
   static_assert(sizeof(GmresState) % sizeof(double2) == 0, "state stride");
   double* nrm2 = &S[0].nrm2;
@@ -97,8 +99,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     return launch_norm2_b(c, v, N, N, nrm2, nrm_stride, nb, rb);
   };
   auto read_nrm2 = [&](std::vector<double>& out) -> int {
-    for (int r = 0; r < nb; ++r)
-      HPS_TRY_HIP(hipMemcpyAsync(hbuf + r, nrm2 + r * nrm_stride, sizeof(double),
+    HPS_TRY_HIP(hipMemcpy2DAsync(hbuf, sizeof(double), nrm2, sizeof(GmresState), sizeof(double), nb,
                                  hipMemcpyDeviceToHost, c->stream));
     HPS_TRY_HIP(hipStreamSynchronize(c->stream));
     out.assign(hbuf, hbuf + nb);
@@ -192,9 +193,9 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
       const bool want = (its % check_every == 0) || last;
       if (want) {
         const int slot = j & 1;
-        for (int r = 0; r < nb; ++r)
-          HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * (slot * nb + r), &S[r].res, 2 * sizeof(double),
-                                     hipMemcpyDeviceToHost, c->stream));
+        if ((rc = launch_gm_collect(c, S, nb, d_res + 2 * slot * nb))) return rc;
+        HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * slot * nb, d_res + 2 * slot * nb,
+                                   2 * sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
         HPS_TRY_HIP(hipEventRecord(evs[slot], c->stream));
       }
       auto converged_at = [&](int step) -> int {
@@ -203,8 +204,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
         bool all = true;
         for (int r = 0; r < nb; ++r) {
           const double res = hbuf[2 * (slot * nb + r)];
-          int bd;
-          std::memcpy(&bd, hbuf + 2 * (slot * nb + r) + 1, sizeof(int));
+          const int bd = hbuf[2 * (slot * nb + r) + 1] != 0.0;
           if (!std::isfinite(res)) return fail(HPS_ERR_NUMERIC, "non-finite residual estimate");
           est[r] = bnorm[r] > 0 ? res / bnorm[r] : 0.0;
           if (bd) breakdown = true;

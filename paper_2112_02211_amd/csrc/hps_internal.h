@@ -64,6 +64,8 @@ struct Workspace {
 
 }  // namespace hps
 
+constexpr int kTimingKinds = 3;
+
 struct hps_ctx {
   int p = 0, n1 = 0, ni = 0, nb = 0, n = 0;
   int E[3] = {0, 0, 0};
@@ -92,13 +94,15 @@ struct hps_ctx {
   void* h_pinned = nullptr;         // small pinned host buffer for scalars
   size_t dev_bytes = 0;
 
-  // optional kernel timing: event pairs per launch kind (0 operator, 1 preconditioner)
-  hipEvent_t ev_solver[2] = {nullptr, nullptr};
+  hipEvent_t ev_solver[2] = {nullptr, nullptr};  // residual-check events of the solvers
+
+  // optional kernel timing: event pairs per launch kind (kTimingKinds: 0 operator,
+  // 1 preconditioner, 2 many-rhs block GEMM)
   int timing = 0;
   std::vector<hipEvent_t> ev_free;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2];
-  double t_ms[2] = {0.0, 0.0};
-  double t_cnt[2] = {0.0, 0.0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[3];
+  double t_ms[3] = {0.0, 0.0, 0.0};
+  double t_cnt[3] = {0.0, 0.0, 0.0};
 };
 
 namespace hps {

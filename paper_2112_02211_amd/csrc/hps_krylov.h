@@ -44,6 +44,7 @@ int launch_cgs_pass(hps_ctx* c, bool update, const double2* V, int64_t ldv, int6
                     double2* out, int64_t obs, int nbatch, const RedBuf& rb);
 int launch_gm_start(hps_ctx* c, GmresState* S, int nb);
 int launch_gm_givens(hps_ctx* c, GmresState* S, int nb, int j);
+int launch_gm_collect(hps_ctx* c, const GmresState* S, int nb, double* out);
 int launch_gm_trisolve(hps_ctx* c, GmresState* S, int nb, int k);
 
 }  // namespace hps

@@ -336,6 +336,14 @@ __global__ __launch_bounds__(64) void k_gm_givens(GmresState* __restrict__ S, in
   for (int i = lane; i <= j + 1; i += 64) col[i] = h[i];
 }
 
+// out[2 b] = residual estimate, out[2 b + 1] = breakdown flag of right-hand side b
+__global__ void k_gm_collect(const GmresState* __restrict__ S, int nb, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  out[2 * b] = S[b].res;
+  out[2 * b + 1] = (double)S[b].breakdown;
+}
+
 // y = R^{-1} g for the leading k x k triangle of the rotated Hessenberg matrix
 // (column-oriented back substitution: after y_i is known every row above it
 // is updated in parallel).  R is staged in LDS when it fits.
@@ -477,6 +485,11 @@ int launch_gm_start(hps_ctx* c, GmresState* S, int nb) {
 int launch_gm_givens(hps_ctx* c, GmresState* S, int nb, int j) {
   hipLaunchKernelGGL(k_gm_givens, dim3(nb), dim3(64), 0, c->stream, S, j, 1e-14);
   return check_hip(hipGetLastError(), "k_gm_givens");
+}
+
+int launch_gm_collect(hps_ctx* c, const GmresState* S, int nb, double* out) {
+  hipLaunchKernelGGL(k_gm_collect, dim3((nb + 63) / 64), dim3(64), 0, c->stream, S, nb, out);
+  return check_hip(hipGetLastError(), "k_gm_collect");
 }
 
 int launch_gm_trisolve(hps_ctx* c, GmresState* S, int nb, int k) {

@@ -256,6 +256,8 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
   int rc = check_hip(hipGetLastError(), "k_precond_pre");
   if (rc) return rc;
   const Blocks& Bk = c->blk[prec];
+  hipEvent_t ev0;
+  if ((rc = timing_begin(c, &ev0))) return rc;
   dim3 g3((unsigned)c->nl, (unsigned)((c->nb + GROWS - 1) / GROWS), (unsigned)((nrhs + GCOLS - 1) / GCOLS));
   switch (prec) {
     case kFP64:
@@ -272,6 +274,7 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
       break;
   }
   if ((rc = check_hip(hipGetLastError(), "k_block_gemm"))) return rc;
+  if ((rc = timing_end(c, 2, ev0))) return rc;
   hipLaunchKernelGGL((k_precond_post<P>), g2, dim3(PB), 0, c->stream, y, Ub, c->d_lambda, c->d_tab,
                      c->N, nrhs);
   return check_hip(hipGetLastError(), "k_precond_post");

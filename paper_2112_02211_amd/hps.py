@@ -215,10 +215,11 @@ class Context:
 
     def kernel_times(self, reset: bool = False) -> dict:
         """Event-timed operator / preconditioner launches since the last reset."""
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * 6)()
         _check(lib().hps_kernel_times(self._h, out, 1 if reset else 0))
         return {"apply_ms": out[0], "apply_launches": int(out[1]),
-                "precond_ms": out[2], "precond_launches": int(out[3])}
+                "precond_ms": out[2], "precond_launches": int(out[3]),
+                "gemm_ms": out[4], "gemm_launches": int(out[5])}
 
     def device_bytes(self) -> int:
         return int(lib().hps_device_bytes(self._h))

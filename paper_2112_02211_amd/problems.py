@@ -240,7 +240,7 @@ def workload(name: str) -> Problem:
     if name == "bumps_16x16x16_p12":
         return bump_problem(name, (16, 16, 16), 12, 80.0, 20, 1, seed=3, restart=50, tol=1e-8)
     if name == "bumps_16x16x16_p10_64rhs":
-        return bump_problem(name, (16, 16, 16), 10, 60.0, 6, 64, seed=4, restart=30, tol=1e-8)
+        return bump_problem(name, (16, 16, 16), 10, 60.0, 6, 64, seed=4, restart=16, tol=1e-8)
     raise KeyError(name)
 
 

@@ -105,3 +105,22 @@ def test_lockstep_equals_individual_solves(hps_mod):
         u1, st1, ok1 = ctx.gmres(dev(S[r]), dev(T[r]), tol=1e-11, restart=20)
         u1 = host(u1)
         assert np.linalg.norm(U[r] - u1) / np.linalg.norm(u1) < 1e-9
+
+
+def test_kernel_timing_counts_launches(hps_mod):
+    # regression: the event-timing API over the single-column and the batched paths
+    prob = P.bump_problem("kt", (2, 2, 1), 8, 10.0, 3, 1, 28, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("fp64", "fp32"))
+    ctx.set_timing(True)
+    ctx.kernel_times(reset=True)
+    x1 = dev(rand_block(ctx.N, 1, 1).reshape(-1))
+    x6 = dev(rand_block(ctx.N, 6, 2).reshape(-1))
+    for _ in range(3):
+        ctx.apply(x1)
+        ctx.precond(x1)
+        ctx.precond(x6, prec="fp32")
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_timing(False)
+    assert kt["apply_launches"] == 3 and kt["precond_launches"] == 6 and kt["gemm_launches"] == 3
+    assert kt["apply_ms"] > 0 and kt["precond_ms"] > kt["gemm_ms"] > 0
+    assert ctx.kernel_times()["precond_launches"] == 0
