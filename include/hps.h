@@ -181,6 +181,22 @@ int hps_set_timing(hps_ctx* c, int enable);
  * reset != 0 clears them. */
 int hps_kernel_times(hps_ctx* c, double out[6], int reset);
 
+/* Device bytes hps_setup keeps for a mesh of n_elem leaves at order p with the
+ * block precisions block_precs (tables, medium, blocks); *transient receives
+ * the extra bytes setup needs while it builds the blocks (NULL allowed).
+ * Returns a negative error code for invalid sizes. */
+int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex_medium,
+                        int64_t* transient);
+
+/* Device bytes hps_gmres needs for a solve with this context (solver
+ * workspaces, which the context keeps for reuse, plus the right-hand side it
+ * assembles for the call).  so as for hps_gmres (NULL = defaults). */
+int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, const hps_solve_opts* so);
+
+/* Release the solver and operator workspaces of an idle context (the blocks,
+ * tables and medium stay).  They are allocated again by the next call. */
+int hps_trim(hps_ctx* c);
+
 /* Device bytes held by the context (blocks, tables, workspaces). */
 int64_t hps_device_bytes(const hps_ctx* c);
 

@@ -385,6 +385,49 @@ void hps_free(hps_ctx* c) {
 
 int64_t hps_num_unknowns(const hps_ctx* c) { return c ? c->N : -1; }
 
+int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex_medium,
+                        int64_t* transient) {
+  if (p < kMinP || p > kMaxP || !n_elem) return fail(HPS_ERR_ARG, "bad sizes");
+  for (int a = 0; a < 3; ++a)
+    if (n_elem[a] < 1) return fail(HPS_ERR_ARG, "bad sizes");
+  const int64_t n1 = p - 2, ni = n1 * n1 * n1, nb = 6 * n1 * n1;
+  const int64_t nl = (int64_t)n_elem[0] * n_elem[1] * n_elem[2];
+  const int precs = block_precs ? block_precs : HPS_PREC_FP64;
+  int64_t bytes = (int64_t)sizeof(double) * tab_size(p) + (int64_t)sizeof(int) * 6 * nl +
+                  nl * ni * (complex_medium ? 16 : 8) + 16 * nl;
+  const int bits[3] = {HPS_PREC_FP64, HPS_PREC_FP32, HPS_PREC_BF16};
+  for (int q = 0; q < 3; ++q) {
+    if (!(precs & bits[q])) continue;
+    const int64_t cw = block_cw(q);
+    const int64_t ncp = (nb + cw - 1) / cw * cw;
+    bytes += nl * ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
+  }
+  if (transient) {
+    const int64_t blk = nb * nb * 16;
+    int64_t chunk = (int64_t)((1ull << 30) / blk);
+    if (chunk < 1) chunk = 1;
+    if (chunk > nl) chunk = nl;
+    // Schur chunk, pivots, P and Q, and room for the solver library's workspace
+    *transient = chunk * (blk + 4 * (nb + 1)) + 16 * ni * nb + (int64_t)(256ll << 20);
+  }
+  return bytes;
+}
+
+int hps_trim(hps_ctx* c) {
+  if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
+  HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch};
+  for (Workspace* w : ws) {
+    if (w->ptr) {
+      HPS_TRY_HIP(hipFree(w->ptr));
+      c->dev_bytes -= w->bytes;
+    }
+    w->ptr = nullptr;
+    w->bytes = 0;
+  }
+  return HPS_OK;
+}
+
 int64_t hps_device_bytes(const hps_ctx* c) { return c ? (int64_t)c->dev_bytes : -1; }
 
 int hps_set_stream(hps_ctx* c, void* stream) {

@@ -269,6 +269,23 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
 
 using namespace hps;
 
+extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, const hps_solve_opts* so) {
+  if (!c || restart < 1 || restart > kMaxRestart || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments");
+  hps_solve_opts o{};
+  if (so) o = *so;
+  const bool flexible = o.solver == HPS_SOLVER_FGMRES ||
+                        (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64);
+  const int64_t nbat = o.solver == HPS_SOLVER_BLOCK ? std::min(nrhs, kMaxBatch) : 1;
+  const int64_t vec = 16 * c->N * nbat;
+  int64_t bytes = vec * ((restart + 1) + (flexible ? restart : 0) + 1);  // basis (+Z) + tmp
+  bytes += (int64_t)sizeof(GmresState) * nbat + 32 * nbat;               // Hessenberg state
+  bytes += (int64_t)kPartSlots * kRedBlocks * 16 * nbat;                  // reduction partials
+  bytes += 16 * nbat * c->nl * c->nb;                                     // face buffer
+  if (nbat >= kBatchedMinRhs) bytes += nbat * c->nl * c->nb * (16 + 16) + 256;  // H, U panels
+  bytes += 16 * c->N * nrhs;                                              // assembled b
+  return bytes;
+}
+
 extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
                          hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st) {
   if (!c || !s || !t || !u || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_gmres");

@@ -85,6 +85,11 @@ SIGNATURES = {
     "hps_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
     "hps_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hps_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
+    "hps_setup_bytes": (ctypes.c_int64, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    "hps_solve_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(_SolveOpts)]),
+    "hps_trim": (ctypes.c_int, [ctypes.c_void_p]),
     "hps_last_error": (ctypes.c_char_p, []),
     "hps_free": (None, [ctypes.c_void_p]),
 }
@@ -221,6 +226,20 @@ class Context:
                 "precond_ms": out[2], "precond_launches": int(out[3]),
                 "gemm_ms": out[4], "gemm_launches": int(out[5])}
 
+    def solve_bytes(self, restart: int, nrhs: int = 1, solver: str = "gmres",
+                    precond_prec: str = "fp64") -> int:
+        """Device bytes a gmres call with these settings needs (library's own plan)."""
+        so = _SolveOpts(SOLVER[solver], 0, 0, PREC[precond_prec], 1)
+        v = int(lib().hps_solve_bytes(self._h, int(restart), int(nrhs), ctypes.byref(so)))
+        if v < 0:
+            raise HPSError(v, lib().hps_last_error().decode())
+        return v
+
+    def trim(self):
+        """Free the solver/operator workspaces (blocks stay resident)."""
+        self._sync_stream()
+        _check(lib().hps_trim(self._h))
+
     def device_bytes(self) -> int:
         return int(lib().hps_device_bytes(self._h))
 
@@ -279,6 +298,19 @@ class Context:
             self.free()
         except Exception:
             pass
+
+
+def setup_bytes(n_elem, p, block_precs=("fp64",), complex_medium=False):
+    """(resident, transient) device bytes of hps_setup for this mesh (no GPU needed)."""
+    bits = 0
+    for name in block_precs:
+        bits |= PREC[name]
+    tr = ctypes.c_int64()
+    ne = (ctypes.c_int * 3)(*[int(e) for e in n_elem])
+    v = int(lib().hps_setup_bytes(int(p), ne, bits, 1 if complex_medium else 0, ctypes.byref(tr)))
+    if v < 0:
+        raise HPSError(v, lib().hps_last_error().decode())
+    return v, int(tr.value)
 
 
 def setup_error(n_elem, p, q, kappa=10.0, lo=(0, 0, 0), hi=(1, 1, 1)):

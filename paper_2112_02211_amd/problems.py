@@ -253,18 +253,30 @@ class Request:
 
 
 def request_stream(n_requests: int = 512, rate: float = 20.0, seed: int = 5,
-                   meshes=(4, 8, 12, 16), orders=(8, 10)) -> List[Request]:
+                   meshes=(4, 8, 12, 16), orders=(8, 10), share: float = 0.0) -> List[Request]:
     """Poisson stream of solve requests with mixed meshes, orders and media.
 
     Each request draws: E1 from ``meshes``, p from ``orders``, points per
     wavelength ppw ~ U[8, 12] with kappa = 2 pi E1 p / ppw, a bump count
-    in {5..20}, bump centres/amplitudes, and one Gaussian source.
+    in {5..20}, bump centres/amplitudes, and one Gaussian source.  With
+    probability ``share`` a request instead reuses the mesh, order, wave
+    number and medium of an earlier request (the same scatterer) and draws
+    only a new source point.
     """
     rng = np.random.default_rng(seed)
     t = 0.0
-    out = []
+    out: List[Request] = []
     for rid in range(n_requests):
         t += rng.exponential(1.0 / rate)
+        if out and share > 0.0 and rng.uniform() < share:
+            base = out[int(rng.integers(0, len(out)))].prob
+            pts = rng.uniform(0.2, 0.8, (1, 3))
+            prob = Problem(name=f"req{rid}", n_elem=base.n_elem, p=base.p, kappa=base.kappa,
+                           eta=base.eta, lo=base.lo, hi=base.hi, bump_centres=base.bump_centres,
+                           bump_amps=base.bump_amps, bump_width=base.bump_width,
+                           source_points=pts, restart=base.restart, tol=base.tol)
+            out.append(Request(rid, t, prob))
+            continue
         e1 = int(rng.choice(meshes))
         p = int(rng.choice(orders))
         ppw = rng.uniform(8.0, 12.0)

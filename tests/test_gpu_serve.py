@@ -1,0 +1,61 @@
+"""The solve server on the GPU: every request's solution is the same when it is
+served alone and when it is served in a mix with others (concurrent slots,
+shared cached operators, lock-step batches), within 1e-8 relative (the solves
+run to 1e-10), and matches the oracle's direct solve.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import hps_oracle as O
+from paper_2112_02211_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _fresh(reqs):
+    return [P.Request(r.rid, r.arrival, dataclasses.replace(r.prob)) for r in reqs]
+
+
+def test_same_result_alone_and_in_the_mix():
+    from paper_2112_02211_amd.serve import Server, ServeConfig, latency_stats
+    reqs = P.request_stream(14, rate=60.0, seed=11, meshes=(2, 3), orders=(6, 8), share=0.5)
+    cfg = ServeConfig(slots=4, tol=1e-10, restart=30)
+    srv = Server(cfg)
+    mix = srv.run(_fresh(reqs))
+    srv.close()
+    st = latency_stats(mix)
+    assert st["all_converged"] and st["requests"] == len(reqs)
+    assert st["p50_ms"] <= st["p99_ms"]
+    assert max(r.batch for r in mix) > 1                      # batching happened
+    spans = sorted((r.start, r.finish) for r in mix)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))  # overlap happened
+    for r in reqs:
+        srv1 = Server(ServeConfig(slots=1, tol=1e-10, restart=30))
+        alone = srv1.run(_fresh([r]), closed_loop=True)[0]
+        srv1.close()
+        got = next(x for x in mix if x.rid == r.rid)
+        err = np.linalg.norm(got.u - alone.u) / np.linalg.norm(alone.u)
+        assert err < 1e-8, (r.rid, err, got.batch)
+    # spot checks against the oracle's direct solve
+    for r in reqs[:3]:
+        op = O.build(r.prob)
+        ud = O.solve_direct(op)
+        got = next(x for x in mix if x.rid == r.rid)
+        assert np.linalg.norm(got.u - ud) / np.linalg.norm(ud) < 1e-8
+
+
+def test_admission_respects_a_small_budget():
+    from paper_2112_02211_amd.serve import Server, ServeConfig
+    reqs = P.request_stream(6, rate=100.0, seed=12, meshes=(3,), orders=(8,), share=0.0)
+    srv = Server(ServeConfig(slots=3, tol=1e-8, restart=20))
+    one = srv._size("x", reqs[0].prob, 1, False)
+    srv.budget = int(1.5 * one)          # room for one job at a time
+    srv.sched.budget = srv.budget
+    res = srv.run(_fresh(reqs), closed_loop=True)
+    srv.close()
+    assert all(r.converged for r in res)
+    spans = sorted((r.start, r.finish) for r in res)
+    assert all(spans[i + 1][0] >= spans[i][1] - 1e-3 for i in range(len(spans) - 1))
