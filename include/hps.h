@@ -96,6 +96,8 @@ typedef struct {
   int use_x0;          /* nonzero: u holds the initial guess on entry */
   int precond_prec;    /* HPS_PREC_* used inside J^-1 (must have been built); 0 = FP64 */
   int check_every;     /* host convergence poll interval in iterations; 0 = 1 */
+  int orth;            /* 0: delayed-reorthogonalization Gram-Schmidt (restart <= 64, else CGS2);
+                          1: classical Gram-Schmidt twice (CGS2) */
 } hps_solve_opts;
 
 typedef struct {

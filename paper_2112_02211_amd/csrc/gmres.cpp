@@ -12,8 +12,11 @@
 //    batched operator and one batched preconditioner application per step,
 //    inner products and rotations per right-hand side.
 //
-// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): two multi-dot
-// passes and two multi-axpy passes per step, each one pass over the basis.
+// Arnoldi orthogonalization: by default the delayed-reorthogonalization
+// process of hps_krylov.h (one reduction pass and one update pass over the
+// basis per step, restart <= 64); otherwise classical Gram-Schmidt applied
+// twice (CGS2) in three passes (h1 = V^H w; w -= V h1 fused with h2 = V^H w;
+// w -= V h2 with the norm).
 // Everything except the loop control lives on the device; the host reads the
 // residual estimates back every check_every steps.
 #include <chrono>
@@ -264,6 +267,189 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
   return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
 }
 
+
+// (F)GMRES(m) with the delayed-reorthogonalization Arnoldi process (two passes
+// over the basis per step, see hps_krylov.h); m <= kMaxDcgs.  Same stopping
+// rules, restart policy and pipelined residual checks as run_gmres.
+int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m, int maxit,
+             int use_x0, int check_every, hps_stats* st) {
+  const int64_t N = c->N;
+  const int nb = job.nrhs;
+  const int64_t NB = N * nb;
+  const size_t vec_bytes = sizeof(double2) * NB;
+  // V (m), candidate U, operator image W, TMP, Z' (m, flexible)
+  const size_t need = vec_bytes * ((size_t)m + 3 + (job.flexible ? m : 0));
+  int rc = ws_reserve(c, &c->w_krylov, need);
+  if (rc) return rc;
+  rc = ws_reserve(c, &c->w_small, sizeof(DcgsState) * nb + 6 * sizeof(double) * nb);
+  if (rc) return rc;
+  RedBuf rb;
+  if ((rc = red_buf(c, kMaxDcgs + 1, nb, &rb))) return rc;
+  double2* V = static_cast<double2*>(c->w_krylov.ptr);
+  double2* U = V + (size_t)m * NB;
+  double2* W = U + NB;
+  double2* TMP = W + NB;
+  double2* Z = job.flexible ? TMP + NB : nullptr;
+  DcgsState* S = static_cast<DcgsState*>(c->w_small.ptr);
+  double* d_res = reinterpret_cast<double*>(S + nb);   // 2 slots x (res, flag) per rhs
+  double* d_nrm = d_res + 4 * nb;                        // norms^2 per rhs
+  static_assert(sizeof(DcgsState) % sizeof(double2) == 0, "state stride");
+  const int64_t sst = sizeof(DcgsState) / sizeof(double2);
+  void* hp = nullptr;
+  if ((rc = pinned(c, &hp))) return rc;
+  double* hbuf = static_cast<double*>(hp);
+  hipEvent_t evs[2];
+  if ((rc = solver_events(c, evs))) return rc;
+  auto Vj = [&](int j) { return V + (size_t)j * NB; };
+  auto Zj = [&](int j) { return Z + (size_t)j * NB; };
+
+  auto read_norms = [&](std::vector<double>& out) -> int {
+    HPS_TRY_HIP(hipMemcpyAsync(hbuf + 4 * nb, d_nrm, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                               c->stream));
+    HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+    out.assign(hbuf + 4 * nb, hbuf + 5 * nb);
+    return HPS_OK;
+  };
+  // first candidate of a cycle: left J^-1 (b - A x), flexible b - A x (unnormalized), and its norm
+  auto residual = [&](bool x_zero) -> int {
+    int e;
+    if (x_zero) {
+      HPS_TRY_HIP(hipMemcpyAsync(TMP, b, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      if ((e = launch_apply(c, x, TMP, nb))) return e;
+      if ((e = launch_sub_from(c, b, TMP, NB))) return e;
+    }
+    if (!job.flexible) {
+      if ((e = launch_precond(c, TMP, U, nb, job.prec))) return e;
+    } else {
+      HPS_TRY_HIP(hipMemcpyAsync(U, TMP, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return launch_norm2_b(c, U, N, N, d_nrm, 1, nb, rb);
+  };
+
+  const double t0 = now();
+  std::vector<double> bn2, beta2;
+  if ((rc = residual(true))) return rc;
+  if ((rc = read_norms(bn2))) return rc;
+  std::vector<double> bnorm(nb);
+  for (int r = 0; r < nb; ++r) bnorm[r] = std::sqrt(bn2[r]);
+  if (use_x0) {
+    if ((rc = residual(false))) return rc;
+    if ((rc = read_norms(beta2))) return rc;
+  } else {
+    HPS_TRY_HIP(hipMemsetAsync(x, 0, vec_bytes, c->stream));
+    beta2 = bn2;
+  }
+  for (int r = 0; r < nb; ++r)
+    if (!std::isfinite(beta2[r]) || !std::isfinite(bn2[r]))
+      return fail(HPS_ERR_NUMERIC, "non-finite residual norm (NaN or Inf in the data)");
+  int its = 0, restarts = 0;
+  std::vector<int> done(nb, 0);
+  std::vector<double> est(nb, 0.0);
+  auto all_done = [&]() {
+    for (int r = 0; r < nb; ++r)
+      if (!done[r]) return false;
+    return true;
+  };
+  for (int r = 0; r < nb; ++r) {
+    done[r] = (bnorm[r] == 0.0) || (std::sqrt(beta2[r]) <= tol * bnorm[r]);
+    est[r] = bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0;
+  }
+  while (!all_done() && its < maxit) {
+    if ((rc = launch_dcgs_start(c, S, nb))) return rc;
+    int pending = -1;
+    int written = 0;      // basis vectors V[0..written-1] written by update passes
+    auto converged_at = [&](int step) -> int {
+      const int slot = step & 1;
+      HPS_TRY_HIP(hipEventSynchronize(evs[slot]));
+      bool all = true;
+      for (int r = 0; r < nb; ++r) {
+        const double res = hbuf[2 * (slot * nb + r)];
+        const bool flag = hbuf[2 * (slot * nb + r) + 1] != 0.0;
+        if (!std::isfinite(res)) return fail(HPS_ERR_NUMERIC, "non-finite residual estimate");
+        est[r] = bnorm[r] > 0 ? res / bnorm[r] : 0.0;
+        if (!(done[r] || res <= tol * bnorm[r] || flag)) all = false;
+      }
+      return all ? 1 : 0;
+    };
+    for (int j = 0; j < m && its < maxit; ++j) {
+      // operator image of the candidate: left J^-1 A u, flexible A M^-1 u (z'_j kept)
+      if (!job.flexible) {
+        if ((rc = launch_apply(c, U, TMP, nb))) return rc;
+        if ((rc = launch_precond(c, TMP, W, nb, job.prec))) return rc;
+      } else {
+        if ((rc = launch_precond(c, U, Zj(j), nb, job.prec))) return rc;
+        if ((rc = launch_apply(c, Zj(j), W, nb))) return rc;
+      }
+      if ((rc = launch_dcgs_reduce(c, V, NB, N, j, U, N, W, N, N, S, nb, rb))) return rc;
+      const int slot = j & 1;
+      if ((rc = launch_dcgs_small(c, S, nb, j, job.flexible ? 1 : 0, 0, d_res + 2 * slot * nb)))
+        return rc;
+      if ((rc = launch_dcgs_update(c, V, NB, N, j, U, N, W, N, N, S, nb))) return rc;
+      written = j + 1;
+      ++its;
+      const bool last = (j == m - 1) || its >= maxit;
+      const bool want = (its % check_every == 0) || last;
+      if (want) {
+        HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * slot * nb, d_res + 2 * slot * nb, 2 * sizeof(double) * nb,
+                                   hipMemcpyDeviceToHost, c->stream));
+        HPS_TRY_HIP(hipEventRecord(evs[slot], c->stream));
+      }
+      if (pending >= 0) {
+        const int cv = converged_at(pending);
+        pending = -1;
+        if (cv < 0) return cv;
+        if (cv) break;
+      }
+      if (last) {
+        const int cv = converged_at(j);
+        if (cv < 0) return cv;
+        break;
+      }
+      if (want) pending = j;
+    }
+    // close the last column: reduction of the current candidate against the
+    // basis (a no-op for right-hand sides whose cycle already stopped)
+    if ((rc = launch_dcgs_reduce(c, V, NB, N, written, U, N, nullptr, 0, N, S, nb, rb))) return rc;
+    if ((rc = launch_dcgs_small(c, S, nb, written, job.flexible ? 1 : 0, 1, d_res))) return rc;
+    if ((rc = launch_dcgs_trisolve(c, S, nb, written, job.flexible ? 1 : 0))) return rc;
+    if ((rc = launch_mupdate_b(c, job.flexible ? Z : V, NB, N, written, S[0].y, sst, 1.0, x, N, N,
+                               nullptr, 0, nb, rb)))
+      return rc;
+    ++restarts;
+    if ((rc = residual(false))) return rc;
+    if ((rc = read_norms(beta2))) return rc;
+    for (int r = 0; r < nb; ++r) {
+      if (!std::isfinite(beta2[r])) return fail(HPS_ERR_NUMERIC, "non-finite residual");
+      const double rr = bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0;
+      if (rr <= tol) done[r] = 1;
+    }
+  }
+  if (st) {
+    double worst_est = 0.0, worst_true = 0.0;
+    for (int r = 0; r < nb; ++r) {
+      worst_est = std::max(worst_est, est[r]);
+      worst_true = std::max(worst_true, bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0);
+    }
+    st->iters = its;
+    st->restarts = restarts;
+    st->converged = all_done() ? 1 : 0;
+    st->lambda_shifted = c->n_shifted;
+    st->rel_res = worst_est;
+    st->true_rel_res = worst_true;
+    st->t_solve = now() - t0;
+    st->bytes_apply = bytes_apply(c);
+    st->bytes_precond = bytes_precond(c, job.prec);
+  }
+  return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
+}
+
+int run_solver(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m,
+               int maxit, int use_x0, int check_every, int orth, hps_stats* st) {
+  if (orth == 0 && m <= kMaxDcgs)
+    return run_dcgs(c, job, b, x, tol, m, maxit, use_x0, check_every, st);
+  return run_gmres(c, job, b, x, tol, m, maxit, use_x0, check_every, st);
+}
 }  // namespace
 }  // namespace hps
 
@@ -320,8 +506,8 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       for (int r0 = 0; r0 < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); r0 += kMaxBatch) {
         job.nrhs = std::min(kMaxBatch, nrhs - r0);
         hps_stats one{};
-        const int r1 = run_gmres(c, job, bvec + (size_t)r0 * c->N, x + (size_t)r0 * c->N, tol,
-                                 restart, maxit, o.use_x0, check_every, &one);
+        const int r1 = run_solver(c, job, bvec + (size_t)r0 * c->N, x + (size_t)r0 * c->N, tol,
+                                  restart, maxit, o.use_x0, check_every, o.orth, &one);
         if (r1 < 0) { rc = r1; break; }
         if (r1 == HPS_NOT_CONVERGED) rc = r1;
         acc.iters = std::max(acc.iters, one.iters);
@@ -340,8 +526,8 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       hps_stats acc{};
       for (int r = 0; r < nrhs; ++r) {
         hps_stats one{};
-        const int r1 = run_gmres(c, job, bvec + (size_t)r * c->N, x + (size_t)r * c->N, tol,
-                                 restart, maxit, o.use_x0, check_every, &one);
+        const int r1 = run_solver(c, job, bvec + (size_t)r * c->N, x + (size_t)r * c->N, tol,
+                                  restart, maxit, o.use_x0, check_every, o.orth, &one);
         if (r1 < 0) { rc = r1; break; }
         if (r1 == HPS_NOT_CONVERGED) rc = r1;
         acc.iters += one.iters;

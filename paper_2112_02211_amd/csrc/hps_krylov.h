@@ -48,3 +48,57 @@ int launch_gm_collect(hps_ctx* c, const GmresState* S, int nb, double* out);
 int launch_gm_trisolve(hps_ctx* c, GmresState* S, int nb, int k);
 
 }  // namespace hps
+
+namespace hps {
+
+// ----------------------------------------------------------------------------
+// Arnoldi with delayed reorthogonalization (two passes over the basis per step).
+// At step j the basis V_0..V_{j-1} is orthonormal and u_j is the candidate for
+// v_j after one projection.  The operator is applied to u_j itself (w = Op u_j);
+// one reduction pass gives a = V^H u_j, b = V^H w, c = ||u_j||^2, d = u_j^H w;
+// then beta = sqrt(c - ||a||^2), column j-1 of the Hessenberg matrix is
+// (g_{j-1} + a, beta), v_j = (u_j - V a) / beta, and one update pass writes v_j
+// and the next candidate u_{j+1} = (w - V b - v_j (d - a^H b) / beta) / beta.
+// The projection of Op v_j on V_j, needed for column j, is
+// g_j = ([b; (d - a^H b) / beta] - Hbar a) / beta.  With a flexible
+// preconditioner the raw preconditioned candidates Z' are kept and the
+// corrections accumulate in an upper triangular T with Z = Z' T.
+constexpr int kMaxDcgs = 64;
+constexpr int kDcgsLd = kMaxDcgs + 1;
+constexpr int kSlotB = 64, kSlotC = 128, kSlotD = 129, kDcgsSlots = 130;
+
+struct DcgsState {
+  double2 H[kDcgsLd * kMaxDcgs];    // Hessenberg matrix as built (column major)
+  double2 R[kDcgsLd * kMaxDcgs];    // its Givens-rotated copy
+  double2 T[kMaxDcgs * kMaxDcgs];   // flexible: Z = Z' T (column major, upper triangular)
+  double2 red[kDcgsSlots];          // finished reductions: a | b | c | d
+  double cs[kMaxDcgs];
+  double2 sn[kMaxDcgs];
+  double2 gls[kDcgsLd];             // right-hand side of the small least-squares problem
+  double2 gprev[kDcgsLd];           // projection of the last operator image (next column)
+  double2 ca[kMaxDcgs];             // update-pass coefficients for u_j
+  double2 cb[kDcgsLd];              // update-pass coefficients for w
+  double2 y[kMaxDcgs];
+  double inv_beta;
+  double beta0;
+  double res;
+  int flag;                         // nonzero: the candidate fell into the basis (stop the cycle)
+  int ncols;                        // finished Hessenberg columns
+};
+
+// reduction pass: partials of a, b (j basis vectors), c, d, finished into S[b].red
+int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int J,
+                       const double2* u, int64_t ubs, const double2* w, int64_t wbs, int64_t n,
+                       DcgsState* S, int nbatch, const RedBuf& rb);
+// small step kernel (one wavefront per right-hand side); final_only: only close column j-1
+int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible, int final_only,
+                      double* res_out);
+// update pass: V[J] = v_j, u <- u_{j+1}
+int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
+                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, const DcgsState* S,
+                       int nbatch);
+int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch);
+// y = R^{-1} gls over the finished columns (at most kmax); flexible: y <- T y
+int launch_dcgs_trisolve(hps_ctx* c, DcgsState* S, int nbatch, int kmax, int flexible);
+
+}  // namespace hps

@@ -21,6 +21,7 @@ HPS_NOT_CONVERGED = 1
 ERRORS = {-1: "ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BREAKDOWN", -6: "NUMERIC"}
 PREC = {"fp64": 1, "fp32": 2, "bf16": 4}
 SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2}
+ORTH = {"dcgs": 0, "cgs2": 1}
 MEDIUM_ZERO, MEDIUM_NODAL, MEDIUM_BUMPS = 0, 1, 2
 
 
@@ -50,7 +51,7 @@ class _Opts(ctypes.Structure):
 
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("max_iters", ctypes.c_int), ("use_x0", ctypes.c_int),
-                ("precond_prec", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("precond_prec", ctypes.c_int), ("check_every", ctypes.c_int), ("orth", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -229,7 +230,7 @@ class Context:
     def solve_bytes(self, restart: int, nrhs: int = 1, solver: str = "gmres",
                     precond_prec: str = "fp64") -> int:
         """Device bytes a gmres call with these settings needs (library's own plan)."""
-        so = _SolveOpts(SOLVER[solver], 0, 0, PREC[precond_prec], 1)
+        so = _SolveOpts(SOLVER[solver], 0, 0, PREC[precond_prec], 1, 0)
         v = int(lib().hps_solve_bytes(self._h, int(restart), int(nrhs), ctypes.byref(so)))
         if v < 0:
             raise HPSError(v, lib().hps_last_error().decode())
@@ -275,12 +276,15 @@ class Context:
 
     def gmres(self, s, t, tol: float = 1e-10, restart: int = 30, u=None, solver: str = "gmres",
               precond_prec: str = "fp64", max_iters: int = 0, check_every: int = 1,
-              use_x0: bool = False, raise_on_nc: bool = False):
-        """Solve A u = b(s, t); returns (u, stats dict, converged flag)."""
+              use_x0: bool = False, raise_on_nc: bool = False, orth: str = "dcgs"):
+        """Solve A u = b(s, t); returns (u, stats dict, converged flag).
+
+        orth: "dcgs" (delayed reorthogonalization, two passes per step; restart
+        <= 64) or "cgs2" (classical Gram-Schmidt twice, three passes)."""
         torch = _torch()
         u = torch.zeros_like(s) if u is None else u
         so = _SolveOpts(SOLVER[solver], int(max_iters), 1 if use_x0 else 0, PREC[precond_prec],
-                        int(check_every))
+                        int(check_every), ORTH[orth])
         st = Stats()
         self._sync_stream()
         rc = lib().hps_gmres(self._h, _dev(s, "s"), _dev(t, "t"), float(tol), int(restart),

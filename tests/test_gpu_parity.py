@@ -157,3 +157,62 @@ def test_gmres_bumps_matches_direct_solve(hps_mod, case):
     ud = O.solve_direct(op)
     assert rel(host(u), ud) < 1e-9
     assert st["true_rel_res"] <= 1e-12 * 1.0001
+
+
+@pytest.mark.parametrize("solver,prec,nrhs", [("gmres", "fp64", 1), ("fgmres", "fp64", 1),
+                                              ("fgmres", "bf16", 1), ("batched", "fp64", 5),
+                                              ("batched", "fp32", 5)])
+def test_two_orthogonalizations_agree(hps_mod, solver, prec, nrhs):
+    # delayed-reorthogonalization Arnoldi vs classical Gram-Schmidt twice: the
+    # same Krylov method, so iteration counts match up to rounding and the
+    # solutions agree to the solver tolerance; both match the direct solve
+    prob = P.bump_problem("o", (2, 2, 2), 8, 14.0, 4, nrhs, 31, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"))
+    op = O.build(prob)
+    xyz = ctx.nodes()
+    S = np.concatenate([P.rhs_data(prob, xyz, r)[0] for r in range(nrhs)])
+    T = np.zeros_like(S)
+    out = {}
+    for orth in ("dcgs", "cgs2"):
+        u, st, ok = ctx.gmres(dev(S), dev(T), tol=1e-11, restart=20, solver=solver,
+                              precond_prec=prec, orth=orth)
+        assert ok
+        out[orth] = (host(u).reshape(nrhs, -1), st)
+    assert abs(out["dcgs"][1]["iters"] - out["cgs2"][1]["iters"]) <= 2
+    for r in range(nrhs):
+        ud = O.solve_direct(op, O.assemble_rhs(op.d, S[r * op.d.N:(r + 1) * op.d.N], np.zeros(op.d.N)))
+        for orth in ("dcgs", "cgs2"):
+            assert rel(out[orth][0][r], ud) < 1e-9, (orth, r)
+
+
+def test_long_restart_uses_cgs2(hps_mod):
+    prob = P.bump_problem("lr", (2, 2, 2), 8, 14.0, 4, 1, 32, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob)
+    op = O.build(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-11, restart=80)
+    assert ok and st["restarts"] == 1
+    assert rel(host(u), O.solve_direct(op)) < 1e-9
+
+
+def test_iteration_limit_reports_not_converged(hps_mod):
+    prob = P.bump_problem("nc", (2, 2, 2), 8, 14.0, 4, 1, 33, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-12, restart=10, max_iters=7)
+    assert not ok and st["converged"] == 0 and st["iters"] == 7
+    assert 0 < st["true_rel_res"] < 1.0
+    from paper_2112_02211_amd.hps import HPSError
+    with pytest.raises(HPSError):
+        ctx.gmres(dev(s), dev(t), tol=1e-12, restart=10, max_iters=7, raise_on_nc=True)
+
+
+def test_nan_input_is_reported(hps_mod):
+    prob = P.bump_problem("nan", (2, 1, 1), 6, 8.0, 2, 1, 34, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    s[5] = np.nan
+    from paper_2112_02211_amd.hps import HPSError
+    with pytest.raises(HPSError) as e:
+        ctx.gmres(dev(s), dev(t), tol=1e-10, restart=10)
+    assert e.value.code == -6

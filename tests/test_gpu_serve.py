@@ -23,8 +23,14 @@ def test_same_result_alone_and_in_the_mix():
     from paper_2112_02211_amd.serve import Server, ServeConfig, latency_stats
     reqs = P.request_stream(14, rate=60.0, seed=11, meshes=(2, 3), orders=(6, 8), share=0.5)
     cfg = ServeConfig(slots=4, tol=1e-10, restart=30)
+    # all requests queued at once: requests on a shared operator are batched
+    # deterministically and the slots run concurrently
     srv = Server(cfg)
-    mix = srv.run(_fresh(reqs))
+    mix = srv.run(_fresh(reqs), closed_loop=True)
+    srv.close()
+    # and the same stream replayed in real time (batching then depends on timing)
+    srv = Server(cfg)
+    live = srv.run(_fresh(reqs))
     srv.close()
     st = latency_stats(mix)
     assert st["all_converged"] and st["requests"] == len(reqs)
@@ -36,9 +42,10 @@ def test_same_result_alone_and_in_the_mix():
         srv1 = Server(ServeConfig(slots=1, tol=1e-10, restart=30))
         alone = srv1.run(_fresh([r]), closed_loop=True)[0]
         srv1.close()
-        got = next(x for x in mix if x.rid == r.rid)
-        err = np.linalg.norm(got.u - alone.u) / np.linalg.norm(alone.u)
-        assert err < 1e-8, (r.rid, err, got.batch)
+        for res in (mix, live):
+            got = next(x for x in res if x.rid == r.rid)
+            err = np.linalg.norm(got.u - alone.u) / np.linalg.norm(alone.u)
+            assert err < 1e-8, (r.rid, err, got.batch)
     # spot checks against the oracle's direct solve
     for r in reqs[:3]:
         op = O.build(r.prob)
