@@ -171,9 +171,14 @@ int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int n
 int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
               hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st);
 
-/* Kernel timing with HIP events recorded on the context's stream around every
- * operator launch (sweep + exchange) and every preconditioner launch, by the
- * solvers and by hps_apply / hps_precond.  enable = 0 switches it off. */
+/* Kernel timing with HIP events attached to the kernel dispatches themselves
+ * (start and end timestamps of the launch) for operator launches (sweep, plus
+ * the exchange when it is a separate kernel), preconditioner launches and the
+ * many-right-hand-side block GEMM, by the solvers and by hps_apply /
+ * hps_precond.  enable = 0 switches it off; enable = k > 0 times every k-th
+ * launch of each kind (each timed launch costs a few microseconds of stream
+ * time, so a period of 8 to 16 keeps a timed solve close to an untimed one).
+ * Negative values: HPS_ERR_ARG. */
 int hps_set_timing(hps_ctx* c, int enable);
 
 /* Totals since the last reset: out[0] = operator milliseconds, out[1] =

@@ -60,31 +60,36 @@ int ws_reserve(hps_ctx* c, Workspace* w, size_t bytes) {
   return HPS_OK;
 }
 
-int timing_begin(hps_ctx* c, hipEvent_t* ev) {
-  *ev = nullptr;
+int timing_pair(hps_ctx* c, int kind, TimedPair* tp) {
+  tp->start = tp->stop = nullptr;
   if (!c->timing) return HPS_OK;
-  if (c->ev_free.empty()) {
+  if (kind < 0 || kind >= kTimingKinds) return fail(HPS_ERR_ARG, "timing kind out of range");
+  if (c->t_seq[kind]++ % c->timing != 0) return HPS_OK;  // not sampled
+  while (c->ev_free.size() < 2) {
     hipEvent_t e;
     HPS_TRY_HIP(hipEventCreate(&e));
     c->ev_free.push_back(e);
   }
-  *ev = c->ev_free.back();
+  tp->start = c->ev_free.back();
   c->ev_free.pop_back();
-  return check_hip(hipEventRecord(*ev, c->stream), "hipEventRecord");
+  tp->stop = c->ev_free.back();
+  c->ev_free.pop_back();
+  return HPS_OK;
 }
 
-int timing_end(hps_ctx* c, int kind, hipEvent_t ev0) {
-  if (!c->timing || !ev0) return HPS_OK;
-  if (kind < 0 || kind >= kTimingKinds) return fail(HPS_ERR_ARG, "timing kind out of range");
-  if (c->ev_free.empty()) {
-    hipEvent_t e;
-    HPS_TRY_HIP(hipEventCreate(&e));
-    c->ev_free.push_back(e);
+void timing_drop(hps_ctx* c, const TimedPair& tp) {
+  if (tp.start) c->ev_free.push_back(tp.start);
+  if (tp.stop) c->ev_free.push_back(tp.stop);
+}
+
+int timing_commit(hps_ctx* c, int kind, const TimedPair& tp) {
+  if (!tp.start) return HPS_OK;
+  if (kind < 0 || kind >= kTimingKinds) {
+    c->ev_free.push_back(tp.start);
+    c->ev_free.push_back(tp.stop);
+    return fail(HPS_ERR_ARG, "timing kind out of range");
   }
-  hipEvent_t ev1 = c->ev_free.back();
-  c->ev_free.pop_back();
-  HPS_TRY_HIP(hipEventRecord(ev1, c->stream));
-  c->ev_pending[kind].emplace_back(ev0, ev1);
+  c->ev_pending[kind].emplace_back(tp.start, tp.stop);
   if (c->ev_pending[kind].size() >= 4096) return timing_collect(c);
   return HPS_OK;
 }
@@ -345,7 +350,9 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
 
 int hps_set_timing(hps_ctx* c, int enable) {
   if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
-  c->timing = enable ? 1 : 0;
+  if (enable < 0) return fail(HPS_ERR_ARG, "timing period must be >= 0");
+  c->timing = enable;
+  for (int k = 0; k < kTimingKinds; ++k) c->t_seq[k] = 0;
   return HPS_OK;
 }
 

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "hps_internal.h"
@@ -47,6 +48,17 @@ double bytes_apply(const hps_ctx* c) {
 double bytes_precond(const hps_ctx* c, int q) {
   const double beta = q == kFP64 ? 16.0 : (q == kFP32 ? 8.0 : 4.0);
   return beta * c->nl * (double)c->nb * c->blk[q].ncp + 32.0 * c->N;
+}
+
+// Algorithmic bytes of the timed apply and preconditioner launches of a solve.
+// Left preconditioning with fewer than kBatchedMinRhs right-hand sides fuses
+// the face exchange into J^{-1}: the apply is the sweep alone (x, y, C and the
+// face buffer written) and J^{-1} also reads the face buffer.
+void solve_bytes_stats(const hps_ctx* c, bool flexible, int nb, int prec, hps_stats* st) {
+  const double face = 16.0 * c->nl * (double)c->nb;
+  const bool fused = !flexible && nb < kBatchedMinRhs;
+  st->bytes_apply = bytes_apply(c) - (fused ? face : 0.0);
+  st->bytes_precond = bytes_precond(c, prec) + (fused ? face : 0.0);
 }
 
 int solver_events(hps_ctx* c, hipEvent_t* evs) {
@@ -166,8 +178,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     for (int j = 0; j < m && its < maxit; ++j) {
       // w_j = J^{-1} A v_j (left) or A M^{-1} v_j (flexible), into V[j+1]
       if (!job.flexible) {
-        if ((rc = launch_apply(c, Vj(j), tmp, nb))) return rc;
-        if ((rc = launch_precond(c, tmp, Vj(j + 1), nb, job.prec))) return rc;
+        if ((rc = launch_op_left(c, Vj(j), tmp, Vj(j + 1), nb, job.prec))) return rc;
       } else {
         if ((rc = launch_precond(c, Vj(j), Zj(j), nb, job.prec))) return rc;
         if ((rc = launch_apply(c, Zj(j), Vj(j + 1), nb))) return rc;
@@ -261,8 +272,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     st->rel_res = worst_est;
     st->true_rel_res = worst_true;
     st->t_solve = now() - t0;
-    st->bytes_apply = bytes_apply(c);
-    st->bytes_precond = bytes_precond(c, job.prec);
+    solve_bytes_stats(c, job.flexible, nb, job.prec, st);
   }
   return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
 }
@@ -291,23 +301,48 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
   double2* TMP = W + NB;
   double2* Z = job.flexible ? TMP + NB : nullptr;
   DcgsState* S = static_cast<DcgsState*>(c->w_small.ptr);
-  double* d_res = reinterpret_cast<double*>(S + nb);   // 2 slots x (res, flag) per rhs
+  double* d_res = reinterpret_cast<double*>(S + nb);   // 4 doubles per rhs (last column)
   double* d_nrm = d_res + 4 * nb;                        // norms^2 per rhs
   static_assert(sizeof(DcgsState) % sizeof(double2) == 0, "state stride");
   const int64_t sst = sizeof(DcgsState) / sizeof(double2);
   void* hp = nullptr;
   if ((rc = pinned(c, &hp))) return rc;
   double* hbuf = static_cast<double*>(hp);
-  hipEvent_t evs[2];
-  if ((rc = solver_events(c, evs))) return rc;
+  // Residual records: the update pass of step j writes {estimate, stopped, tag}
+  // for every right-hand side straight into pinned host memory (slot j & 1),
+  // the tag last with a system-scope release; the host waits for the tag of
+  // the step it reads.  No copy and no event is queued per step.
+  double* hrec = hbuf;                 // 2 slots x nb x 4 doubles
+  double* hnrm = hbuf + 8 * nb;        // norms^2 read back at restarts
+  void* drec_v = nullptr;
+  HPS_TRY_HIP(hipHostGetDevicePointer(&drec_v, hrec, 0));
+  double* drec = static_cast<double*>(drec_v);
+  const uint64_t epoch = (uint64_t)(++c->solve_epoch) << 32;
   auto Vj = [&](int j) { return V + (size_t)j * NB; };
   auto Zj = [&](int j) { return Z + (size_t)j * NB; };
 
   auto read_norms = [&](std::vector<double>& out) -> int {
-    HPS_TRY_HIP(hipMemcpyAsync(hbuf + 4 * nb, d_nrm, sizeof(double) * nb, hipMemcpyDeviceToHost,
-                               c->stream));
+    HPS_TRY_HIP(hipMemcpyAsync(hnrm, d_nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
     HPS_TRY_HIP(hipStreamSynchronize(c->stream));
-    out.assign(hbuf + 4 * nb, hbuf + 5 * nb);
+    out.assign(hnrm, hnrm + nb);
+    return HPS_OK;
+  };
+  // wait until every right-hand side's record in `slot` carries `tag`
+  auto wait_records = [&](int slot, uint64_t tag) -> int {
+    for (int r = 0; r < nb; ++r) {
+      const uint64_t* tp = reinterpret_cast<const uint64_t*>(hrec + 4 * (slot * nb + r) + 2);
+      for (long spins = 1; __atomic_load_n(tp, __ATOMIC_ACQUIRE) != tag; ++spins) {
+        if ((spins & 255) == 0) {
+          const hipError_t e = hipStreamQuery(c->stream);
+          if (e == hipSuccess) {  // all queued work is done: the record must be there
+            if (__atomic_load_n(tp, __ATOMIC_ACQUIRE) == tag) break;
+            return fail(HPS_ERR_DEVICE, "residual record of a finished step is missing");
+          }
+          if (e != hipErrorNotReady) return check_hip(e, "hipStreamQuery");
+        }
+        std::this_thread::yield();
+      }
+    }
     return HPS_OK;
   };
   // first candidate of a cycle: left J^-1 (b - A x), flexible b - A x (unnormalized), and its norm
@@ -358,14 +393,16 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
   while (!all_done() && its < maxit) {
     if ((rc = launch_dcgs_start(c, S, nb))) return rc;
     int pending = -1;
+    uint64_t pending_tag = 0;
     int written = 0;      // basis vectors V[0..written-1] written by update passes
-    auto converged_at = [&](int step) -> int {
+    auto converged_at = [&](int step, uint64_t tag) -> int {
       const int slot = step & 1;
-      HPS_TRY_HIP(hipEventSynchronize(evs[slot]));
+      int e = wait_records(slot, tag);
+      if (e) return e;
       bool all = true;
       for (int r = 0; r < nb; ++r) {
-        const double res = hbuf[2 * (slot * nb + r)];
-        const bool flag = hbuf[2 * (slot * nb + r) + 1] != 0.0;
+        const double res = hrec[4 * (slot * nb + r)];
+        const bool flag = hrec[4 * (slot * nb + r) + 1] != 0.0;
         if (!std::isfinite(res)) return fail(HPS_ERR_NUMERIC, "non-finite residual estimate");
         est[r] = bnorm[r] > 0 ? res / bnorm[r] : 0.0;
         if (!(done[r] || res <= tol * bnorm[r] || flag)) all = false;
@@ -375,43 +412,41 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     for (int j = 0; j < m && its < maxit; ++j) {
       // operator image of the candidate: left J^-1 A u, flexible A M^-1 u (z'_j kept)
       if (!job.flexible) {
-        if ((rc = launch_apply(c, U, TMP, nb))) return rc;
-        if ((rc = launch_precond(c, TMP, W, nb, job.prec))) return rc;
+        if ((rc = launch_op_left(c, U, TMP, W, nb, job.prec))) return rc;
       } else {
         if ((rc = launch_precond(c, U, Zj(j), nb, job.prec))) return rc;
         if ((rc = launch_apply(c, Zj(j), W, nb))) return rc;
       }
       if ((rc = launch_dcgs_reduce(c, V, NB, N, j, U, N, W, N, N, S, nb, rb))) return rc;
       const int slot = j & 1;
-      if ((rc = launch_dcgs_small(c, S, nb, j, job.flexible ? 1 : 0, 0, d_res + 2 * slot * nb)))
-        return rc;
-      if ((rc = launch_dcgs_update(c, V, NB, N, j, U, N, W, N, N, S, nb))) return rc;
-      written = j + 1;
       ++its;
+      const uint64_t tag = epoch | (uint64_t)its;
+      if ((rc = launch_dcgs_update(c, V, NB, N, j, U, N, W, N, N, S, nb, job.flexible ? 1 : 0,
+                                   drec + 4 * slot * nb, tag)))
+        return rc;
+      written = j + 1;
       const bool last = (j == m - 1) || its >= maxit;
       const bool want = (its % check_every == 0) || last;
-      if (want) {
-        HPS_TRY_HIP(hipMemcpyAsync(hbuf + 2 * slot * nb, d_res + 2 * slot * nb, 2 * sizeof(double) * nb,
-                                   hipMemcpyDeviceToHost, c->stream));
-        HPS_TRY_HIP(hipEventRecord(evs[slot], c->stream));
-      }
       if (pending >= 0) {
-        const int cv = converged_at(pending);
+        const int cv = converged_at(pending, pending_tag);
         pending = -1;
         if (cv < 0) return cv;
         if (cv) break;
       }
       if (last) {
-        const int cv = converged_at(j);
+        const int cv = converged_at(j, tag);
         if (cv < 0) return cv;
         break;
       }
-      if (want) pending = j;
+      if (want) {
+        pending = j;
+        pending_tag = tag;
+      }
     }
     // close the last column: reduction of the current candidate against the
     // basis (a no-op for right-hand sides whose cycle already stopped)
     if ((rc = launch_dcgs_reduce(c, V, NB, N, written, U, N, nullptr, 0, N, S, nb, rb))) return rc;
-    if ((rc = launch_dcgs_small(c, S, nb, written, job.flexible ? 1 : 0, 1, d_res))) return rc;
+    if ((rc = launch_dcgs_small(c, S, nb, written, job.flexible ? 1 : 0, 1, d_res, 0))) return rc;
     if ((rc = launch_dcgs_trisolve(c, S, nb, written, job.flexible ? 1 : 0))) return rc;
     if ((rc = launch_mupdate_b(c, job.flexible ? Z : V, NB, N, written, S[0].y, sst, 1.0, x, N, N,
                                nullptr, 0, nb, rb)))
@@ -438,8 +473,7 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     st->rel_res = worst_est;
     st->true_rel_res = worst_true;
     st->t_solve = now() - t0;
-    st->bytes_apply = bytes_apply(c);
-    st->bytes_precond = bytes_precond(c, job.prec);
+    solve_bytes_stats(c, job.flexible, nb, job.prec, st);
   }
   return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <string>
@@ -92,17 +93,19 @@ struct hps_ctx {
   hps::Workspace w_small;           // Hessenberg / Givens state
   hps::Workspace w_batch;           // many-rhs preconditioner: H and U panels
   void* h_pinned = nullptr;         // small pinned host buffer for scalars
+  uint32_t solve_epoch = 0;         // tags the residual records of each solve
   size_t dev_bytes = 0;
 
   hipEvent_t ev_solver[2] = {nullptr, nullptr};  // residual-check events of the solvers
 
   // optional kernel timing: event pairs per launch kind (kTimingKinds: 0 operator,
   // 1 preconditioner, 2 many-rhs block GEMM)
-  int timing = 0;
+  int timing = 0;                   // 0 off, k > 0: time every k-th launch of each kind
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[3];
   double t_ms[3] = {0.0, 0.0, 0.0};
   double t_cnt[3] = {0.0, 0.0, 0.0};
+  uint64_t t_seq[3] = {0, 0, 0};    // launches seen per kind (sampling)
 };
 
 namespace hps {
@@ -130,16 +133,43 @@ int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, int e0, i
 int launch_pack_blocks(hps_ctx* c, const double2* Sinv, int e0, int ne, int prec);
 int launch_node_coords(hps_ctx* c, double* d_xyz);
 
-// kernel timing around a launch (no-op unless c->timing)
-int timing_begin(hps_ctx* c, hipEvent_t* ev);
-int timing_end(hps_ctx* c, int kind, hipEvent_t ev0);
+// Kernel timing (no-op unless c->timing): a pair of events that the launches
+// attach to their own dispatches (hipExtLaunchKernelGGL takes the kernels'
+// start and end timestamps), so timing puts no extra packets on the stream.
+struct TimedPair {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+int timing_pair(hps_ctx* c, int kind, TimedPair* tp);  // kind: 0 apply, 1 J^-1, 2 GEMM
+int timing_commit(hps_ctx* c, int kind, const TimedPair& tp);
+void timing_drop(hps_ctx* c, const TimedPair& tp);  // return unused events to the pool
 int timing_collect(hps_ctx* c);
+
+// Launch on the context's stream; e0 / e1 (either may be null) take the
+// kernel's start / end timestamps.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_k(hps_ctx* c, hipEvent_t e0, hipEvent_t e1, void (*kern)(KArgs...), dim3 g,
+                           dim3 b, Args... args) {
+  hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, args...);
+  return hipGetLastError();
+}
 
 // hot path
 int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs);
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
+// y = J^{-1} A x with the face exchange of A fused into the preconditioner's
+// load (one leaf per workgroup); tmp receives A x without the exchange.  With
+// kBatchedMinRhs or more right-hand sides: launch_apply, then launch_precond.
+int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec);
+// the sweep alone: y = A x without the neighbours' outgoing impedance, which
+// goes to g ([rhs][leaf][6][q^2]); e0 / e1 as in launch_k
+int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
+                 hipEvent_t e1);
+// J^{-1} (y + exchange(g)) for nrhs < kBatchedMinRhs; g == null: J^{-1} y
+int launch_precond_fused(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
+                         int prec, hipEvent_t e0, hipEvent_t e1);
 // many right-hand sides: block product as a GEMM on the matrix cores
-int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
+int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
+                           hipEvent_t e0, hipEvent_t e1);
 constexpr int kBatchedMinRhs = 4;   // from this many right-hand sides on, J^-1 uses the GEMM path
 int launch_assemble_rhs(hps_ctx* c, const double2* s, const double2* t, double2* b, int nrhs);
 

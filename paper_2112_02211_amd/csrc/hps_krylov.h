@@ -76,10 +76,7 @@ struct DcgsState {
   double2 sn[kMaxDcgs];
   double2 gls[kDcgsLd];             // right-hand side of the small least-squares problem
   double2 gprev[kDcgsLd];           // projection of the last operator image (next column)
-  double2 ca[kMaxDcgs];             // update-pass coefficients for u_j
-  double2 cb[kDcgsLd];              // update-pass coefficients for w
   double2 y[kMaxDcgs];
-  double inv_beta;
   double beta0;
   double res;
   int flag;                         // nonzero: the candidate fell into the basis (stop the cycle)
@@ -90,13 +87,17 @@ struct DcgsState {
 int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int J,
                        const double2* u, int64_t ubs, const double2* w, int64_t wbs, int64_t n,
                        DcgsState* S, int nbatch, const RedBuf& rb);
-// small step kernel (one wavefront per right-hand side); final_only: only close column j-1
+// standalone small step (one workgroup per right-hand side); final_only: only close column j-1
 int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible, int final_only,
-                      double* res_out);
+                      double* res_out, uint64_t tag);
 // update pass: V[J] = v_j, u <- u_{j+1}
+// update pass of step J (writes V[J] and the next candidate); its workgroup 0 per
+// right-hand side also runs the small step of J and writes the record
+// res_out[4 r .. 4 r + 2] = {estimate, stopped, tag} (tag last, system-scope
+// release; res_out may be pinned host memory)
 int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
-                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, const DcgsState* S,
-                       int nbatch);
+                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
+                       int nbatch, int flexible, double* res_out, uint64_t tag);
 int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch);
 // y = R^{-1} gls over the finished columns (at most kmax); flexible: y <- T y
 int launch_dcgs_trisolve(hps_ctx* c, DcgsState* S, int nbatch, int kmax, int flexible);

@@ -2,12 +2,13 @@
 //
 // Sweep (Algorithm 1 and the local part of Algorithm 2): one workgroup per leaf
 // stages the leaf's n values in LDS on the full p^3 Chebyshev grid (corner and
-// edge slots are never touched).  Each thread owns one grid line per axis,
-// keeps its p values in registers and contracts them with the rows of D^2 (the
-// line's interior outputs; eq. (leafmat), whose face-column entries give
-// A_ib v_b) and with the end rows of D (the line's two face outputs, eq.
-// (flux)).  The three axis passes accumulate through LDS; the last one
-// subtracts C v (Algorithm 1 with the sign of eq. (leafmat)).  Face rows get
+// edge slots are never touched).  In each of the three axis passes one thread
+// computes one output of one grid line: a contraction of the line's p values
+// with a row of D^2 (the line's interior outputs; eq. (leafmat), whose
+// face-column entries give A_ib v_b) or with an end row of D (the line's two
+// face outputs, eq. (flux)).  Interior outputs accumulate through LDS and a
+// final coalesced loop subtracts C v (Algorithm 1 with the sign of eq.
+// (leafmat)).  Face rows get
 // F v = N v + i eta v_b; the outgoing impedance G v = N v - i eta v_b
 // (eq. (G)) goes to a face buffer.
 //
@@ -39,68 +40,50 @@ struct Leaf {
   }
 };
 
+// Workgroup size: one thread per (line, output) work item of an axis pass,
+// L lines of P outputs each, at most 1024 threads.
 template <int P>
 constexpr int sweep_threads() {
-  return ((P - 2) * (P - 2) + 63) / 64 * 64;
+  return (P - 2) * (P - 2) * P >= 1024 ? 1024 : ((P - 2) * (P - 2) * P + 63) / 64 * 64;
 }
 
-// One axis pass over the lines of one leaf.  AX = 0, 1, 2 (x, y, z).
-template <int P, int AX, bool CC>
+// One axis pass over the lines of one leaf, AX = 0, 1, 2 (x, y, z).  Work item
+// (line, o) contracts the line's p values with row o of R: o = 0 and o = p-1 are
+// the line's two face outputs (outward normal derivative, the end rows of D),
+// 1 .. p-2 its interior outputs (rows of -D^2, whose end columns are A_ib).
+// Interior outputs accumulate in ACC; face outputs go out directly as
+// F v = N v + i eta v_b (this leaf's rows) and G v = N v - i eta v_b (the face
+// buffer read by the neighbour).
+template <int P, int AX>
 __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2* __restrict__ ACC,
-                                          const double* __restrict__ D, const double* __restrict__ D2,
-                                          double eta, double2* __restrict__ yv, double2* __restrict__ gv,
-                                          const void* __restrict__ Cv, int64_t tau, int line) {
+                                          const double* __restrict__ R, double eta,
+                                          double2* __restrict__ yv, double2* __restrict__ gv) {
   using Lf = Leaf<P>;
-  constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI;
-  const int a = line % N1 + 1, b = line / N1 + 1;  // the two other grid coordinates
-  int base, stride;
-  if (AX == 0) { base = (b * P + a) * P; stride = 1; }
-  else if (AX == 1) { base = b * P * P + a; stride = P; }
-  else { base = b * P + a; stride = P * P; }
-  double2 u[P];
-#pragma unroll
-  for (int q = 0; q < P; ++q) u[q] = U[base + q * stride];
-  // interior outputs along the line
-#pragma unroll
-  for (int t = 1; t < P - 1; ++t) {
+  constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI, BD = sweep_threads<P>();
+  for (int w = threadIdx.x; w < L * P; w += BD) {
+    const int line = w / P, o = w - line * P;
+    const int a = line % N1 + 1, b = line / N1 + 1;  // the two other grid coordinates
+    int base, stride;
+    if (AX == 0) { base = (b * P + a) * P; stride = 1; }
+    else if (AX == 1) { base = b * P * P + a; stride = P; }
+    else { base = b * P + a; stride = P * P; }
     double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int q = 0; q < P; ++q) cfma_r(s, D2[t * P + q], u[q]);
-    int m;
-    if (AX == 0) m = (t - 1) + N1 * (a - 1) + L * (b - 1);
-    else if (AX == 1) m = (a - 1) + N1 * (t - 1) + L * (b - 1);
-    else m = (a - 1) + N1 * (b - 1) + L * (t - 1);
-    if (AX == 0) {
-      ACC[m] = make_double2(-s.x, -s.y);
-    } else if (AX == 1) {
-      const double2 c = ACC[m];
-      ACC[m] = make_double2(c.x - s.x, c.y - s.y);
+    for (int q = 0; q < P; ++q) cfma_r(s, R[o * P + q], U[base + q * stride]);
+    if (o == 0 || o == P - 1) {
+      const double2 ue = U[base + o * stride];
+      const int f = 2 * AX + (o ? 1 : 0);
+      yv[NI + f * L + line] = make_double2(s.x - eta * ue.y, s.y + eta * ue.x);
+      gv[f * L + line] = make_double2(s.x + eta * ue.y, s.y - eta * ue.x);
     } else {
-      const double2 c = ACC[m];
-      double2 cu;
-      if (CC) {
-        const double2 cc = static_cast<const double2*>(Cv)[tau * NI + m];
-        cu = cmul(cc, u[t]);
-      } else {
-        const double cr = static_cast<const double*>(Cv)[tau * NI + m];
-        cu = cscale(u[t], cr);
-      }
-      yv[m] = make_double2(c.x - s.x - cu.x, c.y - s.y - cu.y);
+      int m;
+      if (AX == 0) m = (o - 1) + N1 * (a - 1) + L * (b - 1);
+      else if (AX == 1) m = (a - 1) + N1 * (o - 1) + L * (b - 1);
+      else m = (a - 1) + N1 * (b - 1) + L * (o - 1);
+      if (AX == 0) ACC[m] = s;
+      else ACC[m] = make_double2(ACC[m].x + s.x, ACC[m].y + s.y);
     }
   }
-  // the two face outputs of the line: outward normal derivative +/- i eta u
-  double2 lo = make_double2(0.0, 0.0), hi = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < P; ++q) {
-    cfma_r(lo, -D[q], u[q]);
-    cfma_r(hi, D[(P - 1) * P + q], u[q]);
-  }
-  const int flo = 2 * AX, fhi = 2 * AX + 1;
-  const double2 ul = u[0], uh = u[P - 1];
-  yv[NI + flo * L + line] = make_double2(lo.x - eta * ul.y, lo.y + eta * ul.x);
-  yv[NI + fhi * L + line] = make_double2(hi.x - eta * uh.y, hi.y + eta * uh.x);
-  gv[flo * L + line] = make_double2(lo.x + eta * ul.y, lo.y - eta * ul.x);
-  gv[fhi * L + line] = make_double2(hi.x + eta * uh.y, hi.y - eta * uh.x);
 }
 
 template <int P, bool CC>
@@ -108,10 +91,11 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
     const double2* __restrict__ x, double2* __restrict__ y, double2* __restrict__ g,
     const void* __restrict__ Cv, const double* __restrict__ tab, double eta, int64_t nl, int64_t N) {
   using Lf = Leaf<P>;
-  constexpr int L = Lf::L, NN = Lf::NN, NB = Lf::NB;
+  constexpr int NI = Lf::NI, NN = Lf::NN, NB = Lf::NB;
   constexpr int BD = sweep_threads<P>();
   __shared__ double2 U[P * P * P];
-  __shared__ double2 ACC[Lf::NI];
+  __shared__ double2 ACC[NI];
+  __shared__ double R[P * P];
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
   const double2* xv = x + rhs * N + tau * NN;
@@ -119,25 +103,39 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
   double2* gv = g + (rhs * nl + tau) * NB;
   const double* D = tab + tab_off_D(P);
   const double* D2 = tab + tab_off_D2(P);
+  // every load of the leaf is issued before the first LDS store (named
+  // registers, not an array, so that the staging stays in VGPRs)
   constexpr int NLOAD = (NN + BD - 1) / BD;
-  double2 tmp[NLOAD];
-#pragma unroll
-  for (int s = 0; s < NLOAD; ++s) {
-    const int m = threadIdx.x + s * BD;
-    if (m < NN) tmp[s] = xv[m];
+  static_assert(NLOAD <= 4, "leaf larger than four loads per thread");
+  const int m0 = threadIdx.x, m1 = m0 + BD, m2 = m1 + BD, m3 = m2 + BD;
+  double2 t0, t1, t2, t3;
+  if (m0 < NN) t0 = xv[m0];
+  if (NLOAD > 1 && m1 < NN) t1 = xv[m1];
+  if (NLOAD > 2 && m2 < NN) t2 = xv[m2];
+  if (NLOAD > 3 && m3 < NN) t3 = xv[m3];
+  for (int k = threadIdx.x; k < P * P; k += BD) {
+    const int o = k / P, q = k - o * P;
+    R[k] = (o == 0) ? -D[q] : (o == P - 1) ? D[(P - 1) * P + q] : -D2[k];
   }
-#pragma unroll
-  for (int s = 0; s < NLOAD; ++s) {
-    const int m = threadIdx.x + s * BD;
-    if (m < NN) U[Lf::grid_of(m)] = tmp[s];
+  if (m0 < NN) U[Lf::grid_of(m0)] = t0;
+  if (NLOAD > 1 && m1 < NN) U[Lf::grid_of(m1)] = t1;
+  if (NLOAD > 2 && m2 < NN) U[Lf::grid_of(m2)] = t2;
+  if (NLOAD > 3 && m3 < NN) U[Lf::grid_of(m3)] = t3;
+  __syncthreads();
+  axis_pass<P, 0>(U, ACC, R, eta, yv, gv);
+  __syncthreads();
+  axis_pass<P, 1>(U, ACC, R, eta, yv, gv);
+  __syncthreads();
+  axis_pass<P, 2>(U, ACC, R, eta, yv, gv);
+  __syncthreads();
+  // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat))
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const double2 v = U[Lf::grid_of(m)], acc = ACC[m];
+    double2 cu;
+    if (CC) cu = cmul(static_cast<const double2*>(Cv)[tau * NI + m], v);
+    else cu = cscale(v, static_cast<const double*>(Cv)[tau * NI + m]);
+    yv[m] = make_double2(acc.x - cu.x, acc.y - cu.y);
   }
-  __syncthreads();
-  const int line = threadIdx.x;
-  if (line < L) axis_pass<P, 0, CC>(U, ACC, D, D2, eta, yv, gv, Cv, tau, line);
-  __syncthreads();
-  if (line < L) axis_pass<P, 1, CC>(U, ACC, D, D2, eta, yv, gv, Cv, tau, line);
-  __syncthreads();
-  if (line < L) axis_pass<P, 2, CC>(U, ACC, D, D2, eta, yv, gv, Cv, tau, line);
 }
 
 __global__ void k_apply_exchange(double2* __restrict__ y, const double2* __restrict__ g,
@@ -158,50 +156,64 @@ __global__ void k_apply_exchange(double2* __restrict__ y, const double2* __restr
 }
 
 template <int P>
-int sweep_launch(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs) {
+int sweep_launch(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
+                 hipEvent_t e1) {
   dim3 grid((unsigned)c->nl, (unsigned)nrhs);
+  const dim3 block(sweep_threads<P>());
+  hipError_t e;
   if (c->c_complex)
-    hipLaunchKernelGGL((k_apply_sweep<P, true>), grid, dim3(sweep_threads<P>()), 0, c->stream, x, y,
-                       g, c->d_C, c->d_tab, c->eta, c->nl, c->N);
+    e = launch_k(c, e0, e1, k_apply_sweep<P, true>, grid, block, x, y, g, (const void*)c->d_C,
+                 (const double*)c->d_tab, c->eta, c->nl, c->N);
   else
-    hipLaunchKernelGGL((k_apply_sweep<P, false>), grid, dim3(sweep_threads<P>()), 0, c->stream, x,
-                       y, g, c->d_C, c->d_tab, c->eta, c->nl, c->N);
-  return check_hip(hipGetLastError(), "k_apply_sweep");
+    e = launch_k(c, e0, e1, k_apply_sweep<P, false>, grid, block, x, y, g, (const void*)c->d_C,
+                 (const double*)c->d_tab, c->eta, c->nl, c->N);
+  return check_hip(e, "k_apply_sweep");
 }
 
 }  // namespace
+
+int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
+                 hipEvent_t e1) {
+  switch (c->p) {
+    case 4: return sweep_launch<4>(c, x, y, g, nrhs, e0, e1);
+    case 5: return sweep_launch<5>(c, x, y, g, nrhs, e0, e1);
+    case 6: return sweep_launch<6>(c, x, y, g, nrhs, e0, e1);
+    case 7: return sweep_launch<7>(c, x, y, g, nrhs, e0, e1);
+    case 8: return sweep_launch<8>(c, x, y, g, nrhs, e0, e1);
+    case 9: return sweep_launch<9>(c, x, y, g, nrhs, e0, e1);
+    case 10: return sweep_launch<10>(c, x, y, g, nrhs, e0, e1);
+    case 11: return sweep_launch<11>(c, x, y, g, nrhs, e0, e1);
+    case 12: return sweep_launch<12>(c, x, y, g, nrhs, e0, e1);
+    case 13: return sweep_launch<13>(c, x, y, g, nrhs, e0, e1);
+    case 14: return sweep_launch<14>(c, x, y, g, nrhs, e0, e1);
+    case 15: return sweep_launch<15>(c, x, y, g, nrhs, e0, e1);
+    case 16: return sweep_launch<16>(c, x, y, g, nrhs, e0, e1);
+    default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
+  }
+}
 
 int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs) {
   const size_t gbytes = (size_t)nrhs * c->nl * c->nb * sizeof(double2);
   int rc = ws_reserve(c, &c->w_g, gbytes);
   if (rc) return rc;
   double2* g = static_cast<double2*>(c->w_g.ptr);
-  hipEvent_t ev0;
-  if ((rc = timing_begin(c, &ev0))) return rc;
-  switch (c->p) {
-    case 4: rc = sweep_launch<4>(c, x, y, g, nrhs); break;
-    case 5: rc = sweep_launch<5>(c, x, y, g, nrhs); break;
-    case 6: rc = sweep_launch<6>(c, x, y, g, nrhs); break;
-    case 7: rc = sweep_launch<7>(c, x, y, g, nrhs); break;
-    case 8: rc = sweep_launch<8>(c, x, y, g, nrhs); break;
-    case 9: rc = sweep_launch<9>(c, x, y, g, nrhs); break;
-    case 10: rc = sweep_launch<10>(c, x, y, g, nrhs); break;
-    case 11: rc = sweep_launch<11>(c, x, y, g, nrhs); break;
-    case 12: rc = sweep_launch<12>(c, x, y, g, nrhs); break;
-    case 13: rc = sweep_launch<13>(c, x, y, g, nrhs); break;
-    case 14: rc = sweep_launch<14>(c, x, y, g, nrhs); break;
-    case 15: rc = sweep_launch<15>(c, x, y, g, nrhs); break;
-    case 16: rc = sweep_launch<16>(c, x, y, g, nrhs); break;
-    default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
+  TimedPair tp;
+  if ((rc = timing_pair(c, 0, &tp))) return rc;
+  if ((rc = launch_sweep(c, x, y, g, nrhs, tp.start, nullptr))) {
+    timing_drop(c, tp);
+    return rc;
   }
-  if (rc) return rc;
   const int64_t total = c->nl * c->nb;
   const int threads = 256;
-  hipLaunchKernelGGL(k_apply_exchange, dim3((unsigned)((total + threads - 1) / threads), nrhs),
-                     dim3(threads), 0, c->stream, y, g, c->d_nbr, c->ni, c->nb, c->n1 * c->n1, c->nl,
-                     c->N);
-  if ((rc = check_hip(hipGetLastError(), "k_apply_exchange"))) return rc;
-  return timing_end(c, 0, ev0);
+  const hipError_t e = launch_k(c, nullptr, tp.stop, k_apply_exchange,
+                                dim3((unsigned)((total + threads - 1) / threads), nrhs), dim3(threads),
+                                y, (const double2*)g, (const int*)c->d_nbr, c->ni, c->nb, c->n1 * c->n1,
+                                c->nl, c->N);
+  if ((rc = check_hip(e, "k_apply_exchange"))) {
+    timing_drop(c, tp);
+    return rc;
+  }
+  return timing_commit(c, 0, tp);
 }
 
 }  // namespace hps

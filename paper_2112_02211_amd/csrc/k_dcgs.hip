@@ -1,6 +1,8 @@
 // Kernels of the Arnoldi process with delayed reorthogonalization (see
 // hps_krylov.h): per step one reduction pass and one update pass over the
-// basis, plus a one-wavefront kernel for the small Hessenberg / Givens work.
+// basis.  The small Hessenberg / Givens work of a step runs in workgroup 0 of
+// the update pass, off the critical path; a standalone kernel closes the last
+// column of a cycle.
 // Reductions are deterministic (fixed order), as in k_krylov.hip.
 #include "hps_internal.h"
 #include "hps_krylov.h"
@@ -11,7 +13,8 @@ namespace {
 
 constexpr int DW = 8;          // wavefronts of the reduction workgroup (split over k)
 constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
-constexpr int UT = 256;        // update-pass workgroup
+constexpr int UT = 256;        // update-pass (and small-step) workgroup
+constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
 
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
@@ -120,165 +123,246 @@ __global__ void k_dcgs_start(DcgsState* __restrict__ S, int nb) {
   for (int i = 0; i < kDcgsLd; ++i) s.gls[i] = make_double2(0.0, 0.0);
 }
 
-// One step's small work for right-hand side blockIdx.x (see hps_krylov.h).
-__global__ __launch_bounds__(64) void k_dcgs_small(DcgsState* __restrict__ S, int j, int flexible,
-                                                   int final_only, double* __restrict__ res_out,
-                                                   double tiny) {
-  DcgsState& s = S[blockIdx.x];
-  const int lane = threadIdx.x;
-  double* ro = res_out + 2 * blockIdx.x;
-  __shared__ double2 a[kMaxDcgs], b[kMaxDcgs];
-  __shared__ double2 col[kDcgsLd + 1];
-  __shared__ double2 Hs[kDcgsLd * (kMaxDcgs - 1)];   // columns 0 .. j-1 <= 62 of H
-  __shared__ double csl[kMaxDcgs];
-  __shared__ double2 snl[kMaxDcgs];
-  __shared__ double2 Ts[kMaxDcgs * (kMaxDcgs - 1)];  // columns 0 .. j-1 of T
-  if (s.flag) {  // an earlier step stopped this cycle: keep the state as it is
-    if (lane == 0) { ro[0] = s.res; ro[1] = 1.0; }
-    return;
-  }
-  const double2 z2 = make_double2(0.0, 0.0);
-  const double2 al = (lane < j) ? s.red[lane] : z2;
-  const double2 bl = (lane < j && !final_only) ? s.red[kSlotB + lane] : z2;
-  a[lane] = al;
-  b[lane] = bl;
-  const double c = s.red[kSlotC].x;
-  const double2 d = final_only ? z2 : s.red[kSlotD];
-  const double na2 = wave_sum(al.x * al.x + al.y * al.y);
-  const double abr = wave_sum(al.x * bl.x + al.y * bl.y);   // conj(a) b
-  const double abi = wave_sum(al.x * bl.y - al.y * bl.x);
-  const double beta2 = c - na2;
-  if (!(beta2 > tiny * c) || !isfinite(beta2)) {
-    // the candidate lies in the span of the basis: happy breakdown or lost
-    // orthogonality; the cycle ends with the columns finished so far
-    if (lane == 0) { s.flag = 1; ro[0] = s.res; ro[1] = 1.0; }
-    return;
-  }
-  const double beta = sqrt(beta2), inv = 1.0 / beta;
-  const int ld = kDcgsLd;
-  if (j == 0) {
+// Shared memory of the coefficient and small-step phases of one workgroup.
+struct SmallSmem {
+  double2 a[kMaxDcgs];      // a = V^H u_j
+  double2 b[kDcgsLd];       // b = V^H w
+  double2 colh[kDcgsLd];    // Hessenberg column j-1 as built
+  double2 colr[kDcgsLd];    // its Givens-rotated copy
+  double2 sn[kMaxDcgs];
+  double cs[kMaxDcgs];
+  double2 ph[UT / 64][kDcgsLd];  // Hbar a over the stored columns, one partial per wavefront
+  double2 pt[UT / 64][kMaxDcgs]; // T a, likewise
+  double sc[6];                  // beta^2, c, Re/Im a^H b, Re/Im d
+};
+
+// Step coefficients from the finished reductions.  Every workgroup that needs
+// them computes them with the same operations in the same order, so they all
+// take the same breakdown decision.
+struct Coef {
+  double beta2, c, inv;
+  double2 vjw;  // (d - a^H b) / beta
+  bool ok;      // false: the candidate lies in the span of the basis (or is not finite)
+};
+
+__device__ __forceinline__ Coef dcgs_coeffs(const DcgsState& s, int j, bool hasw, SmallSmem& sm,
+                                            double tiny) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const double2 z2 = make_double2(0.0, 0.0);
+    const double2 al = lane < j ? s.red[lane] : z2;
+    const double2 bl = (hasw && lane < j) ? s.red[kSlotB + lane] : z2;
+    sm.a[lane] = al;
+    sm.b[lane] = bl;
+    const double na2 = wave_sum(al.x * al.x + al.y * al.y);
+    const double abr = wave_sum(al.x * bl.x + al.y * bl.y);   // conj(a) b
+    const double abi = wave_sum(al.x * bl.y - al.y * bl.x);
     if (lane == 0) {
+      const double c = s.red[kSlotC].x;
+      const double2 d = hasw ? s.red[kSlotD] : z2;
+      sm.sc[0] = c - na2;
+      sm.sc[1] = c;
+      sm.sc[2] = abr;
+      sm.sc[3] = abi;
+      sm.sc[4] = d.x;
+      sm.sc[5] = d.y;
+    }
+  }
+  __syncthreads();
+  Coef cf;
+  cf.beta2 = sm.sc[0];
+  cf.c = sm.sc[1];
+  cf.ok = (cf.beta2 > tiny * cf.c) && isfinite(cf.beta2);
+  cf.inv = cf.ok ? 1.0 / sqrt(cf.beta2) : 0.0;
+  cf.vjw = make_double2((sm.sc[4] - sm.sc[2]) * cf.inv, (sm.sc[5] - sm.sc[3]) * cf.inv);
+  return cf;
+}
+
+// Record {estimate, stopped, tag} of a step; the tag is stored last with a
+// system-scope release, so a reader that sees the tag sees the rest (ro may
+// point into pinned host memory).
+__device__ __forceinline__ void publish(double* ro, double res, double stopped,
+                                        unsigned long long tag) {
+  ro[0] = res;
+  ro[1] = stopped;
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(ro + 2), tag, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The small work of step j for one right-hand side, by one workgroup of UT
+// threads: column j-1 of the Hessenberg matrix is g_{j-1} + a with beta below
+// it; it is rotated by the earlier Givens rotations and a new rotation zeroes
+// beta (updating the least-squares right-hand side and the residual estimate).
+// Unless final_only, g_j = ([b; vjw] - Hbar a) / beta and, flexible, column j
+// of T are formed.  flag: an earlier step stopped this cycle.  Publishes the
+// record ro = {residual estimate, stopped, tag}.
+__device__ void dcgs_small_step(DcgsState& s, int j, int flexible, int final_only, double* ro,
+                                unsigned long long tag, SmallSmem& sm, const Coef& cf, int flag) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int ld = kDcgsLd;
+  if (flag || !cf.ok) {
+    if (tid == 0) {
+      if (!flag) s.flag = 1;  // the cycle ends with the columns finished so far
+      publish(ro, s.res, 1.0, tag);
+    }
+    return;
+  }
+  const double beta = sqrt(cf.beta2), inv = cf.inv;
+  const double2 z2 = make_double2(0.0, 0.0);
+  // wavefront 0: the state this step reads, loaded before anything waits
+  double2 gp = z2, snv = z2, g0 = z2;
+  double csv = 0.0;
+  if (wv == 0 && j > 0) {
+    if (lane < j) gp = s.gprev[lane];
+    if (lane < j - 1) {
+      csv = s.cs[lane];
+      snv = s.sn[lane];
+    }
+    if (lane == 0) g0 = s.gls[j - 1];
+  }
+  // partial products over the stored columns 0 .. j-2 of H and 0 .. j-1 of T:
+  // thread (wavefront wv, lane i) takes row i and columns 16 wv .. 16 wv + 15.
+  // Out-of-range terms read an in-bounds entry and are discarded by a select.
+  // (Unrolled by 2 only: this runs inside the update pass, whose occupancy
+  // is set by the larger of the two register counts.)
+  if (!final_only) {
+    const int i = lane;
+    double2 ph = z2, pt = z2;
+#pragma unroll 2
+    for (int k = 0; k < 16; ++k) {
+      const int l = 16 * wv + k;
+      const bool in = (l <= j - 2) && (l + 1 >= i) && (i <= j);
+      const int lc = in ? l : 0;
+      const double2 pr = cmul(s.H[i + ld * lc], sm.a[lc]);
+      ph.x += in ? pr.x : 0.0;
+      ph.y += in ? pr.y : 0.0;
+    }
+    if (flexible) {
+#pragma unroll 2
+      for (int k = 0; k < 16; ++k) {
+        const int l = 16 * wv + k;
+        const bool in = (l < j) && (l >= i);
+        const int lc = in ? l : 0;
+        const double2 pr = cmul(s.T[i + kMaxDcgs * lc], sm.a[lc]);
+        pt.x += in ? pr.x : 0.0;
+        pt.y += in ? pr.y : 0.0;
+      }
+    }
+    sm.ph[wv][i] = ph;
+    sm.pt[wv][i] = pt;
+  }
+  if (wv == 0 && j > 0) {
+    // column j-1 as built
+    if (lane < j) {
+      const double2 h = cadd(gp, sm.a[lane]);
+      s.H[lane + ld * (j - 1)] = h;
+      sm.colh[lane] = h;
+    }
+    if (lane == 0) {
+      s.H[j + ld * (j - 1)] = make_double2(beta, 0.0);
+      sm.colh[j] = make_double2(beta, 0.0);
+    }
+    if (lane < j - 1) {
+      sm.cs[lane] = csv;
+      sm.sn[lane] = snv;
+    }
+  }
+  __syncthreads();
+  if (j == 0) {
+    if (tid == 0) {
       s.beta0 = beta;
       s.gls[0] = make_double2(beta, 0.0);
       s.res = beta;
       s.ncols = 0;
     }
-  } else {
-    // finish column j-1: H[0:j, j-1] = gprev + a, H[j, j-1] = beta
-    for (int i = lane; i < j; i += 64) {
-      const double2 h = cadd(s.gprev[i], a[i]);
-      s.H[i + ld * (j - 1)] = h;
-      col[i] = h;
+  } else if (tid == 0) {
+    // earlier rotations, carried in registers; the new rotation zeroes beta
+    double2 cur = sm.colh[0];
+    for (int i = 0; i < j - 1; ++i) {
+      const double cr = sm.cs[i];
+      const double2 sn = sm.sn[i], nx = sm.colh[i + 1];
+      sm.colr[i] = cadd(cscale(cur, cr), cmul(sn, nx));
+      cur = csub(cscale(nx, cr), cmulc(sn, cur));
     }
-    if (lane == 0) {
-      s.H[j + ld * (j - 1)] = make_double2(beta, 0.0);
-      col[j] = make_double2(beta, 0.0);
+    const double am = sqrt(cur.x * cur.x + cur.y * cur.y);
+    const double r = sqrt(am * am + cf.beta2);
+    double cr;
+    double2 sn;
+    if (am == 0.0) {
+      cr = 0.0;
+      sn = make_double2(1.0, 0.0);
+      sm.colr[j - 1] = make_double2(beta, 0.0);
+    } else {
+      cr = am / r;
+      const double2 ph = make_double2(cur.x / am, cur.y / am);
+      sn = make_double2(ph.x * beta / r, ph.y * beta / r);
+      sm.colr[j - 1] = make_double2(ph.x * r, ph.y * r);
     }
-    for (int i = lane; i < j - 1; i += 64) {
-      csl[i] = s.cs[i];
-      snl[i] = s.sn[i];
+    sm.colr[j] = z2;
+    s.cs[j - 1] = cr;
+    s.sn[j - 1] = sn;
+    const double2 g1 = make_double2(-(sn.x * g0.x + sn.y * g0.y), -(sn.x * g0.y - sn.y * g0.x));
+    s.gls[j] = g1;
+    s.gls[j - 1] = cscale(g0, cr);
+    s.res = sqrt(g1.x * g1.x + g1.y * g1.y);
+    s.ncols = j;
+  }
+  if (!final_only && wv == 1) {
+    // g_j = ([b; vjw] - Hbar a) / beta, with column j-1 of Hbar from colh
+    for (int i = lane; i <= j; i += 64) {
+      double2 ha = cadd(cadd(sm.ph[0][i], sm.ph[1][i]), cadd(sm.ph[2][i], sm.ph[3][i]));
+      if (j > 0) ha = cadd(ha, cmul(sm.colh[i], sm.a[j - 1]));
+      const double2 vw = (i < j) ? sm.b[i] : cf.vjw;
+      s.gprev[i] = cscale(csub(vw, ha), inv);
     }
-    __syncthreads();
-    if (lane == 0) {
-      for (int i = 0; i < j - 1; ++i) {
-        const double cr = csl[i];
-        const double2 sn = snl[i];
-        const double2 x0 = col[i], x1 = col[i + 1];
-        col[i] = cadd(cscale(x0, cr), cmul(sn, x1));
-        col[i + 1] = csub(cscale(x1, cr), cmulc(sn, x0));
+    // flexible: z_j = (z'_j - Z_{j-1} a) / beta, i.e. T[:, j] = (e_j - T[:, 0:j] a) / beta
+    if (flexible) {
+      for (int i = lane; i < j; i += 64) {
+        const double2 ta = cadd(cadd(sm.pt[0][i], sm.pt[1][i]), cadd(sm.pt[2][i], sm.pt[3][i]));
+        s.T[i + kMaxDcgs * j] = cscale(ta, -inv);
       }
-      const double2 x0 = col[j - 1];
-      const double am = sqrt(x0.x * x0.x + x0.y * x0.y);
-      const double r = sqrt(am * am + beta2);
-      double cr;
-      double2 sn;
-      if (am == 0.0) {
-        cr = 0.0;
-        sn = make_double2(1.0, 0.0);
-        col[j - 1] = make_double2(beta, 0.0);
-      } else {
-        cr = am / r;
-        const double2 ph = make_double2(x0.x / am, x0.y / am);
-        sn = make_double2(ph.x * beta / r, ph.y * beta / r);
-        col[j - 1] = make_double2(ph.x * r, ph.y * r);
-      }
-      col[j] = make_double2(0.0, 0.0);
-      s.cs[j - 1] = cr;
-      s.sn[j - 1] = sn;
-      const double2 g0 = s.gls[j - 1];
-      const double2 g1 = make_double2(-(sn.x * g0.x + sn.y * g0.y), -(sn.x * g0.y - sn.y * g0.x));
-      s.gls[j] = g1;
-      s.gls[j - 1] = cscale(g0, cr);
-      s.res = sqrt(g1.x * g1.x + g1.y * g1.y);
-      s.ncols = j;
+      if (lane == 0) s.T[j + kMaxDcgs * j] = make_double2(inv, 0.0);
     }
-    __syncthreads();
-    for (int i = lane; i <= j; i += 64) s.R[i + ld * (j - 1)] = col[i];
   }
-  if (final_only) {
-    if (lane == 0) { ro[0] = s.res; ro[1] = 0.0; }
-    return;
-  }
-  // Stage the j finished Hessenberg columns (and T for the flexible variant) in
-  // LDS with every load issued up front: the products below then run at LDS
-  // latency instead of one dependent global load per term.
   __syncthreads();
-  for (int q = lane; q < (j + 1) * j; q += 64) {
-    const int l = q / (j + 1), i = q - l * (j + 1);
-    Hs[i + ld * l] = s.H[i + ld * l];
-  }
-  if (flexible)
-    for (int q = lane; q < j * j; q += 64) {
-      const int l = q / j, i = q - l * j;
-      Ts[i + kMaxDcgs * l] = s.T[i + kMaxDcgs * l];
-    }
-  __syncthreads();
-  // flexible: z_j = (z'_j - Z_{j-1} a) / beta, i.e. T[:, j] = (e_j - T[:, 0:j] a) / beta
-  if (flexible) {
-    for (int i = lane; i < j; i += 64) {
-      double2 acc = z2;
-      for (int l = i; l < j; ++l) acc = cadd(acc, cmul(Ts[i + kMaxDcgs * l], a[l]));
-      s.T[i + kMaxDcgs * j] = cscale(acc, -inv);
-    }
-    if (lane == 0) s.T[j + kMaxDcgs * j] = make_double2(inv, 0.0);
-  }
-  // projection of Op v_j on V_j: g_j = ([b; vjw] - Hbar_{j-1} a) / beta
-  const double2 vjw = cscale(make_double2(d.x - abr, d.y - abi), inv);
-  for (int i = lane; i <= j; i += 64) {
-    double2 ha = z2;
-    for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) ha = cadd(ha, cmul(Hs[i + ld * l], a[l]));
-    const double2 vw = (i < j) ? b[i] : vjw;
-    s.gprev[i] = cscale(csub(vw, ha), inv);
-  }
-  for (int l = lane; l < j; l += 64) {
-    s.ca[l] = a[l];
-    s.cb[l] = b[l];
-  }
-  if (lane == 0) {
-    s.cb[j] = vjw;
-    s.inv_beta = inv;
-    ro[0] = s.res;
-    ro[1] = 0.0;
-  }
+  if (wv == 0 && j > 0)
+    for (int i = lane; i <= j; i += 64) s.R[i + ld * (j - 1)] = sm.colr[i];
+  if (tid == 0) publish(ro, s.res, 0.0, tag);
 }
 
-// V[J] = (u - V_{0..J-1} ca) * inv;  u <- (w - V_{0..J-1} cb - V[J] cb[J]) * inv
+// Standalone small step (closes the last column of a cycle, final_only).
+__global__ __launch_bounds__(UT) void k_dcgs_small(DcgsState* __restrict__ S, int j, int flexible,
+                                                   int final_only, double* __restrict__ res_out,
+                                                   unsigned long long tag, double tiny) {
+  DcgsState& s = S[blockIdx.x];
+  __shared__ SmallSmem sm;
+  const int flag = s.flag;
+  const Coef cf = dcgs_coeffs(s, j, !final_only, sm, tiny);
+  dcgs_small_step(s, j, flexible, final_only, res_out + 4 * blockIdx.x, tag, sm, cf, flag);
+}
+
+// Update pass of step J, with the small step in workgroup 0 of each right-hand side:
+// V[J] = (u - V_{0..J-1} a) / beta;  u <- (w - V_{0..J-1} b - V[J] vjw) / beta.
 __global__ __launch_bounds__(UT) void k_dcgs_update(double2* __restrict__ V, int64_t ldv, int64_t vbs,
                                                     int J, double2* __restrict__ u, int64_t ubs,
                                                     const double2* __restrict__ w, int64_t wbs,
-                                                    int64_t n, const DcgsState* __restrict__ S) {
+                                                    int64_t n, DcgsState* __restrict__ S,
+                                                    int flexible, double* __restrict__ res_out,
+                                                    unsigned long long tag, double tiny) {
   const int bz = blockIdx.z;
-  const DcgsState& s = S[bz];
-  if (s.flag) return;
+  DcgsState& s = S[bz];
+  __shared__ SmallSmem sm;
+  const int flag = s.flag;
+  const Coef cf = dcgs_coeffs(s, J, true, sm, tiny);
+  if (blockIdx.x == 0) dcgs_small_step(s, J, flexible, 0, res_out + 4 * bz, tag, sm, cf, flag);
+  if (flag || !cf.ok) return;
   V += bz * vbs;
   u += bz * ubs;
   w += bz * wbs;
-  __shared__ double2 ca[kMaxDcgs], cb[kDcgsLd];
-  for (int l = threadIdx.x; l < J; l += UT) ca[l] = s.ca[l];
-  for (int l = threadIdx.x; l <= J; l += UT) cb[l] = s.cb[l];
-  const double inv = s.inv_beta;
-  __syncthreads();
-  const double2 cj = cb[J];
+  const double inv = cf.inv;
+  const double2 cj = cf.vjw;
+  const double2* ca = sm.a;
+  const double2* cb = sm.b;
   for (int64_t i = (int64_t)blockIdx.x * UT + threadIdx.x; i < n; i += (int64_t)gridDim.x * UT) {
     double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
     int l = 0;
@@ -378,19 +462,21 @@ int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, i
 }
 
 int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible, int final_only,
-                      double* res_out) {
-  hipLaunchKernelGGL(k_dcgs_small, dim3(nbatch), dim3(64), 0, c->stream, S, j, flexible, final_only,
-                     res_out, 1e-14);
+                      double* res_out, uint64_t tag) {
+  if (j < 0 || j > kMaxDcgs) return fail(HPS_ERR_ARG, "small step beyond the restart limit");
+  hipLaunchKernelGGL(k_dcgs_small, dim3(nbatch), dim3(UT), 0, c->stream, S, j, flexible, final_only,
+                     res_out, (unsigned long long)tag, kBreakdownTol);
   return check_hip(hipGetLastError(), "k_dcgs_small");
 }
 
 int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
-                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, const DcgsState* S,
-                       int nbatch) {
+                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
+                       int nbatch, int flexible, double* res_out, uint64_t tag) {
+  if (J < 0 || J >= kMaxDcgs) return fail(HPS_ERR_ARG, "update beyond the restart limit");
   const int64_t want = (n + UT - 1) / UT;
   const int nblk = (int)std::min<int64_t>(want, 2048);
   hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, 1, nbatch), dim3(UT), 0, c->stream, V, ldv, vbs, J, u,
-                     ubs, w, wbs, n, S);
+                     ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag, kBreakdownTol);
   return check_hip(hipGetLastError(), "k_dcgs_update");
 }
 

@@ -60,6 +60,55 @@ __device__ __forceinline__ void homog_solve(double2* __restrict__ T, const doubl
   __syncthreads();
 }
 
+// Element-parallel form of the same product: one output element per thread,
+// out[.., a, ..] = sum_i M[a][i] in[.., i, ..], with M (row major) in LDS.
+// Same terms in the same order as mode_product, so the results are identical;
+// n1^3 threads work instead of n1^2.
+template <int P, int AX, int BD>
+__device__ __forceinline__ void mode_product_el(const double2* __restrict__ in,
+                                                double2* __restrict__ out,
+                                                const double* __restrict__ M) {
+  constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L;
+  constexpr int stride = AX == 0 ? 1 : (AX == 1 ? N1 : L);
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const int o = (m / stride) % N1;
+    const int base = m - o * stride;
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) cfma_r(s, M[o * N1 + i], in[base + i * stride]);
+    out[m] = s;
+  }
+}
+
+// T <- A~_ii^{-1} T as homog_solve, element-parallel: X is an LDS scratch of
+// n1^3 entries, WV = [W | V] (n1^2 each) staged in LDS.
+template <int P, int BD>
+__device__ __forceinline__ void homog_solve_el(double2* __restrict__ T, double2* __restrict__ X,
+                                               const double* __restrict__ WV,
+                                               const double* __restrict__ tab, double2 lam) {
+  constexpr int N1 = P - 2, NI = N1 * N1 * N1;
+  const double* W = WV;
+  const double* V = WV + N1 * N1;
+  const double* Ed3 = tab + tab_off_ed3(P);
+  mode_product_el<P, 0, BD>(T, X, W);
+  __syncthreads();
+  mode_product_el<P, 1, BD>(X, T, W);
+  __syncthreads();
+  mode_product_el<P, 2, BD>(T, X, W);
+  __syncthreads();
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const double a = -Ed3[m] - lam.x, b = -lam.y;
+    const double den = 1.0 / (a * a + b * b);
+    X[m] = cmul(X[m], make_double2(a * den, -b * den));
+  }
+  __syncthreads();
+  mode_product_el<P, 0, BD>(X, T, V);
+  __syncthreads();
+  mode_product_el<P, 1, BD>(T, X, V);
+  __syncthreads();
+  mode_product_el<P, 2, BD>(X, T, V);
+  __syncthreads();
+}
 
 // h_b = x_b - F_bi f_i for face nodes r (strided by BD): the interior part of the
 // outward normal derivative along the line through each face node (eq. (flux)).

@@ -32,6 +32,10 @@ struct PL {
   static constexpr int RPT = (SLOTS + 1023) / 1024;                    // work items per thread
   static constexpr int BD = ((SLOTS + RPT - 1) / RPT + 63) / 64 * 64;  // workgroup size
   static constexpr int NBP = (NB + 3) / 4 * 4;                         // padded column count
+  // waves per SIMD for two resident workgroups per CU (one if that needs more
+  // than 6, i.e. fewer than 80 VGPRs), given to the compiler as a lower bound
+  static constexpr int MINW2 = 2 * BD / 256;
+  static constexpr int MINW = MINW2 <= 6 ? (MINW2 > 0 ? MINW2 : 1) : (BD / 256 > 0 ? BD / 256 : 1);
 };
 
 // 16-byte column group of the block in each storage precision
@@ -140,10 +144,14 @@ __device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t
   }
 }
 
+// g != null: x is A v without the face exchange and the exchange is done here,
+// while loading: x_b += the neighbour's outgoing impedance on the partner face
+// (the same addition, in the same order, as the exchange kernel of the apply).
 template <int P, int PREC>
-__global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
-    const double2* __restrict__ x, double2* __restrict__ y, const void* __restrict__ blk, int ncp,
-    const double2* __restrict__ lam, const double* __restrict__ tab, int64_t N) {
+__global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
+    const double2* __restrict__ x, const double2* __restrict__ g, const int* __restrict__ nbr,
+    double2* __restrict__ y, const void* __restrict__ blk, int ncp, const double2* __restrict__ lam,
+    const double* __restrict__ tab, int64_t nl, int64_t N) {
   using Q = PL<P>;
   constexpr int N1 = Q::N1, L = Q::L, NI = Q::NI, NB = Q::NB, NN = Q::NN, BD = Q::BD;
   __shared__ double2 T[NI];
@@ -158,12 +166,34 @@ __global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
   const double2 lm = lam[tau];
   const double* D = tab + tab_off_D(P);
   const double* D2 = tab + tab_off_D2(P);
+  // element-parallel Algorithm 3 while the block product's scratch Up can hold
+  // the n1^3 tensor (n1 <= 12); line-wise above that
+  constexpr bool EL = Q::SLOTS >= NI;
+  __shared__ double WV[EL ? 2 * N1 * N1 : 1];
+  if (EL)
+    for (int k = threadIdx.x; k < 2 * N1 * N1; k += BD)
+      WV[k] = k < N1 * N1 ? tab[tab_off_W(P) + k] : tab[tab_off_V(P) + k - N1 * N1];
 
   for (int m = threadIdx.x; m < NI; m += BD) T[m] = xv[m];
-  for (int m = threadIdx.x; m < Q::NBP; m += BD) H[m] = (m < NB) ? xv[NI + m] : make_double2(0.0, 0.0);
+  for (int m = threadIdx.x; m < Q::NBP; m += BD) {
+    double2 v = make_double2(0.0, 0.0);
+    if (m < NB) {
+      v = xv[NI + m];
+      if (g) {
+        const int f = m / L, pos = m - f * L;
+        const int t2 = nbr[tau * 6 + f];
+        if (t2 >= 0) {
+          const double2 gv = g[(rhs * nl + t2) * NB + (f ^ 1) * L + pos];
+          v = make_double2(v.x + gv.x, v.y + gv.y);
+        }
+      }
+    }
+    H[m] = v;
+  }
   __syncthreads();
   // f_i = A~_ii^{-1} x_i
-  homog_solve<P, BD>(T, tab, lm);
+  if constexpr (EL) homog_solve_el<P, BD>(T, Up, WV, tab, lm);
+  else homog_solve<P, BD>(T, tab, lm);
   for (int m = threadIdx.x; m < NI; m += BD) F[m] = T[m];
   // h_b = x_b - F_bi f_i
   face_update<P, BD>(T, H, D);
@@ -174,49 +204,57 @@ __global__ __launch_bounds__(PL<P>::BD) void k_precond_fused(
   // t = A_ib u_b
   interior_from_faces<P, BD>(U, T, D2);
   __syncthreads();
-  homog_solve<P, BD>(T, tab, lm);
+  if constexpr (EL) homog_solve_el<P, BD>(T, Up, WV, tab, lm);
+  else homog_solve<P, BD>(T, tab, lm);
   for (int m = threadIdx.x; m < NI; m += BD) yv[m] = csub(F[m], T[m]);
 }
 
 template <int P>
-int precond_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+int precond_launch(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs, int prec,
+                   hipEvent_t e0, hipEvent_t e1) {
   const Blocks& B = c->blk[prec];
-  dim3 grid((unsigned)c->nl, (unsigned)nrhs);
-  dim3 block(PL<P>::BD);
+  const dim3 grid((unsigned)c->nl, (unsigned)nrhs);
+  const dim3 block(PL<P>::BD);
+  const void* blk = B.data;
+  const int* nbr = c->d_nbr;
+  hipError_t e;
   switch (prec) {
     case kFP64:
-      hipLaunchKernelGGL((k_precond_fused<P, kFP64>), grid, block, 0, c->stream, x, y, B.data,
-                         B.ncp, c->d_lambda, c->d_tab, c->N);
+      e = launch_k(c, e0, e1, k_precond_fused<P, kFP64>, grid, block, x, g, nbr, y, blk, B.ncp,
+                   c->d_lambda, c->d_tab, c->nl, c->N);
       break;
     case kFP32:
-      hipLaunchKernelGGL((k_precond_fused<P, kFP32>), grid, block, 0, c->stream, x, y, B.data,
-                         B.ncp, c->d_lambda, c->d_tab, c->N);
+      e = launch_k(c, e0, e1, k_precond_fused<P, kFP32>, grid, block, x, g, nbr, y, blk, B.ncp,
+                   c->d_lambda, c->d_tab, c->nl, c->N);
       break;
     default:
-      hipLaunchKernelGGL((k_precond_fused<P, kBF16>), grid, block, 0, c->stream, x, y, B.data,
-                         B.ncp, c->d_lambda, c->d_tab, c->N);
+      e = launch_k(c, e0, e1, k_precond_fused<P, kBF16>, grid, block, x, g, nbr, y, blk, B.ncp,
+                   c->d_lambda, c->d_tab, c->nl, c->N);
       break;
   }
-  return check_hip(hipGetLastError(), "k_precond_fused");
+  return check_hip(e, "k_precond_fused");
 }
 
 }  // namespace
 
-static int precond_dispatch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+int launch_precond_fused(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs,
+                         int prec, hipEvent_t e0, hipEvent_t e1) {
+  if (prec < 0 || prec > 2 || !c->blk[prec].data)
+    return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
   switch (c->p) {
-    case 4: return precond_launch<4>(c, x, y, nrhs, prec);
-    case 5: return precond_launch<5>(c, x, y, nrhs, prec);
-    case 6: return precond_launch<6>(c, x, y, nrhs, prec);
-    case 7: return precond_launch<7>(c, x, y, nrhs, prec);
-    case 8: return precond_launch<8>(c, x, y, nrhs, prec);
-    case 9: return precond_launch<9>(c, x, y, nrhs, prec);
-    case 10: return precond_launch<10>(c, x, y, nrhs, prec);
-    case 11: return precond_launch<11>(c, x, y, nrhs, prec);
-    case 12: return precond_launch<12>(c, x, y, nrhs, prec);
-    case 13: return precond_launch<13>(c, x, y, nrhs, prec);
-    case 14: return precond_launch<14>(c, x, y, nrhs, prec);
-    case 15: return precond_launch<15>(c, x, y, nrhs, prec);
-    case 16: return precond_launch<16>(c, x, y, nrhs, prec);
+    case 4: return precond_launch<4>(c, x, g, y, nrhs, prec, e0, e1);
+    case 5: return precond_launch<5>(c, x, g, y, nrhs, prec, e0, e1);
+    case 6: return precond_launch<6>(c, x, g, y, nrhs, prec, e0, e1);
+    case 7: return precond_launch<7>(c, x, g, y, nrhs, prec, e0, e1);
+    case 8: return precond_launch<8>(c, x, g, y, nrhs, prec, e0, e1);
+    case 9: return precond_launch<9>(c, x, g, y, nrhs, prec, e0, e1);
+    case 10: return precond_launch<10>(c, x, g, y, nrhs, prec, e0, e1);
+    case 11: return precond_launch<11>(c, x, g, y, nrhs, prec, e0, e1);
+    case 12: return precond_launch<12>(c, x, g, y, nrhs, prec, e0, e1);
+    case 13: return precond_launch<13>(c, x, g, y, nrhs, prec, e0, e1);
+    case 14: return precond_launch<14>(c, x, g, y, nrhs, prec, e0, e1);
+    case 15: return precond_launch<15>(c, x, g, y, nrhs, prec, e0, e1);
+    case 16: return precond_launch<16>(c, x, g, y, nrhs, prec, e0, e1);
     default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
   }
 }
@@ -224,13 +262,41 @@ static int precond_dispatch(hps_ctx* c, const double2* x, double2* y, int nrhs, 
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
   if (prec < 0 || prec > 2 || !c->blk[prec].data)
     return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
-  hipEvent_t ev0;
-  int rc = timing_begin(c, &ev0);
+  TimedPair tp;
+  int rc = timing_pair(c, 1, &tp);
   if (rc) return rc;
-  if (nrhs >= kBatchedMinRhs) rc = launch_precond_batched(c, x, y, nrhs, prec);
-  else rc = precond_dispatch(c, x, y, nrhs, prec);
-  if (rc) return rc;
-  return timing_end(c, 1, ev0);
+  if (nrhs >= kBatchedMinRhs) rc = launch_precond_batched(c, x, y, nrhs, prec, tp.start, tp.stop);
+  else rc = launch_precond_fused(c, x, nullptr, y, nrhs, prec, tp.start, tp.stop);
+  if (rc) {
+    timing_drop(c, tp);
+    return rc;
+  }
+  return timing_commit(c, 1, tp);
+}
+
+int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec) {
+  int rc;
+  if (nrhs >= kBatchedMinRhs) {
+    if ((rc = launch_apply(c, x, tmp, nrhs))) return rc;
+    return launch_precond(c, tmp, y, nrhs, prec);
+  }
+  if (prec < 0 || prec > 2 || !c->blk[prec].data)
+    return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
+  if ((rc = ws_reserve(c, &c->w_g, (size_t)nrhs * c->nl * c->nb * sizeof(double2)))) return rc;
+  double2* g = static_cast<double2*>(c->w_g.ptr);
+  TimedPair ta, tp;
+  if ((rc = timing_pair(c, 0, &ta))) return rc;
+  if ((rc = launch_sweep(c, x, tmp, g, nrhs, ta.start, ta.stop))) {
+    timing_drop(c, ta);
+    return rc;
+  }
+  if ((rc = timing_commit(c, 0, ta))) return rc;
+  if ((rc = timing_pair(c, 1, &tp))) return rc;
+  if ((rc = launch_precond_fused(c, tmp, g, y, nrhs, prec, tp.start, tp.stop))) {
+    timing_drop(c, tp);
+    return rc;
+  }
+  return timing_commit(c, 1, tp);
 }
 
 }  // namespace hps

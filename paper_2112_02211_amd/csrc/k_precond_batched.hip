@@ -237,52 +237,59 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
 
 template <int P>
 int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec, void* Hb,
-                   double2* Ub) {
-  dim3 g2((unsigned)c->nl, (unsigned)nrhs);
+                   double2* Ub, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 g2((unsigned)c->nl, (unsigned)nrhs);
+  hipError_t e;
   switch (prec) {
     case kFP64:
-      hipLaunchKernelGGL((k_precond_pre<P, kFP64>), g2, dim3(PB), 0, c->stream, x, y, Hb,
-                         c->d_lambda, c->d_tab, c->N, nrhs);
+      e = launch_k(c, e0, nullptr, k_precond_pre<P, kFP64>, g2, dim3(PB), x, y, Hb, c->d_lambda,
+                   c->d_tab, c->N, nrhs);
       break;
     case kFP32:
-      hipLaunchKernelGGL((k_precond_pre<P, kFP32>), g2, dim3(PB), 0, c->stream, x, y, Hb,
-                         c->d_lambda, c->d_tab, c->N, nrhs);
+      e = launch_k(c, e0, nullptr, k_precond_pre<P, kFP32>, g2, dim3(PB), x, y, Hb, c->d_lambda,
+                   c->d_tab, c->N, nrhs);
       break;
     default:
-      hipLaunchKernelGGL((k_precond_pre<P, kBF16>), g2, dim3(PB), 0, c->stream, x, y, Hb,
-                         c->d_lambda, c->d_tab, c->N, nrhs);
+      e = launch_k(c, e0, nullptr, k_precond_pre<P, kBF16>, g2, dim3(PB), x, y, Hb, c->d_lambda,
+                   c->d_tab, c->N, nrhs);
       break;
   }
-  int rc = check_hip(hipGetLastError(), "k_precond_pre");
+  int rc = check_hip(e, "k_precond_pre");
   if (rc) return rc;
   const Blocks& Bk = c->blk[prec];
-  hipEvent_t ev0;
-  if ((rc = timing_begin(c, &ev0))) return rc;
-  dim3 g3((unsigned)c->nl, (unsigned)((c->nb + GROWS - 1) / GROWS), (unsigned)((nrhs + GCOLS - 1) / GCOLS));
+  TimedPair tg;
+  if ((rc = timing_pair(c, 2, &tg))) return rc;
+  const dim3 g3((unsigned)c->nl, (unsigned)((c->nb + GROWS - 1) / GROWS),
+                (unsigned)((nrhs + GCOLS - 1) / GCOLS));
+  const void* blk = Bk.data;
   switch (prec) {
     case kFP64:
-      hipLaunchKernelGGL((k_block_gemm<kFP64>), g3, dim3(64 * GW), 0, c->stream, Bk.data, Bk.ncp, Hb,
-                         Ub, c->nb, nrhs);
+      e = launch_k(c, tg.start, tg.stop, k_block_gemm<kFP64>, g3, dim3(64 * GW), blk, Bk.ncp,
+                   (const void*)Hb, Ub, c->nb, nrhs);
       break;
     case kFP32:
-      hipLaunchKernelGGL((k_block_gemm<kFP32>), g3, dim3(64 * GW), 0, c->stream, Bk.data, Bk.ncp, Hb,
-                         Ub, c->nb, nrhs);
+      e = launch_k(c, tg.start, tg.stop, k_block_gemm<kFP32>, g3, dim3(64 * GW), blk, Bk.ncp,
+                   (const void*)Hb, Ub, c->nb, nrhs);
       break;
     default:
-      hipLaunchKernelGGL((k_block_gemm<kBF16>), g3, dim3(64 * GW), 0, c->stream, Bk.data, Bk.ncp, Hb,
-                         Ub, c->nb, nrhs);
+      e = launch_k(c, tg.start, tg.stop, k_block_gemm<kBF16>, g3, dim3(64 * GW), blk, Bk.ncp,
+                   (const void*)Hb, Ub, c->nb, nrhs);
       break;
   }
-  if ((rc = check_hip(hipGetLastError(), "k_block_gemm"))) return rc;
-  if ((rc = timing_end(c, 2, ev0))) return rc;
-  hipLaunchKernelGGL((k_precond_post<P>), g2, dim3(PB), 0, c->stream, y, Ub, c->d_lambda, c->d_tab,
-                     c->N, nrhs);
-  return check_hip(hipGetLastError(), "k_precond_post");
+  if ((rc = check_hip(e, "k_block_gemm"))) {
+    timing_drop(c, tg);
+    return rc;
+  }
+  if ((rc = timing_commit(c, 2, tg))) return rc;
+  e = launch_k(c, nullptr, e1, k_precond_post<P>, g2, dim3(PB), y, (const double2*)Ub, c->d_lambda,
+               c->d_tab, c->N, nrhs);
+  return check_hip(e, "k_precond_post");
 }
 
 }  // namespace
 
-int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
+                           hipEvent_t e0, hipEvent_t e1) {
   const size_t hel = prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4);
   const size_t hbytes = (size_t)c->nl * nrhs * c->nb * hel;
   const size_t ubytes = (size_t)c->nl * nrhs * c->nb * sizeof(double2);
@@ -292,19 +299,19 @@ int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, i
   void* Hb = c->w_batch.ptr;
   double2* Ub = reinterpret_cast<double2*>(static_cast<char*>(c->w_batch.ptr) + hpad);
   switch (c->p) {
-    case 4: return batched_launch<4>(c, x, y, nrhs, prec, Hb, Ub);
-    case 5: return batched_launch<5>(c, x, y, nrhs, prec, Hb, Ub);
-    case 6: return batched_launch<6>(c, x, y, nrhs, prec, Hb, Ub);
-    case 7: return batched_launch<7>(c, x, y, nrhs, prec, Hb, Ub);
-    case 8: return batched_launch<8>(c, x, y, nrhs, prec, Hb, Ub);
-    case 9: return batched_launch<9>(c, x, y, nrhs, prec, Hb, Ub);
-    case 10: return batched_launch<10>(c, x, y, nrhs, prec, Hb, Ub);
-    case 11: return batched_launch<11>(c, x, y, nrhs, prec, Hb, Ub);
-    case 12: return batched_launch<12>(c, x, y, nrhs, prec, Hb, Ub);
-    case 13: return batched_launch<13>(c, x, y, nrhs, prec, Hb, Ub);
-    case 14: return batched_launch<14>(c, x, y, nrhs, prec, Hb, Ub);
-    case 15: return batched_launch<15>(c, x, y, nrhs, prec, Hb, Ub);
-    case 16: return batched_launch<16>(c, x, y, nrhs, prec, Hb, Ub);
+    case 4: return batched_launch<4>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 5: return batched_launch<5>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 6: return batched_launch<6>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 7: return batched_launch<7>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 8: return batched_launch<8>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 9: return batched_launch<9>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 10: return batched_launch<10>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 11: return batched_launch<11>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 12: return batched_launch<12>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 13: return batched_launch<13>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 14: return batched_launch<14>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 15: return batched_launch<15>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
+    case 16: return batched_launch<16>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
     default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
   }
 }

@@ -215,9 +215,10 @@ class Context:
         _check(lib().hps_lambdas(self._h, out.ctypes.data_as(ctypes.POINTER(_Z))))
         return out
 
-    def set_timing(self, enable: bool = True):
+    def set_timing(self, enable=True, every: int = 1):
+        """Event timing of every `every`-th apply / J^-1 / GEMM launch (off if not enable)."""
         self._sync_stream()
-        _check(lib().hps_set_timing(self._h, 1 if enable else 0))
+        _check(lib().hps_set_timing(self._h, int(every) if enable else 0))
 
     def kernel_times(self, reset: bool = False) -> dict:
         """Event-timed operator / preconditioner launches since the last reset."""
