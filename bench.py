@@ -21,7 +21,6 @@ The JSON line also carries:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,13 +38,6 @@ TIMING_EVERY = 8     # launches per timed launch inside the timed region
 METRIC = "HPS operator applies/s (Munknowns/s) + time-to-1e-8 solve; served p50/p99"
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2112_02211_amd", "csrc", "k_precond.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(workload: str):
     """HBM bytes per preconditioner launch from the committed PMC summary, if it
     was taken on the current kernel source; else None."""
@@ -58,6 +50,7 @@ def read_traffic(workload: str):
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
+    from paper_2112_02211_amd.profile_run import kernel_source_hash
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:

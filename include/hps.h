@@ -150,6 +150,15 @@ int hps_apply(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
  * x, y: device, nrhs * N complex; must not overlap. */
 int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
 
+/* y = J^{-1} A x with the FP64 blocks: the left-preconditioned operator the
+ * GMRES of Sec. 5.2 iterates on (eq. (block_pc) applied after Algorithm 2; its
+ * spectrum is the one Sec. 4.2 studies).  Same result as hps_apply followed by
+ * hps_precond, bit for bit; with fewer than 4 right-hand sides the face
+ * exchange of A runs inside the preconditioner's load (one kernel fewer).
+ * x, y: device, nrhs * N complex; must not overlap.  Uses a context-owned
+ * workspace of nrhs * N complex (released by hps_trim). */
+int hps_op_left(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
+
 /* As hps_precond with the blocks stored in precision prec (HPS_PREC_*; must
  * have been built).  Reduced-precision blocks are applied with FP32 arithmetic. */
 int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec);

@@ -386,6 +386,7 @@ void hps_free(hps_ctx* c) {
   hipFree(c->w_krylov.ptr);
   hipFree(c->w_small.ptr);
   hipFree(c->w_batch.ptr);
+  hipFree(c->w_op.ptr);
   if (c->h_pinned) hipHostFree(c->h_pinned);
   delete c;
 }
@@ -423,7 +424,7 @@ int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex
 int hps_trim(hps_ctx* c) {
   if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
   HPS_TRY_HIP(hipStreamSynchronize(c->stream));
-  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch};
+  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch, &c->w_op};
   for (Workspace* w : ws) {
     if (w->ptr) {
       HPS_TRY_HIP(hipFree(w->ptr));
@@ -495,6 +496,14 @@ int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec) {
 
 int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
   return hps_precond_prec(c, x, y, nrhs, HPS_PREC_FP64);
+}
+
+int hps_op_left(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
+  if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_op_left");
+  int rc = ws_reserve(c, &c->w_op, sizeof(double2) * (size_t)c->N * nrhs);
+  if (rc) return rc;
+  return launch_op_left(c, reinterpret_cast<const double2*>(x), static_cast<double2*>(c->w_op.ptr),
+                        reinterpret_cast<double2*>(y), nrhs, kFP64);
 }
 
 int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int nrhs) {

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libhps.so")
 
 HPS_OK = 0
 HPS_NOT_CONVERGED = 1
+HPS_ERR_ARG, HPS_ERR_UNSUPPORTED, HPS_ERR_OOM = -1, -2, -3
+HPS_ERR_DEVICE, HPS_ERR_BREAKDOWN, HPS_ERR_NUMERIC = -4, -5, -6
 ERRORS = {-1: "ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BREAKDOWN", -6: "NUMERIC"}
 PREC = {"fp64": 1, "fp32": 2, "bf16": 4}
 SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2}
@@ -76,6 +78,7 @@ SIGNATURES = {
     "hps_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "hps_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_op_left": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_precond_prec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int, ctypes.c_int]),
     "hps_assemble_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -265,6 +268,14 @@ class Context:
         y = torch.empty_like(x) if y is None else y
         self._sync_stream()
         _check(lib().hps_precond_prec(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x), PREC[prec]))
+        return y
+
+    def op_left(self, x, y=None):
+        """y = J^{-1} A x (FP64 blocks): the left-preconditioned operator."""
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        self._sync_stream()
+        _check(lib().hps_op_left(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x)))
         return y
 
     def assemble_rhs(self, s, t, b=None):

@@ -1,31 +1,55 @@
-"""Fixed launch sequence for hardware-counter runs of the hot-path kernels.
+"""Profiling helpers for the hot-path kernels.
 
-    python -m paper_2112_02211_amd.profile_run [--workload NAME] [--launches 4]
+    python -m paper_2112_02211_amd.profile_run [run] [--workload NAME] [--launches 4]
+    python -m paper_2112_02211_amd.profile_run pmc-summary --fetch DIR --write DIR --out FILE
+    python -m paper_2112_02211_amd.profile_run trace-summary --stats CSV --out FILE --cmd CMD --title T
 
-Sets up the workload (FP64, FP32 and BF16 blocks), then launches: the
-operator apply, the preconditioner in each block precision, and a plain
-elementwise kernel over --copy-mib MiB (dst = 2 src: each byte read once and
-written once; the known-size reference that calibrates the FETCH_SIZE /
-WRITE_SIZE counters), each --launches times.  Prints one line per phase with its wall time.
+``run`` (the default) is the fixed launch sequence for hardware-counter runs:
+it sets up the workload (FP64, FP32 and BF16 blocks), then launches, each
+--launches times after one warm-up: the operator apply (sweep + exchange),
+the left-preconditioned operator J^{-1} A (sweep, then J^{-1} with the face
+exchange fused into its load: the variant the solver runs and the benchmark's
+roofline times), the preconditioner alone in each block precision, and a
+plain elementwise kernel over --copy-mib MiB (dst = 2 src: each byte read once
+and written once; the known-size reference that calibrates the FETCH_SIZE /
+WRITE_SIZE counters).  Prints one line per phase with its wall time.
+
+``pmc-summary`` turns two rocprofv3 --pmc runs of ``run`` (one FETCH_SIZE, one
+WRITE_SIZE, csv output) into the traffic summary that bench.py reads.
+``trace-summary`` turns a rocprofv3 --kernel-trace --stats kernel_stats.csv
+into a text table.
 """
 import argparse
+import collections
+import csv
+import hashlib
 import os
+import statistics
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+CSRC = os.path.join(ROOT, "paper_2112_02211_amd", "csrc")
+# every source the preconditioner kernel is compiled from
+PRECOND_SOURCES = ("k_precond.hip", "k_leaf.h", "k_common.h", "hps_internal.h")
+COPY_MIB = 1024
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="bumps_8x8x8_p10")
-    ap.add_argument("--launches", type=int, default=4)
-    ap.add_argument("--copy-mib", type=int, default=1024)
-    a = ap.parse_args()
+
+def kernel_source_hash() -> str:
+    """Hash of the preconditioner kernel's sources: counters taken on other
+    sources describe another kernel."""
+    h = hashlib.sha256()
+    for name in PRECOND_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def run(a):
+    import numpy as np
     import torch
     from paper_2112_02211_amd import hps, problems as P
 
@@ -34,7 +58,7 @@ def main():
     rng = np.random.default_rng(0)
     x = torch.from_numpy(rng.standard_normal(ctx.N) + 1j * rng.standard_normal(ctx.N)).cuda()
     y = torch.empty_like(x)
-    phases = [("apply", lambda: ctx.apply(x, y))] + \
+    phases = [("apply", lambda: ctx.apply(x, y)), ("op_left", lambda: ctx.op_left(x, y))] + \
              [(f"precond_{q}", (lambda q=q: ctx.precond(x, y, prec=q))) for q in ("fp64", "fp32", "bf16")]
     n = a.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -50,6 +74,133 @@ def main():
         dt = (time.perf_counter() - t0) / a.launches
         print(f"{name}: {dt * 1e3:.4f} ms per launch", flush=True)
     print(f"copy bytes read = written = {n * 4}")
+
+
+def _counters(path, counter):
+    """{kernel name: [values in dispatch order]} for one counter."""
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    d = collections.defaultdict(list)
+    for r in rows:
+        d[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return d
+
+
+def _find(d, key):
+    hits = [v for k, v in d.items() if key in k]
+    if len(hits) != 1:
+        raise KeyError(f"{key}: {len(hits)} matching kernels")
+    return hits[0]
+
+
+def pmc_summary(a):
+    """Traffic summary of the workload's kernels from a FETCH_SIZE and a
+    WRITE_SIZE run of `run` (one warm-up plus `launches` dispatches per phase)."""
+    from paper_2112_02211_amd import problems as P
+    prob = P.workload(a.workload)
+    p = prob.p
+    n1 = p - 2
+    nl = prob.n_elem[0] * prob.n_elem[1] * prob.n_elem[2]
+    ni, nb = n1 ** 3, 6 * n1 * n1
+    N = nl * (ni + nb)
+    per = a.launches + 1
+    F = _counters(os.path.join(a.fetch, "run_counter_collection.csv"), "FETCH_SIZE")
+    W = _counters(os.path.join(a.write, "run_counter_collection.csv"), "WRITE_SIZE")
+    med = lambda v: statistics.median(v[1:])          # drop the warm-up dispatch
+    ew_f, ew_w = med(_find(F, "MulFunctor<float>")), med(_find(W, "MulFunctor<float>"))
+    copy_kib = a.copy_mib * 1024.0
+    sf, sw = copy_kib / ew_f, copy_kib / ew_w
+    face = 16 * nl * nb
+    ncp = {0: nb, 1: (nb + 1) // 2 * 2, 2: (nb + 3) // 4 * 4}
+    el = {0: 16, 1: 8, 2: 4}
+    L = [f"# HBM traffic of the hot-path kernels, {a.workload} workload",
+         f"# ({prob.n_elem[0]}x{prob.n_elem[1]}x{prob.n_elem[2]} leaves, p={p}, N={N}; one launch "
+         "applies the operator to one vector)",
+         "#",
+         "# commands (R = repository root on the GPU box; one counter per run):",
+         "#   cd /tmp && export TMPDIR=/tmp",
+         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.fetch.rstrip('/'))} "
+         f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}",
+         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.write.rstrip('/'))} "
+         f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}",
+         f"#   python -m paper_2112_02211_amd.profile_run pmc-summary --workload {a.workload} "
+         f"--launches {a.launches} --fetch <fetch dir> --write <write dir> --out <this file>",
+         "#",
+         f"# calibration: elementwise kernel dst = 2 src over {a.copy_mib} MiB float32 (reads and writes "
+         f"{a.copy_mib << 20} bytes)",
+         f"calib_fetch_size_kib: {ew_f:.0f}",
+         f"calib_write_size_kib: {ew_w:.0f}",
+         f"fetch_scale: {sf:.5f}",
+         f"write_scale: {sw:.5f}",
+         "# bytes = FETCH_SIZE[KiB] * 1024 * fetch_scale + WRITE_SIZE[KiB] * 1024 * write_scale",
+         "# (medians over the timed dispatches of each phase)",
+         "#"]
+    fp = _find(F, f"k_precond_fused<{p}, 0>")
+    wp = _find(W, f"k_precond_fused<{p}, 0>")
+    if len(fp) != 2 * per or len(wp) != 2 * per:
+        raise ValueError(f"expected {2 * per} FP64 preconditioner dispatches, got {len(fp)}, {len(wp)}")
+
+    def line(name, f, w, alg):
+        t = f * 1024 * sf + w * 1024 * sw
+        L.append(f"# {name}: FETCH_SIZE {f:.0f} KiB, WRITE_SIZE {w:.0f} KiB per dispatch")
+        L.append(f"{name}_hbm_bytes_per_launch: {t:.0f}")
+        L.append(f"{name}_algorithmic_bytes_per_launch: {alg}")
+        L.append(f"{name}_traffic_over_algorithmic: {t / alg:.4f}")
+        return t
+
+    # op_left runs first: its J^-1 dispatches carry the fused face exchange
+    fused = line("fp64_fused_exchange", statistics.median(fp[1:per]), statistics.median(wp[1:per]),
+                 16 * nl * nb * ncp[0] + 32 * N + face)
+    line("fp64", statistics.median(fp[per + 1:]), statistics.median(wp[per + 1:]),
+         16 * nl * nb * ncp[0] + 32 * N)
+    for q, name in ((1, "fp32"), (2, "bf16")):
+        line(name, med(_find(F, f"k_precond_fused<{p}, {q}>")), med(_find(W, f"k_precond_fused<{p}, {q}>")),
+             el[q] * nl * nb * ncp[q] + 32 * N)
+    sw_f, sw_w = _find(F, f"k_apply_sweep<{p},"), _find(W, f"k_apply_sweep<{p},")
+    line("sweep", statistics.median(sw_f[1:]), statistics.median(sw_w[1:]),
+         32 * N + 8 * nl * ni + face)
+    L += ["#",
+          "# the FP64 J^-1 with the fused exchange is the kernel the benchmark's roofline reports",
+          f"kernel_source_sha256_16: {kernel_source_hash()}",
+          f"hbm_bytes_per_launch: {fused:.0f}"]
+    text = "\n".join(L) + "\n"
+    open(a.out, "w").write(text)
+    print(text)
+
+
+def trace_summary(a):
+    rows = list(csv.DictReader(open(a.stats)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    L = [f"# {a.title}", "#", "# command (R = repository root on the GPU box):",
+         "#   cd /tmp && export TMPDIR=/tmp", f"#   {a.cmd}", "#",
+         f"# {'kernel':70s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>9s} "
+         f"{'max_us':>9s} {'pct':>6s}"]
+    for r in rows[:a.rows]:
+        name = r["Name"].replace("hps::(anonymous namespace)::", "").replace(
+            "HIP_vector_type<double, 2u>", "double2")[:70]
+        L.append(f"  {name:70s} {r['Calls']:>6s} {float(r['TotalDurationNs']) / 1e6:10.2f} "
+                 f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                 f"{float(r['MaxNs']) / 1e3:9.2f} {100 * float(r['TotalDurationNs']) / tot:6.2f}")
+    text = "\n".join(L) + "\n"
+    open(a.out, "w").write(text)
+    print(text)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", nargs="?", default="run", choices=("run", "pmc-summary", "trace-summary"))
+    ap.add_argument("--workload", default="bumps_8x8x8_p10")
+    ap.add_argument("--launches", type=int, default=4)
+    ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--stats")
+    ap.add_argument("--out")
+    ap.add_argument("--cmd", default="")
+    ap.add_argument("--title", default="rocprofv3 kernel statistics")
+    ap.add_argument("--rows", type=int, default=24)
+    a = ap.parse_args()
+    {"run": run, "pmc-summary": pmc_summary, "trace-summary": trace_summary}[a.mode](a)
 
 
 if __name__ == "__main__":

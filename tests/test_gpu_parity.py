@@ -216,3 +216,19 @@ def test_nan_input_is_reported(hps_mod):
     with pytest.raises(HPSError) as e:
         ctx.gmres(dev(s), dev(t), tol=1e-10, restart=10)
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("case,nrhs", [(CASES[0], 1), (CASES[3], 2), (CASES[1], 5)])
+def test_op_left_is_precond_of_apply(hps_mod, case, nrhs):
+    # y = J^-1 A x: bit for bit the two separate calls (the fused face exchange
+    # adds the same terms in the same order), and the oracle's J^-1 A x
+    prob, ctx, op = _setup(hps_mod, case)
+    X = np.concatenate([rand_vec(op.d.N, 40 + r) for r in range(nrhs)])
+    x = dev(X)
+    got = host(ctx.op_left(x))
+    ref = host(ctx.precond(ctx.apply(x)))
+    assert np.array_equal(got, ref)
+    M = O.Precond(op.d, op.b_nodes)
+    for r in range(nrhs):
+        want = M.apply(op.A @ X[r * op.d.N:(r + 1) * op.d.N])
+        assert rel(got[r * op.d.N:(r + 1) * op.d.N], want) < 1e-12
