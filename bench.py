@@ -270,13 +270,28 @@ def run_batched(a, prob):
     gemm_ms = kt["gemm_ms"] / max(1, kt["gemm_launches"])
     prec_ms = kt["precond_ms"] / max(1, kt["precond_launches"])
     app_ms = kt["apply_ms"] / max(1, kt["apply_launches"])
+    # The block GEMM: 8 flops per complex multiply-add; HBM bytes = the blocks
+    # (read once), the H panel (read, block precision) and U (written: FP64 for
+    # FP64 blocks, FP32 otherwise).  Its bound is whichever roof the arithmetic
+    # intensity reaches first: FP32 and FP64 blocks sit above the ridge (MFMA),
+    # BF16 blocks below it (HBM).
+    el = {"fp64": 16, "fp32": 8, "bf16": 4}[prec]
     flops = 8.0 * ctx.nb * ctx.nb * k * ctx.nl
-    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    gbytes = float(ctx.nl) * ctx.nb * (ctx.nb * el + k * el + k * (16 if prec == "fp64" else 8))
     peak = MFMA_PEAK_TFLOPS[prec]
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": f"k_block_gemm ({prec} blocks, {k} right-hand sides)",
-                "avg_launch_ms": round(gemm_ms, 4), "algorithmic_flops_per_launch": flops}
+    intensity = flops / gbytes
+    tflops = flops / (gemm_ms * 1e-3) / 1e12
+    gbs = gbytes / (gemm_ms * 1e-3) / 1e9
+    common = {"traffic": None, "kernel": f"k_block_gemm ({prec} blocks, {k} right-hand sides)",
+              "avg_launch_ms": round(gemm_ms, 4), "algorithmic_flops_per_launch": flops,
+              "algorithmic_bytes_per_launch": gbytes, "flop_per_byte": round(intensity, 1),
+              "ridge_flop_per_byte": round(peak * 1e12 / (HBM_PEAK_GBS * 1e9), 1)}
+    if intensity >= peak * 1e12 / (HBM_PEAK_GBS * 1e9):
+        roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tflops / peak, 4), **common, "hbm_GBs": round(gbs, 1)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), **common, "TFLOPs": round(tflops, 2)}
     # parity spot check: two columns against single-right-hand-side FP64 solves
     errs = []
     for r in (0, k - 1):

@@ -365,11 +365,13 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(double2* __restrict__ V, int
   const double2* cb = sm.b;
   for (int64_t i = (int64_t)blockIdx.x * UT + threadIdx.x; i < n; i += (int64_t)gridDim.x * UT) {
     double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-    int l = 0;
-    for (; l + 8 <= J; l += 8) {
+    // eight basis vectors per round, the last round predicated (its loads still
+    // issue together; coefficients beyond J are zero and so are skipped loads)
+    for (int l = 0; l < J; l += 8) {
       double2 v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = V[(int64_t)(l + q) * ldv + i];
+      for (int q = 0; q < 8; ++q)
+        v[q] = (l + q < J) ? V[(int64_t)(l + q) * ldv + i] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double2 x = ca[l + q], y = cb[l + q];
@@ -378,14 +380,6 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(double2* __restrict__ V, int
         sb.x = fma(v[q].x, y.x, fma(-v[q].y, y.y, sb.x));
         sb.y = fma(v[q].x, y.y, fma(v[q].y, y.x, sb.y));
       }
-    }
-    for (; l < J; ++l) {
-      const double2 v = V[(int64_t)l * ldv + i];
-      const double2 x = ca[l], y = cb[l];
-      sa.x = fma(v.x, x.x, fma(-v.y, x.y, sa.x));
-      sa.y = fma(v.x, x.y, fma(v.y, x.x, sa.y));
-      sb.x = fma(v.x, y.x, fma(-v.y, y.y, sb.x));
-      sb.y = fma(v.x, y.y, fma(v.y, y.x, sb.y));
     }
     const double2 uv = u[i], wv = w[i];
     const double2 vj = make_double2((uv.x - sa.x) * inv, (uv.y - sa.y) * inv);

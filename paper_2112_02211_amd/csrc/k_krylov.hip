@@ -74,9 +74,11 @@ __global__ __launch_bounds__(RT) void k_mupdate(const double2* __restrict__ V, i
   V += bz * vbs;
   w += bz * wbs;
   coef += bz * cbs;
-  __shared__ double2 cs[kMaxRestart + 1];
-  for (int k = threadIdx.x; k < K; k += RT) {
-    const double2 c = coef[k];
+  // coefficients zero-padded to a multiple of 8 (the last round is predicated)
+  __shared__ double2 cs[(kMaxRestart + 1 + 7) / 8 * 8];
+  const int K8 = (K + 7) / 8 * 8;
+  for (int k = threadIdx.x; k < K8; k += RT) {
+    const double2 c = k < K ? coef[k] : make_double2(0.0, 0.0);
     cs[k] = make_double2(sign * c.x, sign * c.y);
   }
   __syncthreads();
@@ -84,23 +86,17 @@ __global__ __launch_bounds__(RT) void k_mupdate(const double2* __restrict__ V, i
   double sq = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)nblk * RT) {
     double2 a = w[i];
-    int k = 0;
-    for (; k + 8 <= K; k += 8) {
+    for (int k = 0; k < K; k += 8) {
       double2 v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(k + u) * ldv + i];
+      for (int u = 0; u < 8; ++u)
+        v[u] = (k + u < K) ? V[(int64_t)(k + u) * ldv + i] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const double2 c = cs[k + u];
         a.x = fma(v[u].x, c.x, fma(-v[u].y, c.y, a.x));
         a.y = fma(v[u].x, c.y, fma(v[u].y, c.x, a.y));
       }
-    }
-    for (; k < K; ++k) {
-      const double2 v = V[(int64_t)k * ldv + i];
-      const double2 c = cs[k];
-      a.x = fma(v.x, c.x, fma(-v.y, c.y, a.x));
-      a.y = fma(v.x, c.y, fma(v.y, c.x, a.y));
     }
     w[i] = a;
     sq = fma(a.x, a.x, fma(a.y, a.y, sq));

@@ -80,6 +80,18 @@ __device__ __forceinline__ void mode_product_el(const double2* __restrict__ in,
   }
 }
 
+// The element-parallel form needs an extra n1^3 LDS tensor; used up to p = 14.
+template <int P>
+constexpr bool kElementParallel = (P <= 14);
+
+// WV = [W | V] (V^{-1} and V, n1^2 each) from the shared table into LDS
+template <int P, int BD>
+__device__ __forceinline__ void stage_wv(double* __restrict__ WV, const double* __restrict__ tab) {
+  constexpr int Q = (P - 2) * (P - 2);
+  for (int k = threadIdx.x; k < 2 * Q; k += BD)
+    WV[k] = k < Q ? tab[tab_off_W(P) + k] : tab[tab_off_V(P) + k - Q];
+}
+
 // T <- A~_ii^{-1} T as homog_solve, element-parallel: X is an LDS scratch of
 // n1^3 entries, WV = [W | V] (n1^2 each) staged in LDS.
 template <int P, int BD>

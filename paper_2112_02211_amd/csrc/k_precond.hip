@@ -170,9 +170,7 @@ __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
   // the n1^3 tensor (n1 <= 12); line-wise above that
   constexpr bool EL = Q::SLOTS >= NI;
   __shared__ double WV[EL ? 2 * N1 * N1 : 1];
-  if (EL)
-    for (int k = threadIdx.x; k < 2 * N1 * N1; k += BD)
-      WV[k] = k < N1 * N1 ? tab[tab_off_W(P) + k] : tab[tab_off_V(P) + k - N1 * N1];
+  if (EL) stage_wv<P, BD>(WV, tab);
 
   for (int m = threadIdx.x; m < NI; m += BD) T[m] = xv[m];
   for (int m = threadIdx.x; m < Q::NBP; m += BD) {

@@ -9,6 +9,8 @@
 //   gemm  per (leaf, 128-row panel, 64-column panel): U = S~^{-1} H on MFMA
 //   post  per (leaf, rhs): y_b = u_b, y_i = f_i - A~_ii^{-1} (A_ib u_b)
 //
+// U is kept in FP32 for FP32 / BF16 blocks (their products accumulate in FP32).
+//
 // The complex product is split into real matrix-core products:
 //   Re U = Re S Re H - Im S Im H,   Im U = Re S Im H + Im S Re H.
 // Precisions: FP64 blocks on v_mfma_f64_16x16x4 (FP64 accumulate), FP32 blocks
@@ -36,6 +38,8 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
 }
 
 // ------------------------------------------------------------------ pre / post
+// (Algorithm 3 line-wise here: these kernels run many small workgroups per CU,
+// where LDS bandwidth, not idle threads, bounds the mode products.)
 template <int P, int PREC>
 __global__ __launch_bounds__(PB) void k_precond_pre(const double2* __restrict__ x,
                                                     double2* __restrict__ y, void* __restrict__ Hb,
@@ -69,9 +73,11 @@ __global__ __launch_bounds__(PB) void k_precond_pre(const double2* __restrict__ 
   }
 }
 
-template <int P>
+// UF: U is stored as float2 (FP32 / BF16 blocks, whose products accumulate in
+// FP32 anyway) instead of double2 (FP64 blocks).
+template <int P, bool UF>
 __global__ __launch_bounds__(PB) void k_precond_post(double2* __restrict__ y,
-                                                     const double2* __restrict__ Ub,
+                                                     const void* __restrict__ Ub,
                                                      const double2* __restrict__ lam,
                                                      const double* __restrict__ tab, int64_t N,
                                                      int nrhs) {
@@ -81,9 +87,15 @@ __global__ __launch_bounds__(PB) void k_precond_post(double2* __restrict__ y,
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
   double2* yv = y + rhs * N + tau * NN;
-  const double2* uv = Ub + (tau * nrhs + rhs) * NB;
+  const int64_t uoff = (tau * nrhs + rhs) * NB;
   for (int r = threadIdx.x; r < NB; r += PB) {
-    const double2 u = uv[r];
+    double2 u;
+    if (UF) {
+      const float2 f = static_cast<const float2*>(Ub)[uoff + r];
+      u = make_double2((double)f.x, (double)f.y);
+    } else {
+      u = static_cast<const double2*>(Ub)[uoff + r];
+    }
     U[r] = u;
     yv[NI + r] = u;
   }
@@ -113,19 +125,23 @@ constexpr int GCOLS = 64;         // right-hand sides per workgroup
 constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
 
 template <int PREC> struct GemmTraits;
-template <> struct GemmTraits<kFP64> { using H = double2; static constexpr int CW = 1, KT = 32; };
-template <> struct GemmTraits<kFP32> { using H = float2; static constexpr int CW = 2, KT = 64; };
-template <> struct GemmTraits<kBF16> { using H = uint32_t; static constexpr int CW = 4, KT = 64; };
+// PAD: extra columns per LDS row of the staged H.  The four k-slot groups of a
+// wavefront read rows CW apart; with 64-entry rows those rows start on the same
+// LDS bank, so the padding shifts them onto disjoint banks (BF16: 16 words
+// apart, conflict-free; FP32: 32 words, the two passes an 8-byte read needs).
+template <> struct GemmTraits<kFP64> { using H = double2; static constexpr int CW = 1, KT = 16, PAD = 0; };
+template <> struct GemmTraits<kFP32> { using H = float2; static constexpr int CW = 2, KT = 64, PAD = 8; };
+template <> struct GemmTraits<kBF16> { using H = uint32_t; static constexpr int CW = 4, KT = 64, PAD = 4; };
 
 template <int PREC>
 __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__ blk, int ncp,
                                                         const void* __restrict__ Hb,
-                                                        double2* __restrict__ Ub, int NB,
+                                                        void* __restrict__ Ub, int NB,
                                                         int nrhs) {
   using TR = GemmTraits<PREC>;
   using HT = typename TR::H;
   constexpr int CW = TR::CW, KT = TR::KT, CH = 4 * CW;  // inner indices per MFMA chunk
-  __shared__ HT Bs[KT][GCOLS];
+  __shared__ HT Bs[KT][GCOLS + TR::PAD];
   const int64_t tau = blockIdx.x;
   const int r0 = blockIdx.y * GROWS;
   const int c0 = blockIdx.z * GCOLS;
@@ -145,6 +161,19 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
     for (int r = 0; r < 4; ++r) { are[t][r] = 0; aim[t][r] = 0; }
   }
 
+  // Block fragments of one stage (KT inner indices), software pipelined: the
+  // loads of stage kt + KT are issued before the products of stage kt, so one
+  // stage of HBM latency is hidden behind the matrix-core work.
+  constexpr int NCH = KT / CH;
+  auto load_stage = [&](int kt, uint4* dst) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int cg = (kt + c * CH) / CW + g;
+      dst[c] = (kt < NB && cg < ncg) ? ld_nt(B + (size_t)cg * NB + rowc) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  uint4 a16[NCH], nx16[NCH];
+  load_stage(0, a16);
   for (int kt = 0; kt < NB; kt += KT) {
     __syncthreads();
     // stage H[c0 .. c0+63][kt .. kt+KT-1] as Bs[inner][col]
@@ -157,14 +186,7 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
       Bs[kin][col] = v;
     }
     __syncthreads();
-    // block fragments of this stage, all issued before use
-    constexpr int NCH = KT / CH;
-    uint4 a16[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int cg = (kt + c * CH) / CW + g;
-      a16[c] = (cg < ncg) ? ld_nt(B + (size_t)cg * NB + rowc) : make_uint4(0, 0, 0, 0);
-    }
+    load_stage(kt + KT, nx16);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const int kin0 = c * CH + CW * g;  // first inner index (within the stage) of this lane
@@ -219,6 +241,8 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
         }
       }
     }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) a16[c] = nx16[c];
   }
   // accumulator lane layout: column c0 + 16 t + li; row r0 + 16 wv + (4 g + r)
   // (FP32, BF16) or r0 + 16 wv + (g + 4 r) (FP64)
@@ -226,18 +250,22 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   for (int t = 0; t < GCT; ++t) {
     const int col = c0 + t * 16 + li;
     if (col >= nrhs) continue;
-    double2* uo = Ub + ((size_t)tau * nrhs + col) * NB;
+    const size_t uo = ((size_t)tau * nrhs + col) * NB;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = r0 + wv * 16 + (PREC == kFP64 ? g + 4 * r : 4 * g + r);
-      if (rr < NB) uo[rr] = make_double2((double)are[t][r], (double)aim[t][r]);
+      if (rr >= NB) continue;
+      if constexpr (PREC == kFP64)
+        static_cast<double2*>(Ub)[uo + rr] = make_double2((double)are[t][r], (double)aim[t][r]);
+      else
+        static_cast<float2*>(Ub)[uo + rr] = make_float2((float)are[t][r], (float)aim[t][r]);
     }
   }
 }
 
 template <int P>
 int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec, void* Hb,
-                   double2* Ub, hipEvent_t e0, hipEvent_t e1) {
+                   void* Ub, hipEvent_t e0, hipEvent_t e1) {
   const dim3 g2((unsigned)c->nl, (unsigned)nrhs);
   hipError_t e;
   switch (prec) {
@@ -281,8 +309,12 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
     return rc;
   }
   if ((rc = timing_commit(c, 2, tg))) return rc;
-  e = launch_k(c, nullptr, e1, k_precond_post<P>, g2, dim3(PB), y, (const double2*)Ub, c->d_lambda,
-               c->d_tab, c->N, nrhs);
+  if (prec == kFP64)
+    e = launch_k(c, nullptr, e1, k_precond_post<P, false>, g2, dim3(PB), y, (const void*)Ub,
+                 c->d_lambda, c->d_tab, c->N, nrhs);
+  else
+    e = launch_k(c, nullptr, e1, k_precond_post<P, true>, g2, dim3(PB), y, (const void*)Ub,
+                 c->d_lambda, c->d_tab, c->N, nrhs);
   return check_hip(e, "k_precond_post");
 }
 
@@ -292,12 +324,12 @@ int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, i
                            hipEvent_t e0, hipEvent_t e1) {
   const size_t hel = prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4);
   const size_t hbytes = (size_t)c->nl * nrhs * c->nb * hel;
-  const size_t ubytes = (size_t)c->nl * nrhs * c->nb * sizeof(double2);
+  const size_t ubytes = (size_t)c->nl * nrhs * c->nb * (prec == kFP64 ? 16 : 8);
   const size_t hpad = (hbytes + 255) / 256 * 256;
   int rc = ws_reserve(c, &c->w_batch, hpad + ubytes);
   if (rc) return rc;
   void* Hb = c->w_batch.ptr;
-  double2* Ub = reinterpret_cast<double2*>(static_cast<char*>(c->w_batch.ptr) + hpad);
+  void* Ub = static_cast<char*>(c->w_batch.ptr) + hpad;
   switch (c->p) {
     case 4: return batched_launch<4>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
     case 5: return batched_launch<5>(c, x, y, nrhs, prec, Hb, Ub, e0, e1);
