@@ -84,24 +84,45 @@ __device__ __forceinline__ void mode_product_el(const double2* __restrict__ in,
 template <int P>
 constexpr bool kElementParallel = (P <= 14);
 
-// WV = [W | V] (V^{-1} and V, n1^2 each) from the shared table into LDS
+// The leaf tables in LDS: LT = [W | V | E_Delta | Dlo | Dhi | C0 | C1] (V^{-1}
+// and V, n1^2 each; the n1^3 eigenvalue sums; the end rows of D and the end
+// columns of D^2 as face_update / interior_from_faces take them, n1 each),
+// kLeafTab<P> doubles.  With them in LDS the leaf arithmetic issues no
+// vector-memory loads (a load there would wait for every earlier load of the
+// wavefront, e.g. the block prefetch).
+template <int P>
+constexpr int kLeafTab = 2 * (P - 2) * (P - 2) + (P - 2) * (P - 2) * (P - 2) + 4 * (P - 2);
+template <int P> constexpr int lt_ed3() { return 2 * (P - 2) * (P - 2); }
+template <int P> constexpr int lt_dlo() { return lt_ed3<P>() + (P - 2) * (P - 2) * (P - 2); }
+template <int P> constexpr int lt_dhi() { return lt_dlo<P>() + (P - 2); }
+template <int P> constexpr int lt_c0() { return lt_dhi<P>() + (P - 2); }
+template <int P> constexpr int lt_c1() { return lt_c0<P>() + (P - 2); }
+
 template <int P, int BD>
-__device__ __forceinline__ void stage_wv(double* __restrict__ WV, const double* __restrict__ tab) {
-  constexpr int Q = (P - 2) * (P - 2);
-  for (int k = threadIdx.x; k < 2 * Q; k += BD)
-    WV[k] = k < Q ? tab[tab_off_W(P) + k] : tab[tab_off_V(P) + k - Q];
+__device__ __forceinline__ void stage_leaf_tables(double* __restrict__ LT, const double* __restrict__ tab) {
+  constexpr int N1 = P - 2, Q = N1 * N1;
+  for (int k = threadIdx.x; k < kLeafTab<P>; k += BD) {
+    double v;
+    if (k < Q) v = tab[tab_off_W(P) + k];
+    else if (k < 2 * Q) v = tab[tab_off_V(P) + k - Q];
+    else if (k < lt_dlo<P>()) v = tab[tab_off_ed3(P) + k - 2 * Q];
+    else if (k < lt_dhi<P>()) v = tab[tab_off_D(P) + 1 + (k - lt_dlo<P>())];
+    else if (k < lt_c0<P>()) v = tab[tab_off_D(P) + (P - 1) * P + 1 + (k - lt_dhi<P>())];
+    else if (k < lt_c1<P>()) v = tab[tab_off_D2(P) + (k - lt_c0<P>() + 1) * P];
+    else v = tab[tab_off_D2(P) + (k - lt_c1<P>() + 1) * P + P - 1];
+    LT[k] = v;
+  }
 }
 
 // T <- A~_ii^{-1} T as homog_solve, element-parallel: X is an LDS scratch of
-// n1^3 entries, WV = [W | V] (n1^2 each) staged in LDS.
+// n1^3 entries, WVE the tables staged by stage_leaf_tables.
 template <int P, int BD>
 __device__ __forceinline__ void homog_solve_el(double2* __restrict__ T, double2* __restrict__ X,
-                                               const double* __restrict__ WV,
-                                               const double* __restrict__ tab, double2 lam) {
+                                               const double* __restrict__ WVE, double2 lam) {
   constexpr int N1 = P - 2, NI = N1 * N1 * N1;
-  const double* W = WV;
-  const double* V = WV + N1 * N1;
-  const double* Ed3 = tab + tab_off_ed3(P);
+  const double* W = WVE;
+  const double* V = WVE + N1 * N1;
+  const double* Ed3 = WVE + 2 * N1 * N1;
   mode_product_el<P, 0, BD>(T, X, W);
   __syncthreads();
   mode_product_el<P, 1, BD>(X, T, W);
@@ -124,9 +145,11 @@ __device__ __forceinline__ void homog_solve_el(double2* __restrict__ T, double2*
 
 // h_b = x_b - F_bi f_i for face nodes r (strided by BD): the interior part of the
 // outward normal derivative along the line through each face node (eq. (flux)).
+// Dlo[t], Dhi[t] (t < n1): entries t + 1 of the first and last rows of D.
 template <int P, int BD>
 __device__ __forceinline__ void face_update(const double2* __restrict__ F, double2* __restrict__ H,
-                                            const double* __restrict__ D) {
+                                            const double* __restrict__ Dlo,
+                                            const double* __restrict__ Dhi) {
   constexpr int N1 = P - 2, L = N1 * N1, NB = 6 * L;
   for (int r = threadIdx.x; r < NB; r += BD) {
     const int f = r / L, pos = r - f * L;
@@ -136,33 +159,50 @@ __device__ __forceinline__ void face_update(const double2* __restrict__ F, doubl
     if (ax == 0) { base = N1 * a + L * b; stride = 1; }
     else if (ax == 1) { base = a + L * b; stride = N1; }
     else { base = a + N1 * b; stride = L; }
-    const int e = hi ? P - 1 : 0;
+    const double* Dr = hi ? Dhi : Dlo;
     const double sg = hi ? 1.0 : -1.0;
     double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int t = 0; t < N1; ++t) cfma_r(s, D[e * P + t + 1], F[base + t * stride]);
+    for (int t = 0; t < N1; ++t) cfma_r(s, Dr[t], F[base + t * stride]);
     const double2 hv = H[r];
     H[r] = make_double2(hv.x - sg * s.x, hv.y - sg * s.y);
   }
 }
 
 // T = A_ib u_b: interior rows of -(Dx^2 + Dy^2 + Dz^2) restricted to face columns.
+// C0[i cs], C1[i cs] (i < n1): the first and last columns of D^2 in row i + 1.
 template <int P, int BD>
 __device__ __forceinline__ void interior_from_faces(const double2* __restrict__ U,
                                                     double2* __restrict__ T,
-                                                    const double* __restrict__ D2) {
+                                                    const double* __restrict__ C0,
+                                                    const double* __restrict__ C1, int cs) {
   constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L;
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
     double2 s = make_double2(0.0, 0.0);
-    cfma_r(s, D2[(i + 1) * P + 0], U[0 * L + j + N1 * k]);
-    cfma_r(s, D2[(i + 1) * P + P - 1], U[1 * L + j + N1 * k]);
-    cfma_r(s, D2[(j + 1) * P + 0], U[2 * L + i + N1 * k]);
-    cfma_r(s, D2[(j + 1) * P + P - 1], U[3 * L + i + N1 * k]);
-    cfma_r(s, D2[(k + 1) * P + 0], U[4 * L + i + N1 * j]);
-    cfma_r(s, D2[(k + 1) * P + P - 1], U[5 * L + i + N1 * j]);
+    cfma_r(s, C0[i * cs], U[0 * L + j + N1 * k]);
+    cfma_r(s, C1[i * cs], U[1 * L + j + N1 * k]);
+    cfma_r(s, C0[j * cs], U[2 * L + i + N1 * k]);
+    cfma_r(s, C1[j * cs], U[3 * L + i + N1 * k]);
+    cfma_r(s, C0[k * cs], U[4 * L + i + N1 * j]);
+    cfma_r(s, C1[k * cs], U[5 * L + i + N1 * j]);
     T[m] = make_double2(-s.x, -s.y);
   }
+}
+
+// The same couplings read straight from the shared table in global memory.
+template <int P, int BD>
+__device__ __forceinline__ void face_update_g(const double2* __restrict__ F, double2* __restrict__ H,
+                                              const double* __restrict__ tab) {
+  const double* D = tab + tab_off_D(P);
+  face_update<P, BD>(F, H, D + 1, D + (P - 1) * P + 1);
+}
+template <int P, int BD>
+__device__ __forceinline__ void interior_from_faces_g(const double2* __restrict__ U,
+                                                      double2* __restrict__ T,
+                                                      const double* __restrict__ tab) {
+  const double* D2 = tab + tab_off_D2(P);
+  interior_from_faces<P, BD>(U, T, D2 + P, D2 + P + P - 1, P);
 }
 
 }  // namespace hps

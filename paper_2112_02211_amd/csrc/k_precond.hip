@@ -47,14 +47,50 @@ template <> struct BlockIO<kBF16> { static constexpr int CW = 4; };
 __device__ __forceinline__ float bf_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
+// The first PF column groups of a thread's first (row, half) work item, loaded
+// before the leaf arithmetic that precedes the block product (Algorithm 3 and
+// the face update), so that HBM is busy during it.  Entries past the item's
+// last column group are zero and are not used.
+template <int P, int PREC, int PF>
+struct BlockPrefetch {
+  uint4 v[PF];
+  __device__ __forceinline__ void issue(const void* __restrict__ blk, int64_t tau, int ncp) {
+    using Q = PL<P>;
+    constexpr int NB = Q::NB, KS = Q::KS;
+    constexpr int CW = BlockIO<PREC>::CW;
+    const int ncg = ncp / CW;
+    const int per = (ncg + KS - 1) / KS;
+    const int slot = threadIdx.x;
+    const bool ok = slot < Q::SLOTS;
+    const int sl = ok ? slot : 0;
+    const int row = sl % NB, q = sl / NB;
+    const int c0 = q * per, c1 = ok ? min(ncg, (q + 1) * per) : c0;
+    const uint4* B = static_cast<const uint4*>(blk) + (size_t)tau * ncg * NB + row;
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+      v[u] = (c0 + u < c1) ? ld_nt(B + (size_t)(c0 + u) * NB) : make_uint4(0, 0, 0, 0);
+  }
+};
+
+template <int P, int PREC>
+struct BlockPrefetch<P, PREC, 0> {
+  uint4 v[1];
+  __device__ __forceinline__ void issue(const void*, int64_t, int) {}
+};
+
+__device__ __forceinline__ double2 as_d2(uint4 a) {
+  return make_double2(__hiloint2double(a.y, a.x), __hiloint2double(a.w, a.z));
+}
+
 // u_b = S~^{-1} h_b for one leaf.  Work item (row r, half q) accumulates the
 // columns of half q of row r; the two halves are combined through LDS.  The
 // block is read once, with non-temporal 16-byte loads (it is not reused before
 // the next preconditioner call, which reads every other block first).
-template <int P, int PREC, int UNR>
+template <int P, int PREC, int UNR, int PF>
 __device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t tau, int ncp,
                                            const double2* __restrict__ H, double2* __restrict__ Up,
-                                           double2* __restrict__ U, double2* __restrict__ yb) {
+                                           double2* __restrict__ U, double2* __restrict__ yb,
+                                           const BlockPrefetch<P, PREC, PF>& pf) {
   using Q = PL<P>;
   constexpr int NB = Q::NB, RPT = Q::RPT, BD = Q::BD, KS = Q::KS;
   constexpr int CW = BlockIO<PREC>::CW;
@@ -79,6 +115,17 @@ __device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t
       double2 acc = make_double2(0.0, 0.0);
       const double2* Br = B + rows[k];
       int cg = cg0[k];
+      if (k == 0) {  // the prefetched column groups first
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          if (cg + u < cg1[k]) {
+            const double2 sv = as_d2(pf.v[u]), h = H[cg + u];
+            acc.x = fma(sv.x, h.x, fma(-sv.y, h.y, acc.x));
+            acc.y = fma(sv.x, h.y, fma(sv.y, h.x, acc.y));
+          }
+        }
+        cg = min(cg1[k], cg + PF);
+      }
       for (; cg + UNR <= cg1[k]; cg += UNR) {
         double2 sv[UNR];
 #pragma unroll
@@ -105,31 +152,39 @@ __device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t
     for (int k = 0; k < RPT; ++k) {
       float2 acc = make_float2(0.f, 0.f);
       const uint4* Br = B + rows[k];
-      for (int cg = cg0[k]; cg < cg1[k]; cg += UNR) {
+      // one 16-byte column group: CW complex entries
+      auto consume = [&](uint4 sv, int cg) {
+        const uint32_t wv[4] = {sv.x, sv.y, sv.z, sv.w};
+#pragma unroll
+        for (int w = 0; w < CW; ++w) {
+          const double2 hv = (cg < cg1[k]) ? H[cg * CW + w] : make_double2(0.0, 0.0);
+          const float hr = (float)hv.x, hi = (float)hv.y;
+          float sr, si;
+          if (PREC == kFP32) {
+            sr = __uint_as_float(wv[2 * w]);
+            si = __uint_as_float(wv[2 * w + 1]);
+          } else {
+            sr = bf_lo(wv[w]);
+            si = bf_hi(wv[w]);
+          }
+          acc.x = fmaf(sr, hr, fmaf(-si, hi, acc.x));
+          acc.y = fmaf(sr, hi, fmaf(si, hr, acc.y));
+        }
+      };
+      int cg0k = cg0[k];
+      if (k == 0) {  // the prefetched column groups first
+#pragma unroll
+        for (int u = 0; u < PF; ++u) consume(pf.v[u], cg0k + u);
+        cg0k = min(cg1[k], cg0k + PF);
+      }
+      for (int cg = cg0k; cg < cg1[k]; cg += UNR) {
         uint4 sv[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
           sv[u] = (cg + u < cg1[k]) ? ld_nt(Br + (size_t)(cg + u) * NB)
                                     : make_uint4(0, 0, 0, 0);
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const uint32_t wv[4] = {sv[u].x, sv[u].y, sv[u].z, sv[u].w};
-#pragma unroll
-          for (int w = 0; w < CW; ++w) {
-            const double2 hv = (cg + u < cg1[k]) ? H[(cg + u) * CW + w] : make_double2(0.0, 0.0);
-            const float hr = (float)hv.x, hi = (float)hv.y;
-            float sr, si;
-            if (PREC == kFP32) {
-              sr = __uint_as_float(wv[2 * w]);
-              si = __uint_as_float(wv[2 * w + 1]);
-            } else {
-              sr = bf_lo(wv[w]);
-              si = bf_hi(wv[w]);
-            }
-            acc.x = fmaf(sr, hr, fmaf(-si, hi, acc.x));
-            acc.y = fmaf(sr, hi, fmaf(si, hr, acc.y));
-          }
-        }
+        for (int u = 0; u < UNR; ++u) consume(sv[u], cg + u);
       }
       if (ok[k]) Up[threadIdx.x + k * BD] = make_double2((double)acc.x, (double)acc.y);
     }
@@ -147,6 +202,13 @@ __device__ __forceinline__ void block_gemv(const void* __restrict__ blk, int64_t
 // g != null: x is A v without the face exchange and the exchange is done here,
 // while loading: x_b += the neighbour's outgoing impedance on the partner face
 // (the same addition, in the same order, as the exchange kernel of the apply).
+// column groups per thread loaded before the leaf arithmetic (fewer for the
+// reduced precisions, whose 16-byte groups hold 2 or 4 entries and whose
+// products need more registers); none above p = 12, where the LDS allows one
+// workgroup per CU and every thread has two work items
+template <int P, int PREC>
+constexpr int kPrefetch = P > 12 ? 0 : (PREC == kFP64 ? 8 : (PREC == kFP32 ? 4 : 2));
+
 template <int P, int PREC>
 __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
     const double2* __restrict__ x, const double2* __restrict__ g, const int* __restrict__ nbr,
@@ -164,13 +226,11 @@ __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
   const double2* xv = x + rhs * N + tau * NN;
   double2* yv = y + rhs * N + tau * NN;
   const double2 lm = lam[tau];
-  const double* D = tab + tab_off_D(P);
-  const double* D2 = tab + tab_off_D2(P);
   // element-parallel Algorithm 3 while the block product's scratch Up can hold
   // the n1^3 tensor (n1 <= 12); line-wise above that
   constexpr bool EL = Q::SLOTS >= NI;
-  __shared__ double WV[EL ? 2 * N1 * N1 : 1];
-  if (EL) stage_wv<P, BD>(WV, tab);
+  __shared__ double LT[EL ? kLeafTab<P> : 1];
+  if (EL) stage_leaf_tables<P, BD>(LT, tab);
 
   for (int m = threadIdx.x; m < NI; m += BD) T[m] = xv[m];
   for (int m = threadIdx.x; m < Q::NBP; m += BD) {
@@ -188,21 +248,28 @@ __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
     }
     H[m] = v;
   }
+  // The first block loads go out now, after every load the leaf arithmetic
+  // needs (loads complete in order, so anything issued later would wait for
+  // them), and arrive while Algorithm 3 and the face update run.
+  BlockPrefetch<P, PREC, kPrefetch<P, PREC>> pf;
+  pf.issue(blk, tau, ncp);
   __syncthreads();
   // f_i = A~_ii^{-1} x_i
-  if constexpr (EL) homog_solve_el<P, BD>(T, Up, WV, tab, lm);
+  if constexpr (EL) homog_solve_el<P, BD>(T, Up, LT, lm);
   else homog_solve<P, BD>(T, tab, lm);
   for (int m = threadIdx.x; m < NI; m += BD) F[m] = T[m];
   // h_b = x_b - F_bi f_i
-  face_update<P, BD>(T, H, D);
+  if constexpr (EL) face_update<P, BD>(T, H, LT + lt_dlo<P>(), LT + lt_dhi<P>());
+  else face_update_g<P, BD>(T, H, tab);
   __syncthreads();
   // u_b = S~^{-1} h_b, written to y_b and kept in LDS
-  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4)>(blk, tau, ncp, H, Up, U, yv + NI);
+  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4), kPrefetch<P, PREC>>(blk, tau, ncp, H, Up, U, yv + NI, pf);
   __syncthreads();
   // t = A_ib u_b
-  interior_from_faces<P, BD>(U, T, D2);
+  if constexpr (EL) interior_from_faces<P, BD>(U, T, LT + lt_c0<P>(), LT + lt_c1<P>(), 1);
+  else interior_from_faces_g<P, BD>(U, T, tab);
   __syncthreads();
-  if constexpr (EL) homog_solve_el<P, BD>(T, Up, WV, tab, lm);
+  if constexpr (EL) homog_solve_el<P, BD>(T, Up, LT, lm);
   else homog_solve<P, BD>(T, tab, lm);
   for (int m = threadIdx.x; m < NI; m += BD) yv[m] = csub(F[m], T[m]);
 }

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(PB) void k_precond_pre(const double2* __restrict__ 
   __syncthreads();
   homog_solve<P, PB>(T, tab, lam[tau]);
   for (int m = threadIdx.x; m < NI; m += PB) yv[m] = T[m];
-  face_update<P, PB>(T, H, tab + tab_off_D(P));
+  face_update_g<P, PB>(T, H, tab);
   __syncthreads();
   const int64_t hoff = (tau * nrhs + rhs) * NB;
   for (int r = threadIdx.x; r < NB; r += PB) {
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(PB) void k_precond_post(double2* __restrict__ y,
     yv[NI + r] = u;
   }
   __syncthreads();
-  interior_from_faces<P, PB>(U, T, tab + tab_off_D2(P));
+  interior_from_faces_g<P, PB>(U, T, tab);
   __syncthreads();
   homog_solve<P, PB>(T, tab, lam[tau]);
   for (int m = threadIdx.x; m < NI; m += PB) yv[m] = csub(yv[m], T[m]);
