@@ -232,3 +232,20 @@ def test_op_left_is_precond_of_apply(hps_mod, case, nrhs):
     for r in range(nrhs):
         want = M.apply(op.A @ X[r * op.d.N:(r + 1) * op.d.N])
         assert rel(got[r * op.d.N:(r + 1) * op.d.N], want) < 1e-12
+
+
+@pytest.mark.parametrize("p", [4, 9, 12, 16])
+def test_single_leaf_constant_medium_preconditioner_is_exact(hps_mod, p):
+    # one leaf, b = 0: the homogenized leaf matrix is the leaf matrix itself and
+    # there is no neighbour, so J^-1 A = I (Sec. 4, eq. (block_pc)); a pin of the
+    # GPU path that needs no oracle (a wrong sign on the faces breaks it)
+    prob = P.plane_wave_problem((1, 1, 1), p, 7.0)
+    ctx = hps_mod.Context.from_problem(prob)
+    x = rand_vec(ctx.N, 50 + p)
+    y = host(ctx.op_left(dev(x)))
+    assert rel(y, x) < 1e-12
+    # and with two leaves the coupling makes it differ from the identity
+    prob2 = P.plane_wave_problem((2, 1, 1), p, 7.0)
+    ctx2 = hps_mod.Context.from_problem(prob2)
+    x2 = rand_vec(ctx2.N, 60 + p)
+    assert rel(host(ctx2.op_left(dev(x2))), x2) > 1e-3
