@@ -467,8 +467,10 @@ int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, 
                        int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
                        int nbatch, int flexible, double* res_out, uint64_t tag) {
   if (J < 0 || J >= kMaxDcgs) return fail(HPS_ERR_ARG, "update beyond the restart limit");
+  // enough workgroups that a thread makes few passes (each pass waits for its
+  // loads); every workgroup recomputes the step coefficients, a few KB from L2
   const int64_t want = (n + UT - 1) / UT;
-  const int nblk = (int)std::min<int64_t>(want, 2048);
+  const int nblk = (int)std::min<int64_t>(want, 8192);
   hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, 1, nbatch), dim3(UT), 0, c->stream, V, ldv, vbs, J, u,
                      ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag, kBreakdownTol);
   return check_hip(hipGetLastError(), "k_dcgs_update");
