@@ -88,7 +88,9 @@ typedef struct {
 /* Solvers for hps_gmres. */
 #define HPS_SOLVER_GMRES 0   /* left preconditioned GMRES(m) on J^-1 A x = J^-1 b (eq. (globalsystem)), FP64 */
 #define HPS_SOLVER_FGMRES 1  /* right preconditioned flexible GMRES(m), FP64 outer; J^-1 in precond_prec */
-#define HPS_SOLVER_BLOCK 2   /* block GMRES(m) over all right-hand sides together */
+#define HPS_SOLVER_BLOCK 2   /* lock-step GMRES(m): one Krylov space per right-hand side, up to 64
+                                advanced together (J^-1 of 4 or more as a GEMM on the matrix
+                                cores); left preconditioned with FP64 blocks, flexible otherwise */
 
 typedef struct {
   int solver;          /* HPS_SOLVER_* (default GMRES) */
@@ -98,6 +100,8 @@ typedef struct {
   int check_every;     /* host convergence poll interval in iterations; 0 = 1 */
   int orth;            /* 0: delayed-reorthogonalization Gram-Schmidt (restart <= 64, else CGS2);
                           1: classical Gram-Schmidt twice (CGS2) */
+  double* rhs_rel_res; /* NULL, or host array of nrhs: on return the final relative residual of
+                          each right-hand side, in the norm its stopping test uses */
 } hps_solve_opts;
 
 typedef struct {
@@ -170,12 +174,16 @@ int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int n
 
 /* Solve A u = b(s, t) (Sec. 4, eq. (globalsystem)) by the solver in so.
  *   s, t     device, nrhs * N complex (see hps_assemble_rhs)
- *   tol      relative residual target: ||J^-1 r|| <= tol ||J^-1 b|| for
- *            HPS_SOLVER_GMRES (the paper's PCRR, Sec. 6), ||r|| <= tol ||b||
- *            for FGMRES and BLOCK (each right-hand side)
+ *   tol      relative residual target, each right-hand side: ||J^-1 r|| <=
+ *            tol ||J^-1 b|| with left preconditioning (HPS_SOLVER_GMRES, and
+ *            BLOCK with FP64 blocks: the paper's PCRR, Sec. 6), ||r|| <= tol ||b||
+ *            for the flexible solvers
  *   restart  Krylov dimension m per cycle (1..200)
  *   u        device, nrhs * N complex: the solution (initial guess if use_x0)
  *   so       NULL = defaults; st may be NULL.
+ * Uses context-owned workspaces (basis, nrhs * N complex for b; released by
+ * hps_trim).  With use_x0 a call continues from u: one call per restart cycle
+ * (max_iters = restart) is the same iteration as one long call.
  * Returns HPS_OK, HPS_NOT_CONVERGED, or an error. */
 int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
               hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st);

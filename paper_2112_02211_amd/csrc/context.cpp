@@ -387,6 +387,7 @@ void hps_free(hps_ctx* c) {
   hipFree(c->w_small.ptr);
   hipFree(c->w_batch.ptr);
   hipFree(c->w_op.ptr);
+  hipFree(c->w_b.ptr);
   if (c->h_pinned) hipHostFree(c->h_pinned);
   delete c;
 }
@@ -424,7 +425,7 @@ int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex
 int hps_trim(hps_ctx* c) {
   if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
   HPS_TRY_HIP(hipStreamSynchronize(c->stream));
-  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch, &c->w_op};
+  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch, &c->w_op, &c->w_b};
   for (Workspace* w : ws) {
     if (w->ptr) {
       HPS_TRY_HIP(hipFree(w->ptr));

@@ -73,6 +73,7 @@ struct Job {
   int nrhs;          // right-hand sides iterated in lock step
   bool flexible;     // right preconditioning with stored Z
   int prec;          // block precision index inside J^{-1}
+  double* rhs_res = nullptr;  // host, nrhs: final relative residual of each right-hand side
 };
 
 // Lock-step (F)GMRES over nb right-hand sides stored one after the other.
@@ -259,6 +260,8 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
       breakdown = false;
     }
   }
+  if (job.rhs_res)
+    for (int r = 0; r < nb; ++r) job.rhs_res[r] = bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0;
   if (st) {
     double worst_est = 0.0, worst_true = 0.0;
     for (int r = 0; r < nb; ++r) {
@@ -460,6 +463,8 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
       if (rr <= tol) done[r] = 1;
     }
   }
+  if (job.rhs_res)
+    for (int r = 0; r < nb; ++r) job.rhs_res[r] = bnorm[r] > 0 ? std::sqrt(beta2[r]) / bnorm[r] : 0.0;
   if (st) {
     double worst_est = 0.0, worst_true = 0.0;
     for (int r = 0; r < nb; ++r) {
@@ -524,10 +529,10 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
   if (o.solver < 0 || o.solver > 2) return fail(HPS_ERR_ARG, "unknown solver");
   if (o.solver == HPS_SOLVER_GMRES && prec != kFP64)
     return fail(HPS_ERR_ARG, "left GMRES runs the FP64 preconditioner; use FGMRES for reduced precision");
-  // b for every right-hand side
-  double2* bvec = nullptr;
-  int rc = dev_alloc(c, (void**)&bvec, sizeof(double2) * c->N * nrhs);
+  // b for every right-hand side, in a workspace kept between calls
+  int rc = ws_reserve(c, &c->w_b, sizeof(double2) * c->N * nrhs);
   if (rc) return rc;
+  double2* bvec = static_cast<double2*>(c->w_b.ptr);
   rc = launch_assemble_rhs(c, reinterpret_cast<const double2*>(s), reinterpret_cast<const double2*>(t),
                            bvec, nrhs);
   double2* x = reinterpret_cast<double2*>(u);
@@ -539,6 +544,7 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       hps_stats acc{};
       for (int r0 = 0; r0 < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); r0 += kMaxBatch) {
         job.nrhs = std::min(kMaxBatch, nrhs - r0);
+        job.rhs_res = o.rhs_rel_res ? o.rhs_rel_res + r0 : nullptr;
         hps_stats one{};
         const int r1 = run_solver(c, job, bvec + (size_t)r0 * c->N, x + (size_t)r0 * c->N, tol,
                                   restart, maxit, o.use_x0, check_every, o.orth, &one);
@@ -559,6 +565,7 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       job.nrhs = 1;
       hps_stats acc{};
       for (int r = 0; r < nrhs; ++r) {
+        job.rhs_res = o.rhs_rel_res ? o.rhs_rel_res + r : nullptr;
         hps_stats one{};
         const int r1 = run_solver(c, job, bvec + (size_t)r * c->N, x + (size_t)r * c->N, tol,
                                   restart, maxit, o.use_x0, check_every, o.orth, &one);
@@ -577,8 +584,6 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       if (st) *st = acc;
     }
   }
-  hipStreamSynchronize(c->stream);
-  hipFree(bvec);
-  c->dev_bytes -= sizeof(double2) * c->N * nrhs;
-  return rc;
+  const int rs = check_hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return rc != HPS_OK && rc != HPS_NOT_CONVERGED ? rc : (rs ? rs : rc);
 }

@@ -93,6 +93,7 @@ struct hps_ctx {
   hps::Workspace w_small;           // Hessenberg / Givens state
   hps::Workspace w_batch;           // many-rhs preconditioner: H and U panels
   hps::Workspace w_op;              // A x inside hps_op_left
+  hps::Workspace w_b;               // assembled right-hand sides inside hps_gmres
   void* h_pinned = nullptr;         // small pinned host buffer for scalars
   uint32_t solve_epoch = 0;         // tags the residual records of each solve
   size_t dev_bytes = 0;

@@ -53,7 +53,8 @@ class _Opts(ctypes.Structure):
 
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("max_iters", ctypes.c_int), ("use_x0", ctypes.c_int),
-                ("precond_prec", ctypes.c_int), ("check_every", ctypes.c_int), ("orth", ctypes.c_int)]
+                ("precond_prec", ctypes.c_int), ("check_every", ctypes.c_int), ("orth", ctypes.c_int),
+                ("rhs_rel_res", ctypes.POINTER(ctypes.c_double))]
 
 
 class Stats(ctypes.Structure):
@@ -295,14 +296,18 @@ class Context:
         <= 64) or "cgs2" (classical Gram-Schmidt twice, three passes)."""
         torch = _torch()
         u = torch.zeros_like(s) if u is None else u
+        nrhs = self._nrhs(s)
+        res = (ctypes.c_double * nrhs)()
         so = _SolveOpts(SOLVER[solver], int(max_iters), 1 if use_x0 else 0, PREC[precond_prec],
-                        int(check_every), ORTH[orth])
+                        int(check_every), ORTH[orth], ctypes.cast(res, ctypes.POINTER(ctypes.c_double)))
         st = Stats()
         self._sync_stream()
         rc = lib().hps_gmres(self._h, _dev(s, "s"), _dev(t, "t"), float(tol), int(restart),
-                             _dev(u, "u"), self._nrhs(s), ctypes.byref(so), ctypes.byref(st))
+                             _dev(u, "u"), nrhs, ctypes.byref(so), ctypes.byref(st))
         _check(rc, allow_nc=not raise_on_nc)
-        return u, st.as_dict(), rc == HPS_OK
+        d = st.as_dict()
+        d["rhs_rel_res"] = list(res)          # final relative residual of each right-hand side
+        return u, d, rc == HPS_OK
 
     def free(self):
         if getattr(self, "_h", None):

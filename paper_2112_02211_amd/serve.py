@@ -14,11 +14,16 @@ work as slots and HBM free up:
   make room; the queue is served oldest first, with backfill of smaller jobs
   while the oldest one waits for memory (bounded, so it cannot starve);
 * **resident operators**: the context of an operator (its dense blocks) stays
-  cached after a solve, so later requests on the same scatterer skip setup;
-* **batching**: queued requests on the same operator (same mesh, order, wave
-  number and medium; different sources) are solved together as one lock-step
-  multi-right-hand-side solve, where the preconditioner's block product is a
-  GEMM on the matrix cores.
+  cached after a job, so later requests on the same scatterer skip setup;
+* **continuous batching by ticks**: a job owns one operator (same mesh, order,
+  wave number and medium; different sources) and advances all its active
+  requests together, one restart cycle per tick, as one lock-step
+  multi-right-hand-side solve (J^-1's block product becomes a GEMM on the
+  matrix cores).  After every tick each converged request is returned and
+  leaves the batch, and queued requests on the same operator join it (as far
+  as the HBM budget allows).  Restarted GMRES starts every cycle from the
+  current iterate, so a request sees the same iteration whether it runs in
+  one call or tick by tick, alone or in a batch.
 
 Latency of a request = completion (solution copied to the host) - arrival.
 `Scheduler` is the policy and has no GPU dependency; `Server` executes it.
@@ -99,6 +104,16 @@ class Scheduler:
                 return None   # the oldest request has waited long enough: no backfill
         return None
 
+    def take(self, key: str, n: int) -> list:
+        """Up to n pending requests on operator `key` (oldest first), removed from
+        the queue: they join the running job of that operator at its next tick."""
+        if n <= 0:
+            return []
+        got = [r for r in self.pending if r.key == key][:n]
+        ids = {id(r) for r in got}
+        self.pending = [r for r in self.pending if id(r) not in ids]
+        return got
+
 
 @dataclass
 class ServeConfig:
@@ -106,10 +121,11 @@ class ServeConfig:
     hbm_fraction: float = 0.85       # of the free device memory at start
     block_prec: str = "fp64"
     precond_prec: str = "fp64"
-    restart: int = 50
+    restart: int = 50                # Krylov dimension of a cycle = one tick
     tol: float = 1e-8
     solver: str = "gmres"            # single right-hand side: "gmres" (left, FP64 J^-1) or "fgmres"
     max_batch: int = 64
+    max_iters: int = 20000           # per request; beyond it the request is returned unconverged
     keep_solution_on_host: bool = True
 
 
@@ -118,19 +134,33 @@ class Result:
     rid: int
     key: str
     arrival: float
-    start: float
+    start: float                     # the request entered a running batch
     finish: float
-    iters: int
-    batch: int
-    setup: bool
+    iters: int                       # Arnoldi steps of the ticks it took part in
+    batch: int                       # largest batch it ran in
+    setup: bool                      # its job built the operator
     converged: bool
-    true_rel_res: float
+    true_rel_res: float              # in the norm of the stopping test
     n_unknowns: int = 0
     u: Optional[np.ndarray] = None
+    job: int = 0
+    ticks: int = 0
 
     @property
     def latency(self) -> float:
         return self.finish - self.arrival
+
+
+@dataclass
+class _Active:
+    req: object
+    s: object
+    t: object
+    u: object
+    start: float
+    iters: int = 0
+    ticks: int = 0
+    batch: int = 1
 
 
 class Server:
@@ -154,6 +184,7 @@ class Server:
         self.streams = [torch.cuda.Stream() for _ in range(cfg.slots)]
         self.free_slots = list(range(cfg.slots))
         self.errors: list = []
+        self.n_jobs = 0
 
     # ---------------------------------------------------------------- sizing
     def _blocks(self):
@@ -192,11 +223,26 @@ class Server:
             ctx.free()
 
     # ------------------------------------------------------------- execution
-    def _run_job(self, slot: int, job: Job):
+    def _activate(self, r, xyz, now: float) -> _Active:
+        torch = self.torch
+        sv, tv = P.rhs_data(r.prob, xyz, 0)
+        s = torch.from_numpy(sv).to("cuda", non_blocking=False)
+        t = torch.from_numpy(tv).to("cuda", non_blocking=False)
+        return _Active(r, s, t, torch.zeros_like(s), now)
+
+    def _grow(self, job: Job, prob, n_old: int, n_new: int) -> bool:
+        """Reserve the extra solver bytes of a larger batch (lock held)."""
+        extra = max(0, self._size(job.key, prob, n_new, True) - self._size(job.key, prob, n_old, True))
+        if self._used() + extra > self.budget:
+            return False
+        self.running_bytes += extra
+        job.need_bytes += extra
+        return True
+
+    def _run_job(self, slot: int, job: Job, job_id: int):
         torch = self.torch
         cfg = self.cfg
         stream = self.streams[slot]
-        t_start = time.perf_counter()
         try:
             with torch.cuda.stream(stream):
                 prob0 = job.requests[0].prob
@@ -209,30 +255,60 @@ class Server:
                 if setup:
                     ctx = self.hps.Context.from_problem(prob0, block_precs=self._blocks())
                 xyz = ctx.nodes()
-                k = len(job.requests)
-                S = np.concatenate([P.rhs_data(r.prob, xyz, 0)[0] for r in job.requests])
-                T = np.concatenate([P.rhs_data(r.prob, xyz, 0)[1] for r in job.requests])
-                s = torch.from_numpy(S).to("cuda", non_blocking=False)
-                t = torch.from_numpy(T).to("cuda", non_blocking=False)
+                N = ctx.N
+                t_now = time.perf_counter()
+                active = [self._activate(r, xyz, t_now) for r in job.requests]
                 single = cfg.solver if cfg.precond_prec == "fp64" else "fgmres"
-                solver = "batched" if k > 1 else single
-                u, st, ok = ctx.gmres(s, t, tol=cfg.tol, restart=cfg.restart, solver=solver,
-                                      precond_prec=cfg.precond_prec)
-                uh = u.cpu().numpy() if cfg.keep_solution_on_host else None
+                while active:
+                    k = len(active)
+                    S = torch.cat([a.s for a in active]) if k > 1 else active[0].s
+                    T = torch.cat([a.t for a in active]) if k > 1 else active[0].t
+                    U = torch.cat([a.u for a in active]) if k > 1 else active[0].u
+                    solver = "batched" if k > 1 else single
+                    _, st, _ = ctx.gmres(S, T, tol=cfg.tol, restart=cfg.restart, u=U, solver=solver,
+                                         precond_prec=cfg.precond_prec, max_iters=cfg.restart,
+                                         use_x0=True)
+                    res = st["rhs_rel_res"]
+                    done, keep = [], []
+                    for i, a in enumerate(active):
+                        a.u = U[i * N:(i + 1) * N]
+                        a.iters += st["iters"]
+                        a.ticks += 1
+                        a.batch = max(a.batch, k)
+                        if res[i] <= cfg.tol or a.iters >= cfg.max_iters:
+                            done.append((a, res[i]))
+                        else:
+                            keep.append(a)
+                    if done:
+                        uh = [a.u.cpu().numpy() if cfg.keep_solution_on_host else None for a, _ in done]
+                        stream.synchronize()
+                        t_fin = time.perf_counter()
+                        with self.lock:
+                            for (a, r_i), u_i in zip(done, uh):
+                                self.results.append(Result(
+                                    a.req.rid, job.key, a.req.t_arrival, a.start, t_fin, a.iters, a.batch,
+                                    setup, bool(r_i <= cfg.tol), float(r_i), N, u_i, job_id, a.ticks))
+                    active = keep
+                    # queued requests on this operator join the batch for the next tick
+                    with self.lock:
+                        joined = []
+                        while len(active) + len(joined) < cfg.max_batch:
+                            nxt = self.sched.take(job.key, 1)
+                            if not nxt:
+                                break
+                            if not self._grow(job, prob0, len(active) + len(joined),
+                                              len(active) + len(joined) + 1):
+                                self.sched.pending.insert(0, nxt[0])   # back to the head of the queue
+                                break
+                            joined += nxt
+                    if joined:
+                        t_now = time.perf_counter()
+                        active += [self._activate(r, xyz, t_now) for r in joined]
                 stream.synchronize()
-                del s, t, u
-            t_fin = time.perf_counter()
             with self.lock:
-                if setup:
-                    self.cache[job.key] = ctx
-                    self.cache_bytes[job.key] = ctx.device_bytes()
-                else:
-                    self.cache_bytes[job.key] = ctx.device_bytes()
-                for i, r in enumerate(job.requests):
-                    self.results.append(Result(
-                        r.rid, job.key, r.t_arrival, t_start, t_fin, st["iters"], k, setup, ok,
-                        st["true_rel_res"], ctx.N,
-                        uh[i * ctx.N:(i + 1) * ctx.N].copy() if uh is not None else None))
+                self.cache[job.key] = ctx
+                self.cache.move_to_end(job.key)
+                self.cache_bytes[job.key] = ctx.device_bytes()
         except Exception as e:  # reported after the run
             with self.lock:
                 self.errors.append((job.key, repr(e)))
@@ -271,7 +347,9 @@ class Server:
                         slot = self.free_slots.pop()
                         self.busy.add(job.key)
                         self.running_bytes += job.need_bytes
-                        th = threading.Thread(target=self._run_job, args=(slot, job), daemon=True)
+                        self.n_jobs += 1
+                        th = threading.Thread(target=self._run_job, args=(slot, job, self.n_jobs),
+                                              daemon=True)
                         th.start()
                         workers.append(th)
                         started = True
@@ -303,8 +381,9 @@ def latency_stats(results: List[Result]) -> dict:
     return {"requests": len(results), "solves_per_s": len(results) / (t_last - t_first),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3), "max_batch": max(r.batch for r in results),
-            "jobs": len({(r.key, r.start) for r in results}),
-            "setups": len({(r.key, r.start) for r in results if r.setup}),
+            "jobs": len({r.job for r in results}),
+            "setups": len({r.job for r in results if r.setup}),
+            "mean_ticks": float(np.mean([r.ticks for r in results])),
             "all_converged": all(r.converged for r in results),
             "operator_applies_munknowns_per_s":
                 float(sum(r.n_unknowns * r.iters for r in results) / (t_last - t_first) / 1e6)}

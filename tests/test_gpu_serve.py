@@ -66,3 +66,51 @@ def test_admission_respects_a_small_budget():
     assert all(r.converged for r in res)
     spans = sorted((r.start, r.finish) for r in res)
     assert all(spans[i + 1][0] >= spans[i][1] - 1e-3 for i in range(len(spans) - 1))
+
+
+def test_late_request_joins_the_running_job():
+    # two requests on one operator, the second arriving 2 ms after the first,
+    # while the first job is still building the operator (setup takes far
+    # longer): it waits while the operator is busy, then joins the running job
+    # at its first tick boundary, and gets the same answer as alone
+    from paper_2112_02211_amd.serve import Server, ServeConfig
+    base = P.bump_problem("j", (3, 3, 3), 8, 24.0, 6, 2, 41, 8, 1e-10)
+    reqs = []
+    for i in range(2):
+        pr = dataclasses.replace(base, source_points=base.source_points[i:i + 1].copy())
+        reqs.append(P.Request(i, 0.0 if i == 0 else 0.002, pr))
+    cfg = ServeConfig(slots=2, tol=1e-10, restart=8)
+    srv = Server(cfg)
+    res = srv.run(_fresh(reqs))
+    srv.close()
+    a, b = sorted(res, key=lambda r: r.rid)
+    assert a.converged and b.converged
+    assert a.ticks > 2
+    assert b.job == a.job and b.batch == 2 and b.start > a.start
+    for r in (a, b):
+        srv1 = Server(ServeConfig(slots=1, tol=1e-10, restart=8))
+        alone = srv1.run(_fresh([reqs[r.rid]]), closed_loop=True)[0]
+        srv1.close()
+        assert np.linalg.norm(r.u - alone.u) / np.linalg.norm(alone.u) < 1e-8
+
+
+def test_per_rhs_residuals_are_reported():
+    from paper_2112_02211_amd import hps
+    prob = P.bump_problem("r", (2, 2, 2), 8, 14.0, 4, 5, 42, 20, 1e-10)
+    ctx = hps.Context.from_problem(prob)
+    xyz = ctx.nodes()
+    S = np.concatenate([P.rhs_data(prob, xyz, r)[0] for r in range(5)])
+    s = torch.from_numpy(S).cuda()
+    t = torch.zeros_like(s)
+    u, st, ok = ctx.gmres(s, t, tol=1e-10, restart=20, solver="batched")
+    assert ok and len(st["rhs_rel_res"]) == 5
+    assert max(st["rhs_rel_res"]) <= 1e-10 and max(st["rhs_rel_res"]) == st["true_rel_res"]
+    # one cycle at a time from the current iterate reaches the same solution
+    u2 = torch.zeros_like(s)
+    for _ in range(50):
+        _, st2, ok2 = ctx.gmres(s, t, tol=1e-10, restart=20, u=u2, solver="batched", max_iters=20,
+                                use_x0=True)
+        if ok2:
+            break
+    assert ok2
+    assert (torch.linalg.norm(u2 - u) / torch.linalg.norm(u)).item() < 1e-8

@@ -80,3 +80,14 @@ def test_request_stream_is_seeded_and_poisson():
         ppw = 2 * np.pi * e1 * p / r.prob.kappa
         assert 8.0 <= ppw <= 12.0 and e1 in (4, 8, 12, 16) and p in (8, 10)
         assert 5 <= len(r.prob.bump_centres) <= 20
+
+
+def test_take_pulls_the_oldest_requests_of_one_operator():
+    s = Scheduler(budget=10_000, size_fn=size_fn)
+    for rid, key in enumerate(["a", "b", "a", "c", "a"]):
+        s.submit(Req(rid, key, 1), now=0.0)
+    got = s.take("a", 2)
+    assert [r.rid for r in got] == [0, 2]
+    assert [r.rid for r in s.pending] == [1, 3, 4]
+    assert s.take("a", 0) == [] and [r.rid for r in s.take("a", 5)] == [4]
+    assert s.take("zzz", 3) == []
