@@ -114,3 +114,18 @@ def test_per_rhs_residuals_are_reported():
             break
     assert ok2
     assert (torch.linalg.norm(u2 - u) / torch.linalg.norm(u)).item() < 1e-8
+
+
+@pytest.mark.parametrize("solver", ["gmres", "fgmres"])
+def test_per_rhs_residual_single_solvers(solver):
+    from paper_2112_02211_amd import hps
+    prob = P.bump_problem("r1", (2, 2, 2), 8, 14.0, 4, 2, 43, 20, 1e-10)
+    ctx = hps.Context.from_problem(prob)
+    xyz = ctx.nodes()
+    S = np.concatenate([P.rhs_data(prob, xyz, r)[0] for r in range(2)])
+    s = torch.from_numpy(S).cuda()
+    t = torch.zeros_like(s)
+    u, st, ok = ctx.gmres(s, t, tol=1e-10, restart=20, solver=solver)
+    assert ok and len(st["rhs_rel_res"]) == 2
+    assert 0.0 < max(st["rhs_rel_res"]) <= 1e-10
+    assert max(st["rhs_rel_res"]) == st["true_rel_res"]
