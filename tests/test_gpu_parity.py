@@ -249,3 +249,32 @@ def test_single_leaf_constant_medium_preconditioner_is_exact(hps_mod, p):
     ctx2 = hps_mod.Context.from_problem(prob2)
     x2 = rand_vec(ctx2.N, 60 + p)
     assert rel(host(ctx2.op_left(dev(x2))), x2) > 1e-3
+
+
+@pytest.mark.parametrize("solver", ["gmres", "fgmres", "batched"])
+def test_zero_right_hand_side_returns_zero(hps_mod, solver):
+    prob = P.bump_problem("z", (2, 2, 1), 6, 8.0, 2, 1, 35, 10, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob)
+    nrhs = 4 if solver == "batched" else 1
+    s = torch.zeros(nrhs * ctx.N, dtype=torch.complex128, device="cuda")
+    u, st, ok = ctx.gmres(s, s.clone(), tol=1e-10, restart=10, solver=solver)
+    assert ok and st["iters"] == 0
+    assert torch.count_nonzero(u).item() == 0
+
+
+@pytest.mark.parametrize("solver", ["gmres", "fgmres"])
+def test_invariant_krylov_space_breakdown(hps_mod, solver):
+    # one leaf, constant medium: J^-1 A = I, so left GMRES meets an invariant
+    # (one-dimensional) Krylov space in its first step (happy breakdown); the
+    # solve must end converged with the exact solution
+    prob = P.plane_wave_problem((1, 1, 1), 8, 7.0)
+    ctx = hps_mod.Context.from_problem(prob)
+    op = O.build(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-12, restart=10, solver=solver)
+    assert ok
+    # one column suffices; its residual is known in the record of step 1 (the
+    # small step of step j finishes column j - 1), which the host reads after
+    # step 2 is queued: three steps at most
+    assert st["iters"] <= (3 if solver == "gmres" else 12)
+    assert rel(host(u), O.solve_direct(op)) < 1e-10
