@@ -251,6 +251,8 @@ def run_batched(a, prob):
         return ctx.gmres(S, T, tol=prob.tol, restart=prob.restart, u=U, solver="batched",
                          precond_prec=prec, check_every=a.check_every)
 
+    # tile shape of the block GEMM for this order, precision and batch (autotuner)
+    shape = ctx.autotune(k, prec, reps=3)
     for _ in range(a.warmup):
         step()
     ctx.set_timing(True, every=TIMING_EVERY)
@@ -311,6 +313,8 @@ def run_batched(a, prob):
         "iters_per_solve": its / a.steps, "converged": bool(ok), "true_rel_res": st["true_rel_res"],
         "err_vs_single_rhs_solves": errs, "setup_s": round(t_setup, 3),
         "precond_batched_ms": round(prec_ms, 4), "apply_ms_all_rhs": round(app_ms, 4),
+        "gemm_tile_shape": {"wavefronts": hps.GEMM_SHAPES[shape][0],
+                            "rhs_per_panel": hps.GEMM_SHAPES[shape][1], "chosen_by": "autotuner"},
         "roofline": roofline,
     }
     if not a.no_cpu_baseline:

@@ -205,6 +205,29 @@ int hps_set_timing(hps_ctx* c, int enable);
  * reset != 0 clears them. */
 int hps_kernel_times(hps_ctx* c, double out[6], int reset);
 
+/* Tile shapes of the many-right-hand-side block GEMM inside J^-1 (4 to 64
+ * right-hand sides; the batching pattern on top of Sec. 4): shape index ->
+ * (wavefronts per workgroup, right-hand sides per column panel): 0 (8, 64),
+ * 1 (8, 32), 2 (8, 16), 3 (4, 64), 4 (4, 32), 5 (4, 16).  All shapes give
+ * identical results.  The library uses the shape recorded for (p, precision,
+ * nrhs) in a process-wide table (thread-safe), else the narrowest column panel
+ * that holds all right-hand sides. */
+#define HPS_GEMM_SHAPES 6
+/* Time every shape on c's blocks of precision prec (HPS_PREC_*, built at setup)
+ * for nrhs right-hand sides (4..64), reps launches each, and record the
+ * fastest for (p, prec, nrhs); *shape_out (may be NULL) receives it.  Uses
+ * the context's panel workspace and synchronizes its stream. */
+int hps_autotune(hps_ctx* c, int nrhs, int prec, int reps, int* shape_out);
+/* Record shape for (p, prec, nrhs); shape = -1 removes the entry. */
+int hps_autotune_set(int p, int prec, int nrhs, int shape);
+/* *shape = the shape the library uses for (p, prec, nrhs). */
+int hps_autotune_get(int p, int prec, int nrhs, int* shape);
+/* Write the table as text, one "gemm p prec nrhs shape ms_per_launch" line per
+ * entry; merge such a file into the table (HPS_ERR_ARG on a malformed line,
+ * the table unchanged). */
+int hps_autotune_save(const char* path);
+int hps_autotune_load(const char* path);
+
 /* Device bytes hps_setup keeps for a mesh of n_elem leaves at order p with the
  * block precisions block_precs (tables, medium, blocks); *transient receives
  * the extra bytes setup needs while it builds the blocks (NULL allowed).

@@ -172,6 +172,18 @@ int launch_precond_fused(hps_ctx* c, const double2* y, const double2* g, double2
 // many right-hand sides: block product as a GEMM on the matrix cores
 int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
                            hipEvent_t e0, hipEvent_t e1);
+// Tile shapes of the block GEMM: index -> (wavefronts per workgroup, column
+// panel): 0 (8, 64), 1 (8, 32), 2 (8, 16), 3 (4, 64), 4 (4, 32), 5 (4, 16).
+constexpr int kGemmShapes = 6;
+// the shape used for (p, block precision index, right-hand sides): the tuned
+// one if the autotuner has recorded it, else the built-in rule
+int gemm_shape(int p, int prec, int nrhs);
+// the GEMM U = S~^{-1} H of one batched J^-1 (H, U panels as launch_precond_batched
+// lays them out)
+hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
+                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1);
+// bytes of the H and U panels of a batched J^-1 (the w_batch workspace)
+size_t batch_panel_bytes(const hps_ctx* c, int nrhs, int prec, size_t* hpad);
 constexpr int kBatchedMinRhs = 4;   // from this many right-hand sides on, J^-1 uses the GEMM path
 int launch_assemble_rhs(hps_ctx* c, const double2* s, const double2* t, double2* b, int nrhs);
 

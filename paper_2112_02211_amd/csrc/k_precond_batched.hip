@@ -119,25 +119,28 @@ __global__ __launch_bounds__(PB) void k_precond_post(double2* __restrict__ y,
 //   FP32 (CW = 2): slot g, s   <-> inner kb + 2 g + s  (two MFMA steps)
 //   BF16 (CW = 4): slot (g, e) <-> inner kb + 4 g + e  (one step, 4 values per lane)
 // H for the column panel is staged in LDS, KT inner indices at a time.
-constexpr int GW = 8;             // wavefronts per workgroup
-constexpr int GROWS = 16 * GW;    // rows per workgroup
-constexpr int GCOLS = 64;         // right-hand sides per workgroup
-constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
+// Tile shape (template): GW wavefronts per workgroup, each owning 16 rows, and a
+// column panel of GCOLS right-hand sides (GCOLS / 16 column tiles per
+// wavefront).  Every shape accumulates the inner index in the same order, so
+// the shapes give identical results; the autotuner picks among them.
 
 template <int PREC> struct GemmTraits;
 // PAD: extra columns per LDS row of the staged H.  The four k-slot groups of a
-// wavefront read rows CW apart; with 64-entry rows those rows start on the same
-// LDS bank, so the padding shifts them onto disjoint banks (BF16: 16 words
-// apart, conflict-free; FP32: 32 words, the two passes an 8-byte read needs).
+// wavefront read rows CW apart; with 16-, 32- or 64-entry rows those rows start
+// on the same LDS bank, so the padding shifts them onto disjoint banks (BF16:
+// 16 words apart, conflict-free; FP32: 32 words, the two passes an 8-byte read
+// needs).
 template <> struct GemmTraits<kFP64> { using H = double2; static constexpr int CW = 1, KT = 16, PAD = 0; };
 template <> struct GemmTraits<kFP32> { using H = float2; static constexpr int CW = 2, KT = 64, PAD = 8; };
 template <> struct GemmTraits<kBF16> { using H = uint32_t; static constexpr int CW = 4, KT = 64, PAD = 4; };
 
-template <int PREC>
+template <int PREC, int GW, int GCOLS>
 __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__ blk, int ncp,
                                                         const void* __restrict__ Hb,
                                                         void* __restrict__ Ub, int NB,
                                                         int nrhs) {
+  constexpr int GROWS = 16 * GW;    // rows per workgroup
+  constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
   using TR = GemmTraits<PREC>;
   using HT = typename TR::H;
   constexpr int CW = TR::CW, KT = TR::KT, CH = 4 * CW;  // inner indices per MFMA chunk
@@ -263,6 +266,39 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   }
 }
 
+template <int PREC, int GW, int GCOLS>
+hipError_t gemm_launch_t(hps_ctx* c, const void* blk, int ncp, const void* Hb, void* Ub, int nrhs,
+                         hipEvent_t e0, hipEvent_t e1) {
+  const dim3 g3((unsigned)c->nl, (unsigned)((c->nb + 16 * GW - 1) / (16 * GW)),
+                (unsigned)((nrhs + GCOLS - 1) / GCOLS));
+  return launch_k(c, e0, e1, k_block_gemm<PREC, GW, GCOLS>, g3, dim3(64 * GW), blk, ncp, Hb, Ub, c->nb,
+                  nrhs);
+}
+
+template <int PREC>
+hipError_t gemm_launch_p(hps_ctx* c, int shape, const void* blk, int ncp, const void* Hb, void* Ub,
+                         int nrhs, hipEvent_t e0, hipEvent_t e1) {
+  switch (shape) {
+    case 0: return gemm_launch_t<PREC, 8, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+    case 1: return gemm_launch_t<PREC, 8, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+    case 2: return gemm_launch_t<PREC, 8, 16>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+    case 3: return gemm_launch_t<PREC, 4, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+    case 4: return gemm_launch_t<PREC, 4, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+    default: return gemm_launch_t<PREC, 4, 16>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+  }
+}
+
+}  // namespace
+
+hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
+                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1) {
+  if (prec == kFP64) return gemm_launch_p<kFP64>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1);
+  if (prec == kFP32) return gemm_launch_p<kFP32>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1);
+  return gemm_launch_p<kBF16>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1);
+}
+
+namespace {
+
 template <int P>
 int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec, void* Hb,
                    void* Ub, hipEvent_t e0, hipEvent_t e1) {
@@ -287,23 +323,8 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
   const Blocks& Bk = c->blk[prec];
   TimedPair tg;
   if ((rc = timing_pair(c, 2, &tg))) return rc;
-  const dim3 g3((unsigned)c->nl, (unsigned)((c->nb + GROWS - 1) / GROWS),
-                (unsigned)((nrhs + GCOLS - 1) / GCOLS));
-  const void* blk = Bk.data;
-  switch (prec) {
-    case kFP64:
-      e = launch_k(c, tg.start, tg.stop, k_block_gemm<kFP64>, g3, dim3(64 * GW), blk, Bk.ncp,
-                   (const void*)Hb, Ub, c->nb, nrhs);
-      break;
-    case kFP32:
-      e = launch_k(c, tg.start, tg.stop, k_block_gemm<kFP32>, g3, dim3(64 * GW), blk, Bk.ncp,
-                   (const void*)Hb, Ub, c->nb, nrhs);
-      break;
-    default:
-      e = launch_k(c, tg.start, tg.stop, k_block_gemm<kBF16>, g3, dim3(64 * GW), blk, Bk.ncp,
-                   (const void*)Hb, Ub, c->nb, nrhs);
-      break;
-  }
+  e = gemm_launch(c, prec, gemm_shape(c->p, prec, nrhs), Bk.data, Bk.ncp, Hb, Ub, nrhs, tg.start,
+                  tg.stop);
   if ((rc = check_hip(e, "k_block_gemm"))) {
     timing_drop(c, tg);
     return rc;
@@ -320,13 +341,18 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
 
 }  // namespace
 
-int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
-                           hipEvent_t e0, hipEvent_t e1) {
+size_t batch_panel_bytes(const hps_ctx* c, int nrhs, int prec, size_t* hpad) {
   const size_t hel = prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4);
   const size_t hbytes = (size_t)c->nl * nrhs * c->nb * hel;
   const size_t ubytes = (size_t)c->nl * nrhs * c->nb * (prec == kFP64 ? 16 : 8);
-  const size_t hpad = (hbytes + 255) / 256 * 256;
-  int rc = ws_reserve(c, &c->w_batch, hpad + ubytes);
+  *hpad = (hbytes + 255) / 256 * 256;
+  return *hpad + ubytes;
+}
+
+int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
+                           hipEvent_t e0, hipEvent_t e1) {
+  size_t hpad = 0;
+  int rc = ws_reserve(c, &c->w_batch, batch_panel_bytes(c, nrhs, prec, &hpad));
   if (rc) return rc;
   void* Hb = c->w_batch.ptr;
   void* Ub = static_cast<char*>(c->w_batch.ptr) + hpad;

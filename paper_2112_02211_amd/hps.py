@@ -80,6 +80,13 @@ SIGNATURES = {
     "hps_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_op_left": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)]),
+    "hps_autotune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "hps_autotune_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
+    "hps_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "hps_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "hps_precond_prec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int, ctypes.c_int]),
     "hps_assemble_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -279,6 +286,14 @@ class Context:
         _check(lib().hps_op_left(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x)))
         return y
 
+    def autotune(self, nrhs: int, prec: str = "fp32", reps: int = 3) -> int:
+        """Time the block-GEMM tile shapes on this operator for nrhs right-hand
+        sides and record the fastest (process-wide); returns its index."""
+        self._sync_stream()
+        out = ctypes.c_int(-1)
+        _check(lib().hps_autotune(self._h, int(nrhs), PREC[prec], int(reps), ctypes.byref(out)))
+        return out.value
+
     def assemble_rhs(self, s, t, b=None):
         torch = _torch()
         b = torch.empty_like(s) if b is None else b
@@ -348,3 +363,25 @@ def setup_error(n_elem, p, q, kappa=10.0, lo=(0, 0, 0), hi=(1, 1, 1)):
     if rc == HPS_OK:
         L.hps_free(h)
     return rc, L.hps_last_error().decode()
+
+
+GEMM_SHAPES = [(8, 64), (8, 32), (8, 16), (4, 64), (4, 32), (4, 16)]   # (wavefronts, panel)
+
+
+def autotune_set(p: int, prec: str, nrhs: int, shape: int):
+    """Record (or with shape = -1 remove) the block-GEMM tile shape for (p, prec, nrhs)."""
+    _check(lib().hps_autotune_set(int(p), PREC[prec], int(nrhs), int(shape)))
+
+
+def autotune_get(p: int, prec: str, nrhs: int) -> int:
+    out = ctypes.c_int(-1)
+    _check(lib().hps_autotune_get(int(p), PREC[prec], int(nrhs), ctypes.byref(out)))
+    return out.value
+
+
+def autotune_save(path: str):
+    _check(lib().hps_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path: str):
+    _check(lib().hps_autotune_load(os.fsencode(path)))

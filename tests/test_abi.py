@@ -107,3 +107,27 @@ def test_setup_bytes_is_the_documented_plan(L, p, n, precs, cplx):
 def test_setup_bytes_rejects_bad_sizes(L):
     assert L.hps_setup_bytes(3, (ctypes.c_int * 3)(1, 1, 1), 1, 0, None) < 0
     assert L.hps_setup_bytes(8, (ctypes.c_int * 3)(1, 0, 1), 1, 0, None) < 0
+
+
+def test_autotune_table_round_trip(L, tmp_path):
+    # the process-wide table of block-GEMM tile shapes: set / get / rule / save / load
+    hps.autotune_set(10, "fp32", 20, 4)
+    assert hps.autotune_get(10, "fp32", 20) == 4
+    assert hps.autotune_get(10, "fp32", 21) == 1      # rule: the 32-column panel
+    assert hps.autotune_get(10, "bf16", 5) == 2       # rule: the 16-column panel
+    assert hps.autotune_get(10, "fp64", 64) == 0      # rule: the 64-column panel
+    path = tmp_path / "shapes.txt"
+    hps.autotune_save(str(path))
+    assert "gemm 10 2 20 4" in path.read_text()
+    hps.autotune_set(10, "fp32", 20, -1)
+    assert hps.autotune_get(10, "fp32", 20) == 1
+    hps.autotune_load(str(path))
+    assert hps.autotune_get(10, "fp32", 20) == 4
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gemm 10 2 20 9 0.1\n")            # shape out of range
+    with pytest.raises(hps.HPSError):
+        hps.autotune_load(str(bad))
+    assert hps.autotune_get(10, "fp32", 20) == 4      # unchanged
+    with pytest.raises(hps.HPSError):
+        hps.autotune_set(10, "fp32", 20, 6)
+    hps.autotune_set(10, "fp32", 20, -1)

@@ -124,3 +124,37 @@ def test_kernel_timing_counts_launches(hps_mod):
     assert kt["apply_launches"] == 3 and kt["precond_launches"] == 6 and kt["gemm_launches"] == 3
     assert kt["apply_ms"] > 0 and kt["precond_ms"] > kt["gemm_ms"] > 0
     assert ctx.kernel_times()["precond_launches"] == 0
+
+
+@pytest.mark.parametrize("nrhs", [4, 17, 40, 64])
+def test_gemm_tile_shapes_give_identical_results(nrhs):
+    # every tile shape accumulates the inner index in the same order: J^-1 on a
+    # ragged number of right-hand sides is bit-identical whichever shape runs
+    from paper_2112_02211_amd import hps
+    prob = P.bump_problem("sh", (2, 2, 2), 8, 12.0, 3, 1, 44, 20, 1e-10)
+    ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"))
+    rng = np.random.default_rng(nrhs)
+    X = rng.standard_normal(nrhs * ctx.N) + 1j * rng.standard_normal(nrhs * ctx.N)
+    x = torch.from_numpy(X).cuda()
+    for prec in ("fp64", "fp32", "bf16"):
+        outs = []
+        for sh in range(len(hps.GEMM_SHAPES)):
+            hps.autotune_set(prob.p, prec, nrhs, sh)
+            y = ctx.precond(x, prec=prec)
+            torch.cuda.synchronize()
+            outs.append(y.cpu().numpy())
+        hps.autotune_set(prob.p, prec, nrhs, -1)
+        for sh, o in enumerate(outs[1:], 1):
+            assert np.array_equal(o, outs[0]), (prec, sh)
+
+
+def test_autotune_picks_and_records_a_shape():
+    from paper_2112_02211_amd import hps
+    prob = P.bump_problem("at", (3, 3, 2), 8, 12.0, 3, 1, 45, 20, 1e-10)
+    ctx = hps.Context.from_problem(prob, block_precs=("fp32",))
+    sh = ctx.autotune(12, "fp32", reps=2)
+    assert 0 <= sh < len(hps.GEMM_SHAPES)
+    assert hps.autotune_get(prob.p, "fp32", 12) == sh
+    hps.autotune_set(prob.p, "fp32", 12, -1)
+    with pytest.raises(hps.HPSError):
+        ctx.autotune(12, "bf16")          # BF16 blocks were not built
