@@ -359,14 +359,29 @@ def l1_eigenvalues(d: Disc) -> np.ndarray:
     return np.linalg.eigvals(D2[1:-1, 1:-1])
 
 
-def homog_lambda(d: Disc, C_int: np.ndarray, eigs: Optional[np.ndarray] = None):
-    """lambda^tau = (max + min)/2 of diag(C_ii) (Sec. 4.1), with the resonance guard.
+def bucket_lambda(lam: complex, kappa: float, delta: float) -> complex:
+    """lambda rounded to the grid of spacing h = delta kappa^2 in its real and
+    imaginary parts: floor(x / h + 1/2) h (nearest grid point, ties upward).
+    Leaves whose rounded lambda agree share one homogenized block (the reuse of
+    one local solver for leaves with roughly the same medium suggested in the
+    remark of Sec. 4.1).  delta = 0 keeps lambda exactly (the paper's method)."""
+    if delta <= 0.0:
+        return complex(lam)
+    h = delta * kappa * kappa
+    return complex(math.floor(lam.real / h + 0.5) * h, math.floor(lam.imag / h + 0.5) * h)
+
+
+def homog_lambda(d: Disc, C_int: np.ndarray, eigs: Optional[np.ndarray] = None,
+                 delta: float = 0.0):
+    """lambda^tau = (max + min)/2 of diag(C_ii) (Sec. 4.1), rounded to the
+    lambda grid when delta > 0 (bucket_lambda), then the resonance guard.
 
     Returns (lambda, shifted_flag).
     """
     C_int = np.asarray(C_int, dtype=np.complex128)
     lam = 0.5 * (C_int.real.max() + C_int.real.min()) + \
         0.5j * (C_int.imag.max() + C_int.imag.min())
+    lam = bucket_lambda(lam, d.kappa, delta)
     if eigs is None:
         eigs = l1_eigenvalues(d)
     e = np.real(eigs)
@@ -376,9 +391,9 @@ def homog_lambda(d: Disc, C_int: np.ndarray, eigs: Optional[np.ndarray] = None):
     return lam, False
 
 
-def homog_leaf_matrix(d: Disc, C_int: np.ndarray, ops=None):
+def homog_leaf_matrix(d: Disc, C_int: np.ndarray, ops=None, delta: float = 0.0):
     """The homogenized leaf matrix: eq. (leaf) with C_ii replaced by lambda^tau I."""
-    lam, shifted = homog_lambda(d, C_int)
+    lam, shifted = homog_lambda(d, C_int, delta=delta)
     A, Gm = leaf_matrices(d, np.full(d.ni, lam), ops)
     return A, Gm, lam, shifted
 
@@ -389,17 +404,19 @@ class Precond:
     Factorizes each needed leaf with dense LU on first use.
     """
 
-    def __init__(self, d: Disc, b_nodes: np.ndarray):
+    def __init__(self, d: Disc, b_nodes: np.ndarray, lambda_bucket: float = 0.0):
         self.d = d
         self.C = c_values(d, b_nodes)
         self.ops = local_ops(d)
         self.lu = {}
         self.lams = {}
+        self.delta = float(lambda_bucket)
 
     def _factor(self, tau):
         if tau not in self.lu:
             d = self.d
-            A, _, lam, _ = homog_leaf_matrix(d, self.C[tau * d.n:tau * d.n + d.ni], self.ops)
+            A, _, lam, _ = homog_leaf_matrix(d, self.C[tau * d.n:tau * d.n + d.ni], self.ops,
+                                             delta=self.delta)
             self.lu[tau] = sla.lu_factor(A)
             self.lams[tau] = lam
         return self.lu[tau]

@@ -244,3 +244,65 @@ def test_rhs_layout():
     assert np.all(b[f2] == 0.0)
     assert np.all(b[d.ni:d.ni + n1 * n1] == 2.0)
     assert np.count_nonzero(b == 0.0) == 2 * n1 * n1
+
+
+# ---------------------------------------------------------------------------
+# lambda buckets: one homogenized block shared by leaves whose rounded lambda
+# agree (the reuse suggested in the remark of Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def test_bucketed_lambda_lies_on_the_grid_within_half_a_step():
+    rng = np.random.default_rng(7)
+    kappa, delta = 40.0, 0.01
+    h = delta * kappa ** 2
+    for _ in range(200):
+        lam = complex(rng.uniform(-3000, 3000), rng.uniform(-500, 500))
+        lt = O.bucket_lambda(lam, kappa, delta)
+        assert abs(lt.real - lam.real) <= h / 2 + 1e-9 and abs(lt.imag - lam.imag) <= h / 2 + 1e-9
+        assert abs(lt.real / h - round(lt.real / h)) < 1e-9
+        assert abs(lt.imag / h - round(lt.imag / h)) < 1e-9
+    assert O.bucket_lambda(1234.5 + 6.7j, kappa, 0.0) == 1234.5 + 6.7j
+
+
+def test_bucketing_keeps_constant_media_exact():
+    # b = 0: every leaf's lambda is kappa^2, a grid point, so the bucketed J^-1
+    # is still the exact inverse of a one-leaf constant-medium operator
+    d = O.make_disc((1, 1, 1), 8, 40.0, 40.0, hi=(0.25, 0.25, 0.25))
+    bn = np.zeros(d.N)
+    A = O.assemble_global(d, bn).toarray()
+    M = O.Precond(d, bn, lambda_bucket=0.01)
+    M._factor(0)
+    assert M.lams[0] == 40.0 ** 2
+    x = np.random.default_rng(3).standard_normal(d.N) + 0j
+    assert np.max(np.abs(M.apply(A @ x) - x)) < 1e-12 * np.max(np.abs(x))
+
+
+def test_bucketed_block_is_the_inverse_at_the_rounded_lambda():
+    prob = P.bump_problem("bk", (2, 2, 2), 8, 14.0, 4, 1, 51, 20, 1e-10)
+    op = O.build(prob)
+    d = op.d
+    M = O.Precond(d, op.b_nodes, lambda_bucket=0.02)
+    C = O.c_values(d, op.b_nodes)
+    rng = np.random.default_rng(4)
+    for tau in (0, 5):
+        lam_exact, _ = O.homog_lambda(d, C[tau * d.n:tau * d.n + d.ni])
+        lt = O.bucket_lambda(lam_exact, d.kappa, 0.02)
+        Ah, _ = O.leaf_matrices(d, np.full(d.ni, lt))
+        x = rng.standard_normal(d.n) + 1j * rng.standard_normal(d.n)
+        w = M.apply_elems(np.tile(Ah @ x, d.nl), [tau])[tau]
+        assert np.max(np.abs(w - x)) < 1e-11 * np.max(np.abs(x))
+        assert M.lams[tau] == lt
+
+
+def test_buckets_shrink_with_the_grid_and_gmres_reaches_the_same_solution():
+    prob = P.bump_problem("bk2", (3, 3, 2), 8, 20.0, 6, 1, 52, 30, 1e-10)
+    op = O.build(prob)
+    d = op.d
+    C = O.c_values(d, op.b_nodes)
+    lams = [O.homog_lambda(d, C[t * d.n:t * d.n + d.ni])[0] for t in range(d.nl)]
+    counts = [len({O.bucket_lambda(l, d.kappa, dl) for l in lams}) for dl in (1e-6, 1e-3, 1e-2, 5e-2)]
+    assert counts == sorted(counts, reverse=True) and counts[-1] < counts[0]
+    M = O.Precond(d, op.b_nodes, lambda_bucket=0.02)
+    x, its, _ = O.gmres_left(lambda v: op.A @ v, M.apply, op.rhs, tol=1e-11, restart=30)
+    ud = O.solve_direct(op)
+    assert np.linalg.norm(x - ud) / np.linalg.norm(ud) < 1e-8
