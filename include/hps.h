@@ -83,6 +83,15 @@ typedef struct {
   int block_precs;     /* OR of HPS_PREC_*; 0 means HPS_PREC_FP64 */
   void* stream;        /* hipStream_t; 0 = default stream */
   int verbose;         /* nonzero: setup timings on stderr */
+  double lambda_bucket;/* 0: one homogenized block per leaf (the paper's method, Sec. 4.1).
+                          delta > 0: each leaf's lambda is rounded to the grid of spacing
+                          delta * kappa^2 in its real and imaginary parts (floor(x / h + 1/2) h)
+                          before the resonance guard, and leaves with equal rounded lambda share
+                          one block (the reuse suggested in the remark of Sec. 4.1); J^-1 is then
+                          the exact inverse of the homogenized leaf matrix at the rounded lambda,
+                          applied as one GEMM per shared block, for any number of right-hand
+                          sides (the largest bucket times nrhs may be at most 1048560 columns,
+                          else the J^-1 calls return HPS_ERR_HIP).  See hps_num_blocks. */
 } hps_opts;
 
 /* Solvers for hps_gmres. */
@@ -140,6 +149,10 @@ int hps_nodes(const hps_ctx* c, double* xyz_host);
 /* Per-leaf homogenization constant lambda^tau (after the resonance guard);
  * lam_host receives (#leaves) complex values. */
 int hps_lambdas(const hps_ctx* c, hps_z* lam_host);
+
+/* Number of stored homogenized blocks: the number of leaves, or of distinct
+ * rounded lambdas with opts.lambda_bucket > 0; -1 for a NULL context. */
+int64_t hps_num_blocks(const hps_ctx* c);
 
 /* Set the stream used by subsequent calls (hipStream_t; 0 = default). */
 int hps_set_stream(hps_ctx* c, void* stream);
@@ -211,12 +224,15 @@ int hps_kernel_times(hps_ctx* c, double out[6], int reset);
  * 1 (8, 32), 2 (8, 16), 3 (4, 64), 4 (4, 32), 5 (4, 16).  All shapes give
  * identical results.  The library uses the shape recorded for (p, precision,
  * nrhs) in a process-wide table (thread-safe), else the narrowest column panel
- * that holds all right-hand sides. */
+ * that holds all right-hand sides.  With lambda buckets the GEMM runs per
+ * bucket and the key's nrhs is the column count of the largest bucket,
+ * min(64, largest bucket's leaves * nrhs). */
 #define HPS_GEMM_SHAPES 6
 /* Time every shape on c's blocks of precision prec (HPS_PREC_*, built at setup)
- * for nrhs right-hand sides (4..64), reps launches each, and record the
- * fastest for (p, prec, nrhs); *shape_out (may be NULL) receives it.  Uses
- * the context's panel workspace and synchronizes its stream. */
+ * for nrhs right-hand sides (4..64; 1..64 with lambda buckets), reps launches
+ * each, and record the fastest under the key above; *shape_out (may be NULL)
+ * receives it.  Uses the context's panel workspace and synchronizes its
+ * stream. */
 int hps_autotune(hps_ctx* c, int nrhs, int prec, int reps, int* shape_out);
 /* Record shape for (p, prec, nrhs); shape = -1 removes the entry. */
 int hps_autotune_set(int p, int prec, int nrhs, int shape);
@@ -232,6 +248,8 @@ int hps_autotune_load(const char* path);
  * block precisions block_precs (tables, medium, blocks); *transient receives
  * the extra bytes setup needs while it builds the blocks (NULL allowed).
  * Returns a negative error code for invalid sizes. */
+/* (With lambda buckets the blocks take at most this much: the plan counts one
+ * block per leaf.) */
 int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex_medium,
                         int64_t* transient);
 

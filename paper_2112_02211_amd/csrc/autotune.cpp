@@ -8,6 +8,7 @@
 // (p, precision, right-hand sides); the table can be saved to and loaded from a
 // text file.  Every shape accumulates in the same order, so the choice never
 // changes results.
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -61,10 +62,16 @@ int gemm_shape(int p, int prec, int nrhs) {
 using namespace hps;
 
 extern "C" int hps_autotune(hps_ctx* c, int nrhs, int prec_flag, int reps, int* shape_out) {
-  if (!c || nrhs < kBatchedMinRhs || nrhs > 64 || reps < 1)
-    return fail(HPS_ERR_ARG, "hps_autotune: needs a context, 4 <= nrhs <= 64 and reps >= 1");
+  if (!c) return fail(HPS_ERR_ARG, "hps_autotune: context is NULL");
+  // lambda buckets: one GEMM per bucket, for any number of right-hand sides,
+  // keyed by the columns of the largest bucket (at most one 64-column panel)
+  const bool bk = c->lambda_bucket > 0.0;
+  if (nrhs < (bk ? 1 : kBatchedMinRhs) || nrhs > 64 || reps < 1)
+    return fail(HPS_ERR_ARG, "hps_autotune: needs nrhs <= 64 (and >= 4 with one block per leaf), reps >= 1");
   const int q = prec_index_of(prec_flag);
   if (q < 0 || !c->blk[q].data) return fail(HPS_ERR_ARG, "hps_autotune: block precision not built");
+  const int key = bk ? std::min<int64_t>(64, (int64_t)c->max_members * nrhs) : nrhs;
+  const int* gofs = bk ? c->d_bofs : nullptr;
   size_t hpad = 0;
   int rc = ws_reserve(c, &c->w_batch, batch_panel_bytes(c, nrhs, q, &hpad));
   if (rc) return rc;
@@ -81,11 +88,13 @@ extern "C" int hps_autotune(hps_ctx* c, int nrhs, int prec_flag, int reps, int* 
   double best_ms = 0.0;
   const Blocks& B = c->blk[q];
   for (int sh = 0; sh < kGemmShapes && rc == HPS_OK; ++sh) {
-    rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr), "gemm");
+    rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr, gofs, c->nblocks,
+                                 c->max_members), "gemm");
     if (rc) break;
     rc = check_hip(hipEventRecord(e0, c->stream), "hipEventRecord");
     for (int r = 0; r < reps && rc == HPS_OK; ++r)
-      rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr), "gemm");
+      rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr, gofs, c->nblocks,
+                                 c->max_members), "gemm");
     if (rc) break;
     rc = check_hip(hipEventRecord(e1, c->stream), "hipEventRecord");
     if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -102,7 +111,7 @@ extern "C" int hps_autotune(hps_ctx* c, int nrhs, int prec_flag, int reps, int* 
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    table()[std::make_tuple(c->p, q, nrhs)] = Entry{best, best_ms};
+    table()[std::make_tuple(c->p, q, key)] = Entry{best, best_ms};
   }
   if (shape_out) *shape_out = best;
   return HPS_OK;

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "hps_internal.h"
@@ -132,6 +133,52 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Lambda buckets: leaves whose (rounded, guarded) lambda are equal share one
+// block.  Buckets are numbered in order of their first leaf; d_bpos gives each
+// leaf's position when the leaves are sorted by bucket (stable in leaf order).
+int make_buckets(hps_ctx* c) {
+  const int64_t nl = c->nl;
+  std::vector<double2> lam(nl);
+  HPS_TRY_HIP(hipMemcpyAsync(lam.data(), c->d_lambda, sizeof(double2) * nl, hipMemcpyDeviceToHost,
+                             c->stream));
+  HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+  auto less = [](const std::pair<double, double>& a, const std::pair<double, double>& b) {
+    return a.first < b.first || (a.first == b.first && a.second < b.second);
+  };
+  std::map<std::pair<double, double>, int, decltype(less)> id(less);
+  std::vector<int> bkt(nl), count;
+  std::vector<double2> blam;
+  for (int64_t t = 0; t < nl; ++t) {
+    const auto key = std::make_pair(lam[t].x, lam[t].y);
+    auto it = id.find(key);
+    if (it == id.end()) {
+      it = id.emplace(key, (int)blam.size()).first;
+      blam.push_back(lam[t]);
+      count.push_back(0);
+    }
+    bkt[t] = it->second;
+    ++count[it->second];
+  }
+  const int nbk = (int)blam.size();
+  std::vector<int> bofs(nbk + 1, 0), fill(nbk, 0), pos(nl);
+  for (int b = 0; b < nbk; ++b) bofs[b + 1] = bofs[b] + count[b];
+  for (int64_t t = 0; t < nl; ++t) pos[t] = bofs[bkt[t]] + fill[bkt[t]]++;
+  int rc;
+  if ((rc = dev_alloc(c, (void**)&c->d_bpos, sizeof(int) * nl))) return rc;
+  if ((rc = dev_alloc(c, (void**)&c->d_bofs, sizeof(int) * (nbk + 1)))) return rc;
+  if ((rc = dev_alloc(c, (void**)&c->d_blam, sizeof(double2) * nbk))) return rc;
+  HPS_TRY_HIP(hipMemcpyAsync(c->d_bpos, pos.data(), sizeof(int) * nl, hipMemcpyHostToDevice, c->stream));
+  HPS_TRY_HIP(hipMemcpyAsync(c->d_bofs, bofs.data(), sizeof(int) * (nbk + 1), hipMemcpyHostToDevice,
+                             c->stream));
+  HPS_TRY_HIP(hipMemcpyAsync(c->d_blam, blam.data(), sizeof(double2) * nbk, hipMemcpyHostToDevice,
+                             c->stream));
+  HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+  c->nblocks = nbk;
+  c->max_members = 1;
+  for (int v : count) c->max_members = std::max(c->max_members, v);
+  return HPS_OK;
+}
+
 // Inverse of every homogenized Schur complement S~^tau, packed per precision.
 int build_blocks(hps_ctx* c, int precs) {
   const int nb = c->nb;
@@ -140,7 +187,7 @@ int build_blocks(hps_ctx* c, int precs) {
     const int cw = block_cw(q);
     Blocks& B = c->blk[q];
     B.ncp = (nb + cw - 1) / cw * cw;
-    B.bytes = (size_t)c->nl * B.ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
+    B.bytes = (size_t)c->nblocks * B.ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
     int rc = dev_alloc(c, &B.data, B.bytes);
     if (rc) return rc;
   }
@@ -157,7 +204,9 @@ int build_blocks(hps_ctx* c, int precs) {
   const size_t blk_bytes = (size_t)nb * nb * sizeof(double2);
   int64_t chunk = (int64_t)((1ull << 30) / blk_bytes);
   if (chunk < 1) chunk = 1;
-  if (chunk > c->nl) chunk = c->nl;
+  if (chunk > c->nblocks) chunk = c->nblocks;
+  // one block per leaf, or per lambda bucket
+  const double2* lam = c->lambda_bucket > 0.0 ? c->d_blam : c->d_lambda;
   double2* S = nullptr;
   rocblas_int *ipiv = nullptr, *info = nullptr;
   rc = dev_alloc(c, (void**)&S, blk_bytes * chunk);
@@ -172,9 +221,9 @@ int build_blocks(hps_ctx* c, int precs) {
   rocblas_set_stream(handle, c->stream);
   std::vector<rocblas_int> hinfo(chunk);
   int status = HPS_OK;
-  for (int64_t e0 = 0; e0 < c->nl && status == HPS_OK; e0 += chunk) {
-    const int ne = (int)std::min<int64_t>(chunk, c->nl - e0);
-    status = launch_build_schur(c, dP, dQ, (int)e0, ne, S);
+  for (int64_t e0 = 0; e0 < c->nblocks && status == HPS_OK; e0 += chunk) {
+    const int ne = (int)std::min<int64_t>(chunk, c->nblocks - e0);
+    status = launch_build_schur(c, dP, dQ, lam, (int)e0, ne, S);
     if (status) break;
     auto* A = reinterpret_cast<rocblas_double_complex*>(S);
     if (rocsolver_zgetrf_strided_batched(handle, nb, nb, A, nb, (rocblas_stride)nb * nb, ipiv, nb,
@@ -186,7 +235,8 @@ int build_blocks(hps_ctx* c, int precs) {
     hipStreamSynchronize(c->stream);
     for (int i = 0; i < ne; ++i)
       if (hinfo[i] != 0) {
-        status = fail(HPS_ERR_NUMERIC, "homogenized Schur complement of leaf " +
+        status = fail(HPS_ERR_NUMERIC, std::string("homogenized Schur complement of ") +
+                                           (c->lambda_bucket > 0.0 ? "bucket " : "leaf ") +
                                            std::to_string(e0 + i) + " is singular");
         break;
       }
@@ -231,6 +281,8 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   if (q != p - 2) return fail(HPS_ERR_UNSUPPORTED, "q must equal p - 2 (face nodes are the interior Chebyshev nodes of each face)");
   if (!(kappa > 0.0) || !std::isfinite(kappa) || !std::isfinite(eta) || eta == 0.0)
     return fail(HPS_ERR_ARG, "kappa must be positive and eta nonzero");
+  if (o && (!(o->lambda_bucket >= 0.0) || !std::isfinite(o->lambda_bucket)))
+    return fail(HPS_ERR_ARG, "lambda_bucket must be a finite number >= 0");
   double hs[3];
   for (int a = 0; a < 3; ++a) {
     if (n_elem[a] < 1) return fail(HPS_ERR_ARG, "n_elem must be >= 1");
@@ -262,6 +314,8 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   c->h = hs[0];
   c->stream = o ? static_cast<hipStream_t>(o->stream) : nullptr;
   c->verbose = o ? o->verbose : 0;
+  c->lambda_bucket = o ? o->lambda_bucket : 0.0;
+  c->nblocks = c->nl;
   hipGetDevice(&c->device);
 
   auto bail = [&](int rc) {
@@ -331,6 +385,7 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   if ((rc = launch_eval_medium(c, b, d_bc, d_ba, nbump))) return bail(rc);
   if ((rc = dev_alloc(c, (void**)&c->d_lambda, sizeof(double2) * c->nl))) return bail(rc);
   if ((rc = launch_lambda(c))) return bail(rc);
+  if (c->lambda_bucket > 0.0 && (rc = make_buckets(c))) return bail(rc);
   if (d_bc) { hipFree(d_bc); c->dev_bytes -= sizeof(double) * 3 * nbump; }
   if (d_ba) { hipFree(d_ba); c->dev_bytes -= sizeof(double2) * nbump; }
   const double t1 = now();
@@ -380,6 +435,9 @@ void hps_free(hps_ctx* c) {
   hipFree(c->d_nbr);
   hipFree(c->d_C);
   hipFree(c->d_lambda);
+  hipFree(c->d_bpos);
+  hipFree(c->d_bofs);
+  hipFree(c->d_blam);
   for (auto& B : c->blk) hipFree(B.data);
   hipFree(c->w_g.ptr);
   hipFree(c->w_red.ptr);
@@ -393,6 +451,8 @@ void hps_free(hps_ctx* c) {
 }
 
 int64_t hps_num_unknowns(const hps_ctx* c) { return c ? c->N : -1; }
+
+int64_t hps_num_blocks(const hps_ctx* c) { return c ? c->nblocks : -1; }
 
 int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex_medium,
                         int64_t* transient) {

@@ -47,7 +47,10 @@ double bytes_apply(const hps_ctx* c) {
 
 double bytes_precond(const hps_ctx* c, int q) {
   const double beta = q == kFP64 ? 16.0 : (q == kFP32 ? 8.0 : 4.0);
-  return beta * c->nl * (double)c->nb * c->blk[q].ncp + 32.0 * c->N;
+  double b = beta * c->nblocks * (double)c->nb * c->blk[q].ncp + 32.0 * c->N;
+  // lambda buckets: the H and U panels go through HBM (written, then read)
+  if (c->lambda_bucket > 0.0) b += 2.0 * c->nl * (double)c->nb * (beta + (q == kFP64 ? 16.0 : 8.0));
+  return b;
 }
 
 // Algorithmic bytes of the timed apply and preconditioner launches of a solve.
@@ -56,7 +59,7 @@ double bytes_precond(const hps_ctx* c, int q) {
 // face buffer written) and J^{-1} also reads the face buffer.
 void solve_bytes_stats(const hps_ctx* c, bool flexible, int nb, int prec, hps_stats* st) {
   const double face = 16.0 * c->nl * (double)c->nb;
-  const bool fused = !flexible && nb < kBatchedMinRhs;
+  const bool fused = !flexible && nb < kBatchedMinRhs && !(c->lambda_bucket > 0.0);
   st->bytes_apply = bytes_apply(c) - (fused ? face : 0.0);
   st->bytes_precond = bytes_precond(c, prec) + (fused ? face : 0.0);
 }
@@ -506,7 +509,8 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
   bytes += (int64_t)sizeof(GmresState) * nbat + 32 * nbat;               // Hessenberg state
   bytes += (int64_t)kPartSlots * kRedBlocks * 16 * nbat;                  // reduction partials
   bytes += 16 * nbat * c->nl * c->nb;                                     // face buffer
-  if (nbat >= kBatchedMinRhs) bytes += nbat * c->nl * c->nb * (16 + 16) + 256;  // H, U panels
+  if (nbat >= kBatchedMinRhs || c->lambda_bucket > 0.0)
+    bytes += nbat * c->nl * c->nb * (16 + 16) + 256;                      // H, U panels
   bytes += 16 * c->N * nrhs;                                              // assembled b
   return bytes;
 }

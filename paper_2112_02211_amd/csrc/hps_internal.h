@@ -82,7 +82,15 @@ struct hps_ctx {
   int* d_nbr = nullptr;             // [nl][6], -1 on the boundary
   int c_complex = 0;                // C stored as complex (else real)
   void* d_C = nullptr;              // [nl][ni] kappa^2 (1 - b) at interior nodes
-  double2* d_lambda = nullptr;      // [nl]
+  double2* d_lambda = nullptr;      // [nl] lambda^tau (rounded when lambda_bucket > 0)
+  // lambda buckets (lambda_bucket > 0): leaves with equal rounded lambda share
+  // one block; buckets are numbered in order of their first leaf
+  double lambda_bucket = 0.0;
+  int64_t nblocks = 0;              // stored blocks: nl, or the number of buckets
+  int* d_bpos = nullptr;            // [nl] position of the leaf in bucket order
+  int* d_bofs = nullptr;            // [nblocks + 1] first position of each bucket
+  double2* d_blam = nullptr;        // [nblocks] the bucket's lambda
+  int max_members = 1;              // leaves in the largest bucket
   int n_shifted = 0;
   hps::Blocks blk[3];
 
@@ -130,8 +138,8 @@ int dev_alloc(hps_ctx* c, void** p, size_t bytes);
 int launch_eval_medium(hps_ctx* c, const hps_medium* b, const double* d_bump_c,
                        const double2* d_bump_a, int nbump);
 int launch_lambda(hps_ctx* c);
-int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, int e0, int ne,
-                       double2* S /* [ne][nb][nb] column major */);
+int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, const double2* lam, int e0,
+                       int ne, double2* S /* [ne][nb][nb] column major */);
 int launch_pack_blocks(hps_ctx* c, const double2* Sinv, int e0, int ne, int prec);
 int launch_node_coords(hps_ctx* c, double* d_xyz);
 
@@ -169,7 +177,8 @@ int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs,
 // J^{-1} (y + exchange(g)) for nrhs < kBatchedMinRhs; g == null: J^{-1} y
 int launch_precond_fused(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
                          int prec, hipEvent_t e0, hipEvent_t e1);
-// many right-hand sides: block product as a GEMM on the matrix cores
+// many right-hand sides: block product as a GEMM on the matrix cores; with lambda
+// buckets (any nrhs) one GEMM per bucket over all its leaves' columns
 int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
                            hipEvent_t e0, hipEvent_t e1);
 // Tile shapes of the block GEMM: index -> (wavefronts per workgroup, column
@@ -181,7 +190,8 @@ int gemm_shape(int p, int prec, int nrhs);
 // the GEMM U = S~^{-1} H of one batched J^-1 (H, U panels as launch_precond_batched
 // lays them out)
 hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
-                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1);
+                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1,
+                       const int* gofs = nullptr, int64_t ngroups = -1, int max_members = 1);
 // bytes of the H and U panels of a batched J^-1 (the w_batch workspace)
 size_t batch_panel_bytes(const hps_ctx* c, int nrhs, int prec, size_t* hpad);
 constexpr int kBatchedMinRhs = 4;   // from this many right-hand sides on, J^-1 uses the GEMM path

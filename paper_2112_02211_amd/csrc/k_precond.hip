@@ -306,6 +306,8 @@ int launch_precond_fused(hps_ctx* c, const double2* x, const double2* g, double2
                          int prec, hipEvent_t e0, hipEvent_t e1) {
   if (prec < 0 || prec > 2 || !c->blk[prec].data)
     return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
+  // the fused kernel reads block tau for leaf tau: one block per leaf only
+  if (c->nblocks != c->nl) return fail(HPS_ERR_ARG, "fused J^-1 needs one block per leaf");
   switch (c->p) {
     case 4: return precond_launch<4>(c, x, g, y, nrhs, prec, e0, e1);
     case 5: return precond_launch<5>(c, x, g, y, nrhs, prec, e0, e1);
@@ -330,7 +332,8 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
   TimedPair tp;
   int rc = timing_pair(c, 1, &tp);
   if (rc) return rc;
-  if (nrhs >= kBatchedMinRhs) rc = launch_precond_batched(c, x, y, nrhs, prec, tp.start, tp.stop);
+  if (nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0)
+    rc = launch_precond_batched(c, x, y, nrhs, prec, tp.start, tp.stop);
   else rc = launch_precond_fused(c, x, nullptr, y, nrhs, prec, tp.start, tp.stop);
   if (rc) {
     timing_drop(c, tp);
@@ -341,7 +344,7 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
 
 int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec) {
   int rc;
-  if (nrhs >= kBatchedMinRhs) {
+  if (nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0) {
     if ((rc = launch_apply(c, x, tmp, nrhs))) return rc;
     return launch_precond(c, tmp, y, nrhs, prec);
   }

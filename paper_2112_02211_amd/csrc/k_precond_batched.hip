@@ -11,6 +11,10 @@
 //
 // U is kept in FP32 for FP32 / BF16 blocks (their products accumulate in FP32).
 //
+// With lambda buckets (leaves sharing one block) the H and U panels are laid
+// out in bucket order and the GEMM runs once per bucket over the columns of
+// all its leaves: the block is read once for the whole bucket.
+//
 // The complex product is split into real matrix-core products:
 //   Re U = Re S Re H - Im S Im H,   Im U = Re S Im H + Im S Re H.
 // Precisions: FP64 blocks on v_mfma_f64_16x16x4 (FP64 accumulate), FP32 blocks
@@ -41,11 +45,13 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
 // (Algorithm 3 line-wise here: these kernels run many small workgroups per CU,
 // where LDS bandwidth, not idle threads, bounds the mode products.)
 template <int P, int PREC>
+// pos != null (lambda buckets): the leaf's panel is at its position in bucket
+// order, so that each bucket's columns are contiguous.
 __global__ __launch_bounds__(PB) void k_precond_pre(const double2* __restrict__ x,
                                                     double2* __restrict__ y, void* __restrict__ Hb,
                                                     const double2* __restrict__ lam,
                                                     const double* __restrict__ tab, int64_t N,
-                                                    int nrhs) {
+                                                    int nrhs, const int* __restrict__ pos) {
   constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
   __shared__ double2 T[NI];
   __shared__ double2 H[NB];
@@ -60,7 +66,7 @@ __global__ __launch_bounds__(PB) void k_precond_pre(const double2* __restrict__ 
   for (int m = threadIdx.x; m < NI; m += PB) yv[m] = T[m];
   face_update_g<P, PB>(T, H, tab);
   __syncthreads();
-  const int64_t hoff = (tau * nrhs + rhs) * NB;
+  const int64_t hoff = ((pos ? (int64_t)pos[tau] : tau) * nrhs + rhs) * NB;
   for (int r = threadIdx.x; r < NB; r += PB) {
     const double2 h = H[r];
     if (PREC == kFP64) {
@@ -80,14 +86,14 @@ __global__ __launch_bounds__(PB) void k_precond_post(double2* __restrict__ y,
                                                      const void* __restrict__ Ub,
                                                      const double2* __restrict__ lam,
                                                      const double* __restrict__ tab, int64_t N,
-                                                     int nrhs) {
+                                                     int nrhs, const int* __restrict__ pos) {
   constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
   __shared__ double2 T[NI];
   __shared__ double2 U[NB];
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
   double2* yv = y + rhs * N + tau * NN;
-  const int64_t uoff = (tau * nrhs + rhs) * NB;
+  const int64_t uoff = ((pos ? (int64_t)pos[tau] : tau) * nrhs + rhs) * NB;
   for (int r = threadIdx.x; r < NB; r += PB) {
     double2 u;
     if (UF) {
@@ -138,23 +144,32 @@ template <int PREC, int GW, int GCOLS>
 __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__ blk, int ncp,
                                                         const void* __restrict__ Hb,
                                                         void* __restrict__ Ub, int NB,
-                                                        int nrhs) {
+                                                        int nrhs, const int* __restrict__ gofs) {
   constexpr int GROWS = 16 * GW;    // rows per workgroup
   constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
   using TR = GemmTraits<PREC>;
   using HT = typename TR::H;
   constexpr int CW = TR::CW, KT = TR::KT, CH = 4 * CW;  // inner indices per MFMA chunk
   __shared__ HT Bs[KT][GCOLS + TR::PAD];
+  // group: a leaf (nrhs columns), or with gofs a lambda bucket, whose columns
+  // are the nrhs columns of each of its leaves, stored contiguously
   const int64_t tau = blockIdx.x;
+  int64_t cb = tau * nrhs;
+  int ncols = nrhs;
+  if (gofs) {
+    cb = (int64_t)gofs[tau] * nrhs;
+    ncols = (gofs[tau + 1] - gofs[tau]) * nrhs;
+  }
   const int r0 = blockIdx.y * GROWS;
   const int c0 = blockIdx.z * GCOLS;
+  if (c0 >= ncols) return;  // a column panel past this group's columns (whole workgroup)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int row = r0 + wv * 16 + li;
   const int rowc = row < NB ? row : NB - 1;  // clamp: loads in bounds, results discarded
   const int ncg = ncp / CW;
   const uint4* B = static_cast<const uint4*>(blk) + (size_t)tau * ncg * NB;
-  const HT* Hl = static_cast<const HT*>(Hb) + (size_t)tau * nrhs * NB;
+  const HT* Hl = static_cast<const HT*>(Hb) + (size_t)cb * NB;
 
   using Acc = typename std::conditional<PREC == kFP64, md4, mf4>::type;
   Acc are[GCT], aim[GCT];
@@ -184,7 +199,7 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
       const int col = idx / KT, kin = idx - col * KT;
       const int cc = c0 + col, kk = kt + kin;
       HT v;
-      if (cc < nrhs && kk < NB) v = Hl[(size_t)cc * NB + kk];
+      if (cc < ncols && kk < NB) v = Hl[(size_t)cc * NB + kk];
       else v = HT{};
       Bs[kin][col] = v;
     }
@@ -252,8 +267,8 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
 #pragma unroll
   for (int t = 0; t < GCT; ++t) {
     const int col = c0 + t * 16 + li;
-    if (col >= nrhs) continue;
-    const size_t uo = ((size_t)tau * nrhs + col) * NB;
+    if (col >= ncols) continue;
+    const size_t uo = ((size_t)cb + col) * NB;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = r0 + wv * 16 + (PREC == kFP64 ? g + 4 * r : 4 * g + r);
@@ -266,35 +281,44 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   }
 }
 
+struct GemmGroups {
+  const int* gofs;   // null: one group per leaf
+  int64_t ngroups;
+  int maxcols;       // columns of the widest group
+};
+
 template <int PREC, int GW, int GCOLS>
 hipError_t gemm_launch_t(hps_ctx* c, const void* blk, int ncp, const void* Hb, void* Ub, int nrhs,
-                         hipEvent_t e0, hipEvent_t e1) {
-  const dim3 g3((unsigned)c->nl, (unsigned)((c->nb + 16 * GW - 1) / (16 * GW)),
-                (unsigned)((nrhs + GCOLS - 1) / GCOLS));
+                         hipEvent_t e0, hipEvent_t e1, const GemmGroups& gg) {
+  const int64_t panels = ((int64_t)gg.maxcols + GCOLS - 1) / GCOLS;
+  if (panels > 65535) return hipErrorInvalidConfiguration;  // grid z limit: too many columns per block
+  const dim3 g3((unsigned)gg.ngroups, (unsigned)((c->nb + 16 * GW - 1) / (16 * GW)), (unsigned)panels);
   return launch_k(c, e0, e1, k_block_gemm<PREC, GW, GCOLS>, g3, dim3(64 * GW), blk, ncp, Hb, Ub, c->nb,
-                  nrhs);
+                  nrhs, gg.gofs);
 }
 
 template <int PREC>
 hipError_t gemm_launch_p(hps_ctx* c, int shape, const void* blk, int ncp, const void* Hb, void* Ub,
-                         int nrhs, hipEvent_t e0, hipEvent_t e1) {
+                         int nrhs, hipEvent_t e0, hipEvent_t e1, const GemmGroups& gg) {
   switch (shape) {
-    case 0: return gemm_launch_t<PREC, 8, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
-    case 1: return gemm_launch_t<PREC, 8, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
-    case 2: return gemm_launch_t<PREC, 8, 16>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
-    case 3: return gemm_launch_t<PREC, 4, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
-    case 4: return gemm_launch_t<PREC, 4, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
-    default: return gemm_launch_t<PREC, 4, 16>(c, blk, ncp, Hb, Ub, nrhs, e0, e1);
+    case 0: return gemm_launch_t<PREC, 8, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+    case 1: return gemm_launch_t<PREC, 8, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+    case 2: return gemm_launch_t<PREC, 8, 16>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+    case 3: return gemm_launch_t<PREC, 4, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+    case 4: return gemm_launch_t<PREC, 4, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+    default: return gemm_launch_t<PREC, 4, 16>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
   }
 }
 
 }  // namespace
 
 hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
-                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1) {
-  if (prec == kFP64) return gemm_launch_p<kFP64>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1);
-  if (prec == kFP32) return gemm_launch_p<kFP32>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1);
-  return gemm_launch_p<kBF16>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1);
+                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1, const int* gofs,
+                       int64_t ngroups, int max_members) {
+  const GemmGroups gg{gofs, gofs ? ngroups : c->nl, gofs ? max_members * nrhs : nrhs};
+  if (prec == kFP64) return gemm_launch_p<kFP64>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+  if (prec == kFP32) return gemm_launch_p<kFP32>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
+  return gemm_launch_p<kBF16>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
 }
 
 namespace {
@@ -303,19 +327,22 @@ template <int P>
 int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec, void* Hb,
                    void* Ub, hipEvent_t e0, hipEvent_t e1) {
   const dim3 g2((unsigned)c->nl, (unsigned)nrhs);
+  // with lambda buckets: panels in bucket order, one GEMM group per bucket
+  const bool bk = c->lambda_bucket > 0.0;
+  const int* pos = bk ? c->d_bpos : nullptr;
   hipError_t e;
   switch (prec) {
     case kFP64:
       e = launch_k(c, e0, nullptr, k_precond_pre<P, kFP64>, g2, dim3(PB), x, y, Hb, c->d_lambda,
-                   c->d_tab, c->N, nrhs);
+                   c->d_tab, c->N, nrhs, pos);
       break;
     case kFP32:
       e = launch_k(c, e0, nullptr, k_precond_pre<P, kFP32>, g2, dim3(PB), x, y, Hb, c->d_lambda,
-                   c->d_tab, c->N, nrhs);
+                   c->d_tab, c->N, nrhs, pos);
       break;
     default:
       e = launch_k(c, e0, nullptr, k_precond_pre<P, kBF16>, g2, dim3(PB), x, y, Hb, c->d_lambda,
-                   c->d_tab, c->N, nrhs);
+                   c->d_tab, c->N, nrhs, pos);
       break;
   }
   int rc = check_hip(e, "k_precond_pre");
@@ -323,8 +350,9 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
   const Blocks& Bk = c->blk[prec];
   TimedPair tg;
   if ((rc = timing_pair(c, 2, &tg))) return rc;
-  e = gemm_launch(c, prec, gemm_shape(c->p, prec, nrhs), Bk.data, Bk.ncp, Hb, Ub, nrhs, tg.start,
-                  tg.stop);
+  const int widest = bk ? std::min(64, c->max_members * nrhs) : nrhs;
+  e = gemm_launch(c, prec, gemm_shape(c->p, prec, widest), Bk.data, Bk.ncp, Hb, Ub, nrhs, tg.start,
+                  tg.stop, bk ? c->d_bofs : nullptr, c->nblocks, c->max_members);
   if ((rc = check_hip(e, "k_block_gemm"))) {
     timing_drop(c, tg);
     return rc;
@@ -332,10 +360,10 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
   if ((rc = timing_commit(c, 2, tg))) return rc;
   if (prec == kFP64)
     e = launch_k(c, nullptr, e1, k_precond_post<P, false>, g2, dim3(PB), y, (const void*)Ub,
-                 c->d_lambda, c->d_tab, c->N, nrhs);
+                 c->d_lambda, c->d_tab, c->N, nrhs, pos);
   else
     e = launch_k(c, nullptr, e1, k_precond_post<P, true>, g2, dim3(PB), y, (const void*)Ub,
-                 c->d_lambda, c->d_tab, c->N, nrhs);
+                 c->d_lambda, c->d_tab, c->N, nrhs, pos);
   return check_hip(e, "k_precond_post");
 }
 

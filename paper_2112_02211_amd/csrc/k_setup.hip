@@ -52,8 +52,11 @@ __global__ void k_eval_medium(int kind, const double* __restrict__ xi, int p, in
 // real and imaginary parts separately.  If -E_Delta - lambda comes within
 // 1e-3 |lambda| of zero (a Dirichlet resonance of the homogenized interior
 // operator, on which the paper is silent) lambda is moved to lambda (1 + 0.01 i).
+// delta > 0: lambda rounded to the grid of spacing delta kappa^2 (real and
+// imaginary parts, floor(x / h + 1/2) h) before the resonance guard.
 __global__ __launch_bounds__(256) void k_lambda(const void* __restrict__ Cv, int c_complex,
                                                 int ni, const double* __restrict__ Ed3,
+                                                double delta, double kappa,
                                                 double2* __restrict__ lam, int* __restrict__ shifted) {
   const int64_t tau = blockIdx.x;
   __shared__ double red[4][256];
@@ -82,8 +85,13 @@ __global__ __launch_bounds__(256) void k_lambda(const void* __restrict__ Cv, int
     }
     __syncthreads();
   }
-  const double lr = 0.5 * (red[0][0] + red[1][0]);
-  const double li = 0.5 * (red[2][0] + red[3][0]);
+  double lr = 0.5 * (red[0][0] + red[1][0]);
+  double li = 0.5 * (red[2][0] + red[3][0]);
+  if (delta > 0.0) {
+    const double h = delta * kappa * kappa;
+    lr = floor(lr / h + 0.5) * h;
+    li = floor(li / h + 0.5) * h;
+  }
   __syncthreads();
   // distance of lambda to the spectrum of -L3
   double dmin = 1e300;
@@ -247,7 +255,8 @@ int launch_lambda(hps_ctx* c) {
   int rc = dev_alloc(c, (void**)&d_sh, sizeof(int) * c->nl);
   if (rc) return rc;
   hipLaunchKernelGGL(k_lambda, dim3((unsigned)c->nl), dim3(256), 0, c->stream, c->d_C,
-                     c->c_complex, c->ni, c->d_tab + tab_off_ed3(c->p), c->d_lambda, d_sh);
+                     c->c_complex, c->ni, c->d_tab + tab_off_ed3(c->p), c->lambda_bucket, c->kappa,
+                     c->d_lambda, d_sh);
   rc = check_hip(hipGetLastError(), "k_lambda");
   if (rc) return rc;
   std::vector<int> sh(c->nl);
@@ -260,11 +269,11 @@ int launch_lambda(hps_ctx* c) {
   return HPS_OK;
 }
 
-int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, int e0, int ne,
-                       double2* S) {
+int launch_build_schur(hps_ctx* c, const double* dP, const double* dQ, const double2* lam, int e0,
+                       int ne, double2* S) {
   dim3 grid((c->nb + SB - 1) / SB, (c->nb + SB - 1) / SB, ne);
   hipLaunchKernelGGL(k_build_schur, grid, dim3(256), 0, c->stream, dP, dQ,
-                     c->d_tab + tab_off_ed3(c->p), c->d_lambda, c->d_tab + tab_off_D(c->p), c->p,
+                     c->d_tab + tab_off_ed3(c->p), lam, c->d_tab + tab_off_D(c->p), c->p,
                      c->nb, c->ni, c->eta, e0, S);
   return check_hip(hipGetLastError(), "k_build_schur");
 }

@@ -48,7 +48,8 @@ class _Medium(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("block_precs", ctypes.c_int), ("stream", ctypes.c_void_p), ("verbose", ctypes.c_int)]
+    _fields_ = [("block_precs", ctypes.c_int), ("stream", ctypes.c_void_p), ("verbose", ctypes.c_int),
+                ("lambda_bucket", ctypes.c_double)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -74,6 +75,7 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_Opts),
                                  ctypes.POINTER(ctypes.c_void_p)]),
     "hps_num_unknowns": (ctypes.c_int64, [ctypes.c_void_p]),
+    "hps_num_blocks": (ctypes.c_int64, [ctypes.c_void_p]),
     "hps_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "hps_lambdas": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Z)]),
     "hps_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -156,7 +158,10 @@ class Context:
     def __init__(self, n_elem: Sequence[int], p: int, kappa: float, eta: Optional[float] = None,
                  lo=(0.0, 0.0, 0.0), hi=None, bump_centres=None, bump_amps=None,
                  bump_width: float = 0.08, nodal_b=None, block_precs=("fp64",),
-                 q: Optional[int] = None, verbose: bool = False):
+                 q: Optional[int] = None, verbose: bool = False, lambda_bucket: float = 0.0):
+        """lambda_bucket = delta > 0 rounds each leaf's homogenized lambda to a
+        grid of spacing delta kappa^2 and builds one block per distinct rounded
+        value (leaves that share it share the block); 0 builds one per leaf."""
         L = lib()
         self.n_elem = tuple(int(e) for e in n_elem)
         self.p = int(p)
@@ -188,7 +193,8 @@ class Context:
         for name in block_precs:
             bits |= PREC[name]
         self.block_precs = tuple(block_precs)
-        opts = _Opts(bits, _stream_ptr(), 1 if verbose else 0)
+        self.lambda_bucket = float(lambda_bucket)
+        opts = _Opts(bits, _stream_ptr(), 1 if verbose else 0, self.lambda_bucket)
         ne = (ctypes.c_int * 3)(*self.n_elem)
         handle = ctypes.c_void_p()
         qq = self.p - 2 if q is None else int(q)
@@ -200,16 +206,19 @@ class Context:
         self.ni, self.nb = n1 ** 3, 6 * n1 * n1
         self.n = self.ni + self.nb
         self.nl = int(np.prod(self.n_elem))
+        self.n_blocks = int(L.hps_num_blocks(handle))
 
     @classmethod
-    def from_problem(cls, prob, block_precs=("fp64",), verbose=False) -> "Context":
+    def from_problem(cls, prob, block_precs=("fp64",), verbose=False,
+                     lambda_bucket: float = 0.0) -> "Context":
         """Context for a problems.Problem (bump medium, or b = 0 for plane waves)."""
         if prob.plane_dir is not None or len(prob.bump_centres) == 0:
             return cls(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi,
-                       block_precs=block_precs, verbose=verbose)
+                       block_precs=block_precs, verbose=verbose, lambda_bucket=lambda_bucket)
         return cls(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi,
                    bump_centres=prob.bump_centres, bump_amps=prob.bump_amps,
-                   bump_width=prob.bump_width, block_precs=block_precs, verbose=verbose)
+                   bump_width=prob.bump_width, block_precs=block_precs, verbose=verbose,
+                   lambda_bucket=lambda_bucket)
 
     # ------------------------------------------------------------------ info
     def _sync_stream(self):

@@ -66,12 +66,12 @@ def test_null_arguments_are_rejected_without_a_device(L):
     L.hps_free(None)   # a no-op
 
 
-def _setup(L, p=8, q=None, n=(2, 2, 2), kappa=10.0, eta=10.0, lo=(0, 0, 0), hi=(1, 1, 1)):
+def _setup(L, p=8, q=None, n=(2, 2, 2), kappa=10.0, eta=10.0, lo=(0, 0, 0), hi=(1, 1, 1), opts=None):
     d = hps._Domain((ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi))
     ne = (ctypes.c_int * 3)(*n)
     out = ctypes.c_void_p()
-    rc = L.hps_setup(ctypes.byref(d), kappa, eta, None, p, p - 2 if q is None else q, ne, None,
-                     ctypes.byref(out))
+    rc = L.hps_setup(ctypes.byref(d), kappa, eta, None, p, p - 2 if q is None else q, ne,
+                     None if opts is None else ctypes.byref(opts), ctypes.byref(out))
     return rc, out
 
 
@@ -83,6 +83,10 @@ def test_setup_argument_checks_run_before_any_device_call(L):
     assert _setup(L, kappa=-1.0)[0] == hps.HPS_ERR_ARG
     assert _setup(L, hi=(1, 1, 0))[0] == hps.HPS_ERR_ARG
     assert _setup(L, n=(2, 2, 2), hi=(1, 1, 2))[0] == hps.HPS_ERR_ARG and "cubes" in _err(L)
+    for bad in (-0.1, float("nan"), float("inf")):
+        rc, out = _setup(L, opts=hps._Opts(1, None, 0, bad))
+        assert rc == hps.HPS_ERR_ARG and "lambda_bucket" in _err(L) and not out.value
+    assert L.hps_num_blocks(None) == -1
 
 
 @pytest.mark.parametrize("p,n,precs,cplx", [(10, (8, 8, 8), 1, 0), (10, (8, 8, 8), 7, 0),
