@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 MIXED_TOL = 1e-10
 TIMING_EVERY = 8     # launches per timed launch inside the timed region
+BUCKET_DELTAS = (1e-3, 1e-2)   # lambda grid spacings (times kappa^2) of the bucketed runs
 METRIC = "HPS operator applies/s (Munknowns/s) + time-to-1e-8 solve; served p50/p99"
 
 
@@ -206,6 +207,37 @@ def main():
                      "true_rel_res": st2["true_rel_res"],
                      "err_vs_oracle": oracle_check(a.workload, uu.cpu().numpy())}
 
+    # NEXT row: lambda buckets (leaves whose homogenized lambda round to the same
+    # grid point share one block; J^-1 becomes one GEMM per shared block).  The
+    # same system and tolerance; reported beside the main line, not as its value.
+    buckets = {}
+    for delta in BUCKET_DELTAS:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bctx = hps.Context.from_problem(prob, lambda_bucket=delta)
+        torch.cuda.synchronize()
+        b_setup = time.perf_counter() - t1
+        ub = torch.zeros_like(s)
+        bctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=ub, check_every=a.check_every)
+        ub.zero_()
+        bctx.set_timing(True, every=TIMING_EVERY)
+        bctx.kernel_times(reset=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, stb, okb = bctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=ub,
+                                 check_every=a.check_every)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ktb = bctx.kernel_times(reset=True)
+        bctx.set_timing(False)
+        buckets[f"delta_{delta:g}"] = {
+            "blocks": bctx.n_blocks, "leaves": bctx.nl, "setup_s": round(b_setup, 3),
+            "device_bytes": bctx.device_bytes(), "solve_ms": round(dt * 1e3, 2),
+            "iters": stb["iters"], "converged": bool(okb), "true_rel_res": stb["true_rel_res"],
+            "precond_avg_launch_ms": round(ktb["precond_ms"] / max(1, ktb["precond_launches"]), 5),
+            "err_vs_oracle": oracle_check(a.workload, ub.cpu().numpy())}
+        del bctx
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Munknowns/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(elapsed / a.steps * 1e3, 3),
@@ -221,6 +253,7 @@ def main():
                          "munknowns_per_s": round(N / (app_ms * 1e-3) / 1e6, 1),
                          "algorithmic_GBs": round(st["bytes_apply"] / (app_ms * 1e-3) / 1e9, 1)},
         "mixed_precision_fgmres": mixed,
+        "lambda_buckets": buckets,
         "roofline": roofline,
     }
     if not a.no_cpu_baseline:
@@ -301,6 +334,37 @@ def run_batched(a, prob):
                              tol=1e-10, restart=30, solver="fgmres", precond_prec=prec)
         ur = U[r * N:(r + 1) * N]
         errs.append(float(torch.linalg.norm(ur - u1) / torch.linalg.norm(u1)))
+    # NEXT row: lambda buckets (leaves whose homogenized lambda round to the same
+    # grid point share one block; J^-1 becomes one GEMM per shared block).  The
+    # same system and tolerance; reported beside the main line, not as its value.
+    buckets = {}
+    for delta in BUCKET_DELTAS:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bctx = hps.Context.from_problem(prob, lambda_bucket=delta)
+        torch.cuda.synchronize()
+        b_setup = time.perf_counter() - t1
+        ub = torch.zeros_like(s)
+        bctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=ub, check_every=a.check_every)
+        ub.zero_()
+        bctx.set_timing(True, every=TIMING_EVERY)
+        bctx.kernel_times(reset=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, stb, okb = bctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=ub,
+                                 check_every=a.check_every)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ktb = bctx.kernel_times(reset=True)
+        bctx.set_timing(False)
+        buckets[f"delta_{delta:g}"] = {
+            "blocks": bctx.n_blocks, "leaves": bctx.nl, "setup_s": round(b_setup, 3),
+            "device_bytes": bctx.device_bytes(), "solve_ms": round(dt * 1e3, 2),
+            "iters": stb["iters"], "converged": bool(okb), "true_rel_res": stb["true_rel_res"],
+            "precond_avg_launch_ms": round(ktb["precond_ms"] / max(1, ktb["precond_launches"]), 5),
+            "err_vs_oracle": oracle_check(a.workload, ub.cpu().numpy())}
+        del bctx
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Munknowns/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(elapsed / a.steps * 1e3, 3),

@@ -89,9 +89,9 @@ typedef struct {
                           before the resonance guard, and leaves with equal rounded lambda share
                           one block (the reuse suggested in the remark of Sec. 4.1); J^-1 is then
                           the exact inverse of the homogenized leaf matrix at the rounded lambda,
-                          applied as one GEMM per shared block, for any number of right-hand
-                          sides (the largest bucket times nrhs may be at most 1048560 columns,
-                          else the J^-1 calls return HPS_ERR_HIP).  See hps_num_blocks. */
+                          applied by GEMMs over runs of up to 16 leaves sharing a block, for
+                          any number of right-hand sides up to 65535 (more: the J^-1 calls
+                          return HPS_ERR_HIP).  See hps_num_blocks. */
 } hps_opts;
 
 /* Solvers for hps_gmres. */
@@ -224,9 +224,9 @@ int hps_kernel_times(hps_ctx* c, double out[6], int reset);
  * 1 (8, 32), 2 (8, 16), 3 (4, 64), 4 (4, 32), 5 (4, 16).  All shapes give
  * identical results.  The library uses the shape recorded for (p, precision,
  * nrhs) in a process-wide table (thread-safe), else the narrowest column panel
- * that holds all right-hand sides.  With lambda buckets the GEMM runs per
- * bucket and the key's nrhs is the column count of the largest bucket,
- * min(64, largest bucket's leaves * nrhs). */
+ * that holds all right-hand sides.  With lambda buckets the GEMM runs over
+ * runs of up to 16 leaves of one bucket, and the key's nrhs is the column
+ * count of the widest run, min(64, its leaves * nrhs). */
 #define HPS_GEMM_SHAPES 6
 /* Time every shape on c's blocks of precision prec (HPS_PREC_*, built at setup)
  * for nrhs right-hand sides (4..64; 1..64 with lambda buckets), reps launches

@@ -46,15 +46,16 @@ int prec_index_of(int flag) {
 
 int prec_flag_of(int q) { return q == kFP64 ? HPS_PREC_FP64 : (q == kFP32 ? HPS_PREC_FP32 : HPS_PREC_BF16); }
 
-// built-in rule: the narrowest column panel that holds every right-hand side
-int rule_shape(int nrhs) { return nrhs <= 16 ? 2 : (nrhs <= 32 ? 1 : 0); }
+// built-in rule: the narrowest column panel that holds every column (8
+// wavefronts per workgroup: measured no slower than 4 on small launches)
+int rule_shape(int ncols) { return ncols <= 16 ? 2 : (ncols <= 32 ? 1 : 0); }
 
 }  // namespace
 
-int gemm_shape(int p, int prec, int nrhs) {
+int gemm_shape(int p, int prec, int ncols) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = table().find(std::make_tuple(p, prec, nrhs));
-  return it != table().end() ? it->second.shape : rule_shape(nrhs);
+  auto it = table().find(std::make_tuple(p, prec, ncols));
+  return it != table().end() ? it->second.shape : rule_shape(ncols);
 }
 
 }  // namespace hps
@@ -70,8 +71,8 @@ extern "C" int hps_autotune(hps_ctx* c, int nrhs, int prec_flag, int reps, int* 
     return fail(HPS_ERR_ARG, "hps_autotune: needs nrhs <= 64 (and >= 4 with one block per leaf), reps >= 1");
   const int q = prec_index_of(prec_flag);
   if (q < 0 || !c->blk[q].data) return fail(HPS_ERR_ARG, "hps_autotune: block precision not built");
-  const int key = bk ? std::min<int64_t>(64, (int64_t)c->max_members * nrhs) : nrhs;
-  const int* gofs = bk ? c->d_bofs : nullptr;
+  const int key = bk ? std::min<int64_t>(64, (int64_t)c->group_leaves * nrhs) : nrhs;
+  const GemmGroups gg{c->d_gofs, c->d_gblk, c->ngroups, c->group_leaves};
   size_t hpad = 0;
   int rc = ws_reserve(c, &c->w_batch, batch_panel_bytes(c, nrhs, q, &hpad));
   if (rc) return rc;
@@ -88,13 +89,13 @@ extern "C" int hps_autotune(hps_ctx* c, int nrhs, int prec_flag, int reps, int* 
   double best_ms = 0.0;
   const Blocks& B = c->blk[q];
   for (int sh = 0; sh < kGemmShapes && rc == HPS_OK; ++sh) {
-    rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr, gofs, c->nblocks,
-                                 c->max_members), "gemm");
+    rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr,
+                                 bk ? &gg : nullptr), "gemm");
     if (rc) break;
     rc = check_hip(hipEventRecord(e0, c->stream), "hipEventRecord");
     for (int r = 0; r < reps && rc == HPS_OK; ++r)
-      rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr, gofs, c->nblocks,
-                                 c->max_members), "gemm");
+      rc = check_hip(gemm_launch(c, q, sh, B.data, B.ncp, Hb, Ub, nrhs, nullptr, nullptr,
+                                 bk ? &gg : nullptr), "gemm");
     if (rc) break;
     rc = check_hip(hipEventRecord(e1, c->stream), "hipEventRecord");
     if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");

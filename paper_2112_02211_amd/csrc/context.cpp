@@ -163,19 +163,32 @@ int make_buckets(hps_ctx* c) {
   std::vector<int> bofs(nbk + 1, 0), fill(nbk, 0), pos(nl);
   for (int b = 0; b < nbk; ++b) bofs[b + 1] = bofs[b] + count[b];
   for (int64_t t = 0; t < nl; ++t) pos[t] = bofs[bkt[t]] + fill[bkt[t]]++;
+  // GEMM groups: each bucket's positions in runs of at most kGroupLeaves
+  std::vector<int> gofs(1, 0), gblk;
+  int group_leaves = 1;
+  for (int b = 0; b < nbk; ++b)
+    for (int s = bofs[b]; s < bofs[b + 1]; s += kGroupLeaves) {
+      const int e = std::min(bofs[b + 1], s + kGroupLeaves);
+      gofs.push_back(e);
+      gblk.push_back(b);
+      group_leaves = std::max(group_leaves, e - s);
+    }
+  const int ng = (int)gblk.size();
   int rc;
   if ((rc = dev_alloc(c, (void**)&c->d_bpos, sizeof(int) * nl))) return rc;
-  if ((rc = dev_alloc(c, (void**)&c->d_bofs, sizeof(int) * (nbk + 1)))) return rc;
   if ((rc = dev_alloc(c, (void**)&c->d_blam, sizeof(double2) * nbk))) return rc;
+  if ((rc = dev_alloc(c, (void**)&c->d_gofs, sizeof(int) * (ng + 1)))) return rc;
+  if ((rc = dev_alloc(c, (void**)&c->d_gblk, sizeof(int) * ng))) return rc;
   HPS_TRY_HIP(hipMemcpyAsync(c->d_bpos, pos.data(), sizeof(int) * nl, hipMemcpyHostToDevice, c->stream));
-  HPS_TRY_HIP(hipMemcpyAsync(c->d_bofs, bofs.data(), sizeof(int) * (nbk + 1), hipMemcpyHostToDevice,
-                             c->stream));
   HPS_TRY_HIP(hipMemcpyAsync(c->d_blam, blam.data(), sizeof(double2) * nbk, hipMemcpyHostToDevice,
                              c->stream));
+  HPS_TRY_HIP(hipMemcpyAsync(c->d_gofs, gofs.data(), sizeof(int) * (ng + 1), hipMemcpyHostToDevice,
+                             c->stream));
+  HPS_TRY_HIP(hipMemcpyAsync(c->d_gblk, gblk.data(), sizeof(int) * ng, hipMemcpyHostToDevice, c->stream));
   HPS_TRY_HIP(hipStreamSynchronize(c->stream));
   c->nblocks = nbk;
-  c->max_members = 1;
-  for (int v : count) c->max_members = std::max(c->max_members, v);
+  c->ngroups = ng;
+  c->group_leaves = group_leaves;
   return HPS_OK;
 }
 
@@ -436,7 +449,8 @@ void hps_free(hps_ctx* c) {
   hipFree(c->d_C);
   hipFree(c->d_lambda);
   hipFree(c->d_bpos);
-  hipFree(c->d_bofs);
+  hipFree(c->d_gofs);
+  hipFree(c->d_gblk);
   hipFree(c->d_blam);
   for (auto& B : c->blk) hipFree(B.data);
   hipFree(c->w_g.ptr);

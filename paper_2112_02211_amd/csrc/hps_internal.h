@@ -88,9 +88,14 @@ struct hps_ctx {
   double lambda_bucket = 0.0;
   int64_t nblocks = 0;              // stored blocks: nl, or the number of buckets
   int* d_bpos = nullptr;            // [nl] position of the leaf in bucket order
-  int* d_bofs = nullptr;            // [nblocks + 1] first position of each bucket
   double2* d_blam = nullptr;        // [nblocks] the bucket's lambda
-  int max_members = 1;              // leaves in the largest bucket
+  // J^-1 GEMM groups: each bucket split into runs of at most kGroupLeaves
+  // consecutive positions, so that one large bucket (the background medium)
+  // spreads over many workgroups
+  int64_t ngroups = 0;
+  int* d_gofs = nullptr;            // [ngroups + 1] first position of each group
+  int* d_gblk = nullptr;            // [ngroups] block (bucket) of each group
+  int group_leaves = 1;             // leaves in the largest group
   int n_shifted = 0;
   hps::Blocks blk[3];
 
@@ -184,14 +189,25 @@ int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, i
 // Tile shapes of the block GEMM: index -> (wavefronts per workgroup, column
 // panel): 0 (8, 64), 1 (8, 32), 2 (8, 16), 3 (4, 64), 4 (4, 32), 5 (4, 16).
 constexpr int kGemmShapes = 6;
-// the shape used for (p, block precision index, right-hand sides): the tuned
-// one if the autotuner has recorded it, else the built-in rule
-int gemm_shape(int p, int prec, int nrhs);
+// the shape used for (p, block precision index, columns of the widest GEMM
+// group): the tuned one if the autotuner has recorded it, else the built-in
+// rule (the narrowest column panel that holds the columns)
+int gemm_shape(int p, int prec, int ncols);
+// leaves per GEMM group with lambda buckets
+constexpr int kGroupLeaves = 16;
+// GEMM groups: group g multiplies block gblk[g] (g if null) with the columns of
+// positions gofs[g] .. gofs[g+1]-1 (nrhs columns each) of the H panel
+struct GemmGroups {
+  const int* gofs;
+  const int* gblk;
+  int64_t ngroups;
+  int max_leaves;   // positions in the largest group
+};
 // the GEMM U = S~^{-1} H of one batched J^-1 (H, U panels as launch_precond_batched
 // lays them out)
 hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
                        void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1,
-                       const int* gofs = nullptr, int64_t ngroups = -1, int max_members = 1);
+                       const GemmGroups* gg = nullptr);
 // bytes of the H and U panels of a batched J^-1 (the w_batch workspace)
 size_t batch_panel_bytes(const hps_ctx* c, int nrhs, int prec, size_t* hpad);
 constexpr int kBatchedMinRhs = 4;   // from this many right-hand sides on, J^-1 uses the GEMM path

@@ -136,7 +136,7 @@ template <int PREC> struct GemmTraits;
 // on the same LDS bank, so the padding shifts them onto disjoint banks (BF16:
 // 16 words apart, conflict-free; FP32: 32 words, the two passes an 8-byte read
 // needs).
-template <> struct GemmTraits<kFP64> { using H = double2; static constexpr int CW = 1, KT = 16, PAD = 0; };
+template <> struct GemmTraits<kFP64> { using H = double2; static constexpr int CW = 1, KT = 32, PAD = 0; };
 template <> struct GemmTraits<kFP32> { using H = float2; static constexpr int CW = 2, KT = 64, PAD = 8; };
 template <> struct GemmTraits<kBF16> { using H = uint32_t; static constexpr int CW = 4, KT = 64, PAD = 4; };
 
@@ -144,21 +144,25 @@ template <int PREC, int GW, int GCOLS>
 __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__ blk, int ncp,
                                                         const void* __restrict__ Hb,
                                                         void* __restrict__ Ub, int NB,
-                                                        int nrhs, const int* __restrict__ gofs) {
+                                                        int nrhs, const int* __restrict__ gofs,
+                                                        const int* __restrict__ gblk) {
   constexpr int GROWS = 16 * GW;    // rows per workgroup
   constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
   using TR = GemmTraits<PREC>;
   using HT = typename TR::H;
   constexpr int CW = TR::CW, KT = TR::KT, CH = 4 * CW;  // inner indices per MFMA chunk
   __shared__ HT Bs[KT][GCOLS + TR::PAD];
-  // group: a leaf (nrhs columns), or with gofs a lambda bucket, whose columns
-  // are the nrhs columns of each of its leaves, stored contiguously
-  const int64_t tau = blockIdx.x;
-  int64_t cb = tau * nrhs;
+  // group: a leaf (nrhs columns), or with gofs a run of leaves of one lambda
+  // bucket, whose columns are the nrhs columns of each leaf, stored
+  // contiguously, and whose block is gblk[group]
+  const int64_t grp = blockIdx.x;
+  int64_t cb = grp * nrhs;
   int ncols = nrhs;
+  int64_t tau = grp;   // block index
   if (gofs) {
-    cb = (int64_t)gofs[tau] * nrhs;
-    ncols = (gofs[tau + 1] - gofs[tau]) * nrhs;
+    cb = (int64_t)gofs[grp] * nrhs;
+    ncols = (gofs[grp + 1] - gofs[grp]) * nrhs;
+    tau = gblk[grp];
   }
   const int r0 = blockIdx.y * GROWS;
   const int c0 = blockIdx.z * GCOLS;
@@ -180,8 +184,9 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   }
 
   // Block fragments of one stage (KT inner indices), software pipelined: the
-  // loads of stage kt + KT are issued before the products of stage kt, so one
-  // stage of HBM latency is hidden behind the matrix-core work.
+  // loads of stage kt + KT (block and H) are issued before the products of
+  // stage kt, so one stage of memory latency is hidden behind the matrix-core
+  // work.
   constexpr int NCH = KT / CH;
   auto load_stage = [&](int kt, uint4* dst) {
 #pragma unroll
@@ -190,21 +195,33 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
       dst[c] = (kt < NB && cg < ncg) ? ld_nt(B + (size_t)cg * NB + rowc) : make_uint4(0, 0, 0, 0);
     }
   };
-  uint4 a16[NCH], nx16[NCH];
-  load_stage(0, a16);
-  for (int kt = 0; kt < NB; kt += KT) {
-    __syncthreads();
-    // stage H[c0 .. c0+63][kt .. kt+KT-1] as Bs[inner][col]
-    for (int idx = threadIdx.x; idx < KT * GCOLS; idx += 64 * GW) {
+  // H[c0 .. c0+GCOLS-1][kt .. kt+KT-1] of one stage, HR entries per thread,
+  // also loaded one stage ahead into registers, then stored as Bs[inner][col]
+  constexpr int HN = KT * GCOLS, HR = (HN + 64 * GW - 1) / (64 * GW);
+  auto load_h = [&](int kt, HT* dst) {
+#pragma unroll
+    for (int i = 0; i < HR; ++i) {
+      const int idx = threadIdx.x + i * 64 * GW;
       const int col = idx / KT, kin = idx - col * KT;
       const int cc = c0 + col, kk = kt + kin;
-      HT v;
-      if (cc < ncols && kk < NB) v = Hl[(size_t)cc * NB + kk];
-      else v = HT{};
-      Bs[kin][col] = v;
+      dst[i] = (idx < HN && cc < ncols && kk < NB) ? Hl[(size_t)cc * NB + kk] : HT{};
+    }
+  };
+  uint4 a16[NCH], nx16[NCH];
+  HT hr[HR];
+  load_stage(0, a16);
+  load_h(0, hr);
+  for (int kt = 0; kt < NB; kt += KT) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < HR; ++i) {
+      const int idx = threadIdx.x + i * 64 * GW;
+      const int col = idx / KT, kin = idx - col * KT;
+      if (idx < HN) Bs[kin][col] = hr[i];
     }
     __syncthreads();
     load_stage(kt + KT, nx16);
+    load_h(kt + KT, hr);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const int kin0 = c * CH + CW * g;  // first inner index (within the stage) of this lane
@@ -281,25 +298,26 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   }
 }
 
-struct GemmGroups {
+struct GemmGrid {
   const int* gofs;   // null: one group per leaf
+  const int* gblk;
   int64_t ngroups;
   int maxcols;       // columns of the widest group
 };
 
 template <int PREC, int GW, int GCOLS>
 hipError_t gemm_launch_t(hps_ctx* c, const void* blk, int ncp, const void* Hb, void* Ub, int nrhs,
-                         hipEvent_t e0, hipEvent_t e1, const GemmGroups& gg) {
+                         hipEvent_t e0, hipEvent_t e1, const GemmGrid& gg) {
   const int64_t panels = ((int64_t)gg.maxcols + GCOLS - 1) / GCOLS;
   if (panels > 65535) return hipErrorInvalidConfiguration;  // grid z limit: too many columns per block
   const dim3 g3((unsigned)gg.ngroups, (unsigned)((c->nb + 16 * GW - 1) / (16 * GW)), (unsigned)panels);
   return launch_k(c, e0, e1, k_block_gemm<PREC, GW, GCOLS>, g3, dim3(64 * GW), blk, ncp, Hb, Ub, c->nb,
-                  nrhs, gg.gofs);
+                  nrhs, gg.gofs, gg.gblk);
 }
 
 template <int PREC>
 hipError_t gemm_launch_p(hps_ctx* c, int shape, const void* blk, int ncp, const void* Hb, void* Ub,
-                         int nrhs, hipEvent_t e0, hipEvent_t e1, const GemmGroups& gg) {
+                         int nrhs, hipEvent_t e0, hipEvent_t e1, const GemmGrid& gg) {
   switch (shape) {
     case 0: return gemm_launch_t<PREC, 8, 64>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
     case 1: return gemm_launch_t<PREC, 8, 32>(c, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
@@ -313,9 +331,9 @@ hipError_t gemm_launch_p(hps_ctx* c, int shape, const void* blk, int ncp, const 
 }  // namespace
 
 hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
-                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1, const int* gofs,
-                       int64_t ngroups, int max_members) {
-  const GemmGroups gg{gofs, gofs ? ngroups : c->nl, gofs ? max_members * nrhs : nrhs};
+                       void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1, const GemmGroups* grp) {
+  const GemmGrid gg = grp ? GemmGrid{grp->gofs, grp->gblk, grp->ngroups, grp->max_leaves * nrhs}
+                          : GemmGrid{nullptr, nullptr, c->nl, nrhs};
   if (prec == kFP64) return gemm_launch_p<kFP64>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
   if (prec == kFP32) return gemm_launch_p<kFP32>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
   return gemm_launch_p<kBF16>(c, shape, blk, ncp, Hb, Ub, nrhs, e0, e1, gg);
@@ -350,9 +368,10 @@ int batched_launch(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,
   const Blocks& Bk = c->blk[prec];
   TimedPair tg;
   if ((rc = timing_pair(c, 2, &tg))) return rc;
-  const int widest = bk ? std::min(64, c->max_members * nrhs) : nrhs;
-  e = gemm_launch(c, prec, gemm_shape(c->p, prec, widest), Bk.data, Bk.ncp, Hb, Ub, nrhs, tg.start,
-                  tg.stop, bk ? c->d_bofs : nullptr, c->nblocks, c->max_members);
+  const GemmGroups gg{c->d_gofs, c->d_gblk, c->ngroups, c->group_leaves};
+  const int cols = bk ? c->group_leaves * nrhs : nrhs;         // widest group
+  e = gemm_launch(c, prec, gemm_shape(c->p, prec, std::min(64, cols)), Bk.data, Bk.ncp, Hb, Ub, nrhs,
+                  tg.start, tg.stop, bk ? &gg : nullptr);
   if ((rc = check_hip(e, "k_block_gemm"))) {
     timing_drop(c, tg);
     return rc;

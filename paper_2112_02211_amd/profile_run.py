@@ -1,6 +1,6 @@
 """Profiling helpers for the hot-path kernels.
 
-    python -m paper_2112_02211_amd.profile_run [run] [--workload NAME] [--launches 4]
+    python -m paper_2112_02211_amd.profile_run [run] [--workload NAME] [--launches 4] [--lambda-bucket D]
     python -m paper_2112_02211_amd.profile_run pmc-summary --fetch DIR --write DIR --out FILE
     python -m paper_2112_02211_amd.profile_run trace-summary --stats CSV --out FILE --cmd CMD --title T
 
@@ -54,7 +54,8 @@ def run(a):
     from paper_2112_02211_amd import hps, problems as P
 
     prob = P.workload(a.workload)
-    ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"))
+    ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"),
+                                   lambda_bucket=a.lambda_bucket)
     rng = np.random.default_rng(0)
     x = torch.from_numpy(rng.standard_normal(ctx.N) + 1j * rng.standard_normal(ctx.N)).cuda()
     y = torch.empty_like(x)
@@ -191,6 +192,8 @@ def main():
     ap.add_argument("mode", nargs="?", default="run", choices=("run", "pmc-summary", "trace-summary"))
     ap.add_argument("--workload", default="bumps_8x8x8_p10")
     ap.add_argument("--launches", type=int, default=4)
+    ap.add_argument("--lambda-bucket", type=float, default=0.0,
+                    help="run: lambda grid spacing (times kappa^2) of shared blocks; 0: one per leaf")
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
     ap.add_argument("--fetch")
     ap.add_argument("--write")

@@ -147,15 +147,15 @@ def test_constant_medium_needs_one_block(hps_mod):
 
 @pytest.mark.parametrize("nrhs", [1, 3, 9])
 def test_bucketed_tile_shapes_give_identical_results(hps_mod, nrhs):
-    # constant medium on 3 x 3 x 3 leaves: one bucket of 27 leaves, so 9
-    # right-hand sides give 243 columns in one group (several column panels
-    # of every shape, ragged last panel)
+    # constant medium on 3 x 3 x 3 leaves: one bucket of 27 leaves, GEMM
+    # groups of 16 and 11 leaves; 9 right-hand sides give 144 and 99 columns
+    # (several column panels of every shape, ragged last panels)
     prob = P.plane_wave_problem((3, 3, 3), 8, 12.0)
     hps = hps_mod
     ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"), lambda_bucket=0.01)
     assert ctx.n_blocks == 1
     xd = dev(rand_block(ctx.N, nrhs, 83).reshape(-1))
-    widest = min(64, ctx.nl * nrhs)
+    widest = min(64, 16 * nrhs)
     for prec in ("fp64", "fp32", "bf16"):
         outs = []
         try:
@@ -192,13 +192,14 @@ def test_bucketed_solves_match_direct_solve(hps_mod, solver, prec, nrhs):
 
 
 
-def test_autotune_on_buckets_keys_by_the_largest_bucket(hps_mod):
+def test_autotune_on_buckets_keys_by_the_widest_group(hps_mod):
     hps = hps_mod
     prob = P.plane_wave_problem((3, 3, 3), 8, 12.0)
     ctx = hps.Context.from_problem(prob, block_precs=("fp32",), lambda_bucket=0.01)
     try:
-        sh = ctx.autotune(1, "fp32", reps=2)      # one right-hand side: 27 columns in the bucket
+        # two right-hand sides: groups of 16 and 11 leaves, 32 columns in the widest
+        sh = ctx.autotune(2, "fp32", reps=2)
         assert 0 <= sh < len(hps.GEMM_SHAPES)
-        assert hps.autotune_get(prob.p, "fp32", 27) == sh
+        assert hps.autotune_get(prob.p, "fp32", 32) == sh
     finally:
-        hps.autotune_set(prob.p, "fp32", 27, -1)
+        hps.autotune_set(prob.p, "fp32", 32, -1)
