@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/hps.h"
+#include "k_common.h"
 
 namespace hps {
 
@@ -46,8 +47,6 @@ struct DevTables {
   const double* W;    // n1 x n1
   const double* E;    // n1
 };
-
-enum BlockPrec { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
 
 // Column-group width (complex numbers per 16-byte group) of the block layout.
 inline int block_cw(int prec) { return prec == kFP64 ? 1 : (prec == kFP32 ? 2 : 4); }

@@ -8,6 +8,9 @@
 
 namespace hps {
 
+// Block precisions (storage of the dense preconditioner blocks).
+enum BlockPrec { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
+
 // Offsets (in doubles) inside the packed device table  D | D2 | V | W | E | xi | Ed3.
 __host__ __device__ constexpr int tab_off_D(int p) { return 0; }
 __host__ __device__ constexpr int tab_off_D2(int p) { return p * p; }

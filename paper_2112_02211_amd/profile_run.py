@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 
 CSRC = os.path.join(ROOT, "paper_2112_02211_amd", "csrc")
 # every source the preconditioner kernel is compiled from
-PRECOND_SOURCES = ("k_precond.hip", "k_leaf.h", "k_common.h", "hps_internal.h")
+PRECOND_SOURCES = ("k_precond_fused.h", "k_leaf.h", "k_common.h")
 COPY_MIB = 1024
 
 
