@@ -210,8 +210,11 @@ class Context:
 
     @classmethod
     def from_problem(cls, prob, block_precs=("fp64",), verbose=False,
-                     lambda_bucket: float = 0.0) -> "Context":
-        """Context for a problems.Problem (bump medium, or b = 0 for plane waves)."""
+                     lambda_bucket: Optional[float] = None) -> "Context":
+        """Context for a problems.Problem (bump medium, or b = 0 for plane waves);
+        lambda_bucket defaults to the problem's own."""
+        if lambda_bucket is None:
+            lambda_bucket = getattr(prob, "lambda_bucket", 0.0)
         if prob.plane_dir is not None or len(prob.bump_centres) == 0:
             return cls(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi,
                        block_precs=block_precs, verbose=verbose, lambda_bucket=lambda_bucket)

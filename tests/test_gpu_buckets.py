@@ -48,7 +48,8 @@ def hps_mod():
 
 # n_elem, p, kappa, bumps, seed, delta
 CASES = [((3, 2, 2), 7, 9.0, 4, 61, 0.02), ((2, 2, 2), 10, 20.0, 4, 62, 0.01),
-         ((3, 3, 2), 8, 20.0, 6, 63, 0.05), ((1, 2, 2), 12, 30.0, 3, 64, 0.005)]
+         ((3, 3, 2), 8, 20.0, 6, 63, 0.05), ((1, 2, 2), 12, 30.0, 3, 64, 0.005),
+         ((2, 2, 1), 16, 20.0, 4, 65, 0.02)]
 
 
 def _oracle_lambdas(op, delta):
