@@ -9,6 +9,9 @@ homogenized leaf matrices with dense LU (no fast diagonalization, no Schur
 complement), so an agreement with the GPU path is an agreement between two
 independent routes.
 
+It also holds the face-reduced form of the same discretization (exact ItI maps
+of the leaves and the face exchange), whose solution is the same discrete u.
+
 Everything is complex128 / float64.  Paper references are to Lucero Lorca,
 Beams, Beecroft and Gillman, "An iterative solver for the HPS discretization
 applied to three dimensional Helmholtz problems" (arXiv 2112.02211).
@@ -545,3 +548,111 @@ def iti_map(d: Disc, C_int: np.ndarray, homogenized: bool = True) -> np.ndarray:
     rhs[d.ni:, :] = np.eye(d.nb)
     U = np.linalg.solve(A, rhs)
     return Gm @ U
+
+
+# ----------------------------------------------------------------------------
+# face-reduced impedance system (exact ItI maps of the leaves, Sec. 2.2, and
+# the interface rule that each leaf's incoming impedance on a shared face is
+# minus its neighbour's outgoing impedance there, eq. (2x2)).  Unknowns: the
+# incoming impedance f on every leaf face, stored [leaf][n_b] in the leaf's
+# face order.  Leaf by leaf, g = R f + h with R the exact ItI map and h the
+# outgoing impedance caused by the interior source; with Pi the exchange
+# (g of the neighbour across each shared face, 0 on the boundary) and t the
+# boundary data, f = t - Pi g, i.e.
+#     (I + Pi R) f = t - Pi h,
+# and u on each leaf is the leaf solve with data (s_i, f).  Every solution of
+# one system gives a solution of the other, so the discrete u is the same as
+# that of A u = b.
+# ----------------------------------------------------------------------------
+
+def face_pi(d: Disc, g: np.ndarray) -> np.ndarray:
+    """(Pi g): on each face of each leaf, the values of g on the neighbour's
+    matching face (same node positions), 0 on domain-boundary faces."""
+    nb, m = d.nb, d.n1 * d.n1
+    out = np.zeros(d.nl * nb, dtype=np.complex128)
+    for tau in range(d.nl):
+        for f in range(6):
+            nbr = neighbour(d, tau, f)
+            if nbr < 0:
+                continue
+            fp = PARTNER[f]
+            out[tau * nb + f * m:tau * nb + (f + 1) * m] = g[nbr * nb + fp * m:nbr * nb + (fp + 1) * m]
+    return out
+
+
+def iti_blocks(d: Disc, b_nodes: np.ndarray) -> list:
+    """Exact ItI map R^tau of every leaf (variable b, no homogenization), each
+    from a dense solve of the leaf system (iti_map)."""
+    C = c_values(d, b_nodes)
+    return [iti_map(d, C[t * d.n:t * d.n + d.ni], homogenized=False) for t in range(d.nl)]
+
+
+def face_apply(d: Disc, R: list, f: np.ndarray) -> np.ndarray:
+    """(I + Pi R) f."""
+    nb = d.nb
+    g = np.concatenate([R[t] @ f[t * nb:(t + 1) * nb] for t in range(d.nl)])
+    return f + face_pi(d, g)
+
+
+def face_rhs(d: Disc, b_nodes: np.ndarray, rhs: np.ndarray) -> np.ndarray:
+    """t - Pi h for the assembled right-hand side rhs of A u = b (s at interior
+    rows, t on boundary faces): h^tau = G^tau u0^tau with u0^tau the leaf
+    solution for source s_i and zero incoming impedance."""
+    C = c_values(d, b_nodes)
+    ops = local_ops(d)
+    n, ni, nb = d.n, d.ni, d.nb
+    h = np.zeros(d.nl * nb, dtype=np.complex128)
+    t = np.zeros(d.nl * nb, dtype=np.complex128)
+    for tau in range(d.nl):
+        A, Gm = leaf_matrices(d, C[tau * n:tau * n + ni], ops)
+        z = np.zeros(n, dtype=np.complex128)
+        z[:ni] = rhs[tau * n:tau * n + ni]
+        h[tau * nb:(tau + 1) * nb] = Gm @ np.linalg.solve(A, z)
+        t[tau * nb:(tau + 1) * nb] = rhs[tau * n + ni:(tau + 1) * n]
+    return t - face_pi(d, h)
+
+
+def face_recover(d: Disc, b_nodes: np.ndarray, rhs: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """u from the incoming impedance f: on each leaf the leaf solve with source
+    s_i at the interior rows and f at the face rows."""
+    C = c_values(d, b_nodes)
+    ops = local_ops(d)
+    n, ni, nb = d.n, d.ni, d.nb
+    u = np.zeros(d.N, dtype=np.complex128)
+    for tau in range(d.nl):
+        A, _ = leaf_matrices(d, C[tau * n:tau * n + ni], ops)
+        z = np.concatenate([rhs[tau * n:tau * n + ni], f[tau * nb:(tau + 1) * nb]])
+        u[tau * n:(tau + 1) * n] = np.linalg.solve(A, z)
+    return u
+
+
+def face_matrix(d: Disc, R: list) -> sp.csr_matrix:
+    """I + Pi R as a sparse matrix (identity plus one dense n1^2 x n_b block per
+    shared face)."""
+    nb, m = d.nb, d.n1 * d.n1
+    rows, cols, vals = [], [], []
+    for tau in range(d.nl):
+        for f in range(6):
+            nbr = neighbour(d, tau, f)
+            if nbr < 0:
+                continue
+            fp = PARTNER[f]
+            blk = R[nbr][fp * m:(fp + 1) * m, :]
+            r, c = np.meshgrid(tau * nb + f * m + np.arange(m), nbr * nb + np.arange(nb), indexing="ij")
+            rows.append(r.ravel())
+            cols.append(c.ravel())
+            vals.append(blk.ravel())
+    K = d.nl * nb
+    M = sp.identity(K, dtype=np.complex128, format="csr")
+    if rows:
+        M = M + sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                              shape=(K, K))
+    return M.tocsr()
+
+
+def solve_face_system(op: OracleProblem, rhs: Optional[np.ndarray] = None):
+    """Direct solve of the face-reduced system, then the leaf solves: returns (f, u)."""
+    b = op.rhs if rhs is None else rhs
+    R = iti_blocks(op.d, op.b_nodes)
+    f = spla.spsolve(face_matrix(op.d, R).tocsc(), face_rhs(op.d, op.b_nodes, b))
+    return f, face_recover(op.d, op.b_nodes, b, f)

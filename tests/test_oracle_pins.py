@@ -306,3 +306,83 @@ def test_buckets_shrink_with_the_grid_and_gmres_reaches_the_same_solution():
     x, its, _ = O.gmres_left(lambda v: op.A @ v, M.apply, op.rhs, tol=1e-11, restart=30)
     ud = O.solve_direct(op)
     assert np.linalg.norm(x - ud) / np.linalg.norm(ud) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# face-reduced impedance system with exact ItI maps: the same discrete
+# solution as A u = b (every leaf solve is unique), reached through the face
+# unknowns alone
+# ---------------------------------------------------------------------------
+
+FACE_MESHES = [((2, 2, 1), 6, 8.0, 53), ((2, 1, 2), 7, 12.0, 43), ((2, 2, 2), 6, 10.0, 43),
+               ((3, 2, 2), 5, 6.0, 50)]
+
+
+@pytest.mark.parametrize("mesh", FACE_MESHES)
+def test_face_system_gives_the_solution_of_the_full_system(mesh):
+    n_elem, p, kappa, seed = mesh
+    op = O.build(P.bump_problem("f", n_elem, p, kappa, 3, 1, seed, 30, 1e-10))
+    f, u = O.solve_face_system(op)
+    ud = O.solve_direct(op)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-12
+    # the face unknowns are the incoming impedance F u of that solution
+    L, Nf = O.local_ops(op.d)
+    d = op.d
+    fd = np.concatenate([Nf @ ud[t * d.n:(t + 1) * d.n] + 1j * d.eta * ud[t * d.n + d.ni:(t + 1) * d.n]
+                         for t in range(d.nl)])
+    assert np.linalg.norm(f - fd) / np.linalg.norm(fd) < 1e-12
+    # and satisfy the matrix-free form of the face system
+    R = O.iti_blocks(d, op.b_nodes)
+    lhs = O.face_apply(d, R, fd)
+    assert np.linalg.norm(lhs - O.face_rhs(d, op.b_nodes, op.rhs)) / np.linalg.norm(lhs) < 1e-12
+
+
+def test_face_system_plane_wave_matches_the_exact_solution():
+    prob = P.plane_wave_problem((2, 2, 2), 8, 10.0)
+    op = O.build(prob)
+    _, u = O.solve_face_system(op)
+    assert 1e-6 < O.rel_err(u, P.plane_wave(prob, op.xyz)) < 1e-3
+    assert np.linalg.norm(u - O.solve_direct(op)) / np.linalg.norm(u) < 1e-12
+
+
+def test_face_exchange_is_an_involution_on_shared_faces():
+    d = O.make_disc((3, 2, 2), 5, 4.0, 4.0, hi=(1.5, 1.0, 1.0))
+    g = np.random.default_rng(5).standard_normal(d.nl * d.nb) + 0j
+    pg = O.face_pi(d, g)
+    ppg = O.face_pi(d, pg)
+    shared = np.zeros(d.nl * d.nb, dtype=bool)
+    m = d.n1 * d.n1
+    for t in range(d.nl):
+        for f in range(6):
+            if O.neighbour(d, t, f) >= 0:
+                shared[t * d.nb + f * m:t * d.nb + (f + 1) * m] = True
+    assert np.array_equal(ppg[shared], g[shared]) and np.all(pg[~shared] == 0)
+    # 3 x 2 x 2 leaves: 2*2*2 + 3*1*2 + 3*2*1 = 20 shared interfaces, two sides each
+    assert shared.sum() == 2 * 20 * m
+
+
+def test_exact_iti_map_preserves_energy_for_real_media_and_contracts_with_absorption():
+    op = O.build(P.bump_problem("f", (2, 1, 1), 7, 12.0, 3, 1, 45, 30, 1e-10))
+    d = op.d
+    C = O.c_values(d, op.b_nodes)
+    for t in range(d.nl):
+        Ci = C[t * d.n:t * d.n + d.ni]
+        ev = np.abs(np.linalg.eigvals(O.iti_map(d, Ci, homogenized=False)))
+        assert np.max(np.abs(ev - 1.0)) < 1e-6
+        e_abs = np.abs(np.linalg.eigvals(O.iti_map(d, Ci - 50.0j, homogenized=False)))
+        assert e_abs.max() < 1.0 + 1e-6 and e_abs.mean() < 0.99
+    # a constant medium on the leaf: the homogenized map is the exact one
+    Cc = np.full(d.ni, d.kappa ** 2 * 0.8 + 0j)
+    assert np.allclose(O.iti_map(d, Cc, homogenized=False), O.iti_map(d, Cc, homogenized=True),
+                       rtol=0, atol=1e-12)
+
+
+def test_oracle_gmres_on_the_face_system_reaches_the_same_solution():
+    op = O.build(P.bump_problem("f", (2, 2, 1), 6, 8.0, 3, 1, 53, 30, 1e-10))
+    d = op.d
+    R = O.iti_blocks(d, op.b_nodes)
+    f, its, _ = O.gmres_left(lambda v: O.face_apply(d, R, v), lambda v: v,
+                             O.face_rhs(d, op.b_nodes, op.rhs), tol=1e-12, restart=30)
+    u = O.face_recover(d, op.b_nodes, op.rhs, f)
+    assert np.linalg.norm(u - O.solve_direct(op)) / np.linalg.norm(u) < 1e-10
+    assert its < 200
