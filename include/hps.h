@@ -100,6 +100,12 @@ typedef struct {
 #define HPS_SOLVER_BLOCK 2   /* lock-step GMRES(m): one Krylov space per right-hand side, up to 64
                                 advanced together (J^-1 of 4 or more as a GEMM on the matrix
                                 cores); left preconditioned with FP64 blocks, flexible otherwise */
+#define HPS_SOLVER_ITI 3     /* GMRES(m) on the face-reduced system (I + Pi R) f = t - Pi h with the
+                                exact ItI maps R of the leaves (Sec. 2.2, interface rule of eq.
+                                (2x2)), no preconditioner, then the leaf solves for u: the same
+                                discrete u.  Needs hps_iti_build; use_x0 and reduced precision are
+                                rejected.  Stopping test on ||t - Pi h - (I + Pi R) f|| relative to
+                                ||t - Pi h||; iterations and residuals refer to the face system. */
 
 typedef struct {
   int solver;          /* HPS_SOLVER_* (default GMRES) */
@@ -176,6 +182,32 @@ int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
  * workspace of nrhs * N complex (released by hps_trim). */
 int hps_op_left(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
 
+/* Face-reduced system with the exact impedance-to-impedance maps (Sec. 2.2):
+ * the unknowns are the incoming impedance f on every leaf face, stored
+ * [rhs][leaf][n_b] in the leaf's face order; a leaf's outgoing impedance is
+ * g = R f + h with R = I - 2 i eta S^-1 (S = F_bb - F_bi A_ii^-1 A_ib, the exact
+ * Schur complement with the variable medium) and h caused by the interior
+ * source; on a shared face the incoming impedance is minus the neighbour's
+ * outgoing one (eq. (2x2)), on the boundary it is t.
+ *
+ * hps_iti_build: forms R and A_ii^-1 of every leaf (rocSOLVER LU and inverse,
+ * rocBLAS batched GEMMs); device memory 16 N_l (n_b^2 + n_i^2) bytes
+ * (hps_iti_bytes), kept until hps_free.  Idempotent.  HPS_ERR_NUMERIC if a
+ * leaf's A_ii or S is singular, HPS_ERR_OOM if the memory is not there. */
+int hps_iti_build(hps_ctx* c);
+/* y = f + Pi (R f): the face-reduced operator (one streaming pass over every
+ * R, then the face exchange).  f, y: device, nrhs * N_l * n_b complex, must
+ * not overlap. */
+int hps_iti_apply(hps_ctx* c, const hps_z* f, hps_z* y, int nrhs);
+/* rhs_f = t - Pi h for the data (s, t) of hps_assemble_rhs (device, nrhs * N
+ * complex); rhs_f: device, nrhs * N_l * n_b. */
+int hps_iti_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* rhs_f, int nrhs);
+/* u from the incoming impedance f: on each leaf the solve with source s at the
+ * interior rows and f at the face rows.  u: device, nrhs * N complex. */
+int hps_iti_recover(hps_ctx* c, const hps_z* s, const hps_z* t, const hps_z* f, hps_z* u, int nrhs);
+/* Device bytes hps_iti_build allocates for this mesh (persistent part). */
+int64_t hps_iti_bytes(int p, const int n_elem[3]);
+
 /* As hps_precond with the blocks stored in precision prec (HPS_PREC_*; must
  * have been built).  Reduced-precision blocks are applied with FP32 arithmetic. */
 int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec);
@@ -214,9 +246,10 @@ int hps_set_timing(hps_ctx* c, int enable);
 /* Totals since the last reset: out[0] = operator milliseconds, out[1] =
  * operator launches, out[2] = preconditioner milliseconds, out[3] =
  * preconditioner launches, out[4] = milliseconds of the many-right-hand-side
- * block GEMM kernel alone, out[5] = its launches.  Synchronizes the stream.
- * reset != 0 clears them. */
-int hps_kernel_times(hps_ctx* c, double out[6], int reset);
+ * block GEMM kernel alone, out[5] = its launches, out[6] = milliseconds of the
+ * ItI block product of the face-reduced system (hps_iti_apply), out[7] = its
+ * launches.  Synchronizes the stream.  reset != 0 clears them. */
+int hps_kernel_times(hps_ctx* c, double out[8], int reset);
 
 /* Tile shapes of the many-right-hand-side block GEMM inside J^-1 (4 to 64
  * right-hand sides; the batching pattern on top of Sec. 4): shape index ->

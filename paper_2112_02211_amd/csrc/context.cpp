@@ -424,7 +424,7 @@ int hps_set_timing(hps_ctx* c, int enable) {
   return HPS_OK;
 }
 
-int hps_kernel_times(hps_ctx* c, double out[6], int reset) {
+int hps_kernel_times(hps_ctx* c, double out[8], int reset) {
   if (!c || !out) return fail(HPS_ERR_ARG, "NULL argument");
   int rc = timing_collect(c);
   if (rc) return rc;
@@ -453,6 +453,11 @@ void hps_free(hps_ctx* c) {
   hipFree(c->d_gblk);
   hipFree(c->d_blam);
   for (auto& B : c->blk) hipFree(B.data);
+  hipFree(c->d_itiR);
+  hipFree(c->d_Ainv);
+  hipFree(c->d_Fbi);
+  hipFree(c->d_Aib);
+  hipFree(c->w_iti.ptr);
   hipFree(c->w_g.ptr);
   hipFree(c->w_red.ptr);
   hipFree(c->w_krylov.ptr);
@@ -499,7 +504,8 @@ int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex
 int hps_trim(hps_ctx* c) {
   if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
   HPS_TRY_HIP(hipStreamSynchronize(c->stream));
-  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch, &c->w_op, &c->w_b};
+  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch, &c->w_op, &c->w_b,
+                     &c->w_iti};
   for (Workspace* w : ws) {
     if (w->ptr) {
       HPS_TRY_HIP(hipFree(w->ptr));

@@ -53,15 +53,46 @@ double bytes_precond(const hps_ctx* c, int q) {
   return b;
 }
 
+struct Job {
+  int nrhs;          // right-hand sides iterated in lock step
+  bool flexible;     // right preconditioning with stored Z
+  int prec;          // block precision index inside J^{-1}
+  double* rhs_res = nullptr;  // host, nrhs: final relative residual of each right-hand side
+  bool face = false; // the face-reduced system (I + Pi R) f (no preconditioner) instead of A
+  int64_t n = 0;     // vector length per right-hand side
+};
+
+// The operator of a job: A and J^{-1}, or the face-reduced operator with the
+// identity in place of the preconditioner.
+int job_apply(hps_ctx* c, const Job& job, const double2* x, double2* y, int nb) {
+  return job.face ? launch_iti_apply(c, x, y, nb) : launch_apply(c, x, y, nb);
+}
+int job_precond(hps_ctx* c, const Job& job, const double2* x, double2* y, int nb) {
+  if (job.face) {
+    HPS_TRY_HIP(hipMemcpyAsync(y, x, sizeof(double2) * job.n * nb, hipMemcpyDeviceToDevice, c->stream));
+    return HPS_OK;
+  }
+  return launch_precond(c, x, y, nb, job.prec);
+}
+int job_op_left(hps_ctx* c, const Job& job, const double2* x, double2* tmp, double2* y, int nb) {
+  return job.face ? launch_iti_apply(c, x, y, nb) : launch_op_left(c, x, tmp, y, nb, job.prec);
+}
+
 // Algorithmic bytes of the timed apply and preconditioner launches of a solve.
 // Left preconditioning with fewer than kBatchedMinRhs right-hand sides fuses
 // the face exchange into J^{-1}: the apply is the sweep alone (x, y, C and the
 // face buffer written) and J^{-1} also reads the face buffer.
-void solve_bytes_stats(const hps_ctx* c, bool flexible, int nb, int prec, hps_stats* st) {
+void solve_bytes_stats(const hps_ctx* c, const Job& job, int nb, hps_stats* st) {
   const double face = 16.0 * c->nl * (double)c->nb;
-  const bool fused = !flexible && nb < kBatchedMinRhs && !(c->lambda_bucket > 0.0);
+  if (job.face) {
+    // the ItI block stream (R, f in, g out) and the exchange (f, g in, y out)
+    st->bytes_apply = face * c->nb + 2.0 * face + 3.0 * face;
+    st->bytes_precond = 0.0;
+    return;
+  }
+  const bool fused = !job.flexible && nb < kBatchedMinRhs && !(c->lambda_bucket > 0.0);
   st->bytes_apply = bytes_apply(c) - (fused ? face : 0.0);
-  st->bytes_precond = bytes_precond(c, prec) + (fused ? face : 0.0);
+  st->bytes_precond = bytes_precond(c, job.prec) + (fused ? face : 0.0);
 }
 
 int solver_events(hps_ctx* c, hipEvent_t* evs) {
@@ -72,18 +103,12 @@ int solver_events(hps_ctx* c, hipEvent_t* evs) {
   return HPS_OK;
 }
 
-struct Job {
-  int nrhs;          // right-hand sides iterated in lock step
-  bool flexible;     // right preconditioning with stored Z
-  int prec;          // block precision index inside J^{-1}
-  double* rhs_res = nullptr;  // host, nrhs: final relative residual of each right-hand side
-};
 
 // Lock-step (F)GMRES over nb right-hand sides stored one after the other.
 // b: nb*N device, x: nb*N device (initial guess if use_x0).
 int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m,
               int maxit, int use_x0, int check_every, hps_stats* st) {
-  const int64_t N = c->N;
+  const int64_t N = job.n;
   const int nb = job.nrhs;
   const int64_t NB = N * nb;  // one batched vector
   // workspace: V (m+1 batched vectors), Z (m, flexible only), tmp
@@ -131,11 +156,11 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     if (x_zero) {
       HPS_TRY_HIP(hipMemcpyAsync(tmp, b, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
     } else {
-      if ((e = launch_apply(c, x, tmp, nb))) return e;
+      if ((e = job_apply(c, job, x, tmp, nb))) return e;
       if ((e = launch_sub_from(c, b, tmp, NB))) return e;
     }
     if (!job.flexible) {
-      if ((e = launch_precond(c, tmp, Vj(0), nb, job.prec))) return e;
+      if ((e = job_precond(c, job, tmp, Vj(0), nb))) return e;
     } else {
       HPS_TRY_HIP(hipMemcpyAsync(Vj(0), tmp, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
     }
@@ -182,7 +207,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     for (int j = 0; j < m && its < maxit; ++j) {
       // w_j = J^{-1} A v_j (left) or A M^{-1} v_j (flexible), into V[j+1]
       if (!job.flexible) {
-        if ((rc = launch_op_left(c, Vj(j), tmp, Vj(j + 1), nb, job.prec))) return rc;
+        if ((rc = job_op_left(c, job, Vj(j), tmp, Vj(j + 1), nb))) return rc;
       } else {
         if ((rc = launch_precond(c, Vj(j), Zj(j), nb, job.prec))) return rc;
         if ((rc = launch_apply(c, Zj(j), Vj(j + 1), nb))) return rc;
@@ -278,7 +303,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     st->rel_res = worst_est;
     st->true_rel_res = worst_true;
     st->t_solve = now() - t0;
-    solve_bytes_stats(c, job.flexible, nb, job.prec, st);
+    solve_bytes_stats(c, job, nb, st);
   }
   return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
 }
@@ -289,7 +314,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
 // rules, restart policy and pipelined residual checks as run_gmres.
 int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m, int maxit,
              int use_x0, int check_every, hps_stats* st) {
-  const int64_t N = c->N;
+  const int64_t N = job.n;
   const int nb = job.nrhs;
   const int64_t NB = N * nb;
   const size_t vec_bytes = sizeof(double2) * NB;
@@ -357,11 +382,11 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     if (x_zero) {
       HPS_TRY_HIP(hipMemcpyAsync(TMP, b, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
     } else {
-      if ((e = launch_apply(c, x, TMP, nb))) return e;
+      if ((e = job_apply(c, job, x, TMP, nb))) return e;
       if ((e = launch_sub_from(c, b, TMP, NB))) return e;
     }
     if (!job.flexible) {
-      if ((e = launch_precond(c, TMP, U, nb, job.prec))) return e;
+      if ((e = job_precond(c, job, TMP, U, nb))) return e;
     } else {
       HPS_TRY_HIP(hipMemcpyAsync(U, TMP, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
     }
@@ -418,7 +443,7 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     for (int j = 0; j < m && its < maxit; ++j) {
       // operator image of the candidate: left J^-1 A u, flexible A M^-1 u (z'_j kept)
       if (!job.flexible) {
-        if ((rc = launch_op_left(c, U, TMP, W, nb, job.prec))) return rc;
+        if ((rc = job_op_left(c, job, U, TMP, W, nb))) return rc;
       } else {
         if ((rc = launch_precond(c, U, Zj(j), nb, job.prec))) return rc;
         if ((rc = launch_apply(c, Zj(j), W, nb))) return rc;
@@ -481,7 +506,7 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     st->rel_res = worst_est;
     st->true_rel_res = worst_true;
     st->t_solve = now() - t0;
-    solve_bytes_stats(c, job.flexible, nb, job.prec, st);
+    solve_bytes_stats(c, job, nb, st);
   }
   return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
 }
@@ -501,6 +526,15 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
   if (!c || restart < 1 || restart > kMaxRestart || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments");
   hps_solve_opts o{};
   if (so) o = *so;
+  if (o.solver == HPS_SOLVER_ITI) {
+    // face vectors: basis + U, W, TMP (DCGS) or basis + tmp (CGS2), the face
+    // right-hand side and solution, the leaf workspace, b, the g buffer
+    const int64_t vf = 16 * c->nl * (int64_t)c->nb;
+    int64_t bytes = vf * (restart + 3) + 2 * vf + iti_ws_bytes(c, 1) + vf;
+    bytes += (int64_t)sizeof(GmresState) + 32 + (int64_t)kPartSlots * kRedBlocks * 16;
+    bytes += 16 * c->N * nrhs;
+    return bytes;
+  }
   const bool flexible = o.solver == HPS_SOLVER_FGMRES ||
                         (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64);
   const int64_t nbat = o.solver == HPS_SOLVER_BLOCK ? std::min(nrhs, kMaxBatch) : 1;
@@ -530,7 +564,13 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
   else if (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64)
     return fail(HPS_ERR_ARG, "unknown precond_prec");
   if (!c->blk[prec].data) return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
-  if (o.solver < 0 || o.solver > 2) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver < 0 || o.solver > 3) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver == HPS_SOLVER_ITI) {
+    if (!c->d_itiR) return fail(HPS_ERR_ARG, "the face-reduced solver needs hps_iti_build first");
+    if (o.use_x0) return fail(HPS_ERR_ARG, "the face-reduced solver starts from f = 0 (use_x0 unsupported)");
+    if (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64)
+      return fail(HPS_ERR_ARG, "the face-reduced solver has no preconditioner (precond_prec must be 0)");
+  }
   if (o.solver == HPS_SOLVER_GMRES && prec != kFP64)
     return fail(HPS_ERR_ARG, "left GMRES runs the FP64 preconditioner; use FGMRES for reduced precision");
   // b for every right-hand side, in a workspace kept between calls
@@ -540,10 +580,47 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
   rc = launch_assemble_rhs(c, reinterpret_cast<const double2*>(s), reinterpret_cast<const double2*>(t),
                            bvec, nrhs);
   double2* x = reinterpret_cast<double2*>(u);
-  if (rc == HPS_OK) {
+  if (rc == HPS_OK && o.solver == HPS_SOLVER_ITI) {
+    // face-reduced system: right-hand side t - Pi h, GMRES on (I + Pi R) f,
+    // then the leaf solves; one right-hand side at a time
+    const int64_t nf = c->nl * (int64_t)c->nb;
+    Job job;
+    job.flexible = false;
+    job.prec = kFP64;
+    job.face = true;
+    job.n = nf;
+    job.nrhs = 1;
+    hps_stats acc{};
+    // face right-hand side and solution after the basis in the Krylov workspace
+    for (int r = 0; r < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); ++r) {
+      int r1 = ws_reserve(c, &c->w_op, sizeof(double2) * 2 * nf);
+      if (r1) { rc = r1; break; }
+      double2* rf = static_cast<double2*>(c->w_op.ptr);
+      double2* ff = rf + nf;
+      if ((r1 = iti_prepare(c, bvec + (size_t)r * c->N, 1, rf))) { rc = r1; break; }
+      job.rhs_res = o.rhs_rel_res ? o.rhs_rel_res + r : nullptr;
+      hps_stats one{};
+      r1 = run_solver(c, job, rf, ff, tol, restart, maxit, 0, check_every, o.orth, &one);
+      if (r1 < 0) { rc = r1; break; }
+      if (r1 == HPS_NOT_CONVERGED) rc = r1;
+      // the workspace of iti_prepare (v, F_bi v) is untouched by the solve
+      if ((r1 = iti_finish(c, ff, x + (size_t)r * c->N, 1))) { rc = r1; break; }
+      acc.iters += one.iters;
+      acc.restarts += one.restarts;
+      acc.rel_res = std::max(acc.rel_res, one.rel_res);
+      acc.true_rel_res = std::max(acc.true_rel_res, one.true_rel_res);
+      acc.t_solve += one.t_solve;
+      acc.bytes_apply = one.bytes_apply;
+      acc.bytes_precond = one.bytes_precond;
+    }
+    acc.converged = rc == HPS_OK;
+    acc.lambda_shifted = c->n_shifted;
+    if (st) *st = acc;
+  } else if (rc == HPS_OK) {
     Job job;
     job.flexible = (o.solver == HPS_SOLVER_FGMRES) || prec != kFP64;
     job.prec = prec;
+    job.n = c->N;
     if (o.solver == HPS_SOLVER_BLOCK) {
       hps_stats acc{};
       for (int r0 = 0; r0 < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); r0 += kMaxBatch) {

@@ -34,6 +34,9 @@ struct HostTables {
 
 // Builds every table; returns an empty string or an error message.
 std::string build_tables(int p, double h, HostTables* t);
+// F_bi, N_bb (F_bb without the i eta I) and A_ib of the leaf matrix, column-major.
+void build_face_operators(const HostTables& t, std::vector<double>* Fbi, std::vector<double>* Nbb,
+                          std::vector<double>* Aib);
 
 // Face f (0..5): axis = f/2, high side = f%2, outward sign -1 / +1.
 inline int face_axis(int f) { return f >> 1; }
@@ -64,7 +67,7 @@ struct Workspace {
 
 }  // namespace hps
 
-constexpr int kTimingKinds = 3;
+constexpr int kTimingKinds = 4;
 
 struct hps_ctx {
   int p = 0, n1 = 0, ni = 0, nb = 0, n = 0;
@@ -97,6 +100,11 @@ struct hps_ctx {
   int group_leaves = 1;             // leaves in the largest group
   int n_shifted = 0;
   hps::Blocks blk[3];
+  // face-reduced system with the exact ItI maps (built by hps_iti_build)
+  double2* d_itiR = nullptr;        // [nl][nb cols][nb rows]  R^tau = I - 2 i eta S^{tau,-1}
+  double2* d_Ainv = nullptr;        // [nl][ni cols][ni rows]  (A_ii^tau)^{-1}
+  double* d_Fbi = nullptr;          // nb x ni, column-major (shared by all leaves)
+  double* d_Aib = nullptr;          // ni x nb, column-major (shared by all leaves)
 
   // reusable workspaces (grown on demand)
   hps::Workspace w_g;               // outgoing impedance buffer
@@ -106,6 +114,7 @@ struct hps_ctx {
   hps::Workspace w_batch;           // many-rhs preconditioner: H and U panels
   hps::Workspace w_op;              // A x inside hps_op_left
   hps::Workspace w_b;               // assembled right-hand sides inside hps_gmres
+  hps::Workspace w_iti;             // face-system solve: v, w, h and q of every leaf
   void* h_pinned = nullptr;         // small pinned host buffer for scalars
   uint32_t solve_epoch = 0;         // tags the residual records of each solve
   size_t dev_bytes = 0;
@@ -113,13 +122,13 @@ struct hps_ctx {
   hipEvent_t ev_solver[2] = {nullptr, nullptr};  // residual-check events of the solvers
 
   // optional kernel timing: event pairs per launch kind (kTimingKinds: 0 operator,
-  // 1 preconditioner, 2 many-rhs block GEMM)
+  // 1 preconditioner, 2 many-rhs block GEMM, 3 ItI block product of the face system)
   int timing = 0;                   // 0 off, k > 0: time every k-th launch of each kind
   std::vector<hipEvent_t> ev_free;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[3];
-  double t_ms[3] = {0.0, 0.0, 0.0};
-  double t_cnt[3] = {0.0, 0.0, 0.0};
-  uint64_t t_seq[3] = {0, 0, 0};    // launches seen per kind (sampling)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kTimingKinds];
+  double t_ms[kTimingKinds] = {0.0, 0.0, 0.0, 0.0};
+  double t_cnt[kTimingKinds] = {0.0, 0.0, 0.0, 0.0};
+  uint64_t t_seq[kTimingKinds] = {0, 0, 0, 0};    // launches seen per kind (sampling)
 };
 
 namespace hps {
@@ -153,7 +162,7 @@ int launch_node_coords(hps_ctx* c, double* d_xyz);
 struct TimedPair {
   hipEvent_t start = nullptr, stop = nullptr;
 };
-int timing_pair(hps_ctx* c, int kind, TimedPair* tp);  // kind: 0 apply, 1 J^-1, 2 GEMM
+int timing_pair(hps_ctx* c, int kind, TimedPair* tp);  // kind: 0 apply, 1 J^-1, 2 GEMM, 3 ItI
 int timing_commit(hps_ctx* c, int kind, const TimedPair& tp);
 void timing_drop(hps_ctx* c, const TimedPair& tp);  // return unused events to the pool
 int timing_collect(hps_ctx* c);
@@ -164,6 +173,13 @@ template <typename... KArgs, typename... Args>
 inline hipError_t launch_k(hps_ctx* c, hipEvent_t e0, hipEvent_t e1, void (*kern)(KArgs...), dim3 g,
                            dim3 b, Args... args) {
   hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, args...);
+  return hipGetLastError();
+}
+// launch_k with dynamic LDS
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_k_lds(hps_ctx* c, hipEvent_t e0, hipEvent_t e1, void (*kern)(KArgs...), dim3 g,
+                               dim3 b, size_t lds, Args... args) {
+  hipExtLaunchKernelGGL(kern, g, b, lds, c->stream, e0, e1, 0, args...);
   return hipGetLastError();
 }
 
@@ -207,6 +223,12 @@ struct GemmGroups {
 hipError_t gemm_launch(hps_ctx* c, int prec, int shape, const void* blk, int ncp, const void* Hb,
                        void* Ub, int nrhs, hipEvent_t e0, hipEvent_t e1,
                        const GemmGroups* gg = nullptr);
+// face-reduced system with the exact ItI maps (k_iti.hip)
+int iti_build(hps_ctx* c);
+int launch_iti_apply(hps_ctx* c, const double2* f, double2* y, int nrhs);   // y = f + Pi R f
+int iti_prepare(hps_ctx* c, const double2* b, int nrhs, double2* rhs_f);    // face right-hand side
+int iti_finish(hps_ctx* c, const double2* f, double2* u, int nrhs);         // leaf recovery
+int64_t iti_ws_bytes(const hps_ctx* c, int nrhs);
 // bytes of the H and U panels of a batched J^-1 (the w_batch workspace)
 size_t batch_panel_bytes(const hps_ctx* c, int nrhs, int prec, size_t* hpad);
 constexpr int kBatchedMinRhs = 4;   // from this many right-hand sides on, J^-1 uses the GEMM path

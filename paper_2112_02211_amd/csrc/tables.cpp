@@ -291,4 +291,49 @@ std::string build_tables(int p, double h, HostTables* t) {
   return std::string();
 }
 
+// The face rows and the interior-to-face coupling of the (exact) leaf matrix,
+// which do not depend on the medium (C sits on the interior diagonal only):
+//   F_bi (nb x ni): on face f (axis ax, endpoint e, outward sign sg) at
+//     tangential position (a, b), sg * D[e][1 + i] at the interior node i of
+//     the normal line through (a, b);
+//   N_bb (nb x nb): the same derivative row at the two face nodes of that
+//     line, sg * D[e][e] on the diagonal and sg * D[e][p-1-e] at the node of
+//     the opposite face (F_bb = N_bb + i eta I);
+//   A_ib (ni x nb): the interior row of node (i0, i1, i2) has -D2[1 + i_ax][e]
+//     at the face node where its line along axis ax ends (endpoint e).
+// All column-major (element (r, c) at c * rows + r).
+void build_face_operators(const HostTables& t, std::vector<double>* Fbi, std::vector<double>* Nbb,
+                          std::vector<double>* Aib) {
+  const int p = t.p, n1 = t.n1, ni = t.ni, nb = t.nb, L = n1 * n1;
+  Fbi->assign((size_t)nb * ni, 0.0);
+  Nbb->assign((size_t)nb * nb, 0.0);
+  Aib->assign((size_t)ni * nb, 0.0);
+  for (int f = 0; f < 6; ++f) {
+    const int ax = face_axis(f);
+    const int e = face_high(f) ? p - 1 : 0;
+    const double sg = face_high(f) ? 1.0 : -1.0;
+    int t1 = -1, t2 = -1;
+    for (int a = 0; a < 3; ++a)
+      if (a != ax) {
+        if (t1 < 0) t1 = a; else t2 = a;
+      }
+    for (int b = 0; b < n1; ++b)
+      for (int a = 0; a < n1; ++a) {
+        const int r = f * L + a + n1 * b;          // face node
+        const int ro = (f ^ 1) * L + a + n1 * b;   // the other end of its normal line
+        for (int i = 0; i < n1; ++i) {
+          int g[3];
+          g[ax] = i;
+          g[t1] = a;
+          g[t2] = b;
+          const int m = g[0] + n1 * (g[1] + n1 * g[2]);
+          (*Fbi)[(size_t)m * nb + r] = sg * t.D[e * p + 1 + i];
+          (*Aib)[(size_t)r * ni + m] = -t.D2[(1 + i) * p + e];
+        }
+        (*Nbb)[(size_t)r * nb + r] += sg * t.D[e * p + e];
+        (*Nbb)[(size_t)ro * nb + r] += sg * t.D[e * p + (p - 1 - e)];
+      }
+  }
+}
+
 }  // namespace hps

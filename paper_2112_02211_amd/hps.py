@@ -22,7 +22,7 @@ HPS_ERR_ARG, HPS_ERR_UNSUPPORTED, HPS_ERR_OOM = -1, -2, -3
 HPS_ERR_DEVICE, HPS_ERR_BREAKDOWN, HPS_ERR_NUMERIC = -4, -5, -6
 ERRORS = {-1: "ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BREAKDOWN", -6: "NUMERIC"}
 PREC = {"fp64": 1, "fp32": 2, "bf16": 4}
-SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2}
+SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2, "iti": 3}
 ORTH = {"dcgs": 0, "cgs2": 1}
 MEDIUM_ZERO, MEDIUM_NODAL, MEDIUM_BUMPS = 0, 1, 2
 
@@ -89,6 +89,13 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int)]),
     "hps_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "hps_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "hps_iti_build": (ctypes.c_int, [ctypes.c_void_p]),
+    "hps_iti_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_iti_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int]),
+    "hps_iti_recover": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int]),
+    "hps_iti_bytes": (ctypes.c_int64, [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "hps_precond_prec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int, ctypes.c_int]),
     "hps_assemble_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -245,11 +252,12 @@ class Context:
 
     def kernel_times(self, reset: bool = False) -> dict:
         """Event-timed operator / preconditioner launches since the last reset."""
-        out = (ctypes.c_double * 6)()
+        out = (ctypes.c_double * 8)()
         _check(lib().hps_kernel_times(self._h, out, 1 if reset else 0))
         return {"apply_ms": out[0], "apply_launches": int(out[1]),
                 "precond_ms": out[2], "precond_launches": int(out[3]),
-                "gemm_ms": out[4], "gemm_launches": int(out[5])}
+                "gemm_ms": out[4], "gemm_launches": int(out[5]),
+                "iti_ms": out[6], "iti_launches": int(out[7])}
 
     def solve_bytes(self, restart: int, nrhs: int = 1, solver: str = "gmres",
                     precond_prec: str = "fp64") -> int:
@@ -297,6 +305,44 @@ class Context:
         self._sync_stream()
         _check(lib().hps_op_left(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x)))
         return y
+
+    # ------------------------------------------------- face-reduced system
+    def iti_build(self):
+        """Form the exact ItI map R and A_ii^{-1} of every leaf (face-reduced system)."""
+        self._sync_stream()
+        _check(lib().hps_iti_build(self._h))
+
+    def _nrhs_face(self, f) -> int:
+        nf = self.nl * self.nb
+        if f.numel() % nf:
+            raise ValueError(f"face vector length {f.numel()} is not a multiple of N_l n_b = {nf}")
+        return f.numel() // nf
+
+    def iti_apply(self, f, y=None):
+        """y = f + Pi (R f): the face-reduced operator."""
+        torch = _torch()
+        y = torch.empty_like(f) if y is None else y
+        self._sync_stream()
+        _check(lib().hps_iti_apply(self._h, _dev(f, "f"), _dev(y, "y"), self._nrhs_face(f)))
+        return y
+
+    def iti_rhs(self, s, t):
+        """t - Pi h: the right-hand side of the face-reduced system."""
+        torch = _torch()
+        nrhs = self._nrhs(s)
+        out = torch.empty(nrhs * self.nl * self.nb, dtype=s.dtype, device=s.device)
+        self._sync_stream()
+        _check(lib().hps_iti_rhs(self._h, _dev(s, "s"), _dev(t, "t"), _dev(out, "rhs_f"), nrhs))
+        return out
+
+    def iti_recover(self, s, t, f):
+        """u from the incoming impedance f (leaf solves with source s)."""
+        torch = _torch()
+        u = torch.empty_like(s)
+        self._sync_stream()
+        _check(lib().hps_iti_recover(self._h, _dev(s, "s"), _dev(t, "t"), _dev(f, "f"), _dev(u, "u"),
+                                     self._nrhs(s)))
+        return u
 
     def autotune(self, nrhs: int, prec: str = "fp32", reps: int = 3) -> int:
         """Time the block-GEMM tile shapes on this operator for nrhs right-hand
@@ -346,6 +392,15 @@ class Context:
             self.free()
         except Exception:
             pass
+
+
+def iti_bytes(n_elem, p) -> int:
+    """Device bytes hps_iti_build keeps for this mesh (no GPU needed)."""
+    ne = (ctypes.c_int * 3)(*[int(e) for e in n_elem])
+    v = int(lib().hps_iti_bytes(int(p), ne))
+    if v < 0:
+        raise HPSError(v, lib().hps_last_error().decode())
+    return v
 
 
 def setup_bytes(n_elem, p, block_precs=("fp64",), complex_medium=False):

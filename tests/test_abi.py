@@ -63,6 +63,10 @@ def test_null_arguments_are_rejected_without_a_device(L):
     assert L.hps_device_bytes(None) < 0
     assert L.hps_trim(None) == hps.HPS_ERR_ARG
     assert L.hps_solve_bytes(None, 30, 1, None) < 0
+    assert L.hps_iti_build(None) == hps.HPS_ERR_ARG
+    assert L.hps_iti_apply(None, z, z, 1) == hps.HPS_ERR_ARG and "hps_iti_apply" in _err(L)
+    assert L.hps_iti_rhs(None, z, z, z, 1) == hps.HPS_ERR_ARG
+    assert L.hps_iti_recover(None, z, z, z, z, 1) == hps.HPS_ERR_ARG
     L.hps_free(None)   # a no-op
 
 
@@ -135,3 +139,14 @@ def test_autotune_table_round_trip(L, tmp_path):
     with pytest.raises(hps.HPSError):
         hps.autotune_set(10, "fp32", 20, 6)
     hps.autotune_set(10, "fp32", 20, -1)
+
+
+def test_iti_bytes_is_the_documented_plan(L):
+    # R (n_b x n_b) and A_ii^-1 (n_i x n_i) complex per leaf, plus F_bi and A_ib (real, shared)
+    for p, n in ((10, (8, 8, 8)), (6, (2, 3, 1))):
+        n1 = p - 2
+        ni, nb, nl = n1 ** 3, 6 * n1 ** 2, n[0] * n[1] * n[2]
+        assert hps.iti_bytes(n, p) == 16 * nl * (nb * nb + ni * ni) + 16 * ni * nb
+    assert hps.iti_bytes((8, 8, 8), 10) == 512 * 16 * (384 ** 2 + 512 ** 2) + 16 * 512 * 384
+    with pytest.raises(hps.HPSError):
+        hps.iti_bytes((8, 0, 8), 10)

@@ -111,3 +111,37 @@ def test_full_size_solve_at_workload_tolerance(c2):
     u = u.cpu().numpy()
     err = np.linalg.norm(u[g["idx"]] - g["u"]) / np.linalg.norm(g["u"])
     assert err < 1e-6, err
+
+
+def test_full_size_face_system(c2):
+    # the face-reduced system with the exact ItI maps at the full size: the
+    # operator on sampled leaves (the oracle forms the maps of each sampled
+    # leaf's neighbours by dense leaf solves), then the solve against the
+    # oracle's converged solution
+    prob, ctx, d, xyz = c2
+    ctx.iti_build()
+    b_nodes = P.bump_field(prob, xyz)
+    C = O.c_values(d, b_nodes)
+    nb, m = d.nb, d.n1 * d.n1
+    f = _rand(d.nl * nb, 33)
+    y = ctx.iti_apply(torch.from_numpy(f).cuda()).cpu().numpy()
+    for tau in _sample_leaves(d)[:5]:
+        want = f[tau * nb:(tau + 1) * nb].copy()
+        for face in range(6):
+            nbr = O.neighbour(d, tau, face)
+            if nbr < 0:
+                continue
+            Rn = O.iti_map(d, C[nbr * d.n:nbr * d.n + d.ni], homogenized=False)
+            fp = O.PARTNER[face]
+            want[face * m:(face + 1) * m] += (Rn @ f[nbr * nb:(nbr + 1) * nb])[fp * m:(fp + 1) * m]
+        got = y[tau * nb:(tau + 1) * nb]
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-12, tau
+    g = _golden()
+    s, t = P.rhs_data(prob, xyz)
+    u, st, ok = ctx.gmres(torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda(), tol=1e-10,
+                          restart=prob.restart, solver="iti")
+    assert ok
+    u = u.cpu().numpy()
+    err = np.linalg.norm(u[g["idx"]] - g["u"]) / np.linalg.norm(g["u"])
+    assert err < 1e-8, err
+    ctx.trim()
