@@ -539,10 +539,13 @@ def run_serving(a):
     # independent requests (every request its own scatterer) with FP64 and BF16
     # blocks, and a stream where half of the requests reuse an earlier
     # request's scatterer (they join its running job or find it cached)
-    for label, prec, share in (("fp64", "fp64", 0.0), ("bf16", "bf16", 0.0),
-                               ("fp64_shared_operators", "fp64", 0.5)):
+    # (and, as a NEXT-row stream, FP64 operators whose blocks are shared on a
+    # lambda grid: setup and memory drop, the same solutions)
+    for label, prec, share, bucket in (("fp64", "fp64", 0.0, 0.0), ("bf16", "bf16", 0.0, 0.0),
+                                       ("fp64_shared_operators", "fp64", 0.5, 0.0),
+                                       ("fp64_lambda_buckets", "fp64", 0.0, 1e-2)):
         cfg = ServeConfig(slots=4, block_prec=prec, precond_prec=prec, solver="fgmres",
-                          restart=50, tol=1e-8)
+                          restart=50, tol=1e-8, lambda_bucket=bucket)
         # service capacity: the first requests back to back
         probe = P.request_stream(a.requests // 4, rate=1.0, seed=5, share=share)
         srv = Server(cfg)

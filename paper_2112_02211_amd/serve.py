@@ -127,6 +127,7 @@ class ServeConfig:
     max_batch: int = 64
     max_iters: int = 20000           # per request; beyond it the request is returned unconverged
     keep_solution_on_host: bool = True
+    lambda_bucket: float = 0.0       # > 0: operators share blocks on a lambda grid of this * kappa^2
 
 
 @dataclass
@@ -253,7 +254,8 @@ class Server:
                         self.cache.move_to_end(job.key)
                 setup = ctx is None
                 if setup:
-                    ctx = self.hps.Context.from_problem(prob0, block_precs=self._blocks())
+                    ctx = self.hps.Context.from_problem(prob0, block_precs=self._blocks(),
+                                                        lambda_bucket=cfg.lambda_bucket)
                 xyz = ctx.nodes()
                 N = ctx.N
                 t_now = time.perf_counter()

@@ -129,3 +129,28 @@ def test_per_rhs_residual_single_solvers(solver):
     assert ok and len(st["rhs_rel_res"]) == 2
     assert 0.0 < max(st["rhs_rel_res"]) <= 1e-10
     assert max(st["rhs_rel_res"]) == st["true_rel_res"]
+
+
+def test_lambda_bucketed_operators_serve_the_same_solutions():
+    # operators whose blocks are shared on a lambda grid change the
+    # preconditioner, not the system: every served solution matches the
+    # unbucketed server's and the oracle's direct solve
+    from paper_2112_02211_amd.serve import Server, ServeConfig, latency_stats
+    reqs = P.request_stream(8, rate=60.0, seed=13, meshes=(2, 3), orders=(6, 8), share=0.5)
+    srv = Server(ServeConfig(slots=3, tol=1e-10, restart=30, lambda_bucket=1e-2))
+    res = srv.run(_fresh(reqs), closed_loop=True)
+    shared = [(ctx.n_blocks, ctx.nl) for ctx in srv.cache.values()]
+    srv.close()
+    assert latency_stats(res)["all_converged"]
+    srv = Server(ServeConfig(slots=3, tol=1e-10, restart=30))
+    ref = srv.run(_fresh(reqs), closed_loop=True)
+    srv.close()
+    for r in reqs:
+        got = next(x for x in res if x.rid == r.rid)
+        want = next(x for x in ref if x.rid == r.rid)
+        assert np.linalg.norm(got.u - want.u) / np.linalg.norm(want.u) < 1e-8, r.rid
+    for r in reqs[:2]:
+        ud = O.solve_direct(O.build(r.prob))
+        got = next(x for x in res if x.rid == r.rid)
+        assert np.linalg.norm(got.u - ud) / np.linalg.norm(ud) < 1e-8
+    assert shared and all(b <= n for b, n in shared) and any(b < n for b, n in shared)
