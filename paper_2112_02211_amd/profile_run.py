@@ -61,6 +61,12 @@ def run(a):
     y = torch.empty_like(x)
     phases = [("apply", lambda: ctx.apply(x, y)), ("op_left", lambda: ctx.op_left(x, y))] + \
              [(f"precond_{q}", (lambda q=q: ctx.precond(x, y, prec=q))) for q in ("fp64", "fp32", "bf16")]
+    if a.iti:
+        # the face-reduced operator (exact ItI maps): its block product and exchange
+        ctx.iti_build()
+        f = torch.from_numpy(rng.standard_normal(ctx.nl * ctx.nb) + 0j).cuda()
+        g = torch.empty_like(f)
+        phases.append(("iti_apply", lambda: ctx.iti_apply(f, g)))
     n = a.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -121,11 +127,13 @@ def pmc_summary(a):
          "# commands (R = repository root on the GPU box; one counter per run):",
          "#   cd /tmp && export TMPDIR=/tmp",
          f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.fetch.rstrip('/'))} "
-         f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}",
+         f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}"
+         f"{' --iti' if a.iti else ''}",
          f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.write.rstrip('/'))} "
-         f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}",
+         f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}"
+         f"{' --iti' if a.iti else ''}",
          f"#   python -m paper_2112_02211_amd.profile_run pmc-summary --workload {a.workload} "
-         f"--launches {a.launches} --fetch <fetch dir> --write <write dir> --out <this file>",
+         f"--launches {a.launches}{' --iti' if a.iti else ''} --fetch <fetch dir> --write <write dir> --out <this file>",
          "#",
          f"# calibration: elementwise kernel dst = 2 src over {a.copy_mib} MiB float32 (reads and writes "
          f"{a.copy_mib << 20} bytes)",
@@ -160,6 +168,11 @@ def pmc_summary(a):
     sw_f, sw_w = _find(F, f"k_apply_sweep<{p},"), _find(W, f"k_apply_sweep<{p},")
     line("sweep", statistics.median(sw_f[1:]), statistics.median(sw_w[1:]),
          32 * N + 8 * nl * ni + face)
+    bg = [k for k in F if "k_bgemv<false" in k]
+    if bg:
+        # the face-reduced operator's block product: R (16 nb^2 per leaf), f in, g out
+        line("iti_block_product", med(_find(F, "k_bgemv<false")), med(_find(W, "k_bgemv<false")),
+             16 * nl * nb * nb + 32 * nl * nb)
     L += ["#",
           "# the FP64 J^-1 with the fused exchange is the kernel the benchmark's roofline reports",
           f"kernel_source_sha256_16: {kernel_source_hash()}",
@@ -192,6 +205,8 @@ def main():
     ap.add_argument("mode", nargs="?", default="run", choices=("run", "pmc-summary", "trace-summary"))
     ap.add_argument("--workload", default="bumps_8x8x8_p10")
     ap.add_argument("--launches", type=int, default=4)
+    ap.add_argument("--iti", action="store_true",
+                    help="run: also the face-reduced operator (builds the exact ItI maps)")
     ap.add_argument("--lambda-bucket", type=float, default=0.0,
                     help="run: lambda grid spacing (times kappa^2) of shared blocks; 0: one per leaf")
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
