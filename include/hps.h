@@ -146,6 +146,25 @@ typedef struct {
 int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b,
               int p, int q, const int n_elem[3], const hps_opts* o, hps_ctx** out);
 
+/* Operator group: nop operators (1 <= nop <= 64) on the same mesh (d, n_elem,
+ * p, q) with their own wave number kappa[op], impedance parameter eta[op] and
+ * medium media[op] (media NULL: all zero), built into one context so that
+ * every launch of the solve covers all of them (the batching of many small
+ * meshes in one launch; the leaves, tables and neighbours are shared, C,
+ * lambda and the blocks are stored per operator).  A vector of a group holds
+ * one right-hand side per operator, [op][N]: hps_apply, hps_precond,
+ * hps_op_left and hps_gmres take nrhs = nop (HPS_ERR_ARG otherwise), and
+ * hps_gmres iterates the nop systems in lock step, each with its own Krylov
+ * space, whatever solver is asked for (GMRES: left FP64; FGMRES or reduced
+ * precision: flexible).  hps_lambdas returns nop * N_l values.  Not combined
+ * with lambda buckets or the face-reduced system (HPS_ERR_UNSUPPORTED).
+ * Errors as hps_setup. */
+int hps_setup_group(const hps_domain* d, int nop, const double* kappa, const double* eta,
+                    const hps_medium* media, int p, int q, const int n_elem[3], const hps_opts* o,
+                    hps_ctx** out);
+/* Operators of a context: 1, or nop of hps_setup_group; -1 for NULL. */
+int hps_num_operators(const hps_ctx* c);
+
 /* N = (#leaves) * (p-2)^2 (p+4). */
 int64_t hps_num_unknowns(const hps_ctx* c);
 
@@ -153,7 +172,7 @@ int64_t hps_num_unknowns(const hps_ctx* c);
 int hps_nodes(const hps_ctx* c, double* xyz_host);
 
 /* Per-leaf homogenization constant lambda^tau (after the resonance guard);
- * lam_host receives (#leaves) complex values. */
+ * lam_host receives (#leaves) complex values (#operators * #leaves for a group). */
 int hps_lambdas(const hps_ctx* c, hps_z* lam_host);
 
 /* Number of stored homogenized blocks: the number of leaves, or of distinct

@@ -200,7 +200,7 @@ int build_blocks(hps_ctx* c, int precs) {
     const int cw = block_cw(q);
     Blocks& B = c->blk[q];
     B.ncp = (nb + cw - 1) / cw * cw;
-    B.bytes = (size_t)c->nblocks * B.ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
+    B.bytes = (size_t)c->nblocks * c->nop * B.ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
     int rc = dev_alloc(c, &B.data, B.bytes);
     if (rc) return rc;
   }
@@ -234,9 +234,14 @@ int build_blocks(hps_ctx* c, int precs) {
   rocblas_set_stream(handle, c->stream);
   std::vector<rocblas_int> hinfo(chunk);
   int status = HPS_OK;
+  // operator by operator (each with its own eta); blocks of operator op start at op * nblocks
+  const double eta0 = c->eta;
+  for (int op = 0; op < c->nop && status == HPS_OK; ++op) {
+  c->eta = c->etas.empty() ? eta0 : c->etas[op];
+  const double2* lam_op = lam + (int64_t)op * c->nblocks;
   for (int64_t e0 = 0; e0 < c->nblocks && status == HPS_OK; e0 += chunk) {
     const int ne = (int)std::min<int64_t>(chunk, c->nblocks - e0);
-    status = launch_build_schur(c, dP, dQ, lam, (int)e0, ne, S);
+    status = launch_build_schur(c, dP, dQ, lam_op, (int)e0, ne, S);
     if (status) break;
     auto* A = reinterpret_cast<rocblas_double_complex*>(S);
     if (rocsolver_zgetrf_strided_batched(handle, nb, nb, A, nb, (rocblas_stride)nb * nb, ipiv, nb,
@@ -250,7 +255,9 @@ int build_blocks(hps_ctx* c, int precs) {
       if (hinfo[i] != 0) {
         status = fail(HPS_ERR_NUMERIC, std::string("homogenized Schur complement of ") +
                                            (c->lambda_bucket > 0.0 ? "bucket " : "leaf ") +
-                                           std::to_string(e0 + i) + " is singular");
+                                           std::to_string(e0 + i) +
+                                           (c->nop > 1 ? " of operator " + std::to_string(op) : "") +
+                                           " is singular");
         break;
       }
     if (status) break;
@@ -260,8 +267,10 @@ int build_blocks(hps_ctx* c, int precs) {
       break;
     }
     for (int q = 0; q < 3 && status == HPS_OK; ++q)
-      if (c->blk[q].data) status = launch_pack_blocks(c, S, (int)e0, ne, q);
+      if (c->blk[q].data) status = launch_pack_blocks(c, S, (int)(op * c->nblocks + e0), ne, q);
   }
+  }
+  c->eta = eta0;
   hipStreamSynchronize(c->stream);
   rocblas_destroy_handle(handle);
   hipFree(S);
@@ -284,18 +293,29 @@ extern "C" {
 
 const char* hps_last_error(void) { return g_err.c_str(); }
 
-int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b, int p, int q,
-              const int n_elem[3], const hps_opts* o, hps_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+// Setup of nop operators on one mesh (nop = 1: hps_setup).  media: nop entries or NULL.
+int setup_impl(const hps_domain* d, int nop, const double* kappas, const double* etas,
+               const hps_medium* media, int p, int q, const int n_elem[3], const hps_opts* o,
+               hps_ctx** out) {
   g_err.clear();
   if (!out) return fail(HPS_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!d || !n_elem) return fail(HPS_ERR_ARG, "domain or n_elem is NULL");
   if (p < kMinP || p > kMaxP) return fail(HPS_ERR_UNSUPPORTED, "p must lie in [4, 16]");
   if (q != p - 2) return fail(HPS_ERR_UNSUPPORTED, "q must equal p - 2 (face nodes are the interior Chebyshev nodes of each face)");
-  if (!(kappa > 0.0) || !std::isfinite(kappa) || !std::isfinite(eta) || eta == 0.0)
-    return fail(HPS_ERR_ARG, "kappa must be positive and eta nonzero");
+  for (int op = 0; op < nop; ++op) {
+    const double kappa = kappas[op], eta = etas[op];
+    if (!(kappa > 0.0) || !std::isfinite(kappa) || !std::isfinite(eta) || eta == 0.0)
+      return fail(HPS_ERR_ARG, "kappa must be positive and eta nonzero");
+  }
   if (o && (!(o->lambda_bucket >= 0.0) || !std::isfinite(o->lambda_bucket)))
     return fail(HPS_ERR_ARG, "lambda_bucket must be a finite number >= 0");
+  if (nop > 1 && o && o->lambda_bucket > 0.0)
+    return fail(HPS_ERR_UNSUPPORTED, "lambda buckets are not available for operator groups");
   double hs[3];
   for (int a = 0; a < 3; ++a) {
     if (n_elem[a] < 1) return fail(HPS_ERR_ARG, "n_elem must be >= 1");
@@ -304,11 +324,14 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   }
   if (std::fabs(hs[1] - hs[0]) > 1e-12 * hs[0] || std::fabs(hs[2] - hs[0]) > 1e-12 * hs[0])
     return fail(HPS_ERR_ARG, "leaves must be cubes");
-  if (b && b->kind == HPS_MEDIUM_BUMPS && b->n_bumps > 0 &&
-      (!b->centres || !b->amps || !(b->width > 0.0)))
-    return fail(HPS_ERR_ARG, "bump medium needs centres, amplitudes and a positive width");
-  if (b && b->kind == HPS_MEDIUM_NODAL && !b->nodal) return fail(HPS_ERR_ARG, "nodal medium is NULL");
-  if (b && (b->kind < 0 || b->kind > 2)) return fail(HPS_ERR_ARG, "unknown medium kind");
+  for (int op = 0; op < nop; ++op) {
+    const hps_medium* b = media ? &media[op] : nullptr;
+    if (b && b->kind == HPS_MEDIUM_BUMPS && b->n_bumps > 0 &&
+        (!b->centres || !b->amps || !(b->width > 0.0)))
+      return fail(HPS_ERR_ARG, "bump medium needs centres, amplitudes and a positive width");
+    if (b && b->kind == HPS_MEDIUM_NODAL && !b->nodal) return fail(HPS_ERR_ARG, "nodal medium is NULL");
+    if (b && (b->kind < 0 || b->kind > 2)) return fail(HPS_ERR_ARG, "unknown medium kind");
+  }
   const int precs = (o && o->block_precs) ? o->block_precs : HPS_PREC_FP64;
   if (precs & ~7) return fail(HPS_ERR_ARG, "unknown block precision bits");
 
@@ -322,8 +345,11 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   for (int a = 0; a < 3; ++a) { c->E[a] = n_elem[a]; c->lo[a] = d->lo[a]; }
   c->nl = (int64_t)n_elem[0] * n_elem[1] * n_elem[2];
   c->N = c->nl * c->n;
-  c->kappa = kappa;
-  c->eta = eta;
+  c->nop = nop;
+  c->kappas.assign(kappas, kappas + nop);
+  c->etas.assign(etas, etas + nop);
+  c->kappa = kappas[0];
+  c->eta = etas[0];
   c->h = hs[0];
   c->stream = o ? static_cast<hipStream_t>(o->stream) : nullptr;
   c->verbose = o ? o->verbose : 0;
@@ -378,29 +404,56 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
                                      hipMemcpyHostToDevice, c->stream), "upload neighbours")))
     return bail(rc);
 
-  // medium: C = kappa^2 (1 - b) at interior nodes
-  int nbump = 0;
-  double* d_bc = nullptr;
-  double2* d_ba = nullptr;
+  // medium: C = kappa^2 (1 - b) at interior nodes, and lambda^tau, operator by
+  // operator into slices of C and lambda (C is complex for all if any needs it)
   c->c_complex = 0;
-  if (b && b->kind == HPS_MEDIUM_NODAL) c->c_complex = 1;
-  if (b && b->kind == HPS_MEDIUM_BUMPS && b->n_bumps > 0) {
-    nbump = b->n_bumps;
-    for (int i = 0; i < nbump; ++i)
-      if (b->amps[i].im != 0.0) c->c_complex = 1;
-    if ((rc = dev_alloc(c, (void**)&d_bc, sizeof(double) * 3 * nbump))) return bail(rc);
-    if ((rc = dev_alloc(c, (void**)&d_ba, sizeof(double2) * nbump))) return bail(rc);
-    hipMemcpyAsync(d_bc, b->centres, sizeof(double) * 3 * nbump, hipMemcpyHostToDevice, c->stream);
-    hipMemcpyAsync(d_ba, b->amps, sizeof(double2) * nbump, hipMemcpyHostToDevice, c->stream);
+  for (int op = 0; op < nop; ++op) {
+    const hps_medium* b = media ? &media[op] : nullptr;
+    if (b && b->kind == HPS_MEDIUM_NODAL) c->c_complex = 1;
+    if (b && b->kind == HPS_MEDIUM_BUMPS)
+      for (int i = 0; i < b->n_bumps; ++i)
+        if (b->amps[i].im != 0.0) c->c_complex = 1;
   }
-  const size_t cbytes = (size_t)c->nl * c->ni * (c->c_complex ? 16 : 8);
-  if ((rc = dev_alloc(c, &c->d_C, cbytes))) return bail(rc);
-  if ((rc = launch_eval_medium(c, b, d_bc, d_ba, nbump))) return bail(rc);
-  if ((rc = dev_alloc(c, (void**)&c->d_lambda, sizeof(double2) * c->nl))) return bail(rc);
-  if ((rc = launch_lambda(c))) return bail(rc);
+  const size_t cslice = (size_t)c->nl * c->ni * (c->c_complex ? 16 : 8);
+  if ((rc = dev_alloc(c, &c->d_C, cslice * nop))) return bail(rc);
+  if ((rc = dev_alloc(c, (void**)&c->d_lambda, sizeof(double2) * c->nl * nop))) return bail(rc);
+  void* const C0 = c->d_C;
+  double2* const lam0 = c->d_lambda;
+  int shifted = 0;
+  for (int op = 0; op < nop && rc == HPS_OK; ++op) {
+    const hps_medium* b = media ? &media[op] : nullptr;
+    int nbump = 0;
+    double* d_bc = nullptr;
+    double2* d_ba = nullptr;
+    if (b && b->kind == HPS_MEDIUM_BUMPS && b->n_bumps > 0) {
+      nbump = b->n_bumps;
+      if ((rc = dev_alloc(c, (void**)&d_bc, sizeof(double) * 3 * nbump))) break;
+      if ((rc = dev_alloc(c, (void**)&d_ba, sizeof(double2) * nbump))) break;
+      hipMemcpyAsync(d_bc, b->centres, sizeof(double) * 3 * nbump, hipMemcpyHostToDevice, c->stream);
+      hipMemcpyAsync(d_ba, b->amps, sizeof(double2) * nbump, hipMemcpyHostToDevice, c->stream);
+    }
+    c->kappa = kappas[op];
+    c->d_C = static_cast<char*>(C0) + cslice * op;
+    c->d_lambda = lam0 + c->nl * op;
+    rc = launch_eval_medium(c, b, d_bc, d_ba, nbump);
+    if (!rc) rc = launch_lambda(c);
+    shifted += c->n_shifted;
+    hipStreamSynchronize(c->stream);
+    if (d_bc) { hipFree(d_bc); c->dev_bytes -= sizeof(double) * 3 * nbump; }
+    if (d_ba) { hipFree(d_ba); c->dev_bytes -= sizeof(double2) * nbump; }
+  }
+  c->d_C = C0;
+  c->d_lambda = lam0;
+  c->kappa = kappas[0];
+  c->n_shifted = shifted;
+  if (rc) return bail(rc);
+  if (nop > 1) {
+    if ((rc = dev_alloc(c, (void**)&c->d_eta, sizeof(double) * nop))) return bail(rc);
+    if ((rc = check_hip(hipMemcpyAsync(c->d_eta, etas, sizeof(double) * nop, hipMemcpyHostToDevice,
+                                       c->stream), "upload eta")))
+      return bail(rc);
+  }
   if (c->lambda_bucket > 0.0 && (rc = make_buckets(c))) return bail(rc);
-  if (d_bc) { hipFree(d_bc); c->dev_bytes -= sizeof(double) * 3 * nbump; }
-  if (d_ba) { hipFree(d_ba); c->dev_bytes -= sizeof(double2) * nbump; }
   const double t1 = now();
   // dense homogenized blocks
   int pb = 0;
@@ -415,6 +468,27 @@ int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b
   *out = c;
   return HPS_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int hps_setup(const hps_domain* d, double kappa, double eta, const hps_medium* b, int p, int q,
+              const int n_elem[3], const hps_opts* o, hps_ctx** out) {
+  return setup_impl(d, 1, &kappa, &eta, b, p, q, n_elem, o, out);
+}
+
+int hps_setup_group(const hps_domain* d, int nop, const double* kappa, const double* eta,
+                    const hps_medium* media, int p, int q, const int n_elem[3], const hps_opts* o,
+                    hps_ctx** out) {
+  g_err.clear();
+  if (out) *out = nullptr;
+  if (nop < 1 || nop > kMaxBatch || !kappa || !eta)
+    return fail(HPS_ERR_ARG, "hps_setup_group: needs 1 <= nop <= 64 and kappa, eta arrays");
+  return setup_impl(d, nop, kappa, eta, media, p, q, n_elem, o, out);
+}
+
+int hps_num_operators(const hps_ctx* c) { return c ? c->nop : -1; }
 
 int hps_set_timing(hps_ctx* c, int enable) {
   if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
@@ -448,6 +522,7 @@ void hps_free(hps_ctx* c) {
   hipFree(c->d_nbr);
   hipFree(c->d_C);
   hipFree(c->d_lambda);
+  hipFree(c->d_eta);
   hipFree(c->d_bpos);
   hipFree(c->d_gofs);
   hipFree(c->d_gblk);
@@ -557,8 +632,8 @@ int hps_nodes(const hps_ctx* c, double* xyz) {
 
 int hps_lambdas(const hps_ctx* c, hps_z* lam) {
   if (!c || !lam) return fail(HPS_ERR_ARG, "NULL argument");
-  int rc = check_hip(hipMemcpyAsync(lam, c->d_lambda, sizeof(double2) * c->nl, hipMemcpyDeviceToHost,
-                                    c->stream), "lambda copy");
+  int rc = check_hip(hipMemcpyAsync(lam, c->d_lambda, sizeof(double2) * c->nl * c->nop,
+                                    hipMemcpyDeviceToHost, c->stream), "lambda copy");
   if (rc) return rc;
   return check_hip(hipStreamSynchronize(c->stream), "lambda copy");
 }

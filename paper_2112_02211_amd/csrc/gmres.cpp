@@ -90,7 +90,7 @@ void solve_bytes_stats(const hps_ctx* c, const Job& job, int nb, hps_stats* st) 
     st->bytes_precond = 0.0;
     return;
   }
-  const bool fused = !job.flexible && nb < kBatchedMinRhs && !(c->lambda_bucket > 0.0);
+  const bool fused = !job.flexible && (nb < kBatchedMinRhs || c->nop > 1) && !(c->lambda_bucket > 0.0);
   st->bytes_apply = bytes_apply(c) - (fused ? face : 0.0);
   st->bytes_precond = bytes_precond(c, job.prec) + (fused ? face : 0.0);
 }
@@ -537,13 +537,13 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
   }
   const bool flexible = o.solver == HPS_SOLVER_FGMRES ||
                         (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64);
-  const int64_t nbat = o.solver == HPS_SOLVER_BLOCK ? std::min(nrhs, kMaxBatch) : 1;
+  const int64_t nbat = (o.solver == HPS_SOLVER_BLOCK || c->nop > 1) ? std::min(nrhs, kMaxBatch) : 1;
   const int64_t vec = 16 * c->N * nbat;
   int64_t bytes = vec * ((restart + 1) + (flexible ? restart : 0) + 1);  // basis (+Z) + tmp
   bytes += (int64_t)sizeof(GmresState) * nbat + 32 * nbat;               // Hessenberg state
   bytes += (int64_t)kPartSlots * kRedBlocks * 16 * nbat;                  // reduction partials
   bytes += 16 * nbat * c->nl * c->nb;                                     // face buffer
-  if (nbat >= kBatchedMinRhs || c->lambda_bucket > 0.0)
+  if ((nbat >= kBatchedMinRhs && c->nop == 1) || c->lambda_bucket > 0.0)
     bytes += nbat * c->nl * c->nb * (16 + 16) + 256;                      // H, U panels
   bytes += 16 * c->N * nrhs;                                              // assembled b
   return bytes;
@@ -565,6 +565,8 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     return fail(HPS_ERR_ARG, "unknown precond_prec");
   if (!c->blk[prec].data) return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
   if (o.solver < 0 || o.solver > 3) return fail(HPS_ERR_ARG, "unknown solver");
+  if (c->nop > 1 && nrhs != c->nop)
+    return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator (nrhs = number of operators)");
   if (o.solver == HPS_SOLVER_ITI) {
     if (!c->d_itiR) return fail(HPS_ERR_ARG, "the face-reduced solver needs hps_iti_build first");
     if (o.use_x0) return fail(HPS_ERR_ARG, "the face-reduced solver starts from f = 0 (use_x0 unsupported)");
@@ -621,7 +623,8 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     job.flexible = (o.solver == HPS_SOLVER_FGMRES) || prec != kFP64;
     job.prec = prec;
     job.n = c->N;
-    if (o.solver == HPS_SOLVER_BLOCK) {
+    // operator groups always run their right-hand sides in lock step (one per operator)
+    if (o.solver == HPS_SOLVER_BLOCK || c->nop > 1) {
       hps_stats acc{};
       for (int r0 = 0; r0 < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); r0 += kMaxBatch) {
         job.nrhs = std::min(kMaxBatch, nrhs - r0);

@@ -83,8 +83,15 @@ struct hps_ctx {
   hps::DevTables dt{};
   int* d_nbr = nullptr;             // [nl][6], -1 on the boundary
   int c_complex = 0;                // C stored as complex (else real)
-  void* d_C = nullptr;              // [nl][ni] kappa^2 (1 - b) at interior nodes
-  double2* d_lambda = nullptr;      // [nl] lambda^tau (rounded when lambda_bucket > 0)
+  void* d_C = nullptr;              // [nop][nl][ni] kappa^2 (1 - b) at interior nodes
+  double2* d_lambda = nullptr;      // [nop][nl] lambda^tau (rounded when lambda_bucket > 0)
+  // operator groups (hps_setup_group): nop operators on the same mesh (same
+  // leaves, tables and neighbours) with their own kappa, eta and medium; C,
+  // lambda and the blocks are stored per operator ([op][...]) and a vector of
+  // the group holds one right-hand side per operator ([op][N])
+  int nop = 1;
+  std::vector<double> kappas, etas;  // per operator
+  double* d_eta = nullptr;           // [nop] (groups only)
   // lambda buckets (lambda_bucket > 0): leaves with equal rounded lambda share
   // one block; buckets are numbered in order of their first leaf
   double lambda_bucket = 0.0;

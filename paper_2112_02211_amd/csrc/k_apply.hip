@@ -89,7 +89,8 @@ __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2
 template <int P, bool CC>
 __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
     const double2* __restrict__ x, double2* __restrict__ y, double2* __restrict__ g,
-    const void* __restrict__ Cv, const double* __restrict__ tab, double eta, int64_t nl, int64_t N) {
+    const void* __restrict__ Cv, const double* __restrict__ tab, double eta, int64_t nl, int64_t N,
+    int64_t cs, const double* __restrict__ etas) {
   using Lf = Leaf<P>;
   constexpr int NI = Lf::NI, NN = Lf::NN, NB = Lf::NB;
   constexpr int BD = sweep_threads<P>();
@@ -103,6 +104,9 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
   double2* gv = g + (rhs * nl + tau) * NB;
   const double* D = tab + tab_off_D(P);
   const double* D2 = tab + tab_off_D2(P);
+  // operator groups: right-hand side rhs belongs to operator rhs (its C and eta)
+  if (etas) eta = etas[rhs];
+  const int64_t cb = rhs * cs + tau * NI;
   // every load of the leaf is issued before the first LDS store (named
   // registers, not an array, so that the staging stays in VGPRs)
   constexpr int NLOAD = (NN + BD - 1) / BD;
@@ -132,8 +136,8 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
   for (int m = threadIdx.x; m < NI; m += BD) {
     const double2 v = U[Lf::grid_of(m)], acc = ACC[m];
     double2 cu;
-    if (CC) cu = cmul(static_cast<const double2*>(Cv)[tau * NI + m], v);
-    else cu = cscale(v, static_cast<const double*>(Cv)[tau * NI + m]);
+    if (CC) cu = cmul(static_cast<const double2*>(Cv)[cb + m], v);
+    else cu = cscale(v, static_cast<const double*>(Cv)[cb + m]);
     yv[m] = make_double2(acc.x - cu.x, acc.y - cu.y);
   }
 }
@@ -161,12 +165,14 @@ int sweep_launch(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs,
   dim3 grid((unsigned)c->nl, (unsigned)nrhs);
   const dim3 block(sweep_threads<P>());
   hipError_t e;
+  const int64_t cs = c->nop > 1 ? c->nl * c->ni : 0;
+  const double* etas = c->nop > 1 ? c->d_eta : nullptr;
   if (c->c_complex)
     e = launch_k(c, e0, e1, k_apply_sweep<P, true>, grid, block, x, y, g, (const void*)c->d_C,
-                 (const double*)c->d_tab, c->eta, c->nl, c->N);
+                 (const double*)c->d_tab, c->eta, c->nl, c->N, cs, etas);
   else
     e = launch_k(c, e0, e1, k_apply_sweep<P, false>, grid, block, x, y, g, (const void*)c->d_C,
-                 (const double*)c->d_tab, c->eta, c->nl, c->N);
+                 (const double*)c->d_tab, c->eta, c->nl, c->N, cs, etas);
   return check_hip(e, "k_apply_sweep");
 }
 
@@ -174,6 +180,8 @@ int sweep_launch(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs,
 
 int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
                  hipEvent_t e1) {
+  // an operator group's kernels read operator rhs's C and eta for right-hand side rhs
+  if (c->nop > 1 && nrhs != c->nop) return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator");
   switch (c->p) {
     case 4: return sweep_launch<4>(c, x, y, g, nrhs, e0, e1);
     case 5: return sweep_launch<5>(c, x, y, g, nrhs, e0, e1);

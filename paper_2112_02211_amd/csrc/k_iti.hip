@@ -256,6 +256,7 @@ int64_t iti_ws_bytes(const hps_ctx* c, int nrhs) {
 
 int iti_build(hps_ctx* c) {
   if (c->d_itiR) return HPS_OK;
+  if (c->nop > 1) return fail(HPS_ERR_UNSUPPORTED, "the face-reduced system is not available for operator groups");
   const int ni = c->ni, nb = c->nb;
   const int64_t nl = c->nl;
   std::vector<double> Fbi, Nbb, Aib;

@@ -31,19 +31,20 @@ int precond_launch(hps_ctx* c, const double2* x, const double2* g, double2* y, i
   const dim3 block(PL<P>::BD);
   const void* blk = B.data;
   const int* nbr = c->d_nbr;
+  const int64_t os = c->nop > 1 ? c->nl : 0;   // operator groups: blocks and lambda per operator
   hipError_t e;
   switch (prec) {
     case kFP64:
       e = launch_k(c, e0, e1, k_precond_fused<P, kFP64>, grid, block, x, g, nbr, y, blk, B.ncp,
-                   c->d_lambda, c->d_tab, c->nl, c->N);
+                   c->d_lambda, c->d_tab, c->nl, c->N, os);
       break;
     case kFP32:
       e = launch_k(c, e0, e1, k_precond_fused<P, kFP32>, grid, block, x, g, nbr, y, blk, B.ncp,
-                   c->d_lambda, c->d_tab, c->nl, c->N);
+                   c->d_lambda, c->d_tab, c->nl, c->N, os);
       break;
     default:
       e = launch_k(c, e0, e1, k_precond_fused<P, kBF16>, grid, block, x, g, nbr, y, blk, B.ncp,
-                   c->d_lambda, c->d_tab, c->nl, c->N);
+                   c->d_lambda, c->d_tab, c->nl, c->N, os);
       break;
   }
   return check_hip(e, "k_precond_fused");
@@ -55,8 +56,9 @@ int launch_precond_fused(hps_ctx* c, const double2* x, const double2* g, double2
                          int prec, hipEvent_t e0, hipEvent_t e1) {
   if (prec < 0 || prec > 2 || !c->blk[prec].data)
     return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
-  // the fused kernel reads block tau for leaf tau: one block per leaf only
+  // the fused kernel reads block tau (+ nl * operator) for leaf tau: one block per leaf only
   if (c->nblocks != c->nl) return fail(HPS_ERR_ARG, "fused J^-1 needs one block per leaf");
+  if (c->nop > 1 && nrhs != c->nop) return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator");
   switch (c->p) {
     case 4: return precond_launch<4>(c, x, g, y, nrhs, prec, e0, e1);
     case 5: return precond_launch<5>(c, x, g, y, nrhs, prec, e0, e1);
@@ -81,7 +83,8 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
   TimedPair tp;
   int rc = timing_pair(c, 1, &tp);
   if (rc) return rc;
-  if (nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0)
+  // the GEMM path shares one block across right-hand sides: not for operator groups
+  if ((nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0) && c->nop == 1)
     rc = launch_precond_batched(c, x, y, nrhs, prec, tp.start, tp.stop);
   else rc = launch_precond_fused(c, x, nullptr, y, nrhs, prec, tp.start, tp.stop);
   if (rc) {
@@ -93,7 +96,7 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
 
 int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec) {
   int rc;
-  if (nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0) {
+  if ((nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0) && c->nop == 1) {
     if ((rc = launch_apply(c, x, tmp, nrhs))) return rc;
     return launch_precond(c, tmp, y, nrhs, prec);
   }

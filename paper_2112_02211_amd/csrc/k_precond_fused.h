@@ -199,7 +199,7 @@ template <int P, int PREC>
 __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
     const double2* __restrict__ x, const double2* __restrict__ g, const int* __restrict__ nbr,
     double2* __restrict__ y, const void* __restrict__ blk, int ncp, const double2* __restrict__ lam,
-    const double* __restrict__ tab, int64_t nl, int64_t N) {
+    const double* __restrict__ tab, int64_t nl, int64_t N, int64_t os) {
   using Q = PL<P>;
   constexpr int N1 = Q::N1, L = Q::L, NI = Q::NI, NB = Q::NB, NN = Q::NN, BD = Q::BD;
   __shared__ double2 T[NI];
@@ -211,7 +211,9 @@ __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
   const int rhs = blockIdx.y;
   const double2* xv = x + rhs * N + tau * NN;
   double2* yv = y + rhs * N + tau * NN;
-  const double2 lm = lam[tau];
+  // block and lambda of this leaf (operator groups: of right-hand side rhs's operator)
+  const int64_t bk = tau + rhs * os;
+  const double2 lm = lam[bk];
   // element-parallel Algorithm 3 while the block product's scratch Up can hold
   // the n1^3 tensor (n1 <= 12); line-wise above that
   constexpr bool EL = Q::SLOTS >= NI;
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
   // needs (loads complete in order, so anything issued later would wait for
   // them), and arrive while Algorithm 3 and the face update run.
   BlockPrefetch<P, PREC, kPrefetch<P, PREC>> pf;
-  pf.issue(blk, tau, ncp);
+  pf.issue(blk, bk, ncp);
   __syncthreads();
   // f_i = A~_ii^{-1} x_i
   if constexpr (EL) homog_solve_el<P, BD>(T, Up, LT, lm);
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(PL<P>::BD, PL<P>::MINW) void k_precond_fused(
   else face_update_g<P, BD>(T, H, tab);
   __syncthreads();
   // u_b = S~^{-1} h_b, written to y_b and kept in LDS
-  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4), kPrefetch<P, PREC>>(blk, tau, ncp, H, Up, U, yv + NI, pf);
+  block_gemv<P, PREC, (PREC == kFP64 ? 8 : 4), kPrefetch<P, PREC>>(blk, bk, ncp, H, Up, U, yv + NI, pf);
   __syncthreads();
   // t = A_ib u_b
   if constexpr (EL) interior_from_faces<P, BD>(U, T, LT + lt_c0<P>(), LT + lt_c1<P>(), 1);

@@ -74,6 +74,11 @@ SIGNATURES = {
                                  ctypes.POINTER(_Medium), ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_Opts),
                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "hps_setup_group": (ctypes.c_int, [ctypes.POINTER(_Domain), ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_Opts),
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "hps_num_operators": (ctypes.c_int, [ctypes.c_void_p]),
     "hps_num_unknowns": (ctypes.c_int64, [ctypes.c_void_p]),
     "hps_num_blocks": (ctypes.c_int64, [ctypes.c_void_p]),
     "hps_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -178,24 +183,9 @@ class Context:
             m = float(max(self.n_elem))
             hi = tuple(float(e) / m for e in self.n_elem)
         dom = _Domain((ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi))
-        med = _Medium()
         self._keep = []
-        if nodal_b is not None:
-            med.kind = MEDIUM_NODAL
-            med.nodal = _dev(nodal_b, "nodal_b")
-            self._keep.append(nodal_b)
-        elif bump_centres is not None and len(bump_centres) > 0:
-            c = np.ascontiguousarray(np.asarray(bump_centres, dtype=np.float64).reshape(-1, 3))
-            a = np.asarray(bump_amps, dtype=np.complex128)
-            za = (_Z * len(a))(*[_Z(float(v.real), float(v.imag)) for v in a])
-            med.kind = MEDIUM_BUMPS
-            med.n_bumps = len(a)
-            med.centres = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            med.amps = za
-            med.width = float(bump_width)
-            self._keep += [c, za]
-        else:
-            med.kind = MEDIUM_ZERO
+        med = _Medium()
+        _fill_medium(med, self._keep, bump_centres, bump_amps, bump_width, nodal_b)
         bits = 0
         for name in block_precs:
             bits |= PREC[name]
@@ -207,6 +197,10 @@ class Context:
         qq = self.p - 2 if q is None else int(q)
         _check(L.hps_setup(ctypes.byref(dom), self.kappa, self.eta, ctypes.byref(med), self.p, qq,
                            ne, ctypes.byref(opts), ctypes.byref(handle)))
+        self._attach(handle)
+
+    def _attach(self, handle):
+        L = lib()
         self._h = handle
         self.N = int(L.hps_num_unknowns(handle))
         n1 = self.p - 2
@@ -214,6 +208,48 @@ class Context:
         self.n = self.ni + self.nb
         self.nl = int(np.prod(self.n_elem))
         self.n_blocks = int(L.hps_num_blocks(handle))
+        self.n_ops = int(L.hps_num_operators(handle))
+
+    @classmethod
+    def group(cls, probs, block_precs=("fp64",), verbose: bool = False) -> "Context":
+        """One context for several problems on the same mesh (n_elem, p, box)
+        with their own kappa, eta and medium: every launch covers all of them,
+        and vectors hold one right-hand side per problem ([op][N])."""
+        L = lib()
+        p0 = probs[0]
+        for pr in probs[1:]:
+            if (tuple(pr.n_elem), pr.p, tuple(pr.lo), tuple(pr.hi)) != (tuple(p0.n_elem), p0.p, tuple(p0.lo),
+                                                                       tuple(p0.hi)):
+                raise ValueError("a group needs the same mesh (n_elem, p, box) for every problem")
+        self = cls.__new__(cls)
+        self.n_elem = tuple(int(e) for e in p0.n_elem)
+        self.p = int(p0.p)
+        self.kappa = float(p0.kappa)
+        self.eta = float(p0.eta)
+        self.lambda_bucket = 0.0
+        self._keep = []
+        k = len(probs)
+        meds = (_Medium * k)()
+        for i, pr in enumerate(probs):
+            if pr.plane_dir is not None or len(pr.bump_centres) == 0:
+                _fill_medium(meds[i], self._keep, None, None, 0.08, None)
+            else:
+                _fill_medium(meds[i], self._keep, pr.bump_centres, pr.bump_amps, pr.bump_width, None)
+        bits = 0
+        for name in block_precs:
+            bits |= PREC[name]
+        self.block_precs = tuple(block_precs)
+        kap = (ctypes.c_double * k)(*[float(pr.kappa) for pr in probs])
+        eta = (ctypes.c_double * k)(*[float(pr.eta) for pr in probs])
+        dom = _Domain((ctypes.c_double * 3)(*p0.lo), (ctypes.c_double * 3)(*p0.hi))
+        opts = _Opts(bits, _stream_ptr(), 1 if verbose else 0, 0.0)
+        ne = (ctypes.c_int * 3)(*self.n_elem)
+        handle = ctypes.c_void_p()
+        _check(L.hps_setup_group(ctypes.byref(dom), k, kap, eta, ctypes.cast(meds, ctypes.c_void_p), self.p,
+                                 self.p - 2, ne, ctypes.byref(opts), ctypes.byref(handle)))
+        self._keep.append(meds)
+        self._attach(handle)
+        return self
 
     @classmethod
     def from_problem(cls, prob, block_precs=("fp64",), verbose=False,
@@ -241,7 +277,7 @@ class Context:
 
     def lambdas(self) -> np.ndarray:
         self._sync_stream()
-        out = np.zeros(self.nl, dtype=np.complex128)
+        out = np.zeros(self.nl * getattr(self, "n_ops", 1), dtype=np.complex128)
         _check(lib().hps_lambdas(self._h, out.ctypes.data_as(ctypes.POINTER(_Z))))
         return out
 
@@ -392,6 +428,26 @@ class Context:
             self.free()
         except Exception:
             pass
+
+
+def _fill_medium(med, keep, bump_centres, bump_amps, bump_width, nodal_b):
+    """Fill an hps_medium: nodal b (device tensor), Gaussian bumps, or zero."""
+    if nodal_b is not None:
+        med.kind = MEDIUM_NODAL
+        med.nodal = _dev(nodal_b, "nodal_b")
+        keep.append(nodal_b)
+    elif bump_centres is not None and len(bump_centres) > 0:
+        c = np.ascontiguousarray(np.asarray(bump_centres, dtype=np.float64).reshape(-1, 3))
+        a = np.asarray(bump_amps, dtype=np.complex128)
+        za = (_Z * len(a))(*[_Z(float(v.real), float(v.imag)) for v in a])
+        med.kind = MEDIUM_BUMPS
+        med.n_bumps = len(a)
+        med.centres = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        med.amps = za
+        med.width = float(bump_width)
+        keep += [c, za]
+    else:
+        med.kind = MEDIUM_ZERO
 
 
 def iti_bytes(n_elem, p) -> int:

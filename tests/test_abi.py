@@ -150,3 +150,20 @@ def test_iti_bytes_is_the_documented_plan(L):
     assert hps.iti_bytes((8, 8, 8), 10) == 512 * 16 * (384 ** 2 + 512 ** 2) + 16 * 512 * 384
     with pytest.raises(hps.HPSError):
         hps.iti_bytes((8, 0, 8), 10)
+
+
+def test_group_setup_argument_checks(L):
+    d = hps._Domain((ctypes.c_double * 3)(0, 0, 0), (ctypes.c_double * 3)(1, 1, 1))
+    ne = (ctypes.c_int * 3)(2, 2, 2)
+    out = ctypes.c_void_p()
+    k = (ctypes.c_double * 3)(10.0, 12.0, 14.0)
+    for nop in (0, 65):
+        assert L.hps_setup_group(ctypes.byref(d), nop, k, k, None, 8, 6, ne, None, ctypes.byref(out)) == hps.HPS_ERR_ARG
+    assert L.hps_setup_group(ctypes.byref(d), 3, None, k, None, 8, 6, ne, None, ctypes.byref(out)) == hps.HPS_ERR_ARG
+    bad = (ctypes.c_double * 3)(10.0, -1.0, 14.0)
+    assert L.hps_setup_group(ctypes.byref(d), 3, bad, k, None, 8, 6, ne, None, ctypes.byref(out)) == hps.HPS_ERR_ARG
+    opts = hps._Opts(1, None, 0, 0.01)
+    assert L.hps_setup_group(ctypes.byref(d), 3, k, k, None, 8, 6, ne, ctypes.byref(opts),
+                             ctypes.byref(out)) == hps.HPS_ERR_UNSUPPORTED and "groups" in _err(L)
+    assert not out.value
+    assert L.hps_num_operators(None) == -1
