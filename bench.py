@@ -209,7 +209,7 @@ def main():
                      "true_rel_res": st2["true_rel_res"],
                      "err_vs_oracle": oracle_check(a.workload, uu.cpu().numpy())}
 
-    # NEXT row: lambda buckets (leaves whose homogenized lambda round to the same
+    # Extension: lambda buckets (leaves whose homogenized lambda round to the same
     # grid point share one block; J^-1 becomes one GEMM per shared block).  The
     # same system and tolerance; reported beside the main line, not as its value.
     buckets = {}
@@ -240,7 +240,7 @@ def main():
             "err_vs_oracle": oracle_check(a.workload, ub.cpu().numpy())}
         del bctx
 
-    # NEXT row: the face-reduced system with the exact ItI maps of the leaves
+    # Extension: the face-reduced system with the exact ItI maps of the leaves
     # (unknowns: incoming impedance on the leaf faces; the same discrete u)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -442,68 +442,6 @@ def run_batched(a, prob):
                              tol=1e-10, restart=30, solver="fgmres", precond_prec=prec)
         ur = U[r * N:(r + 1) * N]
         errs.append(float(torch.linalg.norm(ur - u1) / torch.linalg.norm(u1)))
-    # NEXT row: lambda buckets (leaves whose homogenized lambda round to the same
-    # grid point share one block; J^-1 becomes one GEMM per shared block).  The
-    # same system and tolerance; reported beside the main line, not as its value.
-    buckets = {}
-    for delta in BUCKET_DELTAS:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        bctx = hps.Context.from_problem(prob, lambda_bucket=delta)
-        torch.cuda.synchronize()
-        b_setup = time.perf_counter() - t1
-        ub = torch.zeros_like(s)
-        bctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=ub, check_every=a.check_every)
-        ub.zero_()
-        bctx.set_timing(True, every=TIMING_EVERY)
-        bctx.kernel_times(reset=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, stb, okb = bctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=ub,
-                                 check_every=a.check_every)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        ktb = bctx.kernel_times(reset=True)
-        bctx.set_timing(False)
-        buckets[f"delta_{delta:g}"] = {
-            "blocks": bctx.n_blocks, "leaves": bctx.nl, "setup_s": round(b_setup, 3),
-            "device_bytes": bctx.device_bytes(), "solve_ms": round(dt * 1e3, 2),
-            "iters": stb["iters"], "converged": bool(okb), "true_rel_res": stb["true_rel_res"],
-            "precond_avg_launch_ms": round(ktb["precond_ms"] / max(1, ktb["precond_launches"]), 5),
-            "err_vs_oracle": oracle_check(a.workload, ub.cpu().numpy())}
-        del bctx
-
-    # NEXT row: the face-reduced system with the exact ItI maps of the leaves
-    # (unknowns: incoming impedance on the leaf faces; the same discrete u)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.iti_build()
-    torch.cuda.synchronize()
-    iti_build_s = time.perf_counter() - t1
-    uf = torch.zeros_like(s)
-    ctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=uf, solver="iti", check_every=a.check_every)
-    ctx.set_timing(True, every=TIMING_EVERY)
-    ctx.kernel_times(reset=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    _, sti, oki = ctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=uf, solver="iti",
-                            check_every=a.check_every)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
-    kti = ctx.kernel_times(reset=True)
-    ctx.set_timing(False)
-    r_ms = kti["iti_ms"] / max(1, kti["iti_launches"])
-    r_bytes = 16.0 * ctx.nl * ctx.nb * ctx.nb + 32.0 * ctx.nl * ctx.nb   # R, f in, g out
-    r_gbs = r_bytes / (r_ms * 1e-3) / 1e9
-    iti = {"build_s": round(iti_build_s, 3), "device_bytes": hps.iti_bytes(prob.n_elem, prob.p),
-           "solve_ms": round(dt * 1e3, 2), "iters": sti["iters"], "converged": bool(oki),
-           "face_true_rel_res": sti["true_rel_res"],
-           "err_vs_oracle": oracle_check(a.workload, uf.cpu().numpy()),
-           "iti_block_kernel": {"avg_launch_ms": round(r_ms, 5), "algorithmic_GBs": round(r_gbs, 1),
-                                "frac_of_hbm_peak": round(r_gbs / HBM_PEAK_GBS, 4),
-                                "algorithmic_bytes_per_launch": r_bytes}}
-    ctx.trim()
-
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Munknowns/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(elapsed / a.steps * 1e3, 3),
@@ -539,13 +477,14 @@ def run_serving(a):
     # independent requests (every request its own scatterer) with FP64 and BF16
     # blocks, and a stream where half of the requests reuse an earlier
     # request's scatterer (they join its running job or find it cached)
-    # (and, as a NEXT-row stream, FP64 operators whose blocks are shared on a
-    # lambda grid: setup and memory drop, the same solutions)
-    for label, prec, share, bucket in (("fp64", "fp64", 0.0, 0.0), ("bf16", "bf16", 0.0, 0.0),
-                                       ("fp64_shared_operators", "fp64", 0.5, 0.0),
-                                       ("fp64_lambda_buckets", "fp64", 0.0, 1e-2)):
+    # (and two extensions: FP64 operators whose blocks are shared on a lambda
+    # grid, and lone requests on one mesh solved in operator groups)
+    for label, prec, share, bucket, groups in (("fp64", "fp64", 0.0, 0.0, 0), ("bf16", "bf16", 0.0, 0.0, 0),
+                                               ("fp64_shared_operators", "fp64", 0.5, 0.0, 0),
+                                               ("fp64_lambda_buckets", "fp64", 0.0, 1e-2, 0),
+                                               ("fp64_operator_groups", "fp64", 0.0, 0.0, 8)):
         cfg = ServeConfig(slots=4, block_prec=prec, precond_prec=prec, solver="fgmres",
-                          restart=50, tol=1e-8, lambda_bucket=bucket)
+                          restart=50, tol=1e-8, lambda_bucket=bucket, group_ops=groups)
         # service capacity: the first requests back to back
         probe = P.request_stream(a.requests // 4, rate=1.0, seed=5, share=share)
         srv = Server(cfg)

@@ -25,6 +25,11 @@ work as slots and HBM free up:
   current iterate, so a request sees the same iteration whether it runs in
   one call or tick by tick, alone or in a batch.
 
+* **operator groups** (optional): requests that are alone on their operator
+  but share a mesh (leaf grid, order, box) with other queued requests are
+  solved as one operator group: one context holds all their operators and
+  every launch of the solve covers all of them.
+
 Latency of a request = completion (solution copied to the host) - arrival.
 `Scheduler` is the policy and has no GPU dependency; `Server` executes it.
 """
@@ -53,12 +58,18 @@ def operator_key(prob: P.Problem) -> str:
     return h.hexdigest()[:16]
 
 
+def shape_key(prob: P.Problem) -> tuple:
+    """Problems with equal shape keys share a mesh and can form an operator group."""
+    return (tuple(prob.n_elem), prob.p, tuple(prob.lo), tuple(prob.hi))
+
+
 @dataclass
 class Job:
     key: str
     requests: list
     need_bytes: int
     needs_setup: bool
+    group: bool = False      # an operator group: one request per operator, one shared mesh
 
 
 @dataclass
@@ -72,6 +83,7 @@ class Scheduler:
     size_fn: Callable
     max_batch: int = 64
     starve_s: float = 2.0
+    group_ops: int = 0       # > 1: requests alone on their operator are grouped by mesh, up to this many
     pending: list = field(default_factory=list)
 
     def submit(self, req, now: float):
@@ -93,6 +105,15 @@ class Scheduler:
             seen.add(key)
             batch = [r for r in self.pending if r.key == key][: self.max_batch]
             resident = key in resident_keys
+            if self.group_ops > 1 and len(batch) == 1 and not resident:
+                grp = self._group_for(req, busy_keys, resident_keys)
+                if len(grp) > 1:
+                    need = sum(int(self.size_fn(r.key, r.prob, 1, False)) for r in grp)
+                    if used_bytes + need <= self.budget or used_bytes - evictable_bytes + need <= self.budget:
+                        ids = {id(r) for r in grp}
+                        self.pending = [r for r in self.pending if id(r) not in ids]
+                        gkey = "group:" + "+".join(r.key for r in grp)
+                        return Job(gkey, grp, need, True, group=True)
             need = int(self.size_fn(key, req.prob, len(batch), resident))
             fits = used_bytes + need <= self.budget
             fits_after_evict = used_bytes - evictable_bytes + need <= self.budget
@@ -103,6 +124,22 @@ class Scheduler:
             if i == 0 and head_waits:
                 return None   # the oldest request has waited long enough: no backfill
         return None
+
+    def _group_for(self, head, busy_keys, resident_keys) -> list:
+        """head and the oldest pending requests on other operators of the same
+        mesh that are alone on their operator, neither running nor cached."""
+        shape = shape_key(head.prob)
+        count = collections.Counter(r.key for r in self.pending)
+        grp, keys = [head], {head.key}
+        for r in self.pending:
+            if len(grp) >= self.group_ops:
+                break
+            if r.key in keys or r.key in busy_keys or r.key in resident_keys or count[r.key] > 1:
+                continue
+            if shape_key(r.prob) == shape:
+                grp.append(r)
+                keys.add(r.key)
+        return grp
 
     def take(self, key: str, n: int) -> list:
         """Up to n pending requests on operator `key` (oldest first), removed from
@@ -128,6 +165,8 @@ class ServeConfig:
     max_iters: int = 20000           # per request; beyond it the request is returned unconverged
     keep_solution_on_host: bool = True
     lambda_bucket: float = 0.0       # > 0: operators share blocks on a lambda grid of this * kappa^2
+    group_ops: int = 0               # > 1: requests alone on their operator run in operator groups
+                                     # of up to this many on the same mesh (one launch for all)
 
 
 @dataclass
@@ -181,7 +220,7 @@ class Server:
         self.busy: set = set()
         self.running_bytes = 0
         self.results: List[Result] = []
-        self.sched = Scheduler(self.budget, self._size, cfg.max_batch)
+        self.sched = Scheduler(self.budget, self._size, cfg.max_batch, group_ops=cfg.group_ops)
         self.streams = [torch.cuda.Stream() for _ in range(cfg.slots)]
         self.free_slots = list(range(cfg.slots))
         self.errors: list = []
@@ -240,10 +279,71 @@ class Server:
         job.need_bytes += extra
         return True
 
+    def _run_group(self, stream, job: Job, job_id: int):
+        """An operator group: one context for all operators of the job (same
+        mesh), their requests advanced in lock step one restart cycle per tick;
+        each request is returned when it converges (it keeps riding along, as
+        a no-op, until the whole group has)."""
+        torch = self.torch
+        cfg = self.cfg
+        ctx = self.hps.Context.group([r.prob for r in job.requests], block_precs=self._blocks())
+        try:
+            xyz = ctx.nodes()
+            N = ctx.N
+            t_now = time.perf_counter()
+            act = [self._activate(r, xyz, t_now) for r in job.requests]
+            k = len(act)
+            S = torch.cat([a.s for a in act])
+            T = torch.cat([a.t for a in act])
+            U = torch.zeros_like(S)
+            single = cfg.solver if cfg.precond_prec == "fp64" else "fgmres"
+            left = set(range(k))
+            while left:
+                _, st, _ = ctx.gmres(S, T, tol=cfg.tol, restart=cfg.restart, u=U, solver=single,
+                                     precond_prec=cfg.precond_prec, max_iters=cfg.restart, use_x0=True)
+                res = st["rhs_rel_res"]
+                done = []
+                for i in sorted(left):
+                    a = act[i]
+                    a.iters += st["iters"]
+                    a.ticks += 1
+                    a.batch = k
+                    if res[i] <= cfg.tol or a.iters >= cfg.max_iters:
+                        done.append(i)
+                if done:
+                    uh = [U[i * N:(i + 1) * N].cpu().numpy() if cfg.keep_solution_on_host else None
+                          for i in done]
+                    stream.synchronize()
+                    t_fin = time.perf_counter()
+                    with self.lock:
+                        for i, u_i in zip(done, uh):
+                            a = act[i]
+                            self.results.append(Result(
+                                a.req.rid, a.req.key, a.req.t_arrival, a.start, t_fin, a.iters, k, True,
+                                bool(res[i] <= cfg.tol), float(res[i]), N, u_i, job_id, a.ticks))
+                    left -= set(done)
+            stream.synchronize()
+        finally:
+            ctx.free()
+
     def _run_job(self, slot: int, job: Job, job_id: int):
         torch = self.torch
         cfg = self.cfg
         stream = self.streams[slot]
+        if job.group:
+            try:
+                with torch.cuda.stream(stream):
+                    self._run_group(stream, job, job_id)
+            except Exception as e:  # reported after the run
+                with self.lock:
+                    self.errors.append((job.key, repr(e)))
+            finally:
+                with self.lock:
+                    self.busy.discard(job.key)
+                    self.running_bytes -= job.need_bytes
+                    self.free_slots.append(slot)
+                    self.lock.notify_all()
+            return
         try:
             with torch.cuda.stream(stream):
                 prob0 = job.requests[0].prob

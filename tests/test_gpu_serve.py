@@ -154,3 +154,26 @@ def test_lambda_bucketed_operators_serve_the_same_solutions():
         got = next(x for x in res if x.rid == r.rid)
         assert np.linalg.norm(got.u - ud) / np.linalg.norm(ud) < 1e-8
     assert shared and all(b <= n for b, n in shared) and any(b < n for b, n in shared)
+
+
+def test_operator_groups_serve_the_same_solutions():
+    # requests alone on their operator and sharing a mesh are solved in operator
+    # groups (one launch for all); each solution equals the one served alone
+    from paper_2112_02211_amd.serve import Server, ServeConfig, latency_stats
+    reqs = P.request_stream(10, rate=60.0, seed=14, meshes=(2,), orders=(6,), share=0.0)
+    srv = Server(ServeConfig(slots=2, tol=1e-10, restart=30, group_ops=4))
+    res = srv.run(_fresh(reqs), closed_loop=True)
+    srv.close()
+    st = latency_stats(res)
+    assert st["all_converged"] and st["requests"] == len(reqs)
+    assert max(r.batch for r in res) > 1                         # groups were formed
+    for r in reqs:
+        srv1 = Server(ServeConfig(slots=1, tol=1e-10, restart=30))
+        alone = srv1.run(_fresh([r]), closed_loop=True)[0]
+        srv1.close()
+        got = next(x for x in res if x.rid == r.rid)
+        assert np.linalg.norm(got.u - alone.u) / np.linalg.norm(alone.u) < 1e-8, r.rid
+    op = O.build(reqs[0].prob)
+    got = next(x for x in res if x.rid == reqs[0].rid)
+    ud = O.solve_direct(op)
+    assert np.linalg.norm(got.u - ud) / np.linalg.norm(ud) < 1e-8

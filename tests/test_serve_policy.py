@@ -91,3 +91,30 @@ def test_take_pulls_the_oldest_requests_of_one_operator():
     assert [r.rid for r in s.pending] == [1, 3, 4]
     assert s.take("a", 0) == [] and [r.rid for r in s.take("a", 5)] == [4]
     assert s.take("zzz", 3) == []
+
+
+def test_operator_groups_collect_lone_requests_on_one_mesh():
+    # requests alone on their operator and on the same mesh form one group job
+    # (oldest first, up to group_ops); operators with several requests, running
+    # or cached operators, and other meshes are left alone
+    m8 = P.bump_problem("m", (2, 2, 2), 8, 10.0, 3, 1, 1, 30, 1e-8)
+    m6 = P.bump_problem("m", (2, 2, 2), 6, 10.0, 3, 1, 1, 30, 1e-8)
+    s = Scheduler(budget=10_000, size_fn=size_fn, group_ops=3)
+    for rid, (key, prob) in enumerate([("a", m8), ("b", m6), ("c", m8), ("d", m8), ("d", m8),
+                                       ("e", m8), ("f", m8), ("g", m8)]):
+        s.submit(Req(rid, key, 1, prob), 0.0)
+    j = s.next_job({"f"}, {"e"}, 0, 0.0)
+    assert j.group and [r.rid for r in j.requests] == [0, 2, 7]     # a, c, g (d has two, e cached, f busy)
+    assert j.need_bytes == 3 * size_fn(None, None, 1, False) and j.needs_setup
+    j = s.next_job({"f"}, {"e"}, 0, 0.0)
+    assert not j.group and j.key == "b"                              # no partner on the p = 6 mesh
+    j = s.next_job({"f"}, {"e"}, 0, 0.0)
+    assert not j.group and j.key == "d" and len(j.requests) == 2
+    j = s.next_job({"f"}, {"e"}, 0, 0.0)
+    assert not j.group and j.key == "e" and not j.needs_setup
+    assert s.next_job({"f"}, {"e"}, 0, 0.0) is None                  # f still busy
+    # off by default
+    s = Scheduler(budget=10_000, size_fn=size_fn)
+    for rid, key in enumerate("xyz"):
+        s.submit(Req(rid, key, 1, m8), 0.0)
+    assert not s.next_job(set(), set(), 0, 0.0).group
