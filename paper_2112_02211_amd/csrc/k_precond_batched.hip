@@ -150,7 +150,12 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   constexpr int GCT = GCOLS / 16;   // column tiles per wavefront
   using TR = GemmTraits<PREC>;
   using HT = typename TR::H;
-  constexpr int CW = TR::CW, KT = TR::KT, CH = 4 * CW;  // inner indices per MFMA chunk
+  // inner indices per stage (FP64 with 64-column panels: 16, for the registers)
+  constexpr int KT = (PREC == kFP64 && GCOLS == 64) ? 16 : TR::KT;
+  constexpr int CW = TR::CW, CH = 4 * CW;  // inner indices per MFMA chunk
+  // narrow panels load H one stage ahead (latency-bound small groups); 64-column
+  // panels load it in the stage (registers for occupancy)
+  constexpr bool HPF = GCOLS <= 32;
   __shared__ HT Bs[KT][GCOLS + TR::PAD];
   // group: a leaf (nrhs columns), or with gofs a run of leaves of one lambda
   // bucket, whose columns are the nrhs columns of each leaf, stored
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
     }
   };
   // H[c0 .. c0+GCOLS-1][kt .. kt+KT-1] of one stage, HR entries per thread,
-  // also loaded one stage ahead into registers, then stored as Bs[inner][col]
+  // loaded into registers (one stage ahead when HPF), then stored as Bs[inner][col]
   constexpr int HN = KT * GCOLS, HR = (HN + 64 * GW - 1) / (64 * GW);
   auto load_h = [&](int kt, HT* dst) {
 #pragma unroll
@@ -210,9 +215,10 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
   uint4 a16[NCH], nx16[NCH];
   HT hr[HR];
   load_stage(0, a16);
-  load_h(0, hr);
+  if constexpr (HPF) load_h(0, hr);
   for (int kt = 0; kt < NB; kt += KT) {
     __syncthreads();
+    if constexpr (!HPF) load_h(kt, hr);
 #pragma unroll
     for (int i = 0; i < HR; ++i) {
       const int idx = threadIdx.x + i * 64 * GW;
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
     }
     __syncthreads();
     load_stage(kt + KT, nx16);
-    load_h(kt + KT, hr);
+    if constexpr (HPF) load_h(kt + KT, hr);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const int kin0 = c * CH + CW * g;  // first inner index (within the stage) of this lane
