@@ -234,26 +234,40 @@ __global__ __launch_bounds__(64 * GW) void k_block_gemm(const void* __restrict__
       if constexpr (PREC == kFP64) {
         const double ar = __hiloint2double(a16[c].y, a16[c].x);
         const double ai = __hiloint2double(a16[c].w, a16[c].z);
+        // each accumulator takes its two products of a chunk in the same order as
+        // always (re: ar br, then -ai bi; im: ar bi, then ai br); the products of
+        // different accumulators are interleaved so that no matrix-core
+        // instruction waits on the one just issued
+        double2 bv[GCT];
+#pragma unroll
+        for (int t = 0; t < GCT; ++t) bv[t] = reinterpret_cast<const double2&>(Bs[kin0][t * 16 + li]);
 #pragma unroll
         for (int t = 0; t < GCT; ++t) {
-          const double2 bv = reinterpret_cast<const double2&>(Bs[kin0][t * 16 + li]);
-          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv.x, are[t], 0, 0, 0);
-          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, -bv.y, are[t], 0, 0, 0);
-          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv.y, aim[t], 0, 0, 0);
-          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bv.x, aim[t], 0, 0, 0);
+          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv[t].x, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv[t].y, aim[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < GCT; ++t) {
+          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, -bv[t].y, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bv[t].x, aim[t], 0, 0, 0);
         }
       } else if constexpr (PREC == kFP32) {
         const float a_r[2] = {__uint_as_float(a16[c].x), __uint_as_float(a16[c].z)};
         const float a_i[2] = {__uint_as_float(a16[c].y), __uint_as_float(a16[c].w)};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
+          float2 bv[GCT];
+#pragma unroll
+          for (int t = 0; t < GCT; ++t) bv[t] = reinterpret_cast<const float2&>(Bs[kin0 + s][t * 16 + li]);
 #pragma unroll
           for (int t = 0; t < GCT; ++t) {
-            const float2 bv = reinterpret_cast<const float2&>(Bs[kin0 + s][t * 16 + li]);
-            are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r[s], bv.x, are[t], 0, 0, 0);
-            are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i[s], -bv.y, are[t], 0, 0, 0);
-            aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r[s], bv.y, aim[t], 0, 0, 0);
-            aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i[s], bv.x, aim[t], 0, 0, 0);
+            are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r[s], bv[t].x, are[t], 0, 0, 0);
+            aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r[s], bv[t].y, aim[t], 0, 0, 0);
+          }
+#pragma unroll
+          for (int t = 0; t < GCT; ++t) {
+            are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i[s], -bv[t].y, are[t], 0, 0, 0);
+            aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i[s], bv[t].x, aim[t], 0, 0, 0);
           }
         }
       } else {
