@@ -233,11 +233,13 @@ int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec);
 
 /* Right-hand side b of Sec. 3.1: s at interior nodes, t at face nodes on the
  * boundary of Omega, 0 at interface nodes.  s, t, b: device, nrhs * N complex
- * in library node order (entries of s and t at other nodes are ignored). */
+ * in library node order (entries of s and t at other nodes are ignored); t may
+ * be NULL for zero boundary data (no N-vector of zeros needs to exist).  The
+ * same holds for t in hps_gmres, hps_iti_rhs and hps_iti_recover. */
 int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int nrhs);
 
 /* Solve A u = b(s, t) (Sec. 4, eq. (globalsystem)) by the solver in so.
- *   s, t     device, nrhs * N complex (see hps_assemble_rhs)
+ *   s, t     device, nrhs * N complex (see hps_assemble_rhs; t may be NULL)
  *   tol      relative residual target, each right-hand side: ||J^-1 r|| <=
  *            tol ||J^-1 b|| with left preconditioning (HPS_SOLVER_GMRES, and
  *            BLOCK with FP64 blocks: the paper's PCRR, Sec. 6), ||r|| <= tol ||b||

@@ -663,7 +663,7 @@ int hps_op_left(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
 }
 
 int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int nrhs) {
-  if (!c || !s || !t || !b || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_assemble_rhs");
+  if (!c || !s || !b || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_assemble_rhs");
   return launch_assemble_rhs(c, reinterpret_cast<const double2*>(s),
                              reinterpret_cast<const double2*>(t), reinterpret_cast<double2*>(b), nrhs);
 }

@@ -551,7 +551,7 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
 
 extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
                          hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st) {
-  if (!c || !s || !t || !u || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_gmres");
+  if (!c || !s || !u || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_gmres");
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(HPS_ERR_ARG, "tol must lie in (0, 1)");
   if (restart < 1 || restart > kMaxRestart) return fail(HPS_ERR_ARG, "restart must lie in [1, 200]");
   hps_solve_opts o{};

@@ -485,7 +485,7 @@ extern "C" int hps_iti_apply(hps_ctx* c, const hps_z* f, hps_z* y, int nrhs) {
 }
 
 extern "C" int hps_iti_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* rhs_f, int nrhs) {
-  if (!c || !s || !t || !rhs_f || nrhs < 1) return fail(HPS_ERR_ARG, "hps_iti_rhs: bad arguments");
+  if (!c || !s || !rhs_f || nrhs < 1) return fail(HPS_ERR_ARG, "hps_iti_rhs: bad arguments");
   if (!c->d_itiR) return fail(HPS_ERR_ARG, "hps_iti_rhs: call hps_iti_build first");
   int rc = ws_reserve(c, &c->w_b, sizeof(double2) * c->N * nrhs);
   if (rc) return rc;
@@ -497,7 +497,7 @@ extern "C" int hps_iti_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* rh
 }
 
 extern "C" int hps_iti_recover(hps_ctx* c, const hps_z* s, const hps_z* t, const hps_z* f, hps_z* u, int nrhs) {
-  if (!c || !s || !t || !f || !u || nrhs < 1) return fail(HPS_ERR_ARG, "hps_iti_recover: bad arguments");
+  if (!c || !s || !f || !u || nrhs < 1) return fail(HPS_ERR_ARG, "hps_iti_recover: bad arguments");
   if (!c->d_itiR) return fail(HPS_ERR_ARG, "hps_iti_recover: call hps_iti_build first");
   int rc = ws_reserve(c, &c->w_b, sizeof(double2) * c->N * nrhs);
   if (rc) return rc;

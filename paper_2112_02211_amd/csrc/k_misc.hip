@@ -20,7 +20,7 @@ __global__ void k_assemble_rhs(const double2* __restrict__ s, const double2* __r
     v = s[off];
   } else {
     const int f = (m - ni) / L;
-    v = nbr[tau * 6 + f] < 0 ? t[off] : make_double2(0.0, 0.0);
+    v = (t && nbr[tau * 6 + f] < 0) ? t[off] : make_double2(0.0, 0.0);   // t null: no boundary data
   }
   b[off] = v;
 }

@@ -155,6 +155,11 @@ def _stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _dev_opt(t, name: str):
+    """_dev, or NULL for None (optional arguments such as zero boundary data)."""
+    return None if t is None else _dev(t, name)
+
+
 def _dev(t, name: str):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex128:
@@ -368,7 +373,7 @@ class Context:
         nrhs = self._nrhs(s)
         out = torch.empty(nrhs * self.nl * self.nb, dtype=s.dtype, device=s.device)
         self._sync_stream()
-        _check(lib().hps_iti_rhs(self._h, _dev(s, "s"), _dev(t, "t"), _dev(out, "rhs_f"), nrhs))
+        _check(lib().hps_iti_rhs(self._h, _dev(s, "s"), _dev_opt(t, "t"), _dev(out, "rhs_f"), nrhs))
         return out
 
     def iti_recover(self, s, t, f):
@@ -376,7 +381,7 @@ class Context:
         torch = _torch()
         u = torch.empty_like(s)
         self._sync_stream()
-        _check(lib().hps_iti_recover(self._h, _dev(s, "s"), _dev(t, "t"), _dev(f, "f"), _dev(u, "u"),
+        _check(lib().hps_iti_recover(self._h, _dev(s, "s"), _dev_opt(t, "t"), _dev(f, "f"), _dev(u, "u"),
                                      self._nrhs(s)))
         return u
 
@@ -392,7 +397,7 @@ class Context:
         torch = _torch()
         b = torch.empty_like(s) if b is None else b
         self._sync_stream()
-        _check(lib().hps_assemble_rhs(self._h, _dev(s, "s"), _dev(t, "t"), _dev(b, "b"),
+        _check(lib().hps_assemble_rhs(self._h, _dev(s, "s"), _dev_opt(t, "t"), _dev(b, "b"),
                                       self._nrhs(s)))
         return b
 
@@ -400,6 +405,7 @@ class Context:
               precond_prec: str = "fp64", max_iters: int = 0, check_every: int = 1,
               use_x0: bool = False, raise_on_nc: bool = False, orth: str = "dcgs"):
         """Solve A u = b(s, t); returns (u, stats dict, converged flag).
+        t may be None: zero boundary data.
 
         orth: "dcgs" (delayed reorthogonalization, two passes per step; restart
         <= 64) or "cgs2" (classical Gram-Schmidt twice, three passes)."""
@@ -411,7 +417,7 @@ class Context:
                         int(check_every), ORTH[orth], ctypes.cast(res, ctypes.POINTER(ctypes.c_double)))
         st = Stats()
         self._sync_stream()
-        rc = lib().hps_gmres(self._h, _dev(s, "s"), _dev(t, "t"), float(tol), int(restart),
+        rc = lib().hps_gmres(self._h, _dev(s, "s"), _dev_opt(t, "t"), float(tol), int(restart),
                              _dev(u, "u"), nrhs, ctypes.byref(so), ctypes.byref(st))
         _check(rc, allow_nc=not raise_on_nc)
         d = st.as_dict()

@@ -44,6 +44,7 @@ class Problem:
     restart: int = 30
     tol: float = 1e-10
     lambda_bucket: float = 0.0     # > 0: leaves share blocks on a lambda grid of spacing this * kappa^2
+    max_steps: int = 0             # > 0: benchmark bound on GMRES steps per solve
 
     @property
     def q(self) -> int:
@@ -248,6 +249,15 @@ def workload(name: str) -> Problem:
         # per-leaf blocks would need 725 GB, so the blocks are shared on a lambda grid
         prob = bump_problem(name, (32, 32, 32), 16, 96.0 * np.pi, 20, 1, seed=6, restart=50, tol=1e-8)
         prob.lambda_bucket = 1e-2
+        return prob
+    if name == "bumps_64x64x64_p16":
+        # 64^3 leaves at n_c = 16 (1,027,604,480 unknowns), kappa = 192 pi: 96 wavelengths
+        # across, the 64^3 size of the paper's 8-points-per-wavelength table.  A complex vector
+        # is 16.4 GB, so 288 GB of HBM hold a GMRES basis of restart 8 with the other vectors;
+        # the benchmark bounds the steps per solve
+        prob = bump_problem(name, (64, 64, 64), 16, 192.0 * np.pi, 20, 1, seed=7, restart=8, tol=1e-8)
+        prob.lambda_bucket = 1e-2
+        prob.max_steps = 800
         return prob
     raise KeyError(name)
 

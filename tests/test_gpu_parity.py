@@ -278,3 +278,15 @@ def test_invariant_krylov_space_breakdown(hps_mod, solver):
     # step 2 is queued: three steps at most
     assert st["iters"] <= (3 if solver == "gmres" else 12)
     assert rel(host(u), O.solve_direct(op)) < 1e-10
+
+
+def test_missing_boundary_data_means_zero(hps_mod):
+    # t = None (NULL at the C-ABI): zero boundary data, bit-equal to passing zeros
+    prob, ctx, op = _setup(hps_mod, CASES[1])
+    s, t = P.rhs_data(prob, ctx.nodes())
+    assert not np.any(t)
+    z = np.zeros_like(s)
+    assert np.array_equal(host(ctx.assemble_rhs(dev(s), None)), host(ctx.assemble_rhs(dev(s), dev(z))))
+    u0, _, ok0 = ctx.gmres(dev(s), dev(z), tol=1e-10, restart=30)
+    u1, _, ok1 = ctx.gmres(dev(s), None, tol=1e-10, restart=30)
+    assert ok0 and ok1 and np.array_equal(host(u0), host(u1))
