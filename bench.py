@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--max-steps", type=int, default=0,
                     help="bound on GMRES steps per solve of the shared-block workloads (0: the workload's)")
-    ap.add_argument("--requests", type=int, default=64,
+    ap.add_argument("--requests", type=int, default=512,
                     help="requests of the serving workload (request_stream)")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="block precision of the many-right-hand-side workload")
@@ -511,15 +511,19 @@ def run_serving(a):
         # service capacity: the first requests back to back
         probe = P.request_stream(a.requests // 4, rate=1.0, seed=5, share=share)
         srv = Server(cfg)
-        res = srv.run(fresh(probe), closed_loop=True)
+        res = srv.run(fresh(probe), closed_loop=True, progress_every=32)
         srv.close()
         cap = latency_stats(res)["solves_per_s"]
+        print(f"{label}: capacity {cap:.2f} solves/s from {len(res)} back-to-back requests",
+              file=sys.stderr, flush=True)
         rate = 0.75 * cap
         reqs = P.request_stream(a.requests, rate=rate, seed=5, share=share)
         srv = Server(cfg)
         t0 = time.perf_counter()
-        res = srv.run(fresh(reqs))
+        res = srv.run(fresh(reqs), progress_every=64)
         wall = time.perf_counter() - t0
+        print(f"{label}: {len(res)} requests served at {rate:.2f}/s in {wall:.1f} s",
+              file=sys.stderr, flush=True)
         srv.close()
         st = latency_stats(res)
         st.update({"capacity_solves_per_s": round(cap, 3), "arrival_rate_per_s": round(rate, 3),

@@ -37,6 +37,7 @@ from __future__ import annotations
 
 import collections
 import hashlib
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -422,10 +423,13 @@ class Server:
                 self.lock.notify_all()
 
     def run(self, requests: List[P.Request], time_scale: float = 1.0,
-            closed_loop: bool = False) -> List[Result]:
+            closed_loop: bool = False, progress_every: int = 0) -> List[Result]:
         """Serve a request stream.  Arrivals are replayed in real time (scaled by
-        time_scale), or all at once if closed_loop.  Returns the results."""
+        time_scale), or all at once if closed_loop.  Returns the results.  With
+        progress_every > 0, a line goes to stderr each time that many more
+        requests have finished."""
         t0 = time.perf_counter()
+        reported = 0
         order = sorted(requests, key=lambda r: r.arrival)
         for r in order:
             r.key = operator_key(r.prob)
@@ -455,6 +459,10 @@ class Server:
                         th.start()
                         workers.append(th)
                         started = True
+                if progress_every > 0 and len(self.results) >= reported + progress_every:
+                    reported = len(self.results) - len(self.results) % progress_every
+                    print(f"served {len(self.results)}/{len(arrivals)} requests "
+                          f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
                 if ai >= len(arrivals) and not self.sched.pending and \
                         len(self.free_slots) == self.cfg.slots:
                     break
