@@ -78,9 +78,25 @@ typedef struct {
 #define HPS_PREC_FP64 1
 #define HPS_PREC_FP32 2
 #define HPS_PREC_BF16 4
+/* The FP64 J^-1 in separable form: the same preconditioner (on each leaf the
+ * exact inverse of the homogenized leaf matrix of eq. (block_pc) at lambda^tau)
+ * applied with no stored block.  With the face nodes at the interior Chebyshev
+ * nodes of each face, that matrix couples nodes along grid lines only, and each
+ * face row (eq. (flux) plus i eta) stays on the normal line of its node;
+ * eliminating the two end values of every line (a 2 x 2 system per line)
+ * leaves a Kronecker sum of one complex n1 x n1 line operator on the interior,
+ * which a complex fast diagonalization inverts as Algorithm 3 does the
+ * Dirichlet one.  Setup builds one small table per operator (no dense
+ * inverses, no solver library); J^-1 reads x and writes y once.  In
+ * block_precs: exclusive of HPS_PREC_FP64 (it replaces the FP64 blocks), may be
+ * combined with HPS_PREC_FP32 / HPS_PREC_BF16, and requires lambda_bucket = 0.
+ * Every call that takes an FP64 J^-1 (hps_precond, hps_op_left, hps_gmres with
+ * precond_prec 0 or HPS_PREC_FP64) then uses it; as a prec argument
+ * HPS_PREC_SEPARABLE names it explicitly.  hps_autotune does not apply. */
+#define HPS_PREC_SEPARABLE 8
 
 typedef struct {
-  int block_precs;     /* OR of HPS_PREC_*; 0 means HPS_PREC_FP64 */
+  int block_precs;     /* OR of HPS_PREC_* (see HPS_PREC_SEPARABLE); 0 means HPS_PREC_FP64 */
   void* stream;        /* hipStream_t; 0 = default stream */
   int verbose;         /* nonzero: setup timings on stderr */
   double lambda_bucket;/* 0: one homogenized block per leaf (the paper's method, Sec. 4.1).

@@ -125,6 +125,7 @@ int prec_index(int prec_flag) {
     case HPS_PREC_FP64: return kFP64;
     case HPS_PREC_FP32: return kFP32;
     case HPS_PREC_BF16: return kBF16;
+    case HPS_PREC_SEPARABLE: return kFP64;
     default: return -1;
   }
 }
@@ -333,7 +334,11 @@ int setup_impl(const hps_domain* d, int nop, const double* kappas, const double*
     if (b && (b->kind < 0 || b->kind > 2)) return fail(HPS_ERR_ARG, "unknown medium kind");
   }
   const int precs = (o && o->block_precs) ? o->block_precs : HPS_PREC_FP64;
-  if (precs & ~7) return fail(HPS_ERR_ARG, "unknown block precision bits");
+  if (precs & ~15) return fail(HPS_ERR_ARG, "unknown block precision bits");
+  if ((precs & HPS_PREC_SEPARABLE) && (precs & HPS_PREC_FP64))
+    return fail(HPS_ERR_ARG, "HPS_PREC_SEPARABLE replaces the FP64 blocks (do not set both)");
+  if ((precs & HPS_PREC_SEPARABLE) && o && o->lambda_bucket > 0.0)
+    return fail(HPS_ERR_ARG, "lambda buckets share dense blocks; the separable J^-1 has none");
 
   const double t0 = now();
   hps_ctx* c = new hps_ctx();
@@ -455,12 +460,27 @@ int setup_impl(const hps_domain* d, int nop, const double* kappas, const double*
   }
   if (c->lambda_bucket > 0.0 && (rc = make_buckets(c))) return bail(rc);
   const double t1 = now();
+  // separable form of the FP64 J^-1: one table per operator (its eta)
+  if (precs & HPS_PREC_SEPARABLE) {
+    const int ts = sep_table_size(p);
+    std::vector<double> all((size_t)2 * ts * nop), one;
+    for (int op = 0; op < nop; ++op) {
+      err = build_sep_table(c->tab, etas[op], &one);
+      if (!err.empty()) return bail(fail(HPS_ERR_NUMERIC, err));
+      std::copy(one.begin(), one.end(), all.begin() + (size_t)2 * ts * op);
+    }
+    if ((rc = dev_alloc(c, (void**)&c->d_sep, sizeof(double) * all.size()))) return bail(rc);
+    if ((rc = check_hip(hipMemcpyAsync(c->d_sep, all.data(), sizeof(double) * all.size(),
+                                       hipMemcpyHostToDevice, c->stream), "upload separable tables")))
+      return bail(rc);
+    c->sep = 1;
+  }
   // dense homogenized blocks
   int pb = 0;
   if (precs & HPS_PREC_FP64) pb |= 1 << kFP64;
   if (precs & HPS_PREC_FP32) pb |= 1 << kFP32;
   if (precs & HPS_PREC_BF16) pb |= 1 << kBF16;
-  if ((rc = build_blocks(c, pb))) return bail(rc);
+  if (pb && (rc = build_blocks(c, pb))) return bail(rc);
   if ((rc = check_hip(hipStreamSynchronize(c->stream), "setup"))) return bail(rc);
   if (c->verbose)
     std::fprintf(stderr, "[hps] setup: tables+medium %.3f s, blocks %.3f s, %.2f GB on device\n",
@@ -528,6 +548,7 @@ void hps_free(hps_ctx* c) {
   hipFree(c->d_gblk);
   hipFree(c->d_blam);
   for (auto& B : c->blk) hipFree(B.data);
+  hipFree(c->d_sep);
   hipFree(c->d_itiR);
   hipFree(c->d_Ainv);
   hipFree(c->d_Fbi);
@@ -558,6 +579,7 @@ int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex
   const int precs = block_precs ? block_precs : HPS_PREC_FP64;
   int64_t bytes = (int64_t)sizeof(double) * tab_size(p) + (int64_t)sizeof(int) * 6 * nl +
                   nl * ni * (complex_medium ? 16 : 8) + 16 * nl;
+  if (precs & HPS_PREC_SEPARABLE) bytes += 16 * (int64_t)sep_table_size(p);
   const int bits[3] = {HPS_PREC_FP64, HPS_PREC_FP32, HPS_PREC_BF16};
   for (int q = 0; q < 3; ++q) {
     if (!(precs & bits[q])) continue;
@@ -565,7 +587,9 @@ int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex
     const int64_t ncp = (nb + cw - 1) / cw * cw;
     bytes += nl * ncp * nb * (q == kFP64 ? 16 : (q == kFP32 ? 8 : 4));
   }
-  if (transient) {
+  if (transient && !(precs & (HPS_PREC_FP64 | HPS_PREC_FP32 | HPS_PREC_BF16))) {
+    *transient = 0;   // separable form only: no block build
+  } else if (transient) {
     const int64_t blk = nb * nb * 16;
     int64_t chunk = (int64_t)((1ull << 30) / blk);
     if (chunk < 1) chunk = 1;

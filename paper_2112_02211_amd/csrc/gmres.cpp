@@ -46,6 +46,7 @@ double bytes_apply(const hps_ctx* c) {
 }
 
 double bytes_precond(const hps_ctx* c, int q) {
+  if (q == kFP64 && c->sep) return 32.0 * c->N;   // separable form: x in, y out
   const double beta = q == kFP64 ? 16.0 : (q == kFP32 ? 8.0 : 4.0);
   double b = beta * c->nblocks * (double)c->nb * c->blk[q].ncp + 32.0 * c->N;
   // lambda buckets: the H and U panels go through HBM (written, then read)
@@ -535,15 +536,16 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
     bytes += 16 * c->N * nrhs;
     return bytes;
   }
-  const bool flexible = o.solver == HPS_SOLVER_FGMRES ||
-                        (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64);
+  const bool fp64_pc = o.precond_prec == 0 || o.precond_prec == HPS_PREC_FP64 ||
+                       o.precond_prec == HPS_PREC_SEPARABLE;
+  const bool flexible = o.solver == HPS_SOLVER_FGMRES || !fp64_pc;
   const int64_t nbat = (o.solver == HPS_SOLVER_BLOCK || c->nop > 1) ? std::min(nrhs, kMaxBatch) : 1;
   const int64_t vec = 16 * c->N * nbat;
   int64_t bytes = vec * ((restart + 1) + (flexible ? restart : 0) + 1);  // basis (+Z) + tmp
   bytes += (int64_t)sizeof(GmresState) * nbat + 32 * nbat;               // Hessenberg state
   bytes += (int64_t)kPartSlots * kRedBlocks * 16 * nbat;                  // reduction partials
   bytes += 16 * nbat * c->nl * c->nb;                                     // face buffer
-  if ((nbat >= kBatchedMinRhs && c->nop == 1) || c->lambda_bucket > 0.0)
+  if (((nbat >= kBatchedMinRhs && c->nop == 1) || c->lambda_bucket > 0.0) && !(fp64_pc && c->sep))
     bytes += nbat * c->nl * c->nb * (16 + 16) + 256;                      // H, U panels
   bytes += 16 * c->N * nrhs;                                              // assembled b
   return bytes;
@@ -561,9 +563,12 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
   int prec = kFP64;
   if (o.precond_prec == HPS_PREC_FP32) prec = kFP32;
   else if (o.precond_prec == HPS_PREC_BF16) prec = kBF16;
-  else if (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64)
+  else if (o.precond_prec == HPS_PREC_SEPARABLE) {
+    if (!c->sep) return fail(HPS_ERR_ARG, "the separable J^-1 was not built at setup");
+  } else if (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64)
     return fail(HPS_ERR_ARG, "unknown precond_prec");
-  if (!c->blk[prec].data) return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
+  if (!c->blk[prec].data && !(prec == kFP64 && c->sep))
+    return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
   if (o.solver < 0 || o.solver > 3) return fail(HPS_ERR_ARG, "unknown solver");
   if (c->nop > 1 && nrhs != c->nop)
     return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator (nrhs = number of operators)");

@@ -37,6 +37,12 @@ std::string build_tables(int p, double h, HostTables* t);
 // F_bi, N_bb (F_bb without the i eta I) and A_ib of the leaf matrix, column-major.
 void build_face_operators(const HostTables& t, std::vector<double>* Fbi, std::vector<double>* Nbb,
                           std::vector<double>* Aib);
+// Complex entries of the separable table of one operator: [Wc | Vc | Ec | Fi],
+// n1^2 + n1^2 + n1 + 4 (layout in build_sep_table).
+__host__ __device__ constexpr int sep_table_size(int p) { return 2 * (p - 2) * (p - 2) + (p - 2) + 4; }
+// The separable form of the homogenized leaf solve for impedance parameter eta
+// (2 * sep_table_size(p) doubles, real and imaginary parts interleaved).
+std::string build_sep_table(const HostTables& t, double eta, std::vector<double>* out);
 
 // Face f (0..5): axis = f/2, high side = f%2, outward sign -1 / +1.
 inline int face_axis(int f) { return f >> 1; }
@@ -107,6 +113,10 @@ struct hps_ctx {
   int group_leaves = 1;             // leaves in the largest group
   int n_shifted = 0;
   hps::Blocks blk[3];
+  // separable form of the FP64 J^-1 (block_precs has HPS_PREC_SEPARABLE): no
+  // FP64 blocks; one complex table per operator
+  int sep = 0;
+  double2* d_sep = nullptr;         // [nop][sep_table_size(p)]
   // face-reduced system with the exact ItI maps (built by hps_iti_build)
   double2* d_itiR = nullptr;        // [nl][nb cols][nb rows]  R^tau = I - 2 i eta S^{tau,-1}
   double2* d_Ainv = nullptr;        // [nl][ni cols][ni rows]  (A_ii^tau)^{-1}
@@ -195,7 +205,8 @@ int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs);
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
 // y = J^{-1} A x with the face exchange of A fused into the preconditioner's
 // load (one leaf per workgroup); tmp receives A x without the exchange.  With
-// kBatchedMinRhs or more right-hand sides: launch_apply, then launch_precond.
+// kBatchedMinRhs or more right-hand sides and dense blocks: launch_apply, then
+// launch_precond (the separable form is fused for any nrhs).
 int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec);
 // the sweep alone: y = A x without the neighbours' outgoing impedance, which
 // goes to g ([rhs][leaf][6][q^2]); e0 / e1 as in launch_k
@@ -204,6 +215,9 @@ int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs,
 // J^{-1} (y + exchange(g)) for nrhs < kBatchedMinRhs; g == null: J^{-1} y
 int launch_precond_fused(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
                          int prec, hipEvent_t e0, hipEvent_t e1);
+// J^{-1} (y + exchange(g)) in the separable form (no blocks; any nrhs); g == null: J^{-1} y
+int launch_precond_sep(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
+                       hipEvent_t e0, hipEvent_t e1);
 // many right-hand sides: block product as a GEMM on the matrix cores; with lambda
 // buckets (any nrhs) one GEMM per bucket over all its leaves' columns
 int launch_precond_batched(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec,

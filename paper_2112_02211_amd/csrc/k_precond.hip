@@ -78,6 +78,16 @@ int launch_precond_fused(hps_ctx* c, const double2* x, const double2* g, double2
 }
 
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec) {
+  if (prec == kFP64 && c->sep) {
+    TimedPair tp;
+    int rc = timing_pair(c, 1, &tp);
+    if (rc) return rc;
+    if ((rc = launch_precond_sep(c, x, nullptr, y, nrhs, tp.start, tp.stop))) {
+      timing_drop(c, tp);
+      return rc;
+    }
+    return timing_commit(c, 1, tp);
+  }
   if (prec < 0 || prec > 2 || !c->blk[prec].data)
     return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
   TimedPair tp;
@@ -96,11 +106,12 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
 
 int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec) {
   int rc;
-  if ((nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0) && c->nop == 1) {
+  const bool sep = prec == kFP64 && c->sep;
+  if (!sep && (nrhs >= kBatchedMinRhs || c->lambda_bucket > 0.0) && c->nop == 1) {
     if ((rc = launch_apply(c, x, tmp, nrhs))) return rc;
     return launch_precond(c, tmp, y, nrhs, prec);
   }
-  if (prec < 0 || prec > 2 || !c->blk[prec].data)
+  if (!sep && (prec < 0 || prec > 2 || !c->blk[prec].data))
     return fail(HPS_ERR_ARG, "requested block precision was not built at setup");
   if ((rc = ws_reserve(c, &c->w_g, (size_t)nrhs * c->nl * c->nb * sizeof(double2)))) return rc;
   double2* g = static_cast<double2*>(c->w_g.ptr);
@@ -112,7 +123,8 @@ int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int n
   }
   if ((rc = timing_commit(c, 0, ta))) return rc;
   if ((rc = timing_pair(c, 1, &tp))) return rc;
-  if ((rc = launch_precond_fused(c, tmp, g, y, nrhs, prec, tp.start, tp.stop))) {
+  if ((rc = sep ? launch_precond_sep(c, tmp, g, y, nrhs, tp.start, tp.stop)
+                : launch_precond_fused(c, tmp, g, y, nrhs, prec, tp.start, tp.stop))) {
     timing_drop(c, tp);
     return rc;
   }

@@ -1,0 +1,234 @@
+// y = J^{-1} x in the separable form: the same block-diagonal preconditioner
+// as the dense-block kernel (Sec. 4, eq. (block_pc): on each leaf the exact
+// inverse of the homogenized leaf matrix [[A~_ii, A_ib], [F_bi, F_bb]] with
+// C_ii = lambda^tau I), applied without any stored block.
+//
+// With the face nodes at the interior Chebyshev nodes of each face, every row
+// of the homogenized leaf matrix couples nodes of the three grid lines through
+// its node only, and a face row (eq. (flux) plus i eta) only nodes of the
+// normal line of its face node, which ends at a node of each of the two
+// opposite faces.  Per line, the two end values follow from the 2 x 2 face
+// system of that line,
+//   [u_lo, u_hi] = Fi ([x_lo, x_hi] - Fbi1 u_line),
+// and substituting them into the interior rows leaves the Kronecker sum
+//   K = -(Lt x I x I + I x Lt x I + I x I x Lt) - lambda I,
+//   Lt = D2[1:e, 1:e] - D2[1:e, {0, e}] Fi Fbi1          (complex, n1 x n1),
+// which Lt = Vc diag(Ec) Vc^{-1} diagonalizes as Algorithm 3 does the
+// Dirichlet interior operator, with complex factors.  So, per leaf:
+//
+//   g     = Fi [x_lo, x_hi]                       on every grid line
+//   r_i   = x_i - A_ib g
+//   u_i   = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
+//   u_b   = g - Fi Fbi1 u_line                    on every grid line
+//
+// Cost per leaf O(n1^4) in LDS; the kernel reads x and writes y once (32 bytes
+// per unknown), where the dense form also streams the n_b x n_b block.  The
+// tables (Wc, Vc, Ec, Fi per operator) are built on the host at setup.
+#include "hps_internal.h"
+
+namespace hps {
+namespace {
+
+template <int P>
+struct SL {
+  static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
+  static constexpr int BD0 = (NI + 63) / 64 * 64;
+  static constexpr int BD = BD0 < 64 ? 64 : (BD0 > 1024 ? 1024 : BD0);
+  static constexpr int ST = sep_table_size(P);
+};
+
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+
+// out[.., o, ..] = sum_i M[o][i] in[.., i, ..] along axis AX (M complex, row major)
+template <int P, int AX>
+__device__ __forceinline__ void cmode(const double2* __restrict__ in, double2* __restrict__ out,
+                                      const double2* __restrict__ M) {
+  using S = SL<P>;
+  constexpr int N1 = S::N1, L = S::L, NI = S::NI, BD = S::BD;
+  constexpr int stride = AX == 0 ? 1 : (AX == 1 ? N1 : L);
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const int o = (m / stride) % N1;
+    const int base = m - o * stride;
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) cfma(s, M[o * N1 + i], in[base + i * stride]);
+    out[m] = s;
+  }
+}
+
+// First entry and stride of the grid line along axis ax through face position pos.
+template <int P>
+__device__ __forceinline__ void line_of(int ax, int pos, int& base, int& stride) {
+  constexpr int N1 = P - 2, L = N1 * N1;
+  const int a = pos % N1, b = pos / N1;
+  if (ax == 0) { base = N1 * a + L * b; stride = 1; }
+  else if (ax == 1) { base = a + L * b; stride = N1; }
+  else { base = a + N1 * b; stride = L; }
+}
+
+// g != null: x is A v without the face exchange, added here while loading
+// (x_b += the neighbour's outgoing impedance on the partner face), as in the
+// dense-block kernel.  Operator groups: right-hand side rhs belongs to
+// operator rhs (os = nl: lambda of [rhs][leaf], table of operator rhs).
+template <int P>
+__global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
+    const double2* __restrict__ x, const double2* __restrict__ g, const int* __restrict__ nbr,
+    double2* __restrict__ y, const double2* __restrict__ lam, const double2* __restrict__ sep,
+    const double* __restrict__ tab, int64_t nl, int64_t N, int64_t os) {
+  using S = SL<P>;
+  constexpr int N1 = S::N1, L = S::L, NI = S::NI, NB = S::NB, NN = S::NN, BD = S::BD;
+  __shared__ double2 T[NI];
+  __shared__ double2 X[NI];
+  __shared__ double2 G[NB];
+  __shared__ double2 CT[S::ST];     // Wc | Vc | Ec | Fi
+  __shared__ double RT[4 * N1];     // Dlo | Dhi | C0 | C1
+  const int64_t tau = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const double2* xv = x + rhs * N + tau * NN;
+  double2* yv = y + rhs * N + tau * NN;
+  const double2 lm = lam[tau + rhs * os];
+  const double2* st = sep + (os ? (int64_t)rhs * S::ST : 0);
+  for (int k = threadIdx.x; k < S::ST; k += BD) CT[k] = st[k];
+  for (int k = threadIdx.x; k < 4 * N1; k += BD) {
+    const int t = k % N1, w = k / N1;
+    double v;
+    if (w == 0) v = tab[tab_off_D(P) + 1 + t];                      // D[0][1 + t]
+    else if (w == 1) v = tab[tab_off_D(P) + (P - 1) * P + 1 + t];   // D[p-1][1 + t]
+    else if (w == 2) v = tab[tab_off_D2(P) + (t + 1) * P];          // D2[1 + t][0]
+    else v = tab[tab_off_D2(P) + (t + 1) * P + P - 1];              // D2[1 + t][p-1]
+    RT[k] = v;
+  }
+  for (int m = threadIdx.x; m < NI; m += BD) T[m] = xv[m];
+  for (int m = threadIdx.x; m < NB; m += BD) {
+    double2 v = xv[NI + m];
+    if (g) {
+      const int f = m / L, pos = m - f * L;
+      const int t2 = nbr[tau * 6 + f];
+      if (t2 >= 0) {
+        const double2 gv = g[(rhs * nl + t2) * NB + (f ^ 1) * L + pos];
+        v = make_double2(v.x + gv.x, v.y + gv.y);
+      }
+    }
+    G[m] = v;
+  }
+  __syncthreads();
+  const double2* Wc = CT;
+  const double2* Vc = CT + L;
+  const double2* Ec = CT + 2 * L;
+  const double2 F0 = CT[2 * L + N1], F1 = CT[2 * L + N1 + 1];
+  const double2 F2 = CT[2 * L + N1 + 2], F3 = CT[2 * L + N1 + 3];
+  const double* Dlo = RT;
+  const double* Dhi = RT + N1;
+  const double* C0 = RT + 2 * N1;
+  const double* C1 = RT + 3 * N1;
+  // g = Fi [x_lo, x_hi] on every line, in place
+  for (int ln = threadIdx.x; ln < 3 * L; ln += BD) {
+    const int ax = ln / L, pos = ln - ax * L;
+    const double2 lo = G[2 * ax * L + pos], hi = G[(2 * ax + 1) * L + pos];
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    cfma(a, F0, lo);
+    cfma(a, F1, hi);
+    cfma(b, F2, lo);
+    cfma(b, F3, hi);
+    G[2 * ax * L + pos] = a;
+    G[(2 * ax + 1) * L + pos] = b;
+  }
+  __syncthreads();
+  // r_i = x_i - A_ib g  (A_ib: -D2[1 + i][{0, p-1}] towards the two ends of each line)
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const int i = m % N1, j = (m / N1) % N1, k = m / L;
+    double2 s = T[m];
+    cfma_r(s, C0[i], G[0 * L + j + N1 * k]);
+    cfma_r(s, C1[i], G[1 * L + j + N1 * k]);
+    cfma_r(s, C0[j], G[2 * L + i + N1 * k]);
+    cfma_r(s, C1[j], G[3 * L + i + N1 * k]);
+    cfma_r(s, C0[k], G[4 * L + i + N1 * j]);
+    cfma_r(s, C1[k], G[5 * L + i + N1 * j]);
+    T[m] = s;
+  }
+  __syncthreads();
+  // u_i = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
+  cmode<P, 0>(T, X, Wc);
+  __syncthreads();
+  cmode<P, 1>(X, T, Wc);
+  __syncthreads();
+  cmode<P, 2>(T, X, Wc);
+  __syncthreads();
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const int i = m % N1, j = (m / N1) % N1, k = m / L;
+    const double a = -(Ec[i].x + Ec[j].x + Ec[k].x) - lm.x;
+    const double b = -(Ec[i].y + Ec[j].y + Ec[k].y) - lm.y;
+    const double den = 1.0 / (a * a + b * b);
+    X[m] = cmul(X[m], make_double2(a * den, -b * den));
+  }
+  __syncthreads();
+  cmode<P, 0>(X, T, Vc);
+  __syncthreads();
+  cmode<P, 1>(T, X, Vc);
+  __syncthreads();
+  cmode<P, 2>(X, T, Vc);
+  __syncthreads();
+  for (int m = threadIdx.x; m < NI; m += BD) yv[m] = T[m];
+  // u_b = g - Fi Fbi1 u_line,  Fbi1 u_line = [-sum Dlo u, sum Dhi u]
+  for (int ln = threadIdx.x; ln < 3 * L; ln += BD) {
+    const int ax = ln / L, pos = ln - ax * L;
+    int base, stride;
+    line_of<P>(ax, pos, base, stride);
+    double2 slo = make_double2(0.0, 0.0), shi = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < N1; ++t) {
+      const double2 u = T[base + t * stride];
+      cfma_r(slo, -Dlo[t], u);
+      cfma_r(shi, Dhi[t], u);
+    }
+    double2 a = G[2 * ax * L + pos], b = G[(2 * ax + 1) * L + pos];
+    double2 fa = make_double2(0.0, 0.0), fb = make_double2(0.0, 0.0);
+    cfma(fa, F0, slo);
+    cfma(fa, F1, shi);
+    cfma(fb, F2, slo);
+    cfma(fb, F3, shi);
+    yv[NI + 2 * ax * L + pos] = csub(a, fa);
+    yv[NI + (2 * ax + 1) * L + pos] = csub(b, fb);
+  }
+}
+
+template <int P>
+int sep_launch(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs, hipEvent_t e0,
+               hipEvent_t e1) {
+  const dim3 grid((unsigned)c->nl, (unsigned)nrhs);
+  const dim3 block(SL<P>::BD);
+  const int64_t os = c->nop > 1 ? c->nl : 0;
+  const hipError_t e = launch_k(c, e0, e1, k_precond_sep<P>, grid, block, x, g, c->d_nbr, y,
+                                c->d_lambda, c->d_sep, c->d_tab, c->nl, c->N, os);
+  return check_hip(e, "k_precond_sep");
+}
+
+}  // namespace
+
+int launch_precond_sep(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs,
+                       hipEvent_t e0, hipEvent_t e1) {
+  if (!c->sep || !c->d_sep) return fail(HPS_ERR_ARG, "the separable J^-1 was not built at setup");
+  if (c->nop > 1 && nrhs != c->nop) return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator");
+  if (nrhs > 65535) return fail(HPS_ERR_ARG, "at most 65535 right-hand sides per call");
+  switch (c->p) {
+    case 4: return sep_launch<4>(c, x, g, y, nrhs, e0, e1);
+    case 5: return sep_launch<5>(c, x, g, y, nrhs, e0, e1);
+    case 6: return sep_launch<6>(c, x, g, y, nrhs, e0, e1);
+    case 7: return sep_launch<7>(c, x, g, y, nrhs, e0, e1);
+    case 8: return sep_launch<8>(c, x, g, y, nrhs, e0, e1);
+    case 9: return sep_launch<9>(c, x, g, y, nrhs, e0, e1);
+    case 10: return sep_launch<10>(c, x, g, y, nrhs, e0, e1);
+    case 11: return sep_launch<11>(c, x, g, y, nrhs, e0, e1);
+    case 12: return sep_launch<12>(c, x, g, y, nrhs, e0, e1);
+    case 13: return sep_launch<13>(c, x, g, y, nrhs, e0, e1);
+    case 14: return sep_launch<14>(c, x, g, y, nrhs, e0, e1);
+    case 15: return sep_launch<15>(c, x, g, y, nrhs, e0, e1);
+    case 16: return sep_launch<16>(c, x, g, y, nrhs, e0, e1);
+    default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
+  }
+}
+
+}  // namespace hps

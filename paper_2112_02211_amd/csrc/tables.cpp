@@ -8,6 +8,7 @@
 //   S~ = F_bb - P diag(1 / (-E_Delta - lambda)) Q for every leaf.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <numeric>
 
@@ -144,6 +145,112 @@ bool real_eigenvalues(Mat A, int n, std::vector<double>& ev) {
         double t = 0.0;
         for (int k = i; k < m; ++k) t += B[i * m + k] * Qm[k * m + j];
         A[i * n + j] = t + (i == j ? mu : 0.0);
+      }
+  }
+  return (int)ev.size() == n;
+}
+
+// Complex dense helpers (row major) for the separable form of the homogenized
+// leaf solve.
+using cd = std::complex<double>;
+using CMat = std::vector<cd>;
+
+bool clu_factor(CMat& A, std::vector<int>& piv, int n) {
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int m = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(A[i * n + k]) > std::abs(A[m * n + k])) m = i;
+    piv[k] = m;
+    if (A[m * n + k] == 0.0) return false;
+    if (m != k)
+      for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[m * n + j]);
+    for (int i = k + 1; i < n; ++i) {
+      A[i * n + k] /= A[k * n + k];
+      const cd f = A[i * n + k];
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+    }
+  }
+  return true;
+}
+
+void clu_solve(const CMat& LU, const std::vector<int>& piv, int n, std::vector<cd>& b) {
+  for (int k = 0; k < n; ++k) std::swap(b[k], b[piv[k]]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) b[i] -= LU[i * n + j] * b[j];
+  for (int i = n - 1; i >= 0; --i) {
+    for (int j = i + 1; j < n; ++j) b[i] -= LU[i * n + j] * b[j];
+    b[i] /= LU[i * n + i];
+  }
+}
+
+// Eigenvalues of a complex matrix: shifted QR iteration on the full matrix
+// (complex Householder QR per step, Wilkinson shift from the trailing 2 x 2
+// block, an exceptional shift every 11 steps without deflation), deflating the
+// last row of the active block once it vanishes.
+bool complex_eigenvalues(CMat A, int n, std::vector<cd>& ev) {
+  ev.clear();
+  double anorm = 0.0;
+  for (const cd& v : A) anorm = std::max(anorm, std::abs(v));
+  int m = n, iter = 0;
+  while (m > 0) {
+    if (m == 1) {
+      ev.push_back(A[0]);
+      break;
+    }
+    double off = 0.0;
+    for (int j = 0; j < m - 1; ++j) off = std::max(off, std::abs(A[(m - 1) * n + j]));
+    if (off <= 1e-15 * anorm) {
+      ev.push_back(A[(m - 1) * n + (m - 1)]);
+      --m;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 500) return false;
+    const cd a = A[(m - 2) * n + (m - 2)], b = A[(m - 2) * n + (m - 1)];
+    const cd c = A[(m - 1) * n + (m - 2)], d = A[(m - 1) * n + (m - 1)];
+    const cd tr = 0.5 * (a - d);
+    const cd r = std::sqrt(tr * tr + b * c);
+    const cd l1 = d + tr + r, l2 = d + tr - r;
+    cd mu = (std::abs(l1 - d) < std::abs(l2 - d)) ? l1 : l2;
+    if (iter % 11 == 10) mu += 0.5 * off;
+    CMat B(m * m), Qm(m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) B[i * m + j] = A[i * n + j] - (i == j ? mu : cd(0.0));
+    for (int i = 0; i < m; ++i) Qm[i * m + i] = 1.0;
+    for (int k = 0; k < m - 1; ++k) {
+      double s = 0.0;
+      for (int i = k; i < m; ++i) s += std::norm(B[i * m + k]);
+      s = std::sqrt(s);
+      if (s == 0.0) continue;
+      const cd bkk = B[k * m + k];
+      const cd ph = std::abs(bkk) > 0.0 ? bkk / std::abs(bkk) : cd(1.0);
+      const cd alpha = -ph * s;
+      std::vector<cd> v(m, 0.0);
+      v[k] = bkk - alpha;
+      for (int i = k + 1; i < m; ++i) v[i] = B[i * m + k];
+      double vv = 0.0;
+      for (int i = k; i < m; ++i) vv += std::norm(v[i]);
+      if (vv == 0.0) continue;
+      // B <- (I - 2 v v^H / vv) B ; Qm <- Qm (I - 2 v v^H / vv)
+      for (int j = 0; j < m; ++j) {
+        cd t = 0.0;
+        for (int i = k; i < m; ++i) t += std::conj(v[i]) * B[i * m + j];
+        t *= 2.0 / vv;
+        for (int i = k; i < m; ++i) B[i * m + j] -= t * v[i];
+      }
+      for (int i = 0; i < m; ++i) {
+        cd t = 0.0;
+        for (int j = k; j < m; ++j) t += Qm[i * m + j] * v[j];
+        t *= 2.0 / vv;
+        for (int j = k; j < m; ++j) Qm[i * m + j] -= t * std::conj(v[j]);
+      }
+    }
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        cd t = 0.0;
+        for (int k = i; k < m; ++k) t += B[i * m + k] * Qm[k * m + j];
+        A[i * n + j] = t + (i == j ? mu : cd(0.0));
       }
   }
   return (int)ev.size() == n;
@@ -334,6 +441,109 @@ void build_face_operators(const HostTables& t, std::vector<double>* Fbi, std::ve
         (*Nbb)[(size_t)ro * nb + r] += sg * t.D[e * p + (p - 1 - e)];
       }
   }
+}
+
+// The separable form of the homogenized leaf solve.  The leaf matrix with
+// C_ii = lambda I couples each node only along the three grid lines through
+// it, and every face row (eq. (flux) plus i eta) lies on the normal line of its
+// face node, whose two ends are face nodes of opposite faces.  Eliminating the
+// two end values of every line with the 2 x 2 face system of that line,
+//   [u_lo, u_hi] = Fi ([x_lo, x_hi] - Fbi1 u_line),
+//   Fbb1 = [[-D00 + i eta, -D0e], [De0, Dee + i eta]] (e = p - 1), Fi = Fbb1^{-1},
+//   Fbi1 = [-D[0][1:e]; D[e][1:e]],
+// leaves on the interior the operator -(Lt x I x I + I x Lt x I + I x I x Lt) - lambda
+// with Lt = D2[1:e, 1:e] - D2[1:e, {0, e}] Fi Fbi1, a complex n1 x n1 matrix.
+// With Lt = Vc diag(Ec) Vc^{-1} the interior solve is a fast diagonalization
+// as in Algorithm 3, now with complex factors.  Packed table (complex, row
+// major): [Wc = Vc^{-1} | Vc | Ec | Fi].
+std::string build_sep_table(const HostTables& t, double eta, std::vector<double>* out) {
+  const int p = t.p, n1 = t.n1, e = p - 1;
+  const std::vector<double>& D = t.D;
+  const std::vector<double>& D2 = t.D2;
+  const cd ie(0.0, eta);
+  const cd f00 = -D[0] + ie, f01 = -D[e], f10 = D[e * p], f11 = D[e * p + e] + ie;
+  const cd det = f00 * f11 - f01 * f10;
+  if (std::abs(det) == 0.0) return "face system of a grid line is singular";
+  const cd Fi[4] = {f11 / det, -f01 / det, -f10 / det, f00 / det};
+  CMat Lt(n1 * n1);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      // D2[1 + i][{0, e}] Fi [-D[0][1 + j]; D[e][1 + j]]
+      const cd g0 = Fi[0] * (-D[1 + j]) + Fi[1] * D[e * p + 1 + j];
+      const cd g1 = Fi[2] * (-D[1 + j]) + Fi[3] * D[e * p + 1 + j];
+      Lt[i * n1 + j] = D2[(1 + i) * p + 1 + j] - (D2[(1 + i) * p] * g0 + D2[(1 + i) * p + e] * g1);
+    }
+  double lnorm = 0.0;
+  for (const cd& v : Lt) lnorm = std::max(lnorm, std::abs(v));
+  std::vector<cd> ev;
+  if (!complex_eigenvalues(Lt, n1, ev)) return "eigenvalues of the line operator did not converge";
+  std::sort(ev.begin(), ev.end(), [](const cd& a, const cd& b) {
+    return a.real() != b.real() ? a.real() < b.real() : a.imag() < b.imag();
+  });
+  // eigenvectors by inverse iteration with a slightly perturbed shift
+  CMat V(n1 * n1, 0.0);
+  for (int k = 0; k < n1; ++k) {
+    const cd lam = ev[k];
+    const cd shift = lam + 1e-10 * std::max(std::abs(lam), 1.0);
+    CMat M = Lt;
+    for (int i = 0; i < n1; ++i) M[i * n1 + i] -= shift;
+    std::vector<int> piv;
+    if (!clu_factor(M, piv, n1)) return "inverse iteration: singular shift";
+    std::vector<cd> x(n1);
+    for (int i = 0; i < n1; ++i) x[i] = 1.0 + 0.1 * std::sin(1.7 * i + 0.3 * k);
+    for (int it = 0; it < 4; ++it) {
+      clu_solve(M, piv, n1, x);
+      double nrm = 0.0;
+      for (const cd& v : x) nrm += std::norm(v);
+      nrm = std::sqrt(nrm);
+      for (cd& v : x) v /= nrm;
+    }
+    // phase convention: largest component real and positive
+    int im = 0;
+    for (int i = 1; i < n1; ++i)
+      if (std::abs(x[i]) > std::abs(x[im])) im = i;
+    const cd ph = std::abs(x[im]) / x[im];
+    for (cd& v : x) v *= ph;
+    double r = 0.0;
+    for (int i = 0; i < n1; ++i) {
+      cd s = -lam * x[i];
+      for (int j = 0; j < n1; ++j) s += Lt[i * n1 + j] * x[j];
+      r = std::max(r, std::abs(s));
+    }
+    if (r > 1e-9 * lnorm) return "line operator: eigenvector residual too large";
+    for (int i = 0; i < n1; ++i) V[i * n1 + k] = x[i];
+  }
+  CMat LU = V;
+  std::vector<int> piv;
+  if (!clu_factor(LU, piv, n1)) return "line operator: eigenvector matrix singular";
+  CMat W(n1 * n1);
+  for (int j = 0; j < n1; ++j) {
+    std::vector<cd> col(n1, 0.0);
+    col[j] = 1.0;
+    clu_solve(LU, piv, n1, col);
+    for (int i = 0; i < n1; ++i) W[i * n1 + j] = col[i];
+  }
+  double rec = 0.0;
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      cd s = 0.0;
+      for (int k = 0; k < n1; ++k) s += V[i * n1 + k] * ev[k] * W[k * n1 + j];
+      rec = std::max(rec, std::abs(s - Lt[i * n1 + j]));
+    }
+  if (rec > 1e-9 * lnorm) return "line operator: eigendecomposition reconstruction error too large";
+  out->assign(2 * (size_t)sep_table_size(p), 0.0);
+  auto put = [&](int k, cd v) {
+    (*out)[2 * k] = v.real();
+    (*out)[2 * k + 1] = v.imag();
+  };
+  const int Q = n1 * n1;
+  for (int k = 0; k < Q; ++k) {
+    put(k, W[k]);
+    put(Q + k, V[k]);
+  }
+  for (int k = 0; k < n1; ++k) put(2 * Q + k, ev[k]);
+  for (int k = 0; k < 4; ++k) put(2 * Q + n1 + k, Fi[k]);
+  return std::string();
 }
 
 }  // namespace hps

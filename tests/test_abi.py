@@ -112,6 +112,31 @@ def test_setup_bytes_is_the_documented_plan(L, p, n, precs, cplx):
         assert got - (want - nl * nb * nb * 16) == 1_207_959_552
 
 
+@pytest.mark.parametrize("p,precs", [(10, 8), (16, 8), (8, 8 | 4)])
+def test_setup_bytes_separable_form(L, p, precs):
+    # separable J^-1: one table of 2 n1^2 + n1 + 4 complex entries, no FP64 blocks;
+    # nothing transient unless reduced-precision blocks are built too
+    n = (4, 3, 2)
+    n1 = p - 2
+    ni, nb, nl = n1 ** 3, 6 * n1 ** 2, 24
+    tab = 2 * p * p + 2 * n1 * n1 + n1 + p + ni
+    want = 8 * tab + 4 * 6 * nl + nl * ni * 8 + 16 * nl + 16 * (2 * n1 * n1 + n1 + 4)
+    if precs & 4:
+        want += nl * ((nb + 3) // 4 * 4) * nb * 4
+    tr = ctypes.c_int64()
+    assert L.hps_setup_bytes(p, (ctypes.c_int * 3)(*n), precs, 0, ctypes.byref(tr)) == want
+    assert (tr.value > 0) == bool(precs & 4)
+
+
+def test_setup_rejects_separable_with_fp64_blocks_or_buckets(L):
+    rc, out = _setup(L, opts=hps._Opts(1 | 8, None, 0, 0.0))
+    assert rc == hps.HPS_ERR_ARG and "SEPARABLE" in _err(L) and not out.value
+    rc, out = _setup(L, opts=hps._Opts(8, None, 0, 1e-2))
+    assert rc == hps.HPS_ERR_ARG and "separable" in _err(L) and not out.value
+    rc, out = _setup(L, opts=hps._Opts(16, None, 0, 0.0))
+    assert rc == hps.HPS_ERR_ARG and not out.value
+
+
 def test_setup_bytes_rejects_bad_sizes(L):
     assert L.hps_setup_bytes(3, (ctypes.c_int * 3)(1, 1, 1), 1, 0, None) < 0
     assert L.hps_setup_bytes(8, (ctypes.c_int * 3)(1, 0, 1), 1, 0, None) < 0

@@ -1,0 +1,203 @@
+"""The FP64 J^-1 in separable form (block_precs "separable": no stored blocks)
+against the oracle's J^-1, which LU-factors each homogenized leaf matrix
+densely (eq. (block_pc)).
+
+Parity: J^-1 x at 1e-12 relative (2-norm) and 1e-11 entrywise relative to the
+largest entry, the bar of the dense-block kernel, over p = 4 ... 16, ragged
+meshes, real and absorbing media and operator groups (per-operator eta and
+lambda); J^-1 A x fused equals J^-1 (A x) bit for bit; the solves reach the
+oracle's direct solution to 1e-9 in the same number of steps as with dense
+blocks (the same preconditioner, so the Krylov iterations agree up to rounding).
+Both forms are exact inverses of the same leaf matrix, so they differ from
+the oracle only by rounding: here by at most cond(leaf matrix) * 1e-16, which
+the oracle's own LU also carries (below 1e-12 at these sizes and wave numbers).
+"""
+import numpy as np
+import pytest
+
+from oracle import hps_oracle as O
+from paper_2112_02211_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rand_vec(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+@pytest.fixture(scope="module")
+def hps_mod():
+    from paper_2112_02211_amd import hps
+    hps.lib()
+    return hps
+
+
+# n_elem, p, kappa, bumps, seed: every p from 4 to 16, ragged leaf counts
+CASES = [((1, 1, 1), 4, 3.0, 2, 13), ((2, 1, 2), 5, 6.0, 3, 21), ((3, 2, 2), 7, 9.0, 4, 11),
+         ((2, 2, 2), 8, 10.0, 3, 12), ((1, 1, 5), 9, 12.0, 3, 17), ((2, 3, 1), 10, 20.0, 5, 14),
+         ((1, 2, 1), 11, 18.0, 3, 22), ((1, 2, 2), 12, 30.0, 3, 15), ((1, 1, 2), 13, 22.0, 2, 23),
+         ((2, 1, 1), 14, 26.0, 2, 24), ((1, 1, 1), 15, 28.0, 2, 25), ((2, 1, 1), 16, 25.0, 2, 16),
+         ((1, 1, 1), 6, 8.0, 2, 26)]
+
+
+def _setup(hps_mod, case, precs=("separable",)):
+    n_elem, p, kappa, nbump, seed = case
+    prob = P.bump_problem("s", n_elem, p, kappa, nbump, 1, seed, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=precs)
+    return prob, ctx
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_separable_precond_matches_oracle(hps_mod, case):
+    prob, ctx = _setup(hps_mod, case)
+    op = O.build(prob, with_matrix=False)
+    assert ctx.n_blocks == ctx.nl
+    x = rand_vec(op.d.N, 2)
+    z = host(ctx.precond(dev(x)))
+    za = O.Precond(op.d, op.b_nodes).apply(x)
+    assert rel(z, za) < 1e-12
+    assert np.max(np.abs(z - za)) < 1e-11 * np.max(np.abs(za))
+
+
+def test_separable_absorbing_medium(hps_mod):
+    # complex C (Im b > 0): lambda^tau complex, the same tables
+    prob = P.bump_problem("sa", (2, 2, 1), 8, 12.0, 3, 1, 53, 30, 1e-10)
+    op = O.build(prob, with_matrix=False)
+    bn = op.b_nodes + 0.2j * np.abs(op.b_nodes) + 0.05j
+    ctx = hps_mod.Context(prob.n_elem, prob.p, prob.kappa, prob.eta, prob.lo, prob.hi,
+                          nodal_b=dev(bn), block_precs=("separable",))
+    x = rand_vec(op.d.N, 3)
+    z = host(ctx.precond(dev(x)))
+    za = O.Precond(op.d, bn).apply(x)
+    assert rel(z, za) < 1e-12
+
+
+@pytest.mark.parametrize("case", [CASES[3], CASES[5]])
+def test_separable_equals_dense_blocks(hps_mod, case):
+    # the two forms of the same J^-1, both on the GPU
+    prob, sep = _setup(hps_mod, case)
+    _, dense = _setup(hps_mod, case, ("fp64",))
+    x = dev(rand_vec(sep.N, 4))
+    assert rel(host(sep.precond(x)), host(dense.precond(x))) < 1e-12
+
+
+def test_separable_op_left_is_fused_precond_of_apply(hps_mod):
+    prob, ctx = _setup(hps_mod, CASES[2])
+    X = np.stack([rand_vec(ctx.N, 10 + k) for k in range(5)])
+    xd = dev(X.reshape(-1))
+    got = host(ctx.op_left(xd))
+    want = host(ctx.precond(ctx.apply(xd)))
+    assert np.array_equal(got, want)
+
+
+def test_separable_multi_rhs_is_columnwise_and_deterministic(hps_mod):
+    prob, ctx = _setup(hps_mod, CASES[3])
+    X = np.stack([rand_vec(ctx.N, 20 + k) for k in range(6)])
+    Z = host(ctx.precond(dev(X.reshape(-1)))).reshape(6, -1)
+    for k in range(6):
+        zk = host(ctx.precond(dev(X[k])))
+        assert np.array_equal(Z[k], zk)
+    x = dev(X[0])
+    assert np.array_equal(host(ctx.precond(x)), host(ctx.precond(x)))
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[5]])
+def test_separable_gmres_matches_direct_solve_and_dense_steps(hps_mod, case):
+    prob, sep = _setup(hps_mod, case)
+    _, dense = _setup(hps_mod, case, ("fp64",))
+    op = O.build(prob)
+    s, t = P.rhs_data(prob, sep.nodes())
+    u, st, ok = sep.gmres(dev(s), dev(t), tol=1e-12, restart=30)
+    ud, std, okd = dense.gmres(dev(s), dev(t), tol=1e-12, restart=30)
+    assert ok and okd
+    assert abs(st["iters"] - std["iters"]) <= 1
+    assert rel(host(u), O.solve_direct(op)) < 1e-9
+    assert st["true_rel_res"] <= 1e-12 * 1.0001
+
+
+def test_separable_batched_and_fgmres_with_reduced_blocks(hps_mod):
+    # separable FP64 J^-1 beside BF16 blocks: lock-step solves use the
+    # separable form, FGMRES with BF16 blocks the blocks
+    prob = P.bump_problem("sb", (2, 2, 2), 8, 14.0, 4, 5, 31, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable", "bf16"))
+    op = O.build(prob)
+    xyz = ctx.nodes()
+    S = np.concatenate([P.rhs_data(prob, xyz, r)[0] for r in range(5)])
+    T = np.zeros_like(S)
+    for solver, prec in (("batched", "fp64"), ("batched", "separable"), ("fgmres", "bf16")):
+        u, st, ok = ctx.gmres(dev(S), dev(T), tol=1e-11, restart=20, solver=solver, precond_prec=prec)
+        assert ok, (solver, prec)
+        U = host(u).reshape(5, -1)
+        for r in range(5):
+            rhs = O.assemble_rhs(op.d, S[r * op.d.N:(r + 1) * op.d.N], np.zeros(op.d.N))
+            assert rel(U[r], O.solve_direct(op, rhs)) < 1e-9, (solver, prec, r)
+
+
+def test_separable_operator_group_equals_separate_contexts(hps_mod):
+    # different kappa and eta per operator: one table per operator
+    probs = [P.bump_problem(f"g{i}", (3, 2, 1), 9, k, 4, 1, s, 30, 1e-10)
+             for i, (k, s) in enumerate(zip((10.0, 13.0, 16.5), (31, 32, 33)))]
+    grp = hps_mod.Context.group(probs, block_precs=("separable",))
+    one = [hps_mod.Context.from_problem(pr, block_precs=("separable",)) for pr in probs]
+    N = grp.N
+    X = np.stack([rand_vec(N, 40 + k) for k in range(3)])
+    xd = dev(X.reshape(-1))
+    outs = {"precond": host(grp.precond(xd)), "op_left": host(grp.op_left(xd))}
+    for k in range(3):
+        xk = dev(X[k])
+        want = {"precond": host(one[k].precond(xk)), "op_left": host(one[k].op_left(xk))}
+        for name, got in outs.items():
+            assert np.array_equal(got[k * N:(k + 1) * N], want[name]), (name, k)
+        opk = O.build(probs[k], with_matrix=False)
+        assert rel(outs["precond"][k * N:(k + 1) * N], O.Precond(opk.d, opk.b_nodes).apply(X[k])) < 1e-12
+    S = np.concatenate([P.rhs_data(pr, grp.nodes())[0] for pr in probs])
+    u, st, ok = grp.gmres(dev(S), dev(np.zeros_like(S)), tol=1e-11, restart=30)
+    assert ok
+    U = host(u).reshape(3, -1)
+    for k in range(3):
+        opk = O.build(probs[k])
+        assert rel(U[k], O.solve_direct(opk)) < 1e-9
+
+
+def test_separable_plane_wave(hps_mod):
+    prob = P.workload("plane_2x2x2_p8")
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    op = O.build(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-10, restart=30)
+    assert ok
+    u = host(u)
+    assert rel(u, O.solve_direct(op)) < 1e-9
+    assert 1e-6 < rel(u, P.plane_wave(prob, op.xyz)) < 1e-3
+
+
+def test_separable_option_errors(hps_mod):
+    prob = P.workload("plane_2x2x2_p8")
+    with pytest.raises(hps_mod.HPSError):
+        hps_mod.Context.from_problem(prob, block_precs=("fp64", "separable"))
+    with pytest.raises(hps_mod.HPSError):
+        hps_mod.Context.from_problem(prob, block_precs=("separable",), lambda_bucket=1e-2)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    s, t = P.rhs_data(prob, ctx.nodes())
+    with pytest.raises(hps_mod.HPSError):       # no FP64 blocks to tune
+        ctx.autotune(nrhs=8, prec="fp64")
+    with pytest.raises(hps_mod.HPSError):       # no BF16 blocks built
+        ctx.gmres(dev(s), dev(t), solver="fgmres", precond_prec="bf16")
+    dense = hps_mod.Context.from_problem(prob)
+    with pytest.raises(hps_mod.HPSError):       # separable form not built
+        dense.gmres(dev(s), dev(t), precond_prec="separable")
