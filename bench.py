@@ -5,17 +5,21 @@
 A step is one complete block-Jacobi preconditioned GMRES solve of the
 workload (every hot-path stage: operator sweep + face exchange, the
 homogenized block-Jacobi preconditioner, Arnoldi with delayed
-reorthogonalization, Givens) from x0 = 0 to
-the workload's tolerance.  ``value`` is the throughput of preconditioned
-operator applications inside those solves: N * (Arnoldi steps) / seconds, in
-millions of unknowns per second.  Inputs are resident in HBM before timing.
+reorthogonalization, Givens) from x0 = 0 to the workload's tolerance.  The
+preconditioner is applied in its separable form (the exact inverse of each
+homogenized leaf matrix by a complex fast diagonalization, no stored blocks);
+the same solve with the paper's stored dense blocks is reported beside it.
+``value`` is the throughput of preconditioned operator applications inside
+those solves: N * (Arnoldi steps) / seconds, in millions of unknowns per
+second.  Inputs are resident in HBM before timing.
 
 The JSON line also carries:
-  roofline      the dominant kernel (the preconditioner, which streams one dense
-                n_b x n_b block per leaf) timed with HIP events over the timed
-                region (every TIMING_EVERY-th launch; the events are attached to
-                the dispatches, each costs a few microseconds of stream time),
-                against the 8 TB/s HBM peak;
+  roofline      the dominant kernel of the step (the Arnoldi update pass, which
+                reads the Krylov basis once per step) timed with HIP events over
+                the timed region (every TIMING_EVERY-th launch; the events are
+                attached to the dispatches), against the 8 TB/s HBM peak; the
+                dense-block solve carries the same for its dominant kernel, the
+                block-streaming preconditioner;
   cpu_baseline  the CPU oracle timed on a bounded sample of one GMRES step.
 """
 from __future__ import annotations
@@ -39,10 +43,12 @@ BUCKET_DELTAS = (1e-3, 1e-2)   # lambda grid spacings (times kappa^2) of the buc
 METRIC = "HPS operator applies/s (Munknowns/s) + time-to-1e-8 solve; served p50/p99"
 
 
-def read_traffic(workload: str):
-    """HBM bytes per preconditioner launch from the committed PMC summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_k_precond_fused_{workload}.txt")
+def read_traffic(workload: str, kernel: str = "k_precond_fused"):
+    """HBM bytes per launch of `kernel` (k_precond_fused: the FP64 J^-1 with the
+    fused exchange; k_dcgs_update: the Arnoldi update pass, averaged over the
+    launches of one solve) from the committed PMC summary, if it was taken on
+    the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -52,7 +58,7 @@ def read_traffic(workload: str):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     from paper_2112_02211_amd.profile_run import kernel_source_hash
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -149,53 +155,91 @@ def main():
     if prob.lambda_bucket > 0:
         return run_bucketed(a, prob)
     t0 = time.perf_counter()
-    ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"))
+    ctx = hps.Context.from_problem(prob, block_precs=("separable", "fp32", "bf16"))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     xyz = ctx.nodes()
     s_np, t_np = P.rhs_data(prob, xyz)
     s = torch.from_numpy(s_np).cuda()
     t = torch.from_numpy(t_np).cuda()
+
+    def timed_solves(c, u):
+        """warm-up, then a.steps timed solves with kernel timing on; returns
+        (elapsed, Arnoldi steps, last stats, converged, kernel times, update-pass times)"""
+        for _ in range(a.warmup):
+            c.gmres(s, t, tol=prob.tol, restart=prob.restart, u=u, check_every=a.check_every)
+        c.set_timing(True, every=TIMING_EVERY)
+        c.kernel_times(reset=True)
+        c.arnoldi_times(reset=True)
+        torch.cuda.synchronize()
+        its = 0
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            _, st, ok = c.gmres(s, t, tol=prob.tol, restart=prob.restart, u=u, check_every=a.check_every)
+            its += st["iters"]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kt = c.kernel_times(reset=True)
+        at = c.arnoldi_times(reset=True)
+        c.set_timing(False)
+        return elapsed, its, st, ok, kt, at
+
     u = torch.zeros_like(s)
-
-    def step():
-        return ctx.gmres(s, t, tol=prob.tol, restart=prob.restart, u=u,
-                         check_every=a.check_every)
-
-    for _ in range(a.warmup):
-        step()
-    ctx.set_timing(True, every=TIMING_EVERY)
-    ctx.kernel_times(reset=True)
-    torch.cuda.synchronize()
-    its = 0
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        _, st, ok = step()
-        its += st["iters"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kt = ctx.kernel_times(reset=True)
-    ctx.set_timing(False)
+    elapsed, its, st, ok, kt, at = timed_solves(ctx, u)
     N = ctx.N
     value = N * its / elapsed / 1e6
-
-    # the dominant kernel: the preconditioner (one launch streams every block)
-    prec_ms = kt["precond_ms"] / max(1, kt["precond_launches"])
-    app_ms = kt["apply_ms"] / max(1, kt["apply_launches"])
-    achieved = st["bytes_precond"] / (prec_ms * 1e-3) / 1e9
-    traffic = read_traffic(a.workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_precond_fused (FP64 blocks)",
-                "avg_launch_ms": round(prec_ms, 5),
-                "algorithmic_bytes_per_launch": st["bytes_precond"]}
     u_np = u.cpu().numpy()
     err = oracle_check(a.workload, u_np)
 
-    # The same solve with the blocks in FP64, FP32 and BF16 inside FP64 flexible
-    # GMRES, all stopped by the same true-residual tolerance (equal accuracy:
-    # the error against the oracle is reported next to the time).
-    mixed = {"tol_true_residual": MIXED_TOL}
+    # the dominant kernel: the Arnoldi update pass (per step the basis is read once)
+    upd_ms = at["update_ms"] / max(1, at["update_launches"])
+    upd_bytes = at["update_bytes"] / max(1, at["update_launches"])
+    achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic(a.workload, "k_dcgs_update"),
+                "kernel": "k_dcgs_update (Arnoldi update pass)",
+                "avg_launch_ms": round(upd_ms, 5),
+                "algorithmic_bytes_per_launch": round(upd_bytes)}
+    prec_ms = kt["precond_ms"] / max(1, kt["precond_launches"])
+    app_ms = kt["apply_ms"] / max(1, kt["apply_launches"])
+    sep_gbs = st["bytes_precond"] / (prec_ms * 1e-3) / 1e9
+    precond_kernel = {"kernel": "k_precond_sep (separable J^-1)", "avg_launch_ms": round(prec_ms, 5),
+                      "algorithmic_bytes_per_launch": st["bytes_precond"],
+                      "algorithmic_GBs": round(sep_gbs, 1),
+                      "frac_of_hbm_peak": round(sep_gbs / HBM_PEAK_GBS, 4)}
+
+    # The paper's form of the same preconditioner: one dense S~^{-1} block per
+    # leaf, streamed from HBM by every J^-1 (the same iteration, the same u up
+    # to rounding); its dominant kernel is that block stream.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dctx = hps.Context.from_problem(prob, block_precs=("fp64",))
+    torch.cuda.synchronize()
+    d_setup = time.perf_counter() - t0
+    ud = torch.zeros_like(s)
+    d_el, d_its, std_, okd, ktd, _ = timed_solves(dctx, ud)
+    dprec_ms = ktd["precond_ms"] / max(1, ktd["precond_launches"])
+    d_ach = std_["bytes_precond"] / (dprec_ms * 1e-3) / 1e9
+    dense = {"setup_s": round(d_setup, 3), "device_bytes": dctx.device_bytes(),
+             "solve_ms": round(d_el / a.steps * 1e3, 3), "iters_per_solve": d_its / a.steps,
+             "converged": bool(okd), "true_rel_res": std_["true_rel_res"],
+             "err_vs_oracle": oracle_check(a.workload, ud.cpu().numpy()),
+             "value_munknowns_per_s": round(N * d_its / d_el / 1e6, 1),
+             "roofline": {"bound": "hbm", "achieved": round(d_ach, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(d_ach / HBM_PEAK_GBS, 4),
+                          "traffic": read_traffic(a.workload, "k_precond_fused"),
+                          "kernel": "k_precond_fused (FP64 blocks)",
+                          "avg_launch_ms": round(dprec_ms, 5),
+                          "algorithmic_bytes_per_launch": std_["bytes_precond"]}}
+    del dctx, ud
+
+    # The same solve in FP64 flexible GMRES with J^-1 in FP64 (separable form) and
+    # with FP32 and BF16 stored blocks, all stopped by the same true-residual
+    # tolerance (equal accuracy: the error against the oracle is reported next
+    # to the time).
+    mixed = {"tol_true_residual": MIXED_TOL,
+             "j_inverse_form": {"fp64": "separable", "fp32": "stored blocks", "bf16": "stored blocks"}}
     for pr in ("fp64", "fp32", "bf16"):
         uu = torch.zeros_like(s)
         ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="fgmres",
@@ -280,13 +324,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "n_elem": list(prob.n_elem), "p": prob.p, "q": prob.q,
                    "kappa": prob.kappa, "unknowns": N, "solver": "left-preconditioned GMRES",
+                   "preconditioner": "homogenized block-Jacobi, separable form (exact leaf inverses, no stored blocks)",
                    "restart": prob.restart, "tol": prob.tol},
         "iters_per_solve": its / a.steps, "converged": bool(ok),
         "true_rel_res": st["true_rel_res"], "err_vs_oracle": err,
-        "setup_s": round(t_setup, 3),
+        "setup_s": round(t_setup, 3), "device_bytes": ctx.device_bytes(),
         "apply_kernel": {"avg_launch_ms": round(app_ms, 5),
                          "munknowns_per_s": round(N / (app_ms * 1e-3) / 1e6, 1),
                          "algorithmic_GBs": round(st["bytes_apply"] / (app_ms * 1e-3) / 1e9, 1)},
+        "precond_kernel": precond_kernel,
+        "dense_blocks": dense,
         "mixed_precision_fgmres": mixed,
         "lambda_buckets": buckets,
         "iti_face_system": iti,

@@ -288,6 +288,15 @@ int hps_set_timing(hps_ctx* c, int enable);
  * launches.  Synchronizes the stream.  reset != 0 clears them. */
 int hps_kernel_times(hps_ctx* c, double out[8], int reset);
 
+/* The Arnoldi update pass (one launch per Arnoldi step, the basis read once;
+ * with the dense blocks replaced by the separable J^-1 it is the largest
+ * kernel of a solve), timed like the kinds above: out[0] = milliseconds of the
+ * timed launches, out[1] = their number, out[2] = their algorithmic HBM bytes
+ * (per right-hand side and step j: basis vectors 0..j-1 and two vectors read,
+ * two written, 16 N (j + 4) bytes).  Synchronizes the stream; reset != 0
+ * clears them (independently of hps_kernel_times). */
+int hps_arnoldi_times(hps_ctx* c, double out[3], int reset);
+
 /* Tile shapes of the many-right-hand-side block GEMM inside J^-1 (4 to 64
  * right-hand sides; the batching pattern on top of Sec. 4): shape index ->
  * (wavefronts per workgroup, right-hand sides per column panel): 0 (8, 64),

@@ -83,7 +83,7 @@ void timing_drop(hps_ctx* c, const TimedPair& tp) {
   if (tp.stop) c->ev_free.push_back(tp.stop);
 }
 
-int timing_commit(hps_ctx* c, int kind, const TimedPair& tp) {
+int timing_commit(hps_ctx* c, int kind, const TimedPair& tp, double bytes) {
   if (!tp.start) return HPS_OK;
   if (kind < 0 || kind >= kTimingKinds) {
     c->ev_free.push_back(tp.start);
@@ -91,6 +91,7 @@ int timing_commit(hps_ctx* c, int kind, const TimedPair& tp) {
     return fail(HPS_ERR_ARG, "timing kind out of range");
   }
   c->ev_pending[kind].emplace_back(tp.start, tp.stop);
+  c->ev_bytes[kind].push_back(bytes);
   if (c->ev_pending[kind].size() >= 4096) return timing_collect(c);
   return HPS_OK;
 }
@@ -99,7 +100,8 @@ int timing_collect(hps_ctx* c) {
   static_assert(sizeof(c->ev_pending) / sizeof(c->ev_pending[0]) == kTimingKinds, "timing kinds");
   int rc = HPS_OK;
   for (int k = 0; k < kTimingKinds; ++k) {
-    for (auto& pr : c->ev_pending[k]) {
+    for (size_t i = 0; i < c->ev_pending[k].size(); ++i) {
+      auto& pr = c->ev_pending[k][i];
       if (rc == HPS_OK) {
         float ms = 0.f;
         rc = check_hip(hipEventSynchronize(pr.second), "hipEventSynchronize");
@@ -107,6 +109,7 @@ int timing_collect(hps_ctx* c) {
         if (rc == HPS_OK) {
           c->t_ms[k] += ms;
           c->t_cnt[k] += 1.0;
+          c->t_bytes[k] += c->ev_bytes[k][i];
         }
       }
       // every event goes back to the pool exactly once, also after an error
@@ -114,6 +117,7 @@ int timing_collect(hps_ctx* c) {
       c->ev_free.push_back(pr.second);
     }
     c->ev_pending[k].clear();
+    c->ev_bytes[k].clear();
   }
   return rc;
 }
@@ -522,11 +526,22 @@ int hps_kernel_times(hps_ctx* c, double out[8], int reset) {
   if (!c || !out) return fail(HPS_ERR_ARG, "NULL argument");
   int rc = timing_collect(c);
   if (rc) return rc;
-  for (int k = 0; k < kTimingKinds; ++k) {
+  for (int k = 0; k < 4; ++k) {
     out[2 * k] = c->t_ms[k];
     out[2 * k + 1] = c->t_cnt[k];
-    if (reset) c->t_ms[k] = c->t_cnt[k] = 0.0;
+    if (reset) c->t_ms[k] = c->t_cnt[k] = c->t_bytes[k] = 0.0;
   }
+  return HPS_OK;
+}
+
+int hps_arnoldi_times(hps_ctx* c, double out[3], int reset) {
+  if (!c || !out) return fail(HPS_ERR_ARG, "NULL argument");
+  int rc = timing_collect(c);
+  if (rc) return rc;
+  out[0] = c->t_ms[4];
+  out[1] = c->t_cnt[4];
+  out[2] = c->t_bytes[4];
+  if (reset) c->t_ms[4] = c->t_cnt[4] = c->t_bytes[4] = 0.0;
   return HPS_OK;
 }
 

@@ -73,7 +73,7 @@ struct Workspace {
 
 }  // namespace hps
 
-constexpr int kTimingKinds = 4;
+constexpr int kTimingKinds = 5;
 
 struct hps_ctx {
   int p = 0, n1 = 0, ni = 0, nb = 0, n = 0;
@@ -139,13 +139,16 @@ struct hps_ctx {
   hipEvent_t ev_solver[2] = {nullptr, nullptr};  // residual-check events of the solvers
 
   // optional kernel timing: event pairs per launch kind (kTimingKinds: 0 operator,
-  // 1 preconditioner, 2 many-rhs block GEMM, 3 ItI block product of the face system)
+  // 1 preconditioner, 2 many-rhs block GEMM, 3 ItI block product of the face system,
+  // 4 Arnoldi update pass), with the algorithmic HBM bytes of each timed launch
   int timing = 0;                   // 0 off, k > 0: time every k-th launch of each kind
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kTimingKinds];
-  double t_ms[kTimingKinds] = {0.0, 0.0, 0.0, 0.0};
-  double t_cnt[kTimingKinds] = {0.0, 0.0, 0.0, 0.0};
-  uint64_t t_seq[kTimingKinds] = {0, 0, 0, 0};    // launches seen per kind (sampling)
+  std::vector<double> ev_bytes[kTimingKinds];
+  double t_ms[kTimingKinds] = {};
+  double t_cnt[kTimingKinds] = {};
+  double t_bytes[kTimingKinds] = {};
+  uint64_t t_seq[kTimingKinds] = {};    // launches seen per kind (sampling)
 };
 
 namespace hps {
@@ -179,8 +182,8 @@ int launch_node_coords(hps_ctx* c, double* d_xyz);
 struct TimedPair {
   hipEvent_t start = nullptr, stop = nullptr;
 };
-int timing_pair(hps_ctx* c, int kind, TimedPair* tp);  // kind: 0 apply, 1 J^-1, 2 GEMM, 3 ItI
-int timing_commit(hps_ctx* c, int kind, const TimedPair& tp);
+int timing_pair(hps_ctx* c, int kind, TimedPair* tp);  // kind: 0 apply, 1 J^-1, 2 GEMM, 3 ItI, 4 update
+int timing_commit(hps_ctx* c, int kind, const TimedPair& tp, double bytes = 0.0);
 void timing_drop(hps_ctx* c, const TimedPair& tp);  // return unused events to the pool
 int timing_collect(hps_ctx* c);
 

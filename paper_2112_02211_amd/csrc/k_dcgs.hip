@@ -471,9 +471,19 @@ int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, 
   // loads); every workgroup recomputes the step coefficients, a few KB from L2
   const int64_t want = (n + UT - 1) / UT;
   const int nblk = (int)std::min<int64_t>(want, 8192);
-  hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, 1, nbatch), dim3(UT), 0, c->stream, V, ldv, vbs, J, u,
-                     ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag, kBreakdownTol);
-  return check_hip(hipGetLastError(), "k_dcgs_update");
+  TimedPair tp;
+  int rc = timing_pair(c, 4, &tp);
+  if (rc) return rc;
+  rc = check_hip(launch_k(c, tp.start, tp.stop, k_dcgs_update, dim3(nblk, 1, nbatch), dim3(UT), V, ldv,
+                          vbs, J, u, ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag,
+                          kBreakdownTol),
+                 "k_dcgs_update");
+  if (rc) {
+    timing_drop(c, tp);
+    return rc;
+  }
+  // algorithmic bytes: V_0..J-1, u and w read, V_J and u written
+  return timing_commit(c, 4, tp, 16.0 * (double)(J + 4) * (double)n * nbatch);
 }
 
 int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch) {

@@ -110,6 +110,7 @@ SIGNATURES = {
                                  ctypes.POINTER(_SolveOpts), ctypes.POINTER(Stats)]),
     "hps_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
     "hps_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hps_arnoldi_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     "hps_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     "hps_setup_bytes": (ctypes.c_int64, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
@@ -299,6 +300,13 @@ class Context:
                 "precond_ms": out[2], "precond_launches": int(out[3]),
                 "gemm_ms": out[4], "gemm_launches": int(out[5]),
                 "iti_ms": out[6], "iti_launches": int(out[7])}
+
+    def arnoldi_times(self, reset: bool = False) -> dict:
+        """Event-timed Arnoldi update passes since the last reset, with their
+        algorithmic HBM bytes."""
+        out = (ctypes.c_double * 3)()
+        _check(lib().hps_arnoldi_times(self._h, out, 1 if reset else 0))
+        return {"update_ms": out[0], "update_launches": int(out[1]), "update_bytes": out[2]}
 
     def solve_bytes(self, restart: int, nrhs: int = 1, solver: str = "gmres",
                     precond_prec: str = "fp64") -> int:

@@ -2,6 +2,8 @@
 
     python -m paper_2112_02211_amd.profile_run [run] [--workload NAME] [--launches 4] [--lambda-bucket D]
     python -m paper_2112_02211_amd.profile_run pmc-summary --fetch DIR --write DIR --out FILE
+    python -m paper_2112_02211_amd.profile_run arnoldi [--workload NAME]
+    python -m paper_2112_02211_amd.profile_run arnoldi-summary --fetch DIR --write DIR --run-log FILE --out FILE
     python -m paper_2112_02211_amd.profile_run trace-summary --stats CSV --out FILE --cmd CMD --title T
 
 ``run`` (the default) is the fixed launch sequence for hardware-counter runs:
@@ -16,6 +18,10 @@ WRITE_SIZE counters).  Prints one line per phase with its wall time.
 
 ``pmc-summary`` turns two rocprofv3 --pmc runs of ``run`` (one FETCH_SIZE, one
 WRITE_SIZE, csv output) into the traffic summary that bench.py reads.
+``arnoldi`` solves the workload twice with the separable J^-1 (the second
+solve with every Arnoldi update pass event-timed, printing their number and
+algorithmic bytes), then runs the calibration kernel; ``arnoldi-summary``
+turns its two counter runs into the update pass's traffic summary.
 ``trace-summary`` turns a rocprofv3 --kernel-trace --stats kernel_stats.csv
 into a text table.
 """
@@ -35,14 +41,17 @@ if ROOT not in sys.path:
 CSRC = os.path.join(ROOT, "paper_2112_02211_amd", "csrc")
 # every source the preconditioner kernel is compiled from
 PRECOND_SOURCES = ("k_precond_fused.h", "k_leaf.h", "k_common.h")
+# the Arnoldi kernels and their launchers
+ARNOLDI_SOURCES = ("k_dcgs.hip", "k_common.h")
+KERNEL_SOURCES = {"k_precond_fused": PRECOND_SOURCES, "k_dcgs_update": ARNOLDI_SOURCES}
 COPY_MIB = 1024
 
 
-def kernel_source_hash() -> str:
-    """Hash of the preconditioner kernel's sources: counters taken on other
-    sources describe another kernel."""
+def kernel_source_hash(kernel: str = "k_precond_fused") -> str:
+    """Hash of a profiled kernel's sources: counters taken on other sources
+    describe another kernel."""
     h = hashlib.sha256()
-    for name in PRECOND_SOURCES:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -81,6 +90,83 @@ def run(a):
         dt = (time.perf_counter() - t0) / a.launches
         print(f"{name}: {dt * 1e3:.4f} ms per launch", flush=True)
     print(f"copy bytes read = written = {n * 4}")
+
+
+def _copy_phase(a):
+    import torch
+    n = a.copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(a.launches + 1):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"copy bytes read = written = {n * 4}", flush=True)
+
+
+def arnoldi(a):
+    import torch
+    from paper_2112_02211_amd import hps, problems as P
+
+    prob = P.workload(a.workload)
+    ctx = hps.Context.from_problem(prob, block_precs=("separable",), lambda_bucket=0.0)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    s, t = torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda()
+    _, st, _ = ctx.gmres(s, t, tol=prob.tol, restart=prob.restart)
+    print(f"warm-up solve: {st['iters']} steps", flush=True)
+    ctx.set_timing(True, every=1)
+    ctx.arnoldi_times(reset=True)
+    _, st, _ = ctx.gmres(s, t, tol=prob.tol, restart=prob.restart)
+    at = ctx.arnoldi_times(reset=True)
+    ctx.set_timing(False)
+    print(f"arnoldi_update_launches: {at['update_launches']}", flush=True)
+    print(f"arnoldi_update_algorithmic_bytes: {at['update_bytes']:.0f}", flush=True)
+    print(f"arnoldi_update_ms: {at['update_ms']:.4f}", flush=True)
+    _copy_phase(a)
+
+
+def arnoldi_summary(a):
+    """Traffic of the Arnoldi update pass over the second solve of `arnoldi`."""
+    info = {}
+    for line in open(a.run_log):
+        if line.startswith("arnoldi_update_"):
+            k, v = line.split(":", 1)
+            info[k.strip()] = float(v)
+    K = int(info["arnoldi_update_launches"])
+    alg = info["arnoldi_update_algorithmic_bytes"]
+    F = _counters(os.path.join(a.fetch, "run_counter_collection.csv"), "FETCH_SIZE")
+    W = _counters(os.path.join(a.write, "run_counter_collection.csv"), "WRITE_SIZE")
+    fu, wu = _find(F, "k_dcgs_update"), _find(W, "k_dcgs_update")
+    if len(fu) != 2 * K or len(wu) != 2 * K:
+        raise ValueError(f"expected {2 * K} update dispatches, got {len(fu)}, {len(wu)}")
+    med = lambda v: statistics.median(v[1:])
+    ew_f, ew_w = med(_find(F, "MulFunctor<float>")), med(_find(W, "MulFunctor<float>"))
+    copy_kib = a.copy_mib * 1024.0
+    sf, sw = copy_kib / ew_f, copy_kib / ew_w
+    tot = sum(fu[K:]) * 1024 * sf + sum(wu[K:]) * 1024 * sw
+    cmd = f"python $R/paper_2112_02211_amd/profile_run.py arnoldi --workload {a.workload} --launches {a.launches}"
+    L = [f"# HBM traffic of the Arnoldi update pass (k_dcgs_update), {a.workload} workload, one",
+         "# left-preconditioned GMRES solve with the separable J^-1 (the second of two solves)",
+         "#",
+         "# commands (R = repository root on the GPU box; one counter per run):",
+         "#   cd /tmp && export TMPDIR=/tmp",
+         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.fetch.rstrip('/'))} -o run -- {cmd}",
+         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.write.rstrip('/'))} -o run -- {cmd}",
+         f"#   python -m paper_2112_02211_amd.profile_run arnoldi-summary --workload {a.workload} "
+         f"--launches {a.launches} --fetch <fetch dir> --write <write dir> --run-log <stdout of a run> --out <this file>",
+         "#",
+         f"# calibration: elementwise kernel dst = 2 src over {a.copy_mib} MiB float32",
+         f"fetch_scale: {sf:.5f}",
+         f"write_scale: {sw:.5f}",
+         f"update_launches: {K}",
+         f"update_algorithmic_bytes_total: {alg:.0f}",
+         f"update_hbm_bytes_total: {tot:.0f}",
+         f"traffic_over_algorithmic: {tot / alg:.4f}",
+         f"kernel_source_sha256_16: {kernel_source_hash('k_dcgs_update')}",
+         f"algorithmic_bytes_per_launch: {alg / K:.0f}",
+         f"hbm_bytes_per_launch: {tot / K:.0f}"]
+    text = "\n".join(L) + "\n"
+    open(a.out, "w").write(text)
+    print(text)
 
 
 def _counters(path, counter):
@@ -202,7 +288,8 @@ def trace_summary(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", nargs="?", default="run", choices=("run", "pmc-summary", "trace-summary"))
+    ap.add_argument("mode", nargs="?", default="run",
+                    choices=("run", "pmc-summary", "trace-summary", "arnoldi", "arnoldi-summary"))
     ap.add_argument("--workload", default="bumps_8x8x8_p10")
     ap.add_argument("--launches", type=int, default=4)
     ap.add_argument("--iti", action="store_true",
@@ -213,12 +300,14 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--stats")
+    ap.add_argument("--run-log")
     ap.add_argument("--out")
     ap.add_argument("--cmd", default="")
     ap.add_argument("--title", default="rocprofv3 kernel statistics")
     ap.add_argument("--rows", type=int, default=24)
     a = ap.parse_args()
-    {"run": run, "pmc-summary": pmc_summary, "trace-summary": trace_summary}[a.mode](a)
+    {"run": run, "pmc-summary": pmc_summary, "trace-summary": trace_summary, "arnoldi": arnoldi,
+     "arnoldi-summary": arnoldi_summary}[a.mode](a)
 
 
 if __name__ == "__main__":
