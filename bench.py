@@ -137,6 +137,9 @@ def main():
                     help="requests of the serving workload (request_stream)")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="block precision of the many-right-hand-side workload")
+    ap.add_argument("--precond", default="blocks", choices=["blocks", "separable"],
+                    help="J^-1 of the shared-block workloads: their lambda-bucketed blocks, or the "
+                         "separable form at every leaf's own lambda (no blocks)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -352,12 +355,16 @@ def run_bucketed(a, prob):
     import torch
     from paper_2112_02211_amd import hps, problems as P
 
+    sep = a.precond == "separable"
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx = hps.Context.from_problem(prob)
+    if sep:
+        ctx = hps.Context.from_problem(prob, block_precs=("separable",), lambda_bucket=0.0)
+    else:
+        ctx = hps.Context.from_problem(prob)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    print(f"# setup {t_setup:.2f} s, {ctx.n_blocks} blocks for {ctx.nl} leaves, "
+    print(f"# setup {t_setup:.2f} s, {0 if sep else ctx.n_blocks} blocks for {ctx.nl} leaves, "
           f"{ctx.device_bytes() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     # the Gaussian source at the nodes, evaluated in chunks (a billion-unknown
     # mesh has 25 GB of node coordinates); bump problems have no boundary data,
@@ -398,6 +405,7 @@ def run_bucketed(a, prob):
         step()
     ctx.set_timing(True, every=TIMING_EVERY)
     ctx.kernel_times(reset=True)
+    ctx.arnoldi_times(reset=True)
     torch.cuda.synchronize()
     its = 0
     t0 = time.perf_counter()
@@ -409,14 +417,35 @@ def run_bucketed(a, prob):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = ctx.kernel_times(reset=True)
+    at = ctx.arnoldi_times(reset=True)
     ctx.set_timing(False)
     N = ctx.N
     gemm_ms = kt["gemm_ms"] / max(1, kt["gemm_launches"])
     prec_ms = kt["precond_ms"] / max(1, kt["precond_launches"])
     app_ms = kt["apply_ms"] / max(1, kt["apply_launches"])
-    flops = 8.0 * ctx.nl * ctx.nb * ctx.nb          # complex GEMM, one right-hand side
-    tfs = flops / (gemm_ms * 1e-3) / 1e12
-    peak = MFMA_PEAK_TFLOPS["fp64"]
+    if sep:
+        # no blocks: the dominant kernel is the Arnoldi update pass
+        upd_ms = at["update_ms"] / max(1, at["update_launches"])
+        upd_bytes = at["update_bytes"] / max(1, at["update_launches"])
+        gbs = upd_bytes / (upd_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_dcgs_update (Arnoldi update pass)",
+                    "avg_launch_ms": round(upd_ms, 5), "algorithmic_bytes_per_launch": round(upd_bytes)}
+        pgbs = st["bytes_precond"] / (prec_ms * 1e-3) / 1e9
+        extra = {"precond_kernel": {"kernel": "k_precond_sep (separable J^-1)",
+                                    "avg_launch_ms": round(prec_ms, 5),
+                                    "algorithmic_GBs": round(pgbs, 1),
+                                    "frac_of_hbm_peak": round(pgbs / HBM_PEAK_GBS, 4)}}
+    else:
+        flops = 8.0 * ctx.nl * ctx.nb * ctx.nb          # complex GEMM, one right-hand side
+        tfs = flops / (gemm_ms * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS["fp64"]
+        roofline = {"bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tfs / peak, 4), "traffic": None,
+                    "kernel": "k_block_gemm (FP64 blocks, grouped by bucket)",
+                    "avg_launch_ms": round(gemm_ms, 4), "algorithmic_flops_per_launch": flops}
+        extra = {}
     line = {
         "metric": METRIC, "value": round(N * its / elapsed / 1e6, 1), "unit": "Munknowns/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -424,17 +453,17 @@ def run_bucketed(a, prob):
         "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
         "config": {"workload": a.workload, "n_elem": list(prob.n_elem), "p": prob.p, "q": prob.q,
                    "kappa": prob.kappa, "unknowns": N, "solver": "left-preconditioned GMRES",
-                   "restart": prob.restart, "tol": prob.tol, "lambda_bucket": prob.lambda_bucket,
-                   "blocks": ctx.n_blocks, "leaves": ctx.nl, "max_steps": max_steps},
+                   "restart": prob.restart, "tol": prob.tol,
+                   "preconditioner": ("separable J^-1 at every leaf's own lambda (no blocks)" if sep else
+                                      f"lambda-bucketed blocks, delta {prob.lambda_bucket}"),
+                   "blocks": 0 if sep else ctx.n_blocks, "leaves": ctx.nl, "max_steps": max_steps},
         "iters_per_solve": its / a.steps, "converged": bool(ok),
         "true_rel_res": st["true_rel_res"], "setup_s": round(t_setup, 3),
         "device_GiB": round(ctx.device_bytes() / 2**30, 2),
         "precond_avg_launch_ms": round(prec_ms, 4),
         "apply_avg_launch_ms": round(app_ms, 4),
-        "roofline": {"bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(tfs / peak, 4), "traffic": None,
-                     "kernel": "k_block_gemm (FP64 blocks, grouped by bucket)",
-                     "avg_launch_ms": round(gemm_ms, 4), "algorithmic_flops_per_launch": flops},
+        **extra,
+        "roofline": roofline,
     }
     print(json.dumps(line))
 
@@ -512,6 +541,36 @@ def run_batched(a, prob):
                              tol=1e-10, restart=30, solver="fgmres", precond_prec=prec)
         ur = U[r * N:(r + 1) * N]
         errs.append(float(torch.linalg.norm(ur - u1) / torch.linalg.norm(u1)))
+    # The same lock-step solve with the FP64 J^-1 in separable form (no blocks,
+    # left preconditioning, FP64 throughout)
+    ctx.free()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sctx = hps.Context.from_problem(prob, block_precs=("separable",))
+    torch.cuda.synchronize()
+    s_setup = time.perf_counter() - t1
+    Us = torch.zeros_like(S)
+    sctx.gmres(S, T, tol=prob.tol, restart=prob.restart, u=Us, solver="batched", check_every=a.check_every)
+    sctx.set_timing(True, every=TIMING_EVERY)
+    sctx.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, sts, oks = sctx.gmres(S, T, tol=prob.tol, restart=prob.restart, u=Us, solver="batched",
+                             check_every=a.check_every)
+    torch.cuda.synchronize()
+    s_el = time.perf_counter() - t1
+    skt = sctx.kernel_times(reset=True)
+    sctx.set_timing(False)
+    sp_ms = skt["precond_ms"] / max(1, skt["precond_launches"])
+    separable = {"setup_s": round(s_setup, 3), "solve_ms": round(s_el * 1e3, 1),
+                 "iters_per_rhs": sts["iters"], "converged": bool(oks), "true_rel_res": sts["true_rel_res"],
+                 "value_munknowns_per_s": round(N * k * sts["iters"] / s_el / 1e6, 1),
+                 "precond_all_rhs_ms": round(sp_ms, 4),
+                 "precond_algorithmic_GBs": round(32.0 * N * k / (sp_ms * 1e-3) / 1e9, 1),
+                 "max_rel_diff_vs_block_solve": float(max(
+                     torch.linalg.norm(Us[r * N:(r + 1) * N] - U[r * N:(r + 1) * N]) /
+                     torch.linalg.norm(U[r * N:(r + 1) * N]) for r in (0, k - 1)))}
+    sctx.free()
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Munknowns/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(elapsed / a.steps * 1e3, 3),
@@ -526,6 +585,7 @@ def run_batched(a, prob):
         "precond_batched_ms": round(prec_ms, 4), "apply_ms_all_rhs": round(app_ms, 4),
         "gemm_tile_shape": {"wavefronts": hps.GEMM_SHAPES[shape][0],
                             "rhs_per_panel": hps.GEMM_SHAPES[shape][1], "chosen_by": "autotuner"},
+        "separable_fp64": separable,
         "roofline": roofline,
     }
     if not a.no_cpu_baseline:
