@@ -157,7 +157,7 @@ class Scheduler:
 class ServeConfig:
     slots: int = 4
     hbm_fraction: float = 0.85       # of the free device memory at start
-    block_prec: str = "fp64"
+    block_prec: str = "fp64"         # "separable": the FP64 J^-1 without stored blocks
     precond_prec: str = "fp64"
     restart: int = 50                # Krylov dimension of a cycle = one tick
     tol: float = 1e-8
@@ -228,16 +228,22 @@ class Server:
         self.n_jobs = 0
 
     # ---------------------------------------------------------------- sizing
+    def _fp64_pc(self) -> bool:
+        """J^-1 in FP64 (stored FP64 blocks or the separable form): left GMRES applies."""
+        return self.cfg.precond_prec in ("fp64", "separable")
+
     def _blocks(self):
-        return (self.cfg.block_prec,) if self.cfg.block_prec == self.cfg.precond_prec else \
-            (self.cfg.block_prec, self.cfg.precond_prec)
+        bp, pp = self.cfg.block_prec, self.cfg.precond_prec
+        if bp == "separable" and pp in ("fp64", "separable"):
+            return ("separable",)
+        return (bp,) if bp == pp else (bp, pp)
 
     def _size(self, key, prob, nrhs, resident) -> int:
         setup, transient = self.hps.setup_bytes(prob.n_elem, prob.p, self._blocks(),
                                                 complex_medium=bool(np.any(np.imag(prob.bump_amps))))
         n = prob.n_unknowns
         k = min(nrhs, 64)
-        flexible = self.cfg.precond_prec != "fp64" or self.cfg.solver == "fgmres"
+        flexible = not self._fp64_pc() or self.cfg.solver == "fgmres"
         m = self.cfg.restart
         vec = 16 * n * k
         solve = vec * ((m + 1) + (m if flexible else 0) + 1) + 16 * n * nrhs + \
@@ -297,7 +303,7 @@ class Server:
             S = torch.cat([a.s for a in act])
             T = torch.cat([a.t for a in act])
             U = torch.zeros_like(S)
-            single = cfg.solver if cfg.precond_prec == "fp64" else "fgmres"
+            single = cfg.solver if self._fp64_pc() else "fgmres"
             left = set(range(k))
             while left:
                 _, st, _ = ctx.gmres(S, T, tol=cfg.tol, restart=cfg.restart, u=U, solver=single,
@@ -361,7 +367,7 @@ class Server:
                 N = ctx.N
                 t_now = time.perf_counter()
                 active = [self._activate(r, xyz, t_now) for r in job.requests]
-                single = cfg.solver if cfg.precond_prec == "fp64" else "fgmres"
+                single = cfg.solver if self._fp64_pc() else "fgmres"
                 while active:
                     k = len(active)
                     S = torch.cat([a.s for a in active]) if k > 1 else active[0].s

@@ -177,3 +177,28 @@ def test_operator_groups_serve_the_same_solutions():
     got = next(x for x in res if x.rid == reqs[0].rid)
     ud = O.solve_direct(op)
     assert np.linalg.norm(got.u - ud) / np.linalg.norm(ud) < 1e-8
+
+
+@pytest.mark.parametrize("group_ops", [0, 4])
+def test_separable_operators_serve_the_same_solutions(group_ops):
+    # operators with the separable J^-1 (no stored blocks): the same
+    # preconditioner, so every served solution matches the stored-block server's
+    # and the oracle's direct solve; also in operator groups
+    from paper_2112_02211_amd.serve import Server, ServeConfig, latency_stats
+    reqs = P.request_stream(8, rate=60.0, seed=15, meshes=(2, 3), orders=(6, 8), share=0.5)
+    srv = Server(ServeConfig(slots=3, tol=1e-10, restart=30, block_prec="separable",
+                             group_ops=group_ops))
+    res = srv.run(_fresh(reqs), closed_loop=True)
+    srv.close()
+    assert latency_stats(res)["all_converged"]
+    srv = Server(ServeConfig(slots=3, tol=1e-10, restart=30))
+    ref = srv.run(_fresh(reqs), closed_loop=True)
+    srv.close()
+    for r in reqs:
+        got = next(x for x in res if x.rid == r.rid)
+        want = next(x for x in ref if x.rid == r.rid)
+        assert np.linalg.norm(got.u - want.u) / np.linalg.norm(want.u) < 1e-8, r.rid
+    for r in reqs[:2]:
+        ud = O.solve_direct(O.build(r.prob))
+        got = next(x for x in res if x.rid == r.rid)
+        assert np.linalg.norm(got.u - ud) / np.linalg.norm(ud) < 1e-8
