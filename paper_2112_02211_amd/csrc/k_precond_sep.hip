@@ -21,7 +21,9 @@
 //   u_i   = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
 //   u_b   = g - Fi Fbi1 u_line                    on every grid line
 //
-// Cost per leaf O(n1^4) in LDS; the kernel reads x and writes y once (32 bytes
+// One workgroup per (leaf, right-hand side), the leaf in LDS, six complex mode
+// products (two forms, chosen per order: kLineWise).  Cost per leaf O(n1^4);
+// the kernel reads x and writes y once (32 bytes
 // per unknown), where the dense form also streams the n_b x n_b block.  The
 // tables (Wc, Vc, Ec, Fi per operator) are built on the host at setup.
 #include "hps_internal.h"
@@ -29,23 +31,97 @@
 namespace hps {
 namespace {
 
+// Mode-product form per order, from measurement (J^-1 over about 4 million
+// unknowns for every p = 4 ... 16, both forms): line-wise (a thread owns a grid
+// line and two of its outputs, the n1 inputs in registers, the matrix rows
+// uniform across a wavefront and read through the scalar cache) was 3-32 %
+// faster at p = 8, 10, 11 and 13-16, element-parallel (a thread owns one
+// output; inputs and matrix entries from LDS) 5-30 % faster at p = 4-7 and 9
+// and equal at 12.
+template <int P> constexpr bool kLineWise = (P == 8 || P == 10 || P == 11 || P >= 13);
+
 template <int P>
 struct SL {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
   static constexpr int BD0 = (NI + 63) / 64 * 64;
   static constexpr int BD = BD0 < 64 ? 64 : (BD0 > 1024 ? 1024 : BD0);
   static constexpr int ST = sep_table_size(P);
+  static constexpr bool LW = kLineWise<P>;
+  // line-wise: the LDS tensors pad each x-line to n1 + 1 entries, so the
+  // threads of a wavefront that walk neighbouring x-lines read 16-byte words in
+  // different banks
+  static constexpr int P1 = LW ? N1 + 1 : N1, SZ = P1 * L;
+  // line-wise work items: (output group of R, 64 lines) per wavefront
+  static constexpr int R = 2, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
+  // tables staged in LDS: Ec | Fi, and for the element-parallel form Wc | Vc before them
+  static constexpr int CTN = LW ? N1 + 4 : ST, CT0 = LW ? 0 : 2 * L;
 };
+
+template <int P>
+__device__ __forceinline__ int lidx(int i, int j, int k) {
+  return i + SL<P>::P1 * (j + SL<P>::N1 * k);
+}
 
 __device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
   acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
   acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
 }
 
-// out[.., o, ..] = sum_i M[o][i] in[.., i, ..] along axis AX (M complex, row major)
-template <int P, int AX>
-__device__ __forceinline__ void cmode(const double2* __restrict__ in, double2* __restrict__ out,
-                                      const double2* __restrict__ M) {
+// First entry and stride (padded LDS index) of the grid line along axis ax
+// through position (a, b) of the other two axes, lower axis first.
+template <int P>
+__device__ __forceinline__ void line_of(int ax, int a, int b, int& base, int& stride) {
+  using S = SL<P>;
+  if (ax == 0) { base = S::P1 * (a + S::N1 * b); stride = 1; }
+  else if (ax == 1) { base = a + S::P1 * S::N1 * b; stride = S::P1; }
+  else { base = a + S::P1 * b; stride = S::P1 * S::N1; }
+}
+
+// out[.., o, ..] = sum_i M[o][i] in[.., i, ..] along axis AX (M complex, row
+// major).  SCALE: the output element (i, j, k) is multiplied by
+// 1 / (-(Ec_i + Ec_j + Ec_k) - lambda) (the last forward product).
+// Line-wise form: M in global memory, read at wavefront-uniform addresses.
+template <int P, int AX, bool SCALE>
+__device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2* __restrict__ out,
+                                         const double2* __restrict__ M, const double2* __restrict__ Ec,
+                                         double2 lm) {
+  using S = SL<P>;
+  constexpr int N1 = S::N1, L = S::L, R = S::R, WPG = S::WPG, NW = S::BD / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (int w = wave; w < S::W; w += NW) {
+    const int og = w / WPG;
+    const int line = (w - og * WPG) * 64 + lane;
+    if (line >= L) continue;
+    const int a = line % N1, b = line / N1;
+    int base, stride;
+    line_of<P>(AX, a, b, base, stride);
+    double2 v[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) v[i] = in[base + i * stride];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int o = og * R + r;
+      if (o >= N1) break;
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < N1; ++i) cfma(s, M[o * N1 + i], v[i]);
+      if (SCALE) {   // AX == 2: output element (a, b, o)
+        const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
+        const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
+        const double den = 1.0 / (ar * ar + ai * ai);
+        s = cmul(s, make_double2(ar * den, -ai * den));
+      }
+      out[base + o * stride] = s;
+    }
+  }
+}
+
+// Element-parallel form: one output per thread, M staged in LDS (unpadded tensors).
+template <int P, int AX, bool SCALE>
+__device__ __forceinline__ void cmode_el(const double2* __restrict__ in, double2* __restrict__ out,
+                                         const double2* __restrict__ M, const double2* __restrict__ Ec,
+                                         double2 lm) {
   using S = SL<P>;
   constexpr int N1 = S::N1, L = S::L, NI = S::NI, BD = S::BD;
   constexpr int stride = AX == 0 ? 1 : (AX == 1 ? N1 : L);
@@ -55,18 +131,23 @@ __device__ __forceinline__ void cmode(const double2* __restrict__ in, double2* _
     double2 s = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < N1; ++i) cfma(s, M[o * N1 + i], in[base + i * stride]);
+    if (SCALE) {
+      const int i = m % N1, j = (m / N1) % N1, k = m / L;
+      const double ar = -(Ec[i].x + Ec[j].x + Ec[k].x) - lm.x;
+      const double ai = -(Ec[i].y + Ec[j].y + Ec[k].y) - lm.y;
+      const double den = 1.0 / (ar * ar + ai * ai);
+      s = cmul(s, make_double2(ar * den, -ai * den));
+    }
     out[m] = s;
   }
 }
 
-// First entry and stride of the grid line along axis ax through face position pos.
-template <int P>
-__device__ __forceinline__ void line_of(int ax, int pos, int& base, int& stride) {
-  constexpr int N1 = P - 2, L = N1 * N1;
-  const int a = pos % N1, b = pos / N1;
-  if (ax == 0) { base = N1 * a + L * b; stride = 1; }
-  else if (ax == 1) { base = a + L * b; stride = N1; }
-  else { base = a + N1 * b; stride = L; }
+template <int P, int AX, bool SCALE>
+__device__ __forceinline__ void cmode(const double2* __restrict__ in, double2* __restrict__ out,
+                                      const double2* __restrict__ Mg, const double2* __restrict__ Ml,
+                                      const double2* __restrict__ Ec, double2 lm) {
+  if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE>(in, out, Mg, Ec, lm);
+  else cmode_el<P, AX, SCALE>(in, out, Ml, Ec, lm);
 }
 
 // g != null: x is A v without the face exchange, added here while loading
@@ -80,10 +161,10 @@ __global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
     const double* __restrict__ tab, int64_t nl, int64_t N, int64_t os) {
   using S = SL<P>;
   constexpr int N1 = S::N1, L = S::L, NI = S::NI, NB = S::NB, NN = S::NN, BD = S::BD;
-  __shared__ double2 T[NI];
-  __shared__ double2 X[NI];
+  __shared__ double2 T[S::SZ];
+  __shared__ double2 X[S::SZ];
   __shared__ double2 G[NB];
-  __shared__ double2 CT[S::ST];     // Wc | Vc | Ec | Fi
+  __shared__ double2 CT[S::CTN];    // (Wc | Vc |) Ec | Fi
   __shared__ double RT[4 * N1];     // Dlo | Dhi | C0 | C1
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
@@ -91,7 +172,9 @@ __global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
   double2* yv = y + rhs * N + tau * NN;
   const double2 lm = lam[tau + rhs * os];
   const double2* st = sep + (os ? (int64_t)rhs * S::ST : 0);
-  for (int k = threadIdx.x; k < S::ST; k += BD) CT[k] = st[k];
+  const double2* Wc = st;          // global: read at wavefront-uniform addresses
+  const double2* Vc = st + L;
+  for (int k = threadIdx.x; k < S::CTN; k += BD) CT[k] = st[2 * L - S::CT0 + k];
   for (int k = threadIdx.x; k < 4 * N1; k += BD) {
     const int t = k % N1, w = k / N1;
     double v;
@@ -101,7 +184,10 @@ __global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
     else v = tab[tab_off_D2(P) + (t + 1) * P + P - 1];              // D2[1 + t][p-1]
     RT[k] = v;
   }
-  for (int m = threadIdx.x; m < NI; m += BD) T[m] = xv[m];
+  for (int m = threadIdx.x; m < NI; m += BD) {
+    const int i = m % N1, j = (m / N1) % N1, k = m / L;
+    T[lidx<P>(i, j, k)] = xv[m];
+  }
   for (int m = threadIdx.x; m < NB; m += BD) {
     double2 v = xv[NI + m];
     if (g) {
@@ -115,11 +201,10 @@ __global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
     G[m] = v;
   }
   __syncthreads();
-  const double2* Wc = CT;
-  const double2* Vc = CT + L;
-  const double2* Ec = CT + 2 * L;
-  const double2 F0 = CT[2 * L + N1], F1 = CT[2 * L + N1 + 1];
-  const double2 F2 = CT[2 * L + N1 + 2], F3 = CT[2 * L + N1 + 3];
+  const double2* Ec = CT + S::CT0;
+  const double2* Wl = CT;           // element-parallel form: Wc, Vc in LDS
+  const double2* Vl = CT + L;
+  const double2 F0 = Ec[N1], F1 = Ec[N1 + 1], F2 = Ec[N1 + 2], F3 = Ec[N1 + 3];
   const double* Dlo = RT;
   const double* Dhi = RT + N1;
   const double* C0 = RT + 2 * N1;
@@ -140,43 +225,39 @@ __global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
   // r_i = x_i - A_ib g  (A_ib: -D2[1 + i][{0, p-1}] towards the two ends of each line)
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
-    double2 s = T[m];
+    const int li = lidx<P>(i, j, k);
+    double2 s = T[li];
     cfma_r(s, C0[i], G[0 * L + j + N1 * k]);
     cfma_r(s, C1[i], G[1 * L + j + N1 * k]);
     cfma_r(s, C0[j], G[2 * L + i + N1 * k]);
     cfma_r(s, C1[j], G[3 * L + i + N1 * k]);
     cfma_r(s, C0[k], G[4 * L + i + N1 * j]);
     cfma_r(s, C1[k], G[5 * L + i + N1 * j]);
-    T[m] = s;
+    T[li] = s;
   }
   __syncthreads();
   // u_i = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
-  cmode<P, 0>(T, X, Wc);
+  cmode<P, 0, false>(T, X, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 1>(X, T, Wc);
+  cmode<P, 1, false>(X, T, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 2>(T, X, Wc);
+  cmode<P, 2, true>(T, X, Wc, Wl, Ec, lm);
+  __syncthreads();
+  cmode<P, 0, false>(X, T, Vc, Vl, Ec, lm);
+  __syncthreads();
+  cmode<P, 1, false>(T, X, Vc, Vl, Ec, lm);
+  __syncthreads();
+  cmode<P, 2, false>(X, T, Vc, Vl, Ec, lm);
   __syncthreads();
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
-    const double a = -(Ec[i].x + Ec[j].x + Ec[k].x) - lm.x;
-    const double b = -(Ec[i].y + Ec[j].y + Ec[k].y) - lm.y;
-    const double den = 1.0 / (a * a + b * b);
-    X[m] = cmul(X[m], make_double2(a * den, -b * den));
+    yv[m] = T[lidx<P>(i, j, k)];
   }
-  __syncthreads();
-  cmode<P, 0>(X, T, Vc);
-  __syncthreads();
-  cmode<P, 1>(T, X, Vc);
-  __syncthreads();
-  cmode<P, 2>(X, T, Vc);
-  __syncthreads();
-  for (int m = threadIdx.x; m < NI; m += BD) yv[m] = T[m];
   // u_b = g - Fi Fbi1 u_line,  Fbi1 u_line = [-sum Dlo u, sum Dhi u]
   for (int ln = threadIdx.x; ln < 3 * L; ln += BD) {
     const int ax = ln / L, pos = ln - ax * L;
     int base, stride;
-    line_of<P>(ax, pos, base, stride);
+    line_of<P>(ax, pos % N1, pos / N1, base, stride);
     double2 slo = make_double2(0.0, 0.0), shi = make_double2(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
