@@ -22,21 +22,43 @@
 namespace hps {
 namespace {
 
+// Axis-pass form per order, from measurement (the apply over about 4 million
+// unknowns for every p = 4 ... 16, both forms): line-wise (a thread owns a grid
+// line and SR of its outputs, its p inputs in registers, the table rows uniform
+// across a wavefront and read through the scalar cache, x-lines padded to p + 1
+// in LDS) was 3-19 % faster at p = 8, 9, 12, 13, 14 and 16; element-parallel (a
+// thread owns one output, inputs and table entries from LDS) 1-31 % faster at
+// the other orders.
+template <int P>
+constexpr bool kSweepLineWise = (P == 8 || P == 9 || P == 12 || P == 13 || P == 14 || P == 16);
+
 template <int P>
 struct Leaf {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
-  // grid index ((k P + j) P + i) of local node m
+  static constexpr bool LW = kSweepLineWise<P>;
+  static constexpr int P1 = LW ? P + 1 : P;          // LDS length of an x-line
+  static constexpr int GS = P * P * P1;               // LDS grid size
+  static constexpr int SR = 2, SG = (P + SR - 1) / SR, SWPG = (L + 63) / 64, SW = SG * SWPG;
+  // LDS grid index of grid point (i, j, k)
+  __device__ static __forceinline__ int gidx(int i, int j, int k) { return (k * P + j) * P1 + i; }
+  // LDS grid index of local node m
   __device__ static __forceinline__ int grid_of(int m) {
     if (m < NI) {
       const int i = m % N1 + 1, j = (m / N1) % N1 + 1, k = m / L + 1;
-      return (k * P + j) * P + i;
+      return gidx(i, j, k);
     }
     const int mm = m - NI, f = mm / L, r = mm - f * L;
     const int a = r % N1 + 1, b = r / N1 + 1, e = (f & 1) ? P - 1 : 0;
     const int ax = f >> 1;
-    if (ax == 0) return (b * P + a) * P + e;
-    if (ax == 1) return (b * P + e) * P + a;
-    return (e * P + b) * P + a;
+    if (ax == 0) return gidx(e, a, b);
+    if (ax == 1) return gidx(a, e, b);
+    return gidx(a, b, e);
+  }
+  // first LDS index and stride of the grid line along ax through (a, b) (grid coordinates)
+  __device__ static __forceinline__ void line(int ax, int a, int b, int& base, int& stride) {
+    if (ax == 0) { base = gidx(0, a, b); stride = 1; }
+    else if (ax == 1) { base = gidx(a, 0, b); stride = P1; }
+    else { base = gidx(a, b, 0); stride = P * P1; }
   }
 };
 
@@ -54,34 +76,74 @@ constexpr int sweep_threads() {
 // Interior outputs accumulate in ACC; face outputs go out directly as
 // F v = N v + i eta v_b (this leaf's rows) and G v = N v - i eta v_b (the face
 // buffer read by the neighbour).
+// Output o of the line through (a, b) along AX, s = row o of R times the line:
+// a face output goes to y and to the face buffer, an interior one into ACC.
+template <int P, int AX>
+__device__ __forceinline__ void axis_out(double2 s, double2 ue, int o, int line, int a, int b,
+                                         double2* __restrict__ ACC, double eta,
+                                         double2* __restrict__ yv, double2* __restrict__ gv) {
+  using Lf = Leaf<P>;
+  constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI;
+  if (o == 0 || o == P - 1) {
+    const int f = 2 * AX + (o ? 1 : 0);
+    yv[NI + f * L + line] = make_double2(s.x - eta * ue.y, s.y + eta * ue.x);
+    gv[f * L + line] = make_double2(s.x + eta * ue.y, s.y - eta * ue.x);
+  } else {
+    int m;
+    if (AX == 0) m = (o - 1) + N1 * (a - 1) + L * (b - 1);
+    else if (AX == 1) m = (a - 1) + N1 * (o - 1) + L * (b - 1);
+    else m = (a - 1) + N1 * (b - 1) + L * (o - 1);
+    if (AX == 0) ACC[m] = s;
+    else ACC[m] = make_double2(ACC[m].x + s.x, ACC[m].y + s.y);
+  }
+}
+
 template <int P, int AX>
 __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2* __restrict__ ACC,
-                                          const double* __restrict__ R, double eta,
-                                          double2* __restrict__ yv, double2* __restrict__ gv) {
+                                          const double* __restrict__ R, const double* __restrict__ tab,
+                                          double eta, double2* __restrict__ yv, double2* __restrict__ gv) {
   using Lf = Leaf<P>;
-  constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI, BD = sweep_threads<P>();
-  for (int w = threadIdx.x; w < L * P; w += BD) {
-    const int line = w / P, o = w - line * P;
-    const int a = line % N1 + 1, b = line / N1 + 1;  // the two other grid coordinates
-    int base, stride;
-    if (AX == 0) { base = (b * P + a) * P; stride = 1; }
-    else if (AX == 1) { base = b * P * P + a; stride = P; }
-    else { base = b * P + a; stride = P * P; }
-    double2 s = make_double2(0.0, 0.0);
+  constexpr int N1 = Lf::N1, L = Lf::L, BD = sweep_threads<P>();
+  if constexpr (Lf::LW) {
+    // line-wise: rows of R (o = 0: -D[0][.], o = p-1: D[p-1][.], else -D2[o][.])
+    // straight from the table, at wavefront-uniform addresses
+    const double* D = tab + tab_off_D(P);
+    const double* D2 = tab + tab_off_D2(P);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int w = wave; w < Lf::SW; w += BD / 64) {
+      const int og = w / Lf::SWPG;
+      const int line = (w - og * Lf::SWPG) * 64 + lane;
+      if (line >= L) continue;
+      const int a = line % N1 + 1, b = line / N1 + 1;
+      int base, stride;
+      Lf::line(AX, a, b, base, stride);
+      double2 v[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) cfma_r(s, R[o * P + q], U[base + q * stride]);
-    if (o == 0 || o == P - 1) {
-      const double2 ue = U[base + o * stride];
-      const int f = 2 * AX + (o ? 1 : 0);
-      yv[NI + f * L + line] = make_double2(s.x - eta * ue.y, s.y + eta * ue.x);
-      gv[f * L + line] = make_double2(s.x + eta * ue.y, s.y - eta * ue.x);
-    } else {
-      int m;
-      if (AX == 0) m = (o - 1) + N1 * (a - 1) + L * (b - 1);
-      else if (AX == 1) m = (a - 1) + N1 * (o - 1) + L * (b - 1);
-      else m = (a - 1) + N1 * (b - 1) + L * (o - 1);
-      if (AX == 0) ACC[m] = s;
-      else ACC[m] = make_double2(ACC[m].x + s.x, ACC[m].y + s.y);
+      for (int q = 0; q < P; ++q) v[q] = U[base + q * stride];
+#pragma unroll
+      for (int r = 0; r < Lf::SR; ++r) {
+        const int o = og * Lf::SR + r;
+        if (o >= P) break;
+        const double* row = (o == 0) ? D : (o == P - 1 ? D + (P - 1) * P : D2 + o * P);
+        const double sg = (o == P - 1) ? 1.0 : -1.0;
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < P; ++q) cfma_r(s, sg * row[q], v[q]);
+        axis_out<P, AX>(s, o == 0 ? v[0] : v[P - 1], o, line, a, b, ACC, eta, yv, gv);
+      }
+    }
+  } else {
+    for (int w = threadIdx.x; w < L * P; w += BD) {
+      const int line = w / P, o = w - line * P;
+      const int a = line % N1 + 1, b = line / N1 + 1;  // the two other grid coordinates
+      int base, stride;
+      Lf::line(AX, a, b, base, stride);
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < P; ++q) cfma_r(s, R[o * P + q], U[base + q * stride]);
+      const double2 ue = (o == 0 || o == P - 1) ? U[base + o * stride] : make_double2(0.0, 0.0);
+      axis_out<P, AX>(s, ue, o, line, a, b, ACC, eta, yv, gv);
     }
   }
 }
@@ -94,7 +156,7 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
   using Lf = Leaf<P>;
   constexpr int NI = Lf::NI, NN = Lf::NN, NB = Lf::NB;
   constexpr int BD = sweep_threads<P>();
-  __shared__ double2 U[P * P * P];
+  __shared__ double2 U[Lf::GS];
   __shared__ double2 ACC[NI];
   __shared__ double R[P * P];
   const int64_t tau = blockIdx.x;
@@ -126,11 +188,11 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
   if (NLOAD > 2 && m2 < NN) U[Lf::grid_of(m2)] = t2;
   if (NLOAD > 3 && m3 < NN) U[Lf::grid_of(m3)] = t3;
   __syncthreads();
-  axis_pass<P, 0>(U, ACC, R, eta, yv, gv);
+  axis_pass<P, 0>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
-  axis_pass<P, 1>(U, ACC, R, eta, yv, gv);
+  axis_pass<P, 1>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
-  axis_pass<P, 2>(U, ACC, R, eta, yv, gv);
+  axis_pass<P, 2>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
   // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat))
   for (int m = threadIdx.x; m < NI; m += BD) {
