@@ -95,6 +95,16 @@ typedef struct {
  * HPS_PREC_SEPARABLE names it explicitly.  hps_autotune does not apply. */
 #define HPS_PREC_SEPARABLE 8
 
+/* The table the separable form is applied with, for a leaf of side h at order
+ * p and impedance parameter eta (host only: no device call; for inspection
+ * and tests).  out: host, 2 (2 n1^2 + n1 + 4) doubles, n1 = p - 2, complex
+ * entries with real and imaginary parts interleaved: Wc = Vc^{-1} (n1 x n1,
+ * row major), Vc (the eigenvectors of the line operator Lt as columns, row
+ * major), Ec (its n1 eigenvalues), Fi (the inverse 2 x 2 face system of a line,
+ * row major: rows lo, hi).  HPS_ERR_NUMERIC if the eigendecomposition fails its
+ * reconstruction check. */
+int hps_separable_table(int p, double h, double eta, double* out);
+
 typedef struct {
   int block_precs;     /* OR of HPS_PREC_* (see HPS_PREC_SEPARABLE); 0 means HPS_PREC_FP64 */
   void* stream;        /* hipStream_t; 0 = default stream */

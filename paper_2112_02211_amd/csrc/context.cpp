@@ -584,6 +584,22 @@ int64_t hps_num_unknowns(const hps_ctx* c) { return c ? c->N : -1; }
 
 int64_t hps_num_blocks(const hps_ctx* c) { return c ? c->nblocks : -1; }
 
+int hps_separable_table(int p, double h, double eta, double* out) {
+  g_err.clear();
+  if (!out) return fail(HPS_ERR_ARG, "out is NULL");
+  if (p < kMinP || p > kMaxP) return fail(HPS_ERR_UNSUPPORTED, "p must lie in [4, 16]");
+  if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(eta) || eta == 0.0)
+    return fail(HPS_ERR_ARG, "h must be positive and eta finite and nonzero");
+  HostTables t;
+  std::string err = build_tables(p, h, &t);
+  if (err.empty()) {
+    std::vector<double> tab;
+    err = build_sep_table(t, eta, &tab);
+    if (err.empty()) std::copy(tab.begin(), tab.end(), out);
+  }
+  return err.empty() ? HPS_OK : fail(HPS_ERR_NUMERIC, err);
+}
+
 int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex_medium,
                         int64_t* transient) {
   if (p < kMinP || p > kMaxP || !n_elem) return fail(HPS_ERR_ARG, "bad sizes");

@@ -110,6 +110,8 @@ SIGNATURES = {
                                  ctypes.POINTER(_SolveOpts), ctypes.POINTER(Stats)]),
     "hps_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
     "hps_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hps_separable_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_double)]),
     "hps_arnoldi_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     "hps_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     "hps_setup_bytes": (ctypes.c_int64, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -471,6 +473,18 @@ def iti_bytes(n_elem, p) -> int:
     if v < 0:
         raise HPSError(v, lib().hps_last_error().decode())
     return v
+
+
+def separable_table(p: int, h: float, eta: float):
+    """(Wc, Vc, Ec, Fi) of the separable J^-1 for a leaf of side h (host only)."""
+    n1 = int(p) - 2
+    out = np.zeros(2 * (2 * n1 * n1 + n1 + 4))
+    _check(lib().hps_separable_table(int(p), float(h), float(eta),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    z = out[0::2] + 1j * out[1::2]
+    L = n1 * n1
+    return (z[:L].reshape(n1, n1), z[L:2 * L].reshape(n1, n1), z[2 * L:2 * L + n1],
+            z[2 * L + n1:].reshape(2, 2))
 
 
 def setup_bytes(n_elem, p, block_precs=("fp64",), complex_medium=False):
