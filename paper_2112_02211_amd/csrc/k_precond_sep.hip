@@ -39,18 +39,26 @@ namespace {
 // output; inputs and matrix entries from LDS) 5-30 % faster at p = 4-7 and 9
 // and equal at 12.
 template <int P> constexpr bool kLineWise = (P == 8 || P == 10 || P == 11 || P >= 13);
+// p >= 13: line-wise in place (a thread owns a whole line and all its outputs,
+// written back over its inputs), so no second LDS tensor is needed and two
+// workgroups fit on a CU (measured: 28 % faster at p = 16 on 32^3 leaves, 8 %
+// at p = 15, 2-3 % at p = 13, 14; 4-8 % slower at p = 12)
+template <int P> constexpr bool kInPlace = (P >= 13);
 
 template <int P>
 struct SL {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
+  static constexpr bool LW = kLineWise<P>, IP = kInPlace<P>;
   static constexpr int BD0 = (NI + 63) / 64 * 64;
-  static constexpr int BD = BD0 < 64 ? 64 : (BD0 > 1024 ? 1024 : BD0);
+  // in place: 512 threads and at most 128 VGPRs (four waves per SIMD), so that
+  // two workgroups share a CU
+  static constexpr int BD = IP ? 512 : (BD0 < 64 ? 64 : (BD0 > 1024 ? 1024 : BD0));
+  static constexpr int MINW = IP ? 4 : 1;
   static constexpr int ST = sep_table_size(P);
-  static constexpr bool LW = kLineWise<P>;
   // line-wise: the LDS tensors pad each x-line to n1 + 1 entries, so the
   // threads of a wavefront that walk neighbouring x-lines read 16-byte words in
   // different banks
-  static constexpr int P1 = LW ? N1 + 1 : N1, SZ = P1 * L;
+  static constexpr int P1 = LW ? N1 + 1 : N1, SZ = P1 * L, SZX = IP ? 1 : SZ;
   // line-wise work items: (output group of R, 64 lines) per wavefront
   static constexpr int R = 2, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
   // tables staged in LDS: Ec | Fi, and for the element-parallel form Wc | Vc before them
@@ -142,11 +150,44 @@ __device__ __forceinline__ void cmode_el(const double2* __restrict__ in, double2
   }
 }
 
+// In-place line-wise form: one thread per line computes all n1 outputs of
+// its line from the inputs in its registers and writes them over them (lines
+// along one axis are disjoint, so no other thread reads them in this product).
 template <int P, int AX, bool SCALE>
-__device__ __forceinline__ void cmode(const double2* __restrict__ in, double2* __restrict__ out,
-                                      const double2* __restrict__ Mg, const double2* __restrict__ Ml,
-                                      const double2* __restrict__ Ec, double2 lm) {
-  if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE>(in, out, Mg, Ec, lm);
+__device__ __forceinline__ void cmode_ip(double2* __restrict__ T, const double2* __restrict__ M,
+                                         const double2* __restrict__ Ec, double2 lm) {
+  using S = SL<P>;
+  constexpr int N1 = S::N1, L = S::L, BD = S::BD;
+  for (int line = threadIdx.x; line < L; line += BD) {
+    const int a = line % N1, b = line / N1;
+    int base, stride;
+    line_of<P>(AX, a, b, base, stride);
+    double2 v[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) v[i] = T[base + i * stride];
+#pragma unroll
+    for (int o = 0; o < N1; ++o) {
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < N1; ++i) cfma(s, M[o * N1 + i], v[i]);
+      if (SCALE) {
+        const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
+        const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
+        const double den = 1.0 / (ar * ar + ai * ai);
+        s = cmul(s, make_double2(ar * den, -ai * den));
+      }
+      T[base + o * stride] = s;
+    }
+  }
+}
+
+// One mode product in the order's form; in place, out is in (the result is in T).
+template <int P, int AX, bool SCALE>
+__device__ __forceinline__ void cmode(const double2* in, double2* out, const double2* __restrict__ Mg,
+                                      const double2* __restrict__ Ml, const double2* __restrict__ Ec,
+                                      double2 lm) {
+  if constexpr (SL<P>::IP) cmode_ip<P, AX, SCALE>(const_cast<double2*>(in), Mg, Ec, lm);
+  else if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE>(in, out, Mg, Ec, lm);
   else cmode_el<P, AX, SCALE>(in, out, Ml, Ec, lm);
 }
 
@@ -155,14 +196,14 @@ __device__ __forceinline__ void cmode(const double2* __restrict__ in, double2* _
 // dense-block kernel.  Operator groups: right-hand side rhs belongs to
 // operator rhs (os = nl: lambda of [rhs][leaf], table of operator rhs).
 template <int P>
-__global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
+__global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
     const double2* __restrict__ x, const double2* __restrict__ g, const int* __restrict__ nbr,
     double2* __restrict__ y, const double2* __restrict__ lam, const double2* __restrict__ sep,
     const double* __restrict__ tab, int64_t nl, int64_t N, int64_t os) {
   using S = SL<P>;
   constexpr int N1 = S::N1, L = S::L, NI = S::NI, NB = S::NB, NN = S::NN, BD = S::BD;
   __shared__ double2 T[S::SZ];
-  __shared__ double2 X[S::SZ];
+  __shared__ double2 X[S::SZX];
   __shared__ double2 G[NB];
   __shared__ double2 CT[S::CTN];    // (Wc | Vc |) Ec | Fi
   __shared__ double RT[4 * N1];     // Dlo | Dhi | C0 | C1
@@ -237,17 +278,19 @@ __global__ __launch_bounds__(SL<P>::BD) void k_precond_sep(
   }
   __syncthreads();
   // u_i = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
-  cmode<P, 0, false>(T, X, Wc, Wl, Ec, lm);
+  // (ping-pong T -> X -> T ..., ending in T; in place: all in T)
+  double2* const X1 = S::IP ? T : X;
+  cmode<P, 0, false>(T, X1, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 1, false>(X, T, Wc, Wl, Ec, lm);
+  cmode<P, 1, false>(X1, T, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 2, true>(T, X, Wc, Wl, Ec, lm);
+  cmode<P, 2, true>(T, X1, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 0, false>(X, T, Vc, Vl, Ec, lm);
+  cmode<P, 0, false>(X1, T, Vc, Vl, Ec, lm);
   __syncthreads();
-  cmode<P, 1, false>(T, X, Vc, Vl, Ec, lm);
+  cmode<P, 1, false>(T, X1, Vc, Vl, Ec, lm);
   __syncthreads();
-  cmode<P, 2, false>(X, T, Vc, Vl, Ec, lm);
+  cmode<P, 2, false>(X1, T, Vc, Vl, Ec, lm);
   __syncthreads();
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
