@@ -92,7 +92,10 @@ typedef struct {
  * combined with HPS_PREC_FP32 / HPS_PREC_BF16, and requires lambda_bucket = 0.
  * Every call that takes an FP64 J^-1 (hps_precond, hps_op_left, hps_gmres with
  * precond_prec 0 or HPS_PREC_FP64) then uses it; as a prec argument
- * HPS_PREC_SEPARABLE names it explicitly.  hps_autotune does not apply. */
+ * HPS_PREC_SEPARABLE names it explicitly.  hps_autotune does not apply.  One
+ * launch covers up to 65535 right-hand sides (more: HPS_ERR_ARG); the result
+ * equals the dense-block J^-1 up to rounding (both are exact inverses of the
+ * same leaf matrix). */
 #define HPS_PREC_SEPARABLE 8
 
 /* The table the separable form is applied with, for a leaf of side h at order
