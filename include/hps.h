@@ -120,7 +120,7 @@ typedef struct {
                           the exact inverse of the homogenized leaf matrix at the rounded lambda,
                           applied by GEMMs over runs of up to 16 leaves sharing a block, for
                           any number of right-hand sides up to 65535 (more: the J^-1 calls
-                          return HPS_ERR_HIP).  See hps_num_blocks. */
+                          return HPS_ERR_DEVICE).  See hps_num_blocks. */
 } hps_opts;
 
 /* Solvers for hps_gmres. */
