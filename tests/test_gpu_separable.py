@@ -201,3 +201,22 @@ def test_separable_option_errors(hps_mod):
     dense = hps_mod.Context.from_problem(prob)
     with pytest.raises(hps_mod.HPSError):       # separable form not built
         dense.gmres(dev(s), dev(t), precond_prec="separable")
+
+
+def test_separable_many_right_hand_sides_and_the_limit(hps_mod):
+    # one launch covers up to 65535 right-hand sides (grid y); one leaf at p = 4
+    # keeps 65536 of them at 33 MB
+    prob = P.bump_problem("lim", (1, 1, 1), 4, 3.0, 2, 1, 13, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    op = O.build(prob, with_matrix=False)
+    k = 65535
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((k, ctx.N)) + 1j * rng.standard_normal((k, ctx.N))
+    Z = host(ctx.precond(dev(X.reshape(-1)))).reshape(k, -1)
+    M = O.Precond(op.d, op.b_nodes)
+    for r in (0, 1, k // 2, k - 1):
+        za = M.apply(X[r])
+        assert rel(Z[r], za) < 1e-12, r
+    X1 = np.concatenate([X.reshape(-1), X[0]])
+    with pytest.raises(hps_mod.HPSError):
+        ctx.precond(dev(X1))
