@@ -15,6 +15,8 @@ constexpr int DW = 8;          // wavefronts of the reduction workgroup (split o
 constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
 constexpr int UT = 256;        // update-pass (and small-step) workgroup
 constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
+constexpr int kShortBasis = 8;           // reductions over at most this many basis vectors ...
+constexpr int64_t kLongVector = 1 << 24; // ... of at least this many entries split tiles over wavefronts
 
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
@@ -83,6 +85,91 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const double2* __restrict__ 
     if (lane == 0) {
       pz[(int64_t)kSlotC * nblk + blockIdx.x] = make_double2(cs, 0.0);
       pz[(int64_t)kSlotD * nblk + blockIdx.x] = make_double2(dr, di);
+    }
+  }
+}
+
+// The same partials with the tiles split over the wavefronts instead of the
+// basis vectors (for short bases on long vectors): wavefront ky of workgroup g
+// takes tiles g * DW + ky, g * DW + ky + DW * nblk, ...; each reads the J <= JM
+// basis entries, u and w of its tile once (the split over basis vectors has
+// every wavefront read u and w, and leaves wavefronts idle when J < DW).  The
+// DW wavefront sums are added in a fixed order through LDS.
+template <int JM, bool HASW>
+__global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const double2* __restrict__ V, int64_t ldv,
+                                                       int64_t vbs, int J, const double2* __restrict__ u,
+                                                       int64_t ubs, const double2* __restrict__ w,
+                                                       int64_t wbs, int64_t n,
+                                                       double2* __restrict__ part) {
+  const int bz = blockIdx.z;
+  V += bz * vbs;
+  u += bz * ubs;
+  if (HASW) w += bz * wbs;
+  const int lane = threadIdx.x & 63, ky = threadIdx.x >> 6;
+  double2 aa[JM], ab[JM];
+#pragma unroll
+  for (int k = 0; k < JM; ++k) { aa[k] = make_double2(0.0, 0.0); ab[k] = make_double2(0.0, 0.0); }
+  double cc = 0.0;
+  double2 dd = make_double2(0.0, 0.0);
+  const unsigned nblk = gridDim.x;
+  for (int64_t t0 = ((int64_t)blockIdx.x * DW + ky) * 64; t0 < n; t0 += (int64_t)nblk * DW * 64) {
+    const int64_t i = t0 + lane;
+    const bool ok = i < n;
+    const double2 uv = ok ? u[i] : make_double2(0.0, 0.0);
+    const double2 wv = (HASW && ok) ? w[i] : make_double2(0.0, 0.0);
+    double2 vr[JM];
+#pragma unroll
+    for (int k = 0; k < JM; ++k)
+      vr[k] = (k < J && ok) ? V[(int64_t)k * ldv + i] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < JM; ++k) {
+      aa[k].x = fma(vr[k].x, uv.x, fma(vr[k].y, uv.y, aa[k].x));
+      aa[k].y = fma(vr[k].x, uv.y, fma(-vr[k].y, uv.x, aa[k].y));
+      if (HASW) {
+        ab[k].x = fma(vr[k].x, wv.x, fma(vr[k].y, wv.y, ab[k].x));
+        ab[k].y = fma(vr[k].x, wv.y, fma(-vr[k].y, wv.x, ab[k].y));
+      }
+    }
+    cc = fma(uv.x, uv.x, fma(uv.y, uv.y, cc));
+    if (HASW) {
+      dd.x = fma(uv.x, wv.x, fma(uv.y, wv.y, dd.x));
+      dd.y = fma(uv.x, wv.y, fma(-uv.y, wv.x, dd.y));
+    }
+  }
+  // wavefront sums: slots 0..J-1 (a), JM..JM+J-1 (b), 2 JM (c), 2 JM + 1 (d)
+  constexpr int NS = 2 * JM + 2;
+  __shared__ double2 red[DW][NS];
+#pragma unroll
+  for (int k = 0; k < JM; ++k) {
+    if (k < J) {
+      const double ar = wave_sum(aa[k].x), ai = wave_sum(aa[k].y);
+      if (lane == 0) red[ky][k] = make_double2(ar, ai);
+      if (HASW) {
+        const double br = wave_sum(ab[k].x), bi = wave_sum(ab[k].y);
+        if (lane == 0) red[ky][JM + k] = make_double2(br, bi);
+      }
+    }
+  }
+  {
+    const double cs = wave_sum(cc);
+    const double dr = wave_sum(dd.x), di = wave_sum(dd.y);
+    if (lane == 0) {
+      red[ky][2 * JM] = make_double2(cs, 0.0);
+      red[ky][2 * JM + 1] = make_double2(dr, di);
+    }
+  }
+  __syncthreads();
+  double2* pz = part + (int64_t)bz * kPartSlots * nblk;
+  const int t = threadIdx.x;
+  if (t < NS) {
+    const bool isa = t < J, isb = HASW && t >= JM && t < JM + J, isc = t == 2 * JM,
+               isd = t == 2 * JM + 1;   // d = 0 without w, as the other form writes it
+    if (isa || isb || isc || isd) {
+      double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < DW; ++q) v = cadd(v, red[q][t]);
+      const int slot = isa ? t : (isb ? kSlotB + (t - JM) : (isc ? kSlotC : kSlotD));
+      pz[(int64_t)slot * nblk + blockIdx.x] = v;
     }
   }
 }
@@ -445,7 +532,17 @@ int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, i
       hipLaunchKernelGGL((k_dcgs_reduce<KC, false>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, \
                          u, ubs, w, wbs, n, rb.part);                                           \
   } while (0)
-  if (kc <= 2) HPS_DR(2); else if (kc <= 4) HPS_DR(4); else HPS_DR(8);
+  // short bases on long vectors: tiles split over the wavefronts (measured:
+  // the split over basis vectors reached about 2.5 TB/s for J <= 8 on 1e9-entry
+  // vectors, where half the wavefronts idle and all re-read u and w)
+  if (J <= kShortBasis && n >= kLongVector) {
+    if (hw)
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true>), grid, dim3(DT), 0, c->stream, V, ldv,
+                         vbs, J, u, ubs, w, wbs, n, rb.part);
+    else
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false>), grid, dim3(DT), 0, c->stream, V, ldv,
+                         vbs, J, u, ubs, w, wbs, n, rb.part);
+  } else if (kc <= 2) HPS_DR(2); else if (kc <= 4) HPS_DR(4); else HPS_DR(8);
 #undef HPS_DR
   int rc = check_hip(hipGetLastError(), "k_dcgs_reduce");
   if (rc) return rc;

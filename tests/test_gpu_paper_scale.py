@@ -101,3 +101,32 @@ def test_paper_scale_separable_precond_sampled_leaves(big):
             assert np.linalg.norm(got - w) / np.linalg.norm(w) < 1e-12, tau
     finally:
         sctx.free()
+
+
+def test_paper_scale_short_basis_arnoldi(big):
+    # GMRES(8) on 2 GB vectors: every reduction of the delayed-reorthogonalization
+    # Arnoldi covers at most 8 basis vectors of at least 2^24 entries, the case
+    # whose tiles are split over wavefronts.  After the same 8 and 16 steps the
+    # GMRES iterate is the same vector whatever the orthogonalization, so it is
+    # compared with classical Gram-Schmidt twice (other kernels throughout).
+    from paper_2112_02211_amd import hps
+    prob, _, d, leaves, xyz, b_nodes, x = big
+    sctx = hps.Context.from_problem(prob, block_precs=("separable",), lambda_bucket=0.0)
+    try:
+        s = torch.from_numpy(P.gaussian_source(prob, xyz)).cuda()
+        prev = None
+        for steps in (8, 16):
+            out = {}
+            for orth in ("dcgs", "cgs2"):
+                u, st, ok = sctx.gmres(s, None, tol=1e-12, restart=8, max_iters=steps, orth=orth)
+                assert st["iters"] == steps
+                out[orth] = (u, st["true_rel_res"])
+            ud, uc = out["dcgs"][0], out["cgs2"][0]
+            assert float(torch.linalg.norm(ud - uc) / torch.linalg.norm(uc)) < 1e-9
+            assert abs(out["dcgs"][1] - out["cgs2"][1]) < 1e-8 * out["cgs2"][1]
+            del ud, uc, out
+            res = sctx.gmres(s, None, tol=1e-12, restart=8, max_iters=steps)[1]["true_rel_res"]
+            assert res < 0.5 and (prev is None or res < 0.8 * prev)
+            prev = res
+    finally:
+        sctx.free()
