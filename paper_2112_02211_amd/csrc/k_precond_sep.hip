@@ -165,18 +165,29 @@ __device__ __forceinline__ void cmode_ip(double2* __restrict__ T, const double2*
     double2 v[N1];
 #pragma unroll
     for (int i = 0; i < N1; ++i) v[i] = T[base + i * stride];
+    // two outputs at a time (four independent accumulation chains); each
+    // output's terms are still added in the order i = 0 .. n1-1
 #pragma unroll
-    for (int o = 0; o < N1; ++o) {
-      double2 s = make_double2(0.0, 0.0);
+    for (int o0 = 0; o0 < N1; o0 += 2) {
+      double2 s[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
 #pragma unroll
-      for (int i = 0; i < N1; ++i) cfma(s, M[o * N1 + i], v[i]);
-      if (SCALE) {
-        const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
-        const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
-        const double den = 1.0 / (ar * ar + ai * ai);
-        s = cmul(s, make_double2(ar * den, -ai * den));
+      for (int i = 0; i < N1; ++i) {
+        cfma(s[0], M[o0 * N1 + i], v[i]);
+        if (o0 + 1 < N1) cfma(s[1], M[(o0 + 1) * N1 + i], v[i]);
       }
-      T[base + o * stride] = s;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int o = o0 + h;
+        if (o >= N1) break;
+        double2 r = s[h];
+        if (SCALE) {
+          const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
+          const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
+          const double den = 1.0 / (ar * ar + ai * ai);
+          r = cmul(r, make_double2(ar * den, -ai * den));
+        }
+        T[base + o * stride] = r;
+      }
     }
   }
 }
