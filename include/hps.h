@@ -136,6 +136,16 @@ typedef struct {
                                 rejected.  Stopping test on ||t - Pi h - (I + Pi R) f|| relative to
                                 ||t - Pi h||; iterations and residuals refer to the face system. */
 
+#define HPS_SOLVER_BGMRES 4  /* block GMRES(m): all right-hand sides (up to 64) in one block Krylov
+                                space, left preconditioned with the FP64 J^-1 (blocks or separable);
+                                block Arnoldi by classical Gram-Schmidt twice, CholQR2 (on column-
+                                equilibrated Gram matrices) for each new block, the block least-
+                                squares problem by Householder reflections on the host.  Each
+                                right-hand side is checked on its own PCRR; the block iterates
+                                until all pass; "iters" counts block steps.  HPS_ERR_BREAKDOWN if a
+                                block's columns become linearly dependent (identical right-hand
+                                sides, say): the lock-step solver has no such limit. */
+
 typedef struct {
   int solver;          /* HPS_SOLVER_* (default GMRES) */
   int max_iters;       /* total Arnoldi steps; 0 = 20000 */

@@ -538,6 +538,16 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
   }
   const bool fp64_pc = o.precond_prec == 0 || o.precond_prec == HPS_PREC_FP64 ||
                        o.precond_prec == HPS_PREC_SEPARABLE;
+  if (o.solver == HPS_SOLVER_BGMRES) {
+    // basis ((m+1) k vectors), W, TMP, J^-1 B, small matrices, the face buffer
+    // and (dense blocks, k >= 4) the GEMM panels of J^-1, the assembled b
+    const int64_t k = std::min(nrhs, kMaxBatch);
+    int64_t bytes = 16 * c->N * k * (restart + 4) + 16 * (int64_t)(restart + 1) * k * k + 1024;
+    bytes += 16 * k * c->nl * c->nb;
+    if (!c->sep && k >= kBatchedMinRhs) bytes += k * c->nl * c->nb * 32 + 256;
+    bytes += 16 * c->N * nrhs;
+    return bytes;
+  }
   const bool flexible = o.solver == HPS_SOLVER_FGMRES || !fp64_pc;
   const int64_t nbat = (o.solver == HPS_SOLVER_BLOCK || c->nop > 1) ? std::min(nrhs, kMaxBatch) : 1;
   const int64_t vec = 16 * c->N * nbat;
@@ -569,7 +579,12 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     return fail(HPS_ERR_ARG, "unknown precond_prec");
   if (!c->blk[prec].data && !(prec == kFP64 && c->sep))
     return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
-  if (o.solver < 0 || o.solver > 3) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver < 0 || o.solver > 4) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver == HPS_SOLVER_BGMRES) {
+    if (prec != kFP64) return fail(HPS_ERR_ARG, "block GMRES runs the FP64 preconditioner");
+    if (c->nop > 1) return fail(HPS_ERR_UNSUPPORTED, "block GMRES: operator groups run lock-step");
+    if (nrhs > kMaxBatch) return fail(HPS_ERR_ARG, "block GMRES: at most 64 right-hand sides");
+  }
   if (c->nop > 1 && nrhs != c->nop)
     return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator (nrhs = number of operators)");
   if (o.solver == HPS_SOLVER_ITI) {
@@ -623,6 +638,16 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     acc.converged = rc == HPS_OK;
     acc.lambda_shifted = c->n_shifted;
     if (st) *st = acc;
+  } else if (rc == HPS_OK && o.solver == HPS_SOLVER_BGMRES) {
+    rc = run_block_gmres(c, prec, bvec, x, nrhs, tol, restart, maxit, o.use_x0 != 0, o.rhs_rel_res, st);
+    if (st) {
+      Job job;
+      job.flexible = false;
+      job.prec = prec;
+      job.n = c->N;
+      job.nrhs = nrhs;
+      solve_bytes_stats(c, job, nrhs, st);
+    }
   } else if (rc == HPS_OK) {
     Job job;
     job.flexible = (o.solver == HPS_SOLVER_FGMRES) || prec != kFP64;

@@ -218,6 +218,9 @@ int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs,
 // J^{-1} (y + exchange(g)) for nrhs < kBatchedMinRhs; g == null: J^{-1} y
 int launch_precond_fused(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
                          int prec, hipEvent_t e0, hipEvent_t e1);
+// block GMRES(m) on k right-hand sides, left preconditioned with the FP64 J^-1 (block_gmres.cpp)
+int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, double tol, int m,
+                    int maxit, bool use_x0, double* rhs_res, hps_stats* st);
 // J^{-1} (y + exchange(g)) in the separable form (no blocks; any nrhs); g == null: J^{-1} y
 int launch_precond_sep(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
                        hipEvent_t e0, hipEvent_t e1);

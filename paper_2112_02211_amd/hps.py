@@ -22,7 +22,7 @@ HPS_ERR_ARG, HPS_ERR_UNSUPPORTED, HPS_ERR_OOM = -1, -2, -3
 HPS_ERR_DEVICE, HPS_ERR_BREAKDOWN, HPS_ERR_NUMERIC = -4, -5, -6
 ERRORS = {-1: "ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BREAKDOWN", -6: "NUMERIC"}
 PREC = {"fp64": 1, "fp32": 2, "bf16": 4, "separable": 8}
-SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2, "iti": 3}
+SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2, "iti": 3, "block_gmres": 4}
 ORTH = {"dcgs": 0, "cgs2": 1}
 MEDIUM_ZERO, MEDIUM_NODAL, MEDIUM_BUMPS = 0, 1, 2
 
