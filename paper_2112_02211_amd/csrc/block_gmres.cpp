@@ -48,10 +48,49 @@ int zgemm(rocblas_handle h, bool ca, int m, int n, int64_t kk, cd alpha, const d
                  "rocblas_zgemm");
 }
 
+// Split-K scratch: partial products of C = A^H B over chunks of the long
+// dimension (the product's m x n tiles are too few to fill the GPU), summed by
+// a matrix-vector product with a vector of ones.
+struct SplitK {
+  static constexpr int kChunks = 256;
+  double2* part = nullptr;   // kChunks + 1 partial m x n products
+  double2* ones = nullptr;   // kChunks + 1 ones
+  int64_t cap = 0;           // entries of one partial
+};
+
+// C (m x n) = A^H B with A (K x m, lda), B (K x n, ldb), K long.
+int zgemm_ct(rocblas_handle h, int m, int n, int64_t K, const double2* A, int64_t lda, const double2* B,
+             int64_t ldb, double2* C, const SplitK& sk) {
+  const int64_t L = (K + SplitK::kChunks - 1) / SplitK::kChunks;
+  const int full = (int)(K / L);
+  const int64_t rest = K - (int64_t)full * L;
+  if ((int64_t)m * n > sk.cap || L < 4096) return zgemm(h, true, m, n, K, 1.0, A, lda, B, ldb, 0.0, C, m);
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  if (rocblas_zgemm_strided_batched(
+          h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, (rocblas_int)L, &one,
+          reinterpret_cast<const rocblas_double_complex*>(A), (rocblas_int)lda, L,
+          reinterpret_cast<const rocblas_double_complex*>(B), (rocblas_int)ldb, L, &zero,
+          reinterpret_cast<rocblas_double_complex*>(sk.part), m, (rocblas_stride)m * n, full) !=
+      rocblas_status_success)
+    return fail(HPS_ERR_DEVICE, "rocblas_zgemm_strided_batched failed");
+  int nparts = full;
+  if (rest > 0) {
+    int rc = zgemm(h, true, m, n, rest, 1.0, A + (int64_t)full * L, lda, B + (int64_t)full * L, ldb, 0.0,
+                   sk.part + (int64_t)full * m * n, m);
+    if (rc) return rc;
+    ++nparts;
+  }
+  return blas_ok(rocblas_zgemv(h, rocblas_operation_none, m * n, nparts, &one,
+                               reinterpret_cast<const rocblas_double_complex*>(sk.part), m * n,
+                               reinterpret_cast<const rocblas_double_complex*>(sk.ones), 1, &zero,
+                               reinterpret_cast<rocblas_double_complex*>(C), 1),
+                 "rocblas_zgemv");
+}
+
 // Gram matrix G = X^H X (k x k) of the k columns of X (N x k), on the host.
 int gram(hps_ctx* c, rocblas_handle h, const double2* X, int64_t N, int k, double2* dG,
-         std::vector<cd>& G) {
-  int rc = zgemm(h, true, k, k, N, 1.0, X, N, X, N, 0.0, dG, k);
+         std::vector<cd>& G, const SplitK& sk) {
+  int rc = zgemm_ct(h, k, k, N, X, N, X, N, dG, sk);
   if (rc) return rc;
   G.resize((size_t)k * k);
   HPS_TRY_HIP(hipMemcpyAsync(G.data(), dG, sizeof(double2) * k * k, hipMemcpyDeviceToHost, c->stream));
@@ -109,12 +148,12 @@ std::vector<cd> tri_mul(const std::vector<cd>& A, const std::vector<cd>& B, int 
 // second N x k buffer.  HPS_ERR_BREAKDOWN when the columns are (numerically)
 // dependent.
 int cholqr2(hps_ctx* c, rocblas_handle h, const double2* X, double2* tmp, double2* dst, int64_t N,
-            int k, double2* dG, std::vector<cd>& R) {
+            int k, double2* dG, std::vector<cd>& R, const SplitK& sk) {
   std::vector<cd> G, R1, R2;
   const double2* src = X;
   double2* outs[2] = {tmp, dst};
   for (int pass = 0; pass < 2; ++pass) {
-    int rc = gram(c, h, src, N, k, dG, G);
+    int rc = gram(c, h, src, N, k, dG, G, sk);
     if (rc) return rc;
     std::vector<cd>& Rp = pass ? R2 : R1;
     // Cholesky of the column-equilibrated Gram matrix D^-1 G D^-1 (D = its
@@ -171,8 +210,10 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
   const int64_t nk = N * k;
   const int K = (m + 1) * k;   // rows of the block Hessenberg matrix
   // workspace: basis V ((m+1) k columns), W, TMP, PB = J^-1 B, small matrices
+  const int64_t pcap = (int64_t)m * k * k;   // largest partial: (m k) x k
   const size_t bytes = sizeof(double2) * ((size_t)nk * (m + 1) + 3 * (size_t)nk) +
-                       sizeof(double2) * ((size_t)K * k + 64);
+                       sizeof(double2) * ((size_t)K * k + 64) +
+                       sizeof(double2) * ((size_t)(SplitK::kChunks + 1) * (pcap + 1));
   int rc = ws_reserve(c, &c->w_krylov, bytes);
   if (rc) return rc;
   double2* V = static_cast<double2*>(c->w_krylov.ptr);
@@ -180,6 +221,16 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
   double2* TMP = W + nk;
   double2* PB = TMP + nk;
   double2* dS = PB + nk;   // K x k small matrices (H column blocks, Y, R^-1)
+  SplitK sk;
+  sk.part = dS + (size_t)K * k + 64;
+  sk.ones = sk.part + (size_t)(SplitK::kChunks + 1) * pcap;
+  sk.cap = pcap;
+  {
+    std::vector<double2> ones(SplitK::kChunks + 1, make_double2(1.0, 0.0));
+    HPS_TRY_HIP(hipMemcpyAsync(sk.ones, ones.data(), sizeof(double2) * ones.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+  }
   Blas bl;
   if (rocblas_create_handle(&bl.h) != rocblas_status_success)
     return fail(HPS_ERR_DEVICE, "rocblas_create_handle failed");
@@ -188,7 +239,7 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
   // J^-1 B and its column norms
   if ((rc = launch_precond(c, b, PB, k, prec))) return rc;
   std::vector<cd> G;
-  if ((rc = gram(c, bl.h, PB, N, k, dS, G))) return rc;
+  if ((rc = gram(c, bl.h, PB, N, k, dS, G, sk))) return rc;
   std::vector<double> bnorm(k), res(k, 0.0), est(k, 0.0);
   for (int r = 0; r < k; ++r) bnorm[r] = std::sqrt(std::max(0.0, G[r + (size_t)k * r].real()));
   int its = 0, restarts = 0;
@@ -202,7 +253,7 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
       if ((e = launch_op_left(c, x, TMP, W, k, prec))) return e;
       if ((e = launch_sub_from(c, PB, W, nk))) return e;   // W = PB - W
     }
-    if ((e = gram(c, bl.h, W, N, k, dS, G))) return e;
+    if ((e = gram(c, bl.h, W, N, k, dS, G, sk))) return e;
     all_done = true;
     for (int r = 0; r < k; ++r) {
       res[r] = bnorm[r] > 0 ? std::sqrt(std::max(0.0, G[r + (size_t)k * r].real())) / bnorm[r] : 0.0;
@@ -215,7 +266,7 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
   while (!all_done && its < maxit) {
     // V_0 R_0 = R
     std::vector<cd> R0;
-    if ((rc = cholqr2(c, bl.h, W, TMP, V, N, k, dS, R0))) return rc;
+    if ((rc = cholqr2(c, bl.h, W, TMP, V, N, k, dS, R0, sk))) return rc;
     // host: block Hessenberg H (K x m k, column major), right-hand side S (K x k)
     std::vector<cd> H((size_t)K * m * k, 0.0), S((size_t)K * k, 0.0);
     for (int j = 0; j < k; ++j)
@@ -231,7 +282,7 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
       const int cols = (j + 1) * k;
       std::vector<cd> hc((size_t)cols * k, 0.0);
       for (int pass = 0; pass < 2; ++pass) {
-        if ((rc = zgemm(bl.h, true, cols, k, N, 1.0, V, N, W, N, 0.0, dS, cols))) return rc;
+        if ((rc = zgemm_ct(bl.h, cols, k, N, V, N, W, N, dS, sk))) return rc;
         std::vector<cd> part((size_t)cols * k);
         HPS_TRY_HIP(hipMemcpyAsync(part.data(), dS, sizeof(double2) * cols * k, hipMemcpyDeviceToHost,
                                    c->stream));
@@ -241,7 +292,7 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
       }
       // V_{j+1} R_{j+1} = W
       std::vector<cd> Rn;
-      if ((rc = cholqr2(c, bl.h, W, TMP, V + (size_t)nk * (j + 1), N, k, dS, Rn))) return rc;
+      if ((rc = cholqr2(c, bl.h, W, TMP, V + (size_t)nk * (j + 1), N, k, dS, Rn, sk))) return rc;
       // block column j of H: rows 0 .. (j+1)k from hc, rows (j+1)k .. (j+2)k from Rn
       for (int cc = 0; cc < k; ++cc) {
         cd* col = &H[(size_t)K * (j * k + cc)];

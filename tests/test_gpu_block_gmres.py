@@ -108,3 +108,20 @@ def test_block_gmres_dependent_rhs_and_bad_options(hps_mod):
     grp = hps_mod.Context.group([_problem(1, seed=35), _problem(1, seed=36)])
     with pytest.raises(hps_mod.HPSError):
         grp.gmres(dev(S2), dev(T2), solver="block_gmres")
+
+
+def test_block_gmres_long_vectors_split_products(hps_mod):
+    # 1.55 million unknowns: the block products V^H W and the Gram matrices
+    # run split over chunks of the vector length (partials summed); the block
+    # solve agrees with the lock-step one
+    k = 3
+    prob = P.bump_problem("bgl", (12, 12, 12), 10, 30.0, 6, k, 41, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    assert ctx.N > 256 * 4096
+    S, T = _rhs(prob, ctx.nodes(), k)
+    ub, stb, okb = ctx.gmres(dev(S), dev(T), tol=1e-10, restart=30, solver="block_gmres")
+    ul, stl, okl = ctx.gmres(dev(S), dev(T), tol=1e-10, restart=30, solver="batched")
+    assert okb and okl and stb["true_rel_res"] <= 1e-10
+    Ub, Ul = host(ub).reshape(k, -1), host(ul).reshape(k, -1)
+    for r in range(k):
+        assert rel(Ub[r], Ul[r]) < 1e-7, r
