@@ -44,6 +44,7 @@ CASES = [
     ((1, 2, 2), 12, 30.0, 3, 15),
     ((2, 1, 1), 16, 25.0, 2, 16),
     ((1, 1, 5), 9, 12.0, 3, 17),
+    ((1, 2, 1), 15, 24.0, 2, 18),
 ]
 
 
