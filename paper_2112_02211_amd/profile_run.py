@@ -4,6 +4,8 @@
     python -m paper_2112_02211_amd.profile_run pmc-summary --fetch DIR --write DIR --out FILE
     python -m paper_2112_02211_amd.profile_run arnoldi [--workload NAME]
     python -m paper_2112_02211_amd.profile_run arnoldi-summary --fetch DIR --write DIR --run-log FILE --out FILE
+    python -m paper_2112_02211_amd.profile_run gemm [--workload NAME] [--rhs 64]
+    python -m paper_2112_02211_amd.profile_run gemm-summary --pmc-dir DIR --out FILE
     python -m paper_2112_02211_amd.profile_run trace-summary --stats CSV --out FILE --cmd CMD --title T
 
 ``run`` (the default) is the fixed launch sequence for hardware-counter runs:
@@ -22,6 +24,10 @@ WRITE_SIZE, csv output) into the traffic summary that bench.py reads.
 solve with every Arnoldi update pass event-timed, printing their number and
 algorithmic bytes), then runs the calibration kernel; ``arnoldi-summary``
 turns its two counter runs into the update pass's traffic summary.
+``gemm`` launches J^{-1} on --rhs right-hand sides (the block product as a
+GEMM on the matrix cores) with FP64, FP32 and BF16 blocks; ``gemm-summary``
+turns one counter run of it (MfmaUtil and the MFMA operation counts) into the
+matrix-core summary of the block GEMM.
 ``trace-summary`` turns a rocprofv3 --kernel-trace --stats kernel_stats.csv
 into a text table.
 """
@@ -30,6 +36,7 @@ import collections
 import csv
 import hashlib
 import os
+import re
 import statistics
 import sys
 import time
@@ -169,6 +176,72 @@ def arnoldi_summary(a):
     print(text)
 
 
+def gemm(a):
+    import numpy as np
+    import torch
+    from paper_2112_02211_amd import hps, problems as P
+
+    prob = P.workload(a.workload)
+    ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"))
+    rng = np.random.default_rng(0)
+    X = torch.from_numpy(rng.standard_normal(a.rhs * ctx.N) + 1j * rng.standard_normal(a.rhs * ctx.N)).cuda()
+    Y = torch.empty_like(X)
+    for q in ("fp64", "fp32", "bf16"):
+        shape = ctx.autotune(a.rhs, q, reps=1)
+        for _ in range(a.launches + 1):
+            ctx.precond(X, Y, prec=q)
+        torch.cuda.synchronize()
+        print(f"gemm {q}: shape {shape}, {a.launches + 1} launches", flush=True)
+    print(f"gemm_algorithmic_flops: {8.0 * ctx.nl * ctx.nb * ctx.nb * a.rhs:.0f}", flush=True)
+
+
+def gemm_summary(a):
+    """Matrix-core counters of the block GEMM from one `gemm` run under
+    rocprofv3 --pmc MfmaUtil MfmaFlopsF64 MfmaFlopsF32 MfmaFlopsBF16."""
+    from paper_2112_02211_amd import problems as P
+    prob = P.workload(a.workload)
+    n1 = prob.p - 2
+    nl = prob.n_elem[0] * prob.n_elem[1] * prob.n_elem[2]
+    nb = 6 * n1 * n1
+    alg = 8.0 * nl * nb * nb * a.rhs
+    path = os.path.join(a.pmc_dir, "run_counter_collection.csv")
+    rows = list(csv.DictReader(open(path)))
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        if "k_block_gemm" in r["Kernel_Name"]:
+            per[(r["Kernel_Name"], int(r["Dispatch_Id"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    L = [f"# Matrix-core counters of the block GEMM of J^-1 on {a.rhs} right-hand sides, {a.workload}",
+         f"# ({prob.n_elem[0]}x{prob.n_elem[1]}x{prob.n_elem[2]} leaves, p={prob.p}: {nl} blocks of {nb} x {nb})",
+         "#",
+         "# command (R = repository root on the GPU box):",
+         "#   cd /tmp && export TMPDIR=/tmp",
+         f"#   rocprofv3 --pmc MfmaUtil MfmaFlopsF64 MfmaFlopsF32 MfmaFlopsBF16 --output-format csv "
+         f"-d $R/gpurun_out/{os.path.basename(a.pmc_dir.rstrip('/'))} -o run -- python "
+         f"$R/paper_2112_02211_amd/profile_run.py gemm --workload {a.workload} --rhs {a.rhs} --launches {a.launches}",
+         f"#   python -m paper_2112_02211_amd.profile_run gemm-summary --workload {a.workload} --rhs {a.rhs} "
+         f"--launches {a.launches} --pmc-dir <that dir> --out <this file>",
+         "#",
+         f"# algorithmic flops per launch: 8 N_leaves n_b^2 k = {alg:.0f}",
+         "# MfmaUtil: MFMA busy cycles / (active cycles x SIMDs), percent; MFMA flops = MOPS x 512",
+         "# (medians over the dispatches after the first of each kernel)"]
+    byk = collections.defaultdict(list)
+    for (name, did), cnt in sorted(per.items(), key=lambda kv: kv[0][1]):
+        byk[name].append({k: sum(v) for k, v in cnt.items()})
+    for name, ds in byk.items():
+        ds = ds[1:] if len(ds) > 1 else ds
+        util = statistics.median(d.get("MfmaUtil", float("nan")) for d in ds)
+        fl = {t: statistics.median(d.get(f"MfmaFlops{t}", 0.0) for d in ds) for t in ("F64", "F32", "BF16")}
+        total = sum(fl.values())
+        m = re.search(r"(k_block_gemm<[^>]*>)", name)
+        short = m.group(1) if m else name.split("(")[0]
+        L.append(f"{short}: MfmaUtil {util:.1f} %, MFMA flops per launch {total:.4g} "
+                 f"(F64 {fl['F64']:.4g}, F32 {fl['F32']:.4g}, BF16 {fl['BF16']:.4g}), "
+                 f"hardware / algorithmic {total / alg:.3f}, launches {len(ds)}")
+    text = "\n".join(L) + "\n"
+    open(a.out, "w").write(text)
+    print(text)
+
+
 def _counters(path, counter):
     """{kernel name: [values in dispatch order]} for one counter."""
     rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
@@ -289,7 +362,8 @@ def trace_summary(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", nargs="?", default="run",
-                    choices=("run", "pmc-summary", "trace-summary", "arnoldi", "arnoldi-summary"))
+                    choices=("run", "pmc-summary", "trace-summary", "arnoldi", "arnoldi-summary", "gemm",
+                             "gemm-summary"))
     ap.add_argument("--workload", default="bumps_8x8x8_p10")
     ap.add_argument("--launches", type=int, default=4)
     ap.add_argument("--iti", action="store_true",
@@ -301,13 +375,15 @@ def main():
     ap.add_argument("--write")
     ap.add_argument("--stats")
     ap.add_argument("--run-log")
+    ap.add_argument("--rhs", type=int, default=64)
+    ap.add_argument("--pmc-dir")
     ap.add_argument("--out")
     ap.add_argument("--cmd", default="")
     ap.add_argument("--title", default="rocprofv3 kernel statistics")
     ap.add_argument("--rows", type=int, default=24)
     a = ap.parse_args()
     {"run": run, "pmc-summary": pmc_summary, "trace-summary": trace_summary, "arnoldi": arnoldi,
-     "arnoldi-summary": arnoldi_summary}[a.mode](a)
+     "arnoldi-summary": arnoldi_summary, "gemm": gemm, "gemm-summary": gemm_summary}[a.mode](a)
 
 
 if __name__ == "__main__":
