@@ -16,7 +16,9 @@ constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
 constexpr int UT = 256;        // update-pass (and small-step) workgroup
 constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
 constexpr int kShortBasis = 8;           // reductions over at most this many basis vectors ...
-constexpr int64_t kLongVector = 1 << 24; // ... of at least this many entries split tiles over wavefronts
+constexpr int64_t kLongVector = 1 << 22; // ... of at least this many entries split tiles over wavefronts
+                                         // (measured: 3 % slower on 0.46M-entry vectors, where u and w
+                                         // re-reads hit in cache; faster from 6.5M entries on)
 
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
