@@ -125,3 +125,21 @@ def test_block_gmres_long_vectors_split_products(hps_mod):
     Ub, Ul = host(ub).reshape(k, -1), host(ul).reshape(k, -1)
     for r in range(k):
         assert rel(Ub[r], Ul[r]) < 1e-7, r
+
+
+def test_block_gmres_resumes_from_an_initial_guess(hps_mod):
+    # a bounded first call (not converged), then the same solve resumed from
+    # its iterate: the result matches the direct solves
+    k = 4
+    prob = _problem(k, seed=37)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    op = O.build(prob)
+    S, T = _rhs(prob, ctx.nodes(), k)
+    u, st, ok = ctx.gmres(dev(S), dev(T), tol=1e-11, restart=6, max_iters=6, solver="block_gmres")
+    assert not ok and st["iters"] == 6
+    u, st2, ok2 = ctx.gmres(dev(S), dev(T), tol=1e-11, restart=6, u=u, use_x0=True, solver="block_gmres")
+    assert ok2 and st2["true_rel_res"] <= 1e-11
+    U = host(u).reshape(k, -1)
+    for r in range(k):
+        rhs = O.assemble_rhs(op.d, S[r * op.d.N:(r + 1) * op.d.N], np.zeros(op.d.N))
+        assert rel(U[r], O.solve_direct(op, rhs)) < 1e-9, r
