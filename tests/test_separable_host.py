@@ -108,3 +108,25 @@ def test_separable_table_errors():
     assert L.hps_separable_table(8, 0.1, 0.0, out) == hps.HPS_ERR_ARG
     assert L.hps_separable_table(8, -0.1, 1.0, out) == hps.HPS_ERR_ARG
     assert L.hps_separable_table(8, 0.1, 1.0, None) == hps.HPS_ERR_ARG
+
+
+@pytest.mark.parametrize("p", [4, 7, 10])
+def test_leaf_matrix_couples_along_grid_lines_only(p):
+    # the structure the separable form rests on, read off the oracle's leaf
+    # matrix: an interior row couples only nodes on the three grid lines through
+    # its node; a face row (eq. (flux) plus i eta) only nodes on the normal line
+    # of its face node, which ends at a node of the opposite face
+    d = O.make_disc((1, 1, 1), p, 10.0, 10.0)
+    A, _ = O.leaf_matrices(d, np.full(d.ni, 50.0), O.local_ops(d))
+    ref = O.leaf_nodes_ref(d)          # (n, 3) grid indices of the local nodes
+    for row in range(d.n):
+        cols = np.nonzero(A[row])[0]
+        diff = ref[cols] != ref[row]     # coordinates that differ from the row's node
+        if row < d.ni:
+            assert np.all(diff.sum(axis=1) <= 1), row
+        else:
+            f = (row - d.ni) // (d.n1 ** 2)
+            ax = f // 2
+            assert np.all(diff.sum(axis=1) <= 1) and not np.any(np.delete(diff, ax, axis=1)), row
+            ends = cols[(ref[cols][:, ax] == 0) | (ref[cols][:, ax] == p - 1)]
+            assert len(ends) == 2, row     # its own node and the opposite face's
