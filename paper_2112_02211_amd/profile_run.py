@@ -171,6 +171,23 @@ def arnoldi_summary(a):
          f"kernel_source_sha256_16: {kernel_source_hash('k_dcgs_update')}",
          f"algorithmic_bytes_per_launch: {alg / K:.0f}",
          f"hbm_bytes_per_launch: {tot / K:.0f}"]
+    # the separable J^-1 of the same solves (x in, y out, the neighbours' face
+    # data read by the fused exchange): medians over its dispatches
+    from paper_2112_02211_amd import problems as P
+    prob = P.workload(a.workload)
+    n1 = prob.p - 2
+    nl = prob.n_elem[0] * prob.n_elem[1] * prob.n_elem[2]
+    Nn = nl * (n1 ** 3 + 6 * n1 * n1)
+    sk = [k for k in F if f"k_precond_sep<{prob.p}>" in k]
+    if sk:
+        fs, ws = _find(F, f"k_precond_sep<{prob.p}>"), _find(W, f"k_precond_sep<{prob.p}>")
+        t_sep = statistics.median(f * 1024 * sf + w * 1024 * sw for f, w in zip(fs, ws))
+        a_sep = 32.0 * Nn + 16.0 * nl * 6 * n1 * n1
+        L += ["#", "# separable J^-1 (k_precond_sep) in the same solves, exchange fused",
+              f"precond_sep_launches: {len(fs)}",
+              f"precond_sep_algorithmic_bytes_per_launch: {a_sep:.0f}",
+              f"precond_sep_hbm_bytes_per_launch: {t_sep:.0f}",
+              f"precond_sep_traffic_over_algorithmic: {t_sep / a_sep:.4f}"]
     text = "\n".join(L) + "\n"
     open(a.out, "w").write(text)
     print(text)
