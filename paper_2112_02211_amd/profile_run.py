@@ -54,6 +54,11 @@ KERNEL_SOURCES = {"k_precond_fused": PRECOND_SOURCES, "k_dcgs_update": ARNOLDI_S
 COPY_MIB = 1024
 
 
+def _rel(path):
+    """An output folder as the profiled command named it: relative to the repository root."""
+    return os.path.relpath(os.path.abspath(path), os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
 def kernel_source_hash(kernel: str = "k_precond_fused") -> str:
     """Hash of a profiled kernel's sources: counters taken on other sources
     describe another kernel."""
@@ -154,10 +159,10 @@ def arnoldi_summary(a):
     L = [f"# HBM traffic of the Arnoldi update pass (k_dcgs_update), {a.workload} workload, one",
          "# left-preconditioned GMRES solve with the separable J^-1 (the second of two solves)",
          "#",
-         "# commands (R = repository root on the GPU box; one counter per run):",
+         "# commands (R = repository root; one counter per run):",
          "#   cd /tmp && export TMPDIR=/tmp",
-         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.fetch.rstrip('/'))} -o run -- {cmd}",
-         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.write.rstrip('/'))} -o run -- {cmd}",
+         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/{_rel(a.fetch)} -o run -- {cmd}",
+         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/{_rel(a.write)} -o run -- {cmd}",
          f"#   python -m paper_2112_02211_amd.profile_run arnoldi-summary --workload {a.workload} "
          f"--launches {a.launches} --fetch <fetch dir> --write <write dir> --run-log <stdout of a run> --out <this file>",
          "#",
@@ -230,10 +235,10 @@ def gemm_summary(a):
     L = [f"# Matrix-core counters of the block GEMM of J^-1 on {a.rhs} right-hand sides, {a.workload}",
          f"# ({prob.n_elem[0]}x{prob.n_elem[1]}x{prob.n_elem[2]} leaves, p={prob.p}: {nl} blocks of {nb} x {nb})",
          "#",
-         "# command (R = repository root on the GPU box):",
+         "# command (R = repository root):",
          "#   cd /tmp && export TMPDIR=/tmp",
          f"#   rocprofv3 --pmc MfmaUtil MfmaFlopsF64 MfmaFlopsF32 MfmaFlopsBF16 --output-format csv "
-         f"-d $R/gpurun_out/{os.path.basename(a.pmc_dir.rstrip('/'))} -o run -- python "
+         f"-d $R/{_rel(a.pmc_dir)} -o run -- python "
          f"$R/paper_2112_02211_amd/profile_run.py gemm --workload {a.workload} --rhs {a.rhs} --launches {a.launches}",
          f"#   python -m paper_2112_02211_amd.profile_run gemm-summary --workload {a.workload} --rhs {a.rhs} "
          f"--launches {a.launches} --pmc-dir <that dir> --out <this file>",
@@ -300,12 +305,12 @@ def pmc_summary(a):
          f"# ({prob.n_elem[0]}x{prob.n_elem[1]}x{prob.n_elem[2]} leaves, p={p}, N={N}; one launch "
          "applies the operator to one vector)",
          "#",
-         "# commands (R = repository root on the GPU box; one counter per run):",
+         "# commands (R = repository root; one counter per run):",
          "#   cd /tmp && export TMPDIR=/tmp",
-         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.fetch.rstrip('/'))} "
+         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/{_rel(a.fetch)} "
          f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}"
          f"{' --iti' if a.iti else ''}",
-         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/{os.path.basename(a.write.rstrip('/'))} "
+         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/{_rel(a.write)} "
          f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}"
          f"{' --iti' if a.iti else ''}",
          f"#   python -m paper_2112_02211_amd.profile_run pmc-summary --workload {a.workload} "
@@ -361,7 +366,7 @@ def pmc_summary(a):
 def trace_summary(a):
     rows = list(csv.DictReader(open(a.stats)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
-    L = [f"# {a.title}", "#", "# command (R = repository root on the GPU box):",
+    L = [f"# {a.title}", "#", "# command (R = repository root):",
          "#   cd /tmp && export TMPDIR=/tmp", f"#   {a.cmd}", "#",
          f"# {'kernel':70s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>9s} "
          f"{'max_us':>9s} {'pct':>6s}"]
