@@ -15,6 +15,7 @@ constexpr int DW = 8;          // wavefronts of the reduction workgroup (split o
 constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
 constexpr int UT = 256;        // update-pass (and small-step) workgroup
 constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
+constexpr int64_t kMidVector = 1 << 24;  // reduction grid sizes below / from here
 constexpr int kShortBasis = 8;           // reductions over at most this many basis vectors ...
 constexpr int64_t kLongVector = 1 << 22; // ... of at least this many entries split tiles over wavefronts
                                          // (measured: 3 % slower on 0.46M-entry vectors, where u and w
@@ -522,7 +523,11 @@ int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, i
   if (J > kMaxDcgs || nbatch > rb.nbatch) return fail(HPS_ERR_ARG, "reduction too large");
   const int64_t tiles = (n + 63) / 64;
   const int kc = (J + DW - 1) / DW;
-  const int nblk = (int)std::min<int64_t>(tiles, kc <= 2 ? 1024 : 512);
+  // workgroups: fewer partials to finish on vectors up to 2^24 entries (measured
+  // on 0.46M and 6.5M entries: 512 / 256 beat 1024 / 512 by 3.1 % and 1.4 % per
+  // solve, 256 / 128 lost 5-12 %); longer vectors keep 1024 / 512
+  const bool mid = n < kMidVector;
+  const int nblk = (int)std::min<int64_t>(tiles, kc <= 2 ? (mid ? 512 : 1024) : (mid ? 256 : 512));
   dim3 grid(nblk, 1, nbatch);
   const bool hw = w != nullptr;
 #define HPS_DR(KC)                                                                              \
