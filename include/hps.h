@@ -165,6 +165,7 @@ typedef struct {
   int lambda_shifted;   /* number of leaves whose lambda was moved off a resonance */
   double rel_res;       /* final residual estimate, relative (preconditioned for GMRES) */
   double true_rel_res;  /* recomputed at the end from x: same norm as rel_res */
+  double t_setup;       /* seconds hps_setup took for this context (host wall clock) */
   double t_solve;       /* seconds, host wall clock around the solve */
   double bytes_apply;   /* algorithmic HBM bytes of one hps_apply */
   double bytes_precond; /* algorithmic HBM bytes of one hps_precond */

@@ -404,7 +404,11 @@ def homog_leaf_matrix(d: Disc, C_int: np.ndarray, ops=None, delta: float = 0.0):
 class Precond:
     """J^{-1}: block diagonal, each block the inverse of the homogenized leaf matrix.
 
-    Factorizes each needed leaf with dense LU on first use.
+    Factorizes each needed leaf with dense LU on first use.  The homogenized
+    leaf matrix depends on the leaf only through its lambda, so with lambda
+    buckets (delta > 0) the leaves whose rounded lambda agree share one LU
+    factorization, and apply() solves each shared factorization once for all
+    of its leaves' blocks at once (the same per-leaf solves, batched).
     """
 
     def __init__(self, d: Disc, b_nodes: np.ndarray, lambda_bucket: float = 0.0):
@@ -414,13 +418,23 @@ class Precond:
         self.lu = {}
         self.lams = {}
         self.delta = float(lambda_bucket)
+        self._shared = {}      # rounded lambda -> LU (delta > 0 only)
+        self._eigs = l1_eigenvalues(d)
 
     def _factor(self, tau):
         if tau not in self.lu:
             d = self.d
-            A, _, lam, _ = homog_leaf_matrix(d, self.C[tau * d.n:tau * d.n + d.ni], self.ops,
-                                             delta=self.delta)
-            self.lu[tau] = sla.lu_factor(A)
+            if self.delta > 0.0:
+                lam, _ = homog_lambda(d, self.C[tau * d.n:tau * d.n + d.ni], self._eigs,
+                                      delta=self.delta)
+                if lam not in self._shared:
+                    A, _ = leaf_matrices(d, np.full(d.ni, lam), self.ops)
+                    self._shared[lam] = sla.lu_factor(A)
+                self.lu[tau] = self._shared[lam]
+            else:
+                A, _, lam, _ = homog_leaf_matrix(d, self.C[tau * d.n:tau * d.n + d.ni],
+                                                 self.ops, delta=self.delta)
+                self.lu[tau] = sla.lu_factor(A)
             self.lams[tau] = lam
         return self.lu[tau]
 
@@ -432,6 +446,16 @@ class Precond:
     def apply(self, x: np.ndarray) -> np.ndarray:
         d = self.d
         y = np.zeros_like(x, dtype=np.complex128)
+        if self.delta > 0.0:
+            groups = {}
+            for tau in range(d.nl):
+                self._factor(tau)
+                groups.setdefault(self.lams[tau], []).append(tau)
+            xs = x.reshape(d.nl, d.n)
+            ys = y.reshape(d.nl, d.n)
+            for lam, taus in groups.items():
+                ys[taus] = sla.lu_solve(self._shared[lam], xs[taus].T).T
+            return y
         for tau, w in self.apply_elems(x, range(d.nl)).items():
             y[tau * d.n:(tau + 1) * d.n] = w
         return y

@@ -378,6 +378,7 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
     st->restarts = restarts;
     st->converged = all_done ? 1 : 0;
     st->lambda_shifted = c->n_shifted;
+    st->t_setup = c->t_setup;
     st->rel_res = we;
     st->true_rel_res = wt;
     st->t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() - t0;

@@ -486,6 +486,7 @@ int setup_impl(const hps_domain* d, int nop, const double* kappas, const double*
   if (precs & HPS_PREC_BF16) pb |= 1 << kBF16;
   if (pb && (rc = build_blocks(c, pb))) return bail(rc);
   if ((rc = check_hip(hipStreamSynchronize(c->stream), "setup"))) return bail(rc);
+  c->t_setup = now() - t0;
   if (c->verbose)
     std::fprintf(stderr, "[hps] setup: tables+medium %.3f s, blocks %.3f s, %.2f GB on device\n",
                  t1 - t0, now() - t1, c->dev_bytes / 1e9);

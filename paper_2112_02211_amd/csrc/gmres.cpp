@@ -301,6 +301,7 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
     st->restarts = restarts;
     st->converged = all_done() ? 1 : 0;
     st->lambda_shifted = c->n_shifted;
+    st->t_setup = c->t_setup;
     st->rel_res = worst_est;
     st->true_rel_res = worst_true;
     st->t_solve = now() - t0;
@@ -504,6 +505,7 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     st->restarts = restarts;
     st->converged = all_done() ? 1 : 0;
     st->lambda_shifted = c->n_shifted;
+    st->t_setup = c->t_setup;
     st->rel_res = worst_est;
     st->true_rel_res = worst_true;
     st->t_solve = now() - t0;
@@ -637,6 +639,7 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     }
     acc.converged = rc == HPS_OK;
     acc.lambda_shifted = c->n_shifted;
+      acc.t_setup = c->t_setup;
     if (st) *st = acc;
   } else if (rc == HPS_OK && o.solver == HPS_SOLVER_BGMRES) {
     rc = run_block_gmres(c, prec, bvec, x, nrhs, tol, restart, maxit, o.use_x0 != 0, o.rhs_rel_res, st);
@@ -674,6 +677,7 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       }
       acc.converged = rc == HPS_OK;
       acc.lambda_shifted = c->n_shifted;
+      acc.t_setup = c->t_setup;
       if (st) *st = acc;
     } else {
       job.nrhs = 1;
@@ -695,6 +699,7 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       }
       acc.converged = rc == HPS_OK;
       acc.lambda_shifted = c->n_shifted;
+      acc.t_setup = c->t_setup;
       if (st) *st = acc;
     }
   }

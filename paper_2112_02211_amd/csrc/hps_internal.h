@@ -112,6 +112,7 @@ struct hps_ctx {
   int* d_gblk = nullptr;            // [ngroups] block (bucket) of each group
   int group_leaves = 1;             // leaves in the largest group
   int n_shifted = 0;
+  double t_setup = 0.0;  // seconds of hps_setup (host wall clock, device synchronized)
   hps::Blocks blk[3];
   // separable form of the FP64 J^-1 (block_precs has HPS_PREC_SEPARABLE): no
   // FP64 blocks; one complex table per operator

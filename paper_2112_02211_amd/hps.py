@@ -61,7 +61,8 @@ class _SolveOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("lambda_shifted", ctypes.c_int), ("rel_res", ctypes.c_double),
-                ("true_rel_res", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double), ("t_setup", ctypes.c_double),
+                ("t_solve", ctypes.c_double),
                 ("bytes_apply", ctypes.c_double), ("bytes_precond", ctypes.c_double)]
 
     def as_dict(self) -> dict:

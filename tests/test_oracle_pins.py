@@ -170,6 +170,104 @@ def test_lambda_midrange_special_cases():
     assert abs(lam - 20.0) < 1e-12
 
 
+# ---------------------------------------------------------------------------
+# the resonance guard: -E_Delta - lambda vanishes when lambda meets a Dirichlet
+# eigenvalue of the leaf interior (Sec. 4.1 divides by it; the paper is silent).
+# The oracle then moves lambda to lambda (1 + 0.01 i).
+
+def _lowest_dirichlet_eigenvalue(d):
+    # from the assembled 3D interior operator -(Dxx + Dyy + Dzz) (local_ops),
+    # not from the 1D eigenvalues the guard itself uses
+    L, _ = O.local_ops(d)
+    ev = np.linalg.eigvals(L[:, :d.ni])
+    assert np.max(np.abs(ev.imag)) < 1e-9 * np.max(np.abs(ev.real))
+    return float(np.min(ev.real))
+
+
+@pytest.mark.parametrize("p", [8, 10])
+def test_lowest_dirichlet_eigenvalue_of_a_leaf_is_three_pi_squared(p):
+    # closed form: the Dirichlet Laplacian on the unit cube has lowest eigenvalue 3 pi^2
+    d = O.make_disc((1, 1, 1), p, 5.0, 5.0)
+    mu0 = _lowest_dirichlet_eigenvalue(d)
+    assert abs(mu0 - 3 * np.pi ** 2) < 1e-5 * 3 * np.pi ** 2
+
+
+@pytest.mark.parametrize("rel, shifted", [(2e-4, True), (-5e-4, True), (3e-3, False), (-2e-3, False)])
+def test_resonance_guard_threshold(rel, shifted):
+    d = O.make_disc((1, 1, 1), 8, 5.0, 5.0)
+    mu0 = _lowest_dirichlet_eigenvalue(d)
+    lam0 = mu0 * (1.0 + rel)
+    lam, sh = O.homog_lambda(d, np.full(d.ni, lam0 + 0j))
+    assert sh == shifted
+    if shifted:
+        assert lam == lam0 * (1.0 + 0.01j)
+    else:
+        assert lam == lam0
+
+
+def test_resonance_guard_makes_the_homogenized_interior_invertible():
+    d = O.make_disc((1, 1, 1), 8, 5.0, 5.0)
+    mu0 = _lowest_dirichlet_eigenvalue(d)
+    lam0 = mu0 * (1.0 + 2e-4)
+    L, _ = O.local_ops(d)
+    Lii = L[:, :d.ni]
+    smin = lambda M: np.linalg.svd(M, compute_uv=False)[-1]
+    # unshifted: within 2e-4 mu0 of singular; shifted: the eigenvalue distance is
+    # 0.01 |lambda| (Lii is not normal, so its smallest singular value is a little less)
+    assert smin(Lii - lam0 * np.eye(d.ni)) < 2.5e-4 * mu0
+    lam, sh = O.homog_lambda(d, np.full(d.ni, lam0 + 0j))
+    assert sh and smin(Lii - lam * np.eye(d.ni)) > 0.009 * abs(lam0)
+
+
+def test_shifted_block_is_the_inverse_of_the_leaf_matrix_at_the_shifted_lambda():
+    # a constant medium at a resonant C: J^{-1} is then the exact inverse of the
+    # global one-leaf matrix (assemble_global) whose C is lambda (1 + 0.01 i), and
+    # no longer the inverse of the leaf's own matrix
+    kappa = 10.0
+    d = O.make_disc((1, 1, 1), 8, kappa, kappa)
+    mu0 = _lowest_dirichlet_eigenvalue(d)
+    c0 = mu0 * (1.0 + 2e-4)
+    bn = np.full(d.N, 1.0 - c0 / kappa ** 2, dtype=complex)
+    M = O.Precond(d, bn)
+    x = np.random.default_rng(5).standard_normal(d.N) + 1j * np.random.default_rng(6).standard_normal(d.N)
+    bs = np.full(d.N, 1.0 - c0 * (1.0 + 0.01j) / kappa ** 2)
+    As = O.assemble_global(d, bs)
+    assert np.linalg.norm(M.apply(As @ x) - x) < 1e-12 * np.linalg.norm(x)
+    A = O.assemble_global(d, bn)
+    assert np.linalg.norm(M.apply(A @ x) - x) > 1e-3 * np.linalg.norm(x)
+    assert abs(M.lams[0] - c0 * (1.0 + 0.01j)) < 1e-14 * c0
+
+
+def test_shifted_leaves_leave_the_solution_unchanged():
+    # 2^3 leaves, piecewise-constant medium, leaf 0 at a resonant C: the guard
+    # moves only the preconditioner, GMRES still reaches the direct solution
+    kappa = 10.0
+    prob = P.bump_problem("res", (2, 2, 2), 8, kappa, 0, 1, seed=9, restart=30, tol=1e-12)
+    d = O.make_disc(prob.n_elem, prob.p, kappa, kappa, prob.lo, prob.hi)
+    mu0 = _lowest_dirichlet_eigenvalue(d)
+    bn = resonant_medium(d, mu0, kappa)
+    A = O.assemble_global(d, bn)
+    xyz = O.node_coords(d)
+    rhs = O.assemble_rhs(d, P.gaussian_source(prob, xyz), np.zeros(d.N, dtype=complex))
+    M = O.Precond(d, bn)
+    x, its, _ = O.gmres_left(lambda v: A @ v, M.apply, rhs, tol=1e-12, restart=30)
+    flags = [O.homog_lambda(d, O.c_values(d, bn)[t * d.n:t * d.n + d.ni])[1] for t in range(d.nl)]
+    assert flags == [True] + [False] * 7
+    u = O.solve_direct(O.OracleProblem(d, xyz, bn, A, rhs))
+    assert np.linalg.norm(x - u) < 1e-9 * np.linalg.norm(u)
+
+
+def resonant_medium(d, mu0, kappa):
+    """b constant on each leaf: leaf 0 has C = kappa^2 (1 - b) = mu0 (1 + 2e-4),
+    within the guard of the lowest Dirichlet eigenvalue mu0 of a leaf; the others
+    have C = kappa^2 (1 - 0.05 tau), below mu0 and away from it."""
+    bn = np.zeros(d.N, dtype=complex)
+    for tau in range(d.nl):
+        b = 1.0 - mu0 * (1.0 + 2e-4) / kappa ** 2 if tau == 0 else 0.05 * tau
+        bn[tau * d.n:(tau + 1) * d.n] = b
+    return bn
+
+
 def test_homogenized_iti_map_is_unitary_for_real_medium():
     # For a real, constant coefficient the ItI map is unitary (Sec. 1.1; the
     # impedance coupling avoids artificial resonances), and R = I - 2 i eta S^{-1}
