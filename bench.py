@@ -3,15 +3,18 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 A step is one complete block-Jacobi preconditioned GMRES solve of the
-workload (every hot-path stage: operator sweep + face exchange, the
+workload (every hot-path stage: operator sweep, face exchange, the
 homogenized block-Jacobi preconditioner, Arnoldi with delayed
 reorthogonalization, Givens) from x0 = 0 to the workload's tolerance.  The
+default workload is the largest single-GPU configuration, 16^3 leaves at
+p = 12 (6,553,600 unknowns, kappa = 80, 20 Gaussian bumps).  The
 preconditioner is applied in its separable form (the exact inverse of each
 homogenized leaf matrix by a complex fast diagonalization, no stored blocks);
-the same solve with the paper's stored dense blocks is reported beside it.
-``value`` is the throughput of preconditioned operator applications inside
-those solves: N * (Arnoldi steps) / seconds, in millions of unknowns per
-second.  Inputs are resident in HBM before timing.
+the same solve with the paper's stored dense blocks and the reduced-precision
+solves at equal accuracy are reported beside it.  ``value`` is the throughput
+of preconditioned operator applications inside those solves: N * (Arnoldi
+steps) / seconds, in millions of unknowns per second.  Inputs are resident in
+HBM before timing.
 
 The JSON line also carries:
   roofline      the dominant kernel of the step (the Arnoldi update pass, which
@@ -20,6 +23,9 @@ The JSON line also carries:
                 attached to the dispatches), against the 8 TB/s HBM peak; the
                 dense-block solve carries the same for its dominant kernel, the
                 block-streaming preconditioner;
+  secondary     the same measurements on the 8^3, p = 10 workload, with the
+                lambda-bucketed and face-reduced solves;
+  serving       a bounded run of the mixed request stream (solves/s, p50/p99);
   cpu_baseline  the CPU oracle timed on a bounded sample of one GMRES step.
 """
 from __future__ import annotations
@@ -38,6 +44,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 MIXED_TOL = 1e-10
+IR_INNER_TOL = 1e-5  # inner (FP32) relative tolerance of iterative refinement
 TIMING_EVERY = 8     # launches per timed launch inside the timed region
 BUCKET_DELTAS = (1e-3, 1e-2)   # lambda grid spacings (times kappa^2) of the bucketed runs
 METRIC = "HPS operator applies/s (Munknowns/s) + time-to-1e-8 solve; served p50/p99"
@@ -98,20 +105,22 @@ def cpu_baseline(prob) -> dict:
     M.apply_elems(y, sample)
     t_p = (time.perf_counter() - t0) * (op.d.nl / len(sample))
     # classical Arnoldi step at the middle of a restart-50 cycle: 25 MGS projections
-    V = [x / np.linalg.norm(x)] + [rng.standard_normal(op.d.N) + 0j for _ in range(2)]
+    # against 25 distinct basis vectors (each a full N-vector in its own memory,
+    # as in a real cycle; not a few vectors that stay in cache)
+    V = [x / np.linalg.norm(x)] + [np.roll(x, 7919 * (i + 1)) for i in range(24)]
     t0 = time.perf_counter()
     w = y.copy()
-    for i in range(25):
-        v = V[i % len(V)]
+    for v in V:
         w -= np.vdot(v, w) * v
     t_o = time.perf_counter() - t0
+    del V
     t_step = t_a + t_p + t_o
     return {"value": op.d.N / t_step / 1e6, "unit": "Munknowns/s", "cores": int(blas_threads),
             "kind": "oracle",
             "sample": (f"one oracle GMRES step (one right-hand side) on the same workload: {a_desc} "
                        f"({t_a * 1e3:.1f} ms), J^-1 by dense-LU leaf solves on "
                        f"{len(sample)} of {op.d.nl} leaves scaled to all ({t_p * 1e3:.0f} ms), "
-                       f"25 MGS projections ({t_o * 1e3:.0f} ms)")}
+                       f"25 MGS projections against 25 distinct basis vectors ({t_o * 1e3:.0f} ms)")}
 
 
 def oracle_check(name: str, u: np.ndarray):
@@ -123,18 +132,26 @@ def oracle_check(name: str, u: np.ndarray):
     return float(np.linalg.norm(u[idx] - g["u"]) / np.linalg.norm(g["u"]))
 
 
+DEFAULT_WORKLOAD = "bumps_16x16x16_p12"   # the largest single-GPU configuration
+SECONDARY_WORKLOAD = "bumps_8x8x8_p10"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="bumps_8x8x8_p10")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="default workload only: skip the 8^3 line and the serving leg")
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--max-steps", type=int, default=0,
                     help="bound on GMRES steps per solve of the shared-block workloads (0: the workload's)")
     ap.add_argument("--requests", type=int, default=512,
                     help="requests of the serving workload (request_stream)")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving leg of the default line")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="block precision of the many-right-hand-side workload")
     ap.add_argument("--precond", default="blocks", choices=["blocks", "separable"],
@@ -145,9 +162,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU decomposition is a design note only)"}))
         sys.exit(2)
-
     import torch
-    from paper_2112_02211_amd import hps, problems as P
+    from paper_2112_02211_amd import problems as P
 
     torch.cuda.set_device(0)
     if a.workload == "request_stream":
@@ -157,19 +173,53 @@ def main():
         return run_batched(a, prob)
     if prob.lambda_bucket > 0:
         return run_bucketed(a, prob)
+    full = a.workload != DEFAULT_WORKLOAD
+    line = solve_line(a, prob, a.steps, a.warmup, extensions=full)
+    if not full and not a.no_secondary:
+        progress(f"secondary workload {SECONDARY_WORKLOAD}")
+        sec = solve_line(a, P.workload(SECONDARY_WORKLOAD), 5, 1, extensions=True)
+        for k in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            sec.pop(k, None)
+        line["secondary"] = {SECONDARY_WORKLOAD: sec}
+        progress(f"serving leg ({a.serve_requests} requests)")
+        line["serving"] = serving_leg(a.serve_requests)
+    if not a.no_cpu_baseline:
+        progress("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(line), flush=True)
+
+
+def progress(msg: str):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def solve_line(a, prob, steps: int, warmup: int, extensions: bool) -> dict:
+    """One single-right-hand-side workload: the timed FP64 solves with the
+    separable J^-1 (the line's value), their kernels, the reduced-precision
+    solves at equal accuracy and the paper's stored blocks; with extensions
+    also the lambda-bucketed and face-reduced solves."""
+    import torch
+    from paper_2112_02211_amd import hps, problems as P
+
+    name = prob.name
+    big = prob.n_unknowns > 4_000_000
+    # per-solve repetitions of the side measurements: one at the big size
+    reps = 1 if big else 2
+    progress(f"{name}: setup")
     t0 = time.perf_counter()
     ctx = hps.Context.from_problem(prob, block_precs=("separable", "fp32", "bf16"))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     xyz = ctx.nodes()
     s_np, t_np = P.rhs_data(prob, xyz)
+    del xyz
     s = torch.from_numpy(s_np).cuda()
     t = torch.from_numpy(t_np).cuda()
 
-    def timed_solves(c, u):
-        """warm-up, then a.steps timed solves with kernel timing on; returns
+    def timed_solves(c, u, k, w):
+        """w warm-up, then k timed solves with kernel timing on; returns
         (elapsed, Arnoldi steps, last stats, converged, kernel times, update-pass times)"""
-        for _ in range(a.warmup):
+        for _ in range(w):
             c.gmres(s, t, tol=prob.tol, restart=prob.restart, u=u, check_every=a.check_every)
         c.set_timing(True, every=TIMING_EVERY)
         c.kernel_times(reset=True)
@@ -177,7 +227,7 @@ def main():
         torch.cuda.synchronize()
         its = 0
         t0 = time.perf_counter()
-        for _ in range(a.steps):
+        for _ in range(k):
             _, st, ok = c.gmres(s, t, tol=prob.tol, restart=prob.restart, u=u, check_every=a.check_every)
             its += st["iters"]
         torch.cuda.synchronize()
@@ -187,12 +237,12 @@ def main():
         c.set_timing(False)
         return elapsed, its, st, ok, kt, at
 
+    progress(f"{name}: {warmup} + {steps} FP64 solves, separable J^-1")
     u = torch.zeros_like(s)
-    elapsed, its, st, ok, kt, at = timed_solves(ctx, u)
+    elapsed, its, st, ok, kt, at = timed_solves(ctx, u, steps, warmup)
     N = ctx.N
     value = N * its / elapsed / 1e6
-    u_np = u.cpu().numpy()
-    err = oracle_check(a.workload, u_np)
+    err = oracle_check(name, u.cpu().numpy())
 
     # the dominant kernel: the Arnoldi update pass (per step the basis is read once)
     upd_ms = at["update_ms"] / max(1, at["update_launches"])
@@ -200,42 +250,27 @@ def main():
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(a.workload, "k_dcgs_update"),
+                "traffic": read_traffic(name, "k_dcgs_update"),
                 "kernel": "k_dcgs_update (Arnoldi update pass)",
                 "avg_launch_ms": round(upd_ms, 5),
                 "algorithmic_bytes_per_launch": round(upd_bytes)}
     prec_ms = kt["precond_ms"] / max(1, kt["precond_launches"])
     app_ms = kt["apply_ms"] / max(1, kt["apply_launches"])
     sep_gbs = st["bytes_precond"] / (prec_ms * 1e-3) / 1e9
-    precond_kernel = {"kernel": "k_precond_sep (separable J^-1)", "avg_launch_ms": round(prec_ms, 5),
+    app_gbs = st["bytes_apply"] / (app_ms * 1e-3) / 1e9
+    # the apply inside the solve is the sweep alone (k_apply_sweep: x, C in; y and
+    # the face buffer out); the exchange is fused into J^-1's load
+    apply_kernel = {"kernel": "k_apply_sweep (operator sweep; exchange fused into J^-1)",
+                    "avg_launch_ms": round(app_ms, 5),
+                    "munknowns_per_s": round(N / (app_ms * 1e-3) / 1e6, 1),
+                    "algorithmic_bytes_per_launch": st["bytes_apply"],
+                    "algorithmic_GBs": round(app_gbs, 1),
+                    "frac_of_hbm_peak": round(app_gbs / HBM_PEAK_GBS, 4)}
+    precond_kernel = {"kernel": "k_precond_sep (separable J^-1, exchange fused)",
+                      "avg_launch_ms": round(prec_ms, 5),
                       "algorithmic_bytes_per_launch": st["bytes_precond"],
                       "algorithmic_GBs": round(sep_gbs, 1),
                       "frac_of_hbm_peak": round(sep_gbs / HBM_PEAK_GBS, 4)}
-
-    # The paper's form of the same preconditioner: one dense S~^{-1} block per
-    # leaf, streamed from HBM by every J^-1 (the same iteration, the same u up
-    # to rounding); its dominant kernel is that block stream.
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dctx = hps.Context.from_problem(prob, block_precs=("fp64",))
-    torch.cuda.synchronize()
-    d_setup = time.perf_counter() - t0
-    ud = torch.zeros_like(s)
-    d_el, d_its, std_, okd, ktd, _ = timed_solves(dctx, ud)
-    dprec_ms = ktd["precond_ms"] / max(1, ktd["precond_launches"])
-    d_ach = std_["bytes_precond"] / (dprec_ms * 1e-3) / 1e9
-    dense = {"setup_s": round(d_setup, 3), "device_bytes": dctx.device_bytes(),
-             "solve_ms": round(d_el / a.steps * 1e3, 3), "iters_per_solve": d_its / a.steps,
-             "converged": bool(okd), "true_rel_res": std_["true_rel_res"],
-             "err_vs_oracle": oracle_check(a.workload, ud.cpu().numpy()),
-             "value_munknowns_per_s": round(N * d_its / d_el / 1e6, 1),
-             "roofline": {"bound": "hbm", "achieved": round(d_ach, 1), "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": round(d_ach / HBM_PEAK_GBS, 4),
-                          "traffic": read_traffic(a.workload, "k_precond_fused"),
-                          "kernel": "k_precond_fused (FP64 blocks)",
-                          "avg_launch_ms": round(dprec_ms, 5),
-                          "algorithmic_bytes_per_launch": std_["bytes_precond"]}}
-    del dctx, ud
 
     # The same solve in FP64 flexible GMRES with J^-1 in FP64 (separable form) and
     # with FP32 and BF16 stored blocks, all stopped by the same true-residual
@@ -244,25 +279,121 @@ def main():
     mixed = {"tol_true_residual": MIXED_TOL,
              "j_inverse_form": {"fp64": "separable", "fp32": "stored blocks", "bf16": "stored blocks"}}
     for pr in ("fp64", "fp32", "bf16"):
+        progress(f"{name}: FGMRES, {pr} J^-1")
         uu = torch.zeros_like(s)
         ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="fgmres",
                   precond_prec=pr, check_every=a.check_every)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="fgmres",
-                                precond_prec=pr, check_every=a.check_every)
+        for _ in range(reps):
+            _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="fgmres",
+                                    precond_prec=pr, check_every=a.check_every)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
+        dt = (time.perf_counter() - t1) / reps
         mixed[pr] = {"solve_ms": round(dt * 1e3, 2), "solves_per_s": round(1.0 / dt, 2),
                      "iters": st2["iters"], "converged": ok2,
                      "true_rel_res": st2["true_rel_res"],
-                     "err_vs_oracle": oracle_check(a.workload, uu.cpu().numpy())}
+                     "err_vs_oracle": oracle_check(name, uu.cpu().numpy())}
+        del uu
+    # iterative refinement: FP64 residual and update, FP32 inner GMRES (FP32
+    # vectors and basis, separable J^-1), stopped at the same true residual
+    progress(f"{name}: iterative refinement, FP32 inner solves")
+    uu = torch.zeros_like(s)
+    ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="ir", inner_tol=IR_INNER_TOL,
+              check_every=a.check_every)
+    ctx.set_timing(True, every=TIMING_EVERY)
+    ctx.kernel_times(reset=True)
+    ctx.arnoldi_times(reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="ir",
+                                inner_tol=IR_INNER_TOL, check_every=a.check_every)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / reps
+    kti = ctx.kernel_times(reset=True)
+    ati = ctx.arnoldi_times(reset=True)
+    ctx.set_timing(False)
+    i_upd_ms = ati["update_ms"] / max(1, ati["update_launches"])
+    i_upd_gbs = ati["update_bytes"] / max(1, ati["update_launches"]) / (i_upd_ms * 1e-3) / 1e9
+    mixed["ir_fp32_inner"] = {
+        "solve_ms": round(dt * 1e3, 2), "solves_per_s": round(1.0 / dt, 2),
+        "inner_steps": st2["iters"], "refinements": st2["restarts"], "inner_tol": IR_INNER_TOL,
+        "converged": ok2, "true_rel_res": st2["true_rel_res"],
+        "err_vs_oracle": oracle_check(name, uu.cpu().numpy()),
+        "speedup_vs_fp64_fgmres": round(mixed["fp64"]["solve_ms"] / (dt * 1e3), 3),
+        "inner_kernels": {
+            "apply_avg_launch_ms": round(kti["apply_ms"] / max(1, kti["apply_launches"]), 5),
+            "precond_avg_launch_ms": round(kti["precond_ms"] / max(1, kti["precond_launches"]), 5),
+            "arnoldi_update_avg_launch_ms": round(i_upd_ms, 5),
+            "arnoldi_update_algorithmic_GBs": round(i_upd_gbs, 1)}}
+    mixed["j_inverse_form"]["ir_fp32_inner"] = "separable, FP32 vectors"
+    del uu
+    ctx.trim()
 
+    # The paper's form of the same preconditioner: one dense S~^{-1} block per
+    # leaf, streamed from HBM by every J^-1 (the same iteration, the same u up
+    # to rounding); its dominant kernel is that block stream.
+    progress(f"{name}: FP64 stored blocks")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dctx = hps.Context.from_problem(prob, block_precs=("fp64",))
+    torch.cuda.synchronize()
+    d_setup = time.perf_counter() - t0
+    ud = torch.zeros_like(s)
+    d_el, d_its, std_, okd, ktd, _ = timed_solves(dctx, ud, reps, 1)
+    dprec_ms = ktd["precond_ms"] / max(1, ktd["precond_launches"])
+    d_ach = std_["bytes_precond"] / (dprec_ms * 1e-3) / 1e9
+    dense = {"setup_s": round(d_setup, 3), "device_bytes": dctx.device_bytes(),
+             "solve_ms": round(d_el / reps * 1e3, 3), "iters_per_solve": d_its / reps,
+             "converged": bool(okd), "true_rel_res": std_["true_rel_res"],
+             "err_vs_oracle": oracle_check(name, ud.cpu().numpy()),
+             "value_munknowns_per_s": round(N * d_its / d_el / 1e6, 1),
+             "roofline": {"bound": "hbm", "achieved": round(d_ach, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(d_ach / HBM_PEAK_GBS, 4),
+                          "traffic": read_traffic(name, "k_precond_fused"),
+                          "kernel": "k_precond_fused (FP64 blocks)",
+                          "avg_launch_ms": round(dprec_ms, 5),
+                          "algorithmic_bytes_per_launch": std_["bytes_precond"]}}
+    dctx.free()
+    del dctx, ud
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Munknowns/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(elapsed / steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": name, "n_elem": list(prob.n_elem), "p": prob.p, "q": prob.q,
+                   "kappa": prob.kappa, "unknowns": N, "solver": "left-preconditioned GMRES",
+                   "preconditioner": "homogenized block-Jacobi, separable form (exact leaf inverses, no stored blocks)",
+                   "restart": prob.restart, "tol": prob.tol},
+        "iters_per_solve": its / steps, "converged": bool(ok),
+        "true_rel_res": st["true_rel_res"], "err_vs_oracle": err,
+        "setup_s": round(t_setup, 3), "device_bytes": ctx.device_bytes(),
+        "apply_kernel": apply_kernel,
+        "precond_kernel": precond_kernel,
+        "dense_blocks": dense,
+        "mixed_precision_fgmres": mixed,
+        "roofline": roofline,
+    }
+    if extensions:
+        line.update(extension_solves(a, ctx, prob, s, t))
+    ctx.free()
+    return line
+
+
+def extension_solves(a, ctx, prob, s, t) -> dict:
+    """lambda buckets and the face-reduced system on the same system."""
+    import torch
+    from paper_2112_02211_amd import hps
+
+    name = prob.name
     # Extension: lambda buckets (leaves whose homogenized lambda round to the same
     # grid point share one block; J^-1 becomes one GEMM per shared block).  The
     # same system and tolerance; reported beside the main line, not as its value.
     buckets = {}
     for delta in BUCKET_DELTAS:
+        progress(f"{name}: lambda buckets, delta {delta:g}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         bctx = hps.Context.from_problem(prob, lambda_bucket=delta)
@@ -286,11 +417,13 @@ def main():
             "device_bytes": bctx.device_bytes(), "solve_ms": round(dt * 1e3, 2),
             "iters": stb["iters"], "converged": bool(okb), "true_rel_res": stb["true_rel_res"],
             "precond_avg_launch_ms": round(ktb["precond_ms"] / max(1, ktb["precond_launches"]), 5),
-            "err_vs_oracle": oracle_check(a.workload, ub.cpu().numpy())}
+            "err_vs_oracle": oracle_check(name, ub.cpu().numpy())}
+        bctx.free()
         del bctx
 
     # Extension: the face-reduced system with the exact ItI maps of the leaves
     # (unknowns: incoming impedance on the leaf faces; the same discrete u)
+    progress(f"{name}: face-reduced system")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.iti_build()
@@ -314,37 +447,53 @@ def main():
     iti = {"build_s": round(iti_build_s, 3), "device_bytes": hps.iti_bytes(prob.n_elem, prob.p),
            "solve_ms": round(dt * 1e3, 2), "iters": sti["iters"], "converged": bool(oki),
            "face_true_rel_res": sti["true_rel_res"],
-           "err_vs_oracle": oracle_check(a.workload, uf.cpu().numpy()),
+           "err_vs_oracle": oracle_check(name, uf.cpu().numpy()),
            "iti_block_kernel": {"avg_launch_ms": round(r_ms, 5), "algorithmic_GBs": round(r_gbs, 1),
                                 "frac_of_hbm_peak": round(r_gbs / HBM_PEAK_GBS, 4),
                                 "algorithmic_bytes_per_launch": r_bytes}}
     ctx.trim()
+    return {"lambda_buckets": buckets, "iti_face_system": iti}
 
-    line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "Munknowns/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(elapsed / a.steps * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
-        "data": "synthetic",
-        "config": {"workload": a.workload, "n_elem": list(prob.n_elem), "p": prob.p, "q": prob.q,
-                   "kappa": prob.kappa, "unknowns": N, "solver": "left-preconditioned GMRES",
-                   "preconditioner": "homogenized block-Jacobi, separable form (exact leaf inverses, no stored blocks)",
-                   "restart": prob.restart, "tol": prob.tol},
-        "iters_per_solve": its / a.steps, "converged": bool(ok),
-        "true_rel_res": st["true_rel_res"], "err_vs_oracle": err,
-        "setup_s": round(t_setup, 3), "device_bytes": ctx.device_bytes(),
-        "apply_kernel": {"avg_launch_ms": round(app_ms, 5),
-                         "munknowns_per_s": round(N / (app_ms * 1e-3) / 1e6, 1),
-                         "algorithmic_GBs": round(st["bytes_apply"] / (app_ms * 1e-3) / 1e9, 1)},
-        "precond_kernel": precond_kernel,
-        "dense_blocks": dense,
-        "mixed_precision_fgmres": mixed,
-        "lambda_buckets": buckets,
-        "iti_face_system": iti,
-        "roofline": roofline,
-    }
-    if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob)
-    print(json.dumps(line))
+
+def serving_leg(n_requests: int) -> dict:
+    """A bounded run of the serving pattern: the first n_requests of the mixed
+    request stream (meshes 4^3 ... 16^3, p in {8, 10}, 8-12 points per
+    wavelength, 5-20 bumps, one source each), Poisson arrivals at 75 % of the
+    capacity measured on the first quarter of them back to back, served with
+    continuous batching by the separable FP64 operators; solves/s and p50/p99
+    latency."""
+    import dataclasses
+    from paper_2112_02211_amd import problems as P
+    from paper_2112_02211_amd.serve import Server, ServeConfig, latency_stats
+
+    def fresh(rs):
+        return [P.Request(r.rid, r.arrival, dataclasses.replace(r.prob)) for r in rs]
+
+    cfg = ServeConfig(slots=4, block_prec="separable", precond_prec="fp64", solver="fgmres",
+                      restart=50, tol=1e-8)
+    probe = P.request_stream(max(4, n_requests // 4), rate=1.0, seed=5)
+    srv = Server(cfg)
+    res = srv.run(fresh(probe), closed_loop=True)
+    srv.close()
+    cap = latency_stats(res)["solves_per_s"]
+    rate = 0.75 * cap
+    reqs = P.request_stream(n_requests, rate=rate, seed=5)
+    srv = Server(cfg)
+    t0 = time.perf_counter()
+    res = srv.run(fresh(reqs))
+    wall = time.perf_counter() - t0
+    srv.close()
+    st = latency_stats(res)
+    return {"requests": len(res), "served_p50_ms": round(st["p50_ms"], 2),
+            "served_p99_ms": round(st["p99_ms"], 2), "solves_per_s": round(st["solves_per_s"], 3),
+            "capacity_solves_per_s": round(cap, 3), "arrival_rate_per_s": round(rate, 3),
+            "mean_ms": round(st["mean_ms"], 2), "max_batch": st["max_batch"], "jobs": st["jobs"],
+            "all_converged": st["all_converged"], "wall_s": round(wall, 2),
+            "max_true_rel_res": max(r.true_rel_res for r in res),
+            "operator_applies_munknowns_per_s": round(st["operator_applies_munknowns_per_s"], 1),
+            "config": {"meshes": [4, 8, 12, 16], "orders": [8, 10], "ppw": [8, 12], "tol": 1e-8,
+                       "solver": "FGMRES, separable FP64 J^-1; requests on one operator in lock step",
+                       "slots": 4, "arrivals": "Poisson at 75 % of measured capacity", "seed": 5}}
 
 
 def run_bucketed(a, prob):

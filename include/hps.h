@@ -145,6 +145,16 @@ typedef struct {
                                 until all pass; "iters" counts block steps.  HPS_ERR_BREAKDOWN if a
                                 block's columns become linearly dependent (identical right-hand
                                 sides, say): the lock-step solver has no such limit. */
+#define HPS_SOLVER_IR 5      /* iterative refinement: an FP64 outer loop on the true residual
+                                r = b - A x (FP64 operator), each correction d from an inner left-
+                                preconditioned GMRES(m) whose vectors are stored in complex FP32
+                                (basis, operator and J^-1 kernels read and write FP32, arithmetic
+                                FP64 inside), started from 0 on r / ||r|| and stopped at the
+                                preconditioned residual reduction inner_tol; x += ||r|| d in FP64.
+                                Stops when ||r|| <= tol ||b||.  Needs the separable J^-1
+                                (HPS_PREC_SEPARABLE; no operator groups); "iters" counts inner
+                                steps, "restarts" refinement steps; bytes_apply / bytes_precond
+                                are those of the inner FP32 launches. */
 
 typedef struct {
   int solver;          /* HPS_SOLVER_* (default GMRES) */
@@ -156,6 +166,8 @@ typedef struct {
                           1: classical Gram-Schmidt twice (CGS2) */
   double* rhs_rel_res; /* NULL, or host array of nrhs: on return the final relative residual of
                           each right-hand side, in the norm its stopping test uses */
+  double inner_tol;    /* HPS_SOLVER_IR: relative tolerance of each inner FP32 solve (its
+                          preconditioned residual reduction); 0 = 1e-5 */
 } hps_solve_opts;
 
 typedef struct {
@@ -293,6 +305,16 @@ int hps_assemble_rhs(hps_ctx* c, const hps_z* s, const hps_z* t, hps_z* b, int n
  * Returns HPS_OK, HPS_NOT_CONVERGED, or an error. */
 int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol, int restart,
               hps_z* u, int nrhs, const hps_solve_opts* so, hps_stats* st);
+
+/* The inner operators of HPS_SOLVER_IR on vectors stored in complex FP32
+ * (interleaved re, im floats): y = J^{-1} A x (eq. (block_pc) after Algorithm 2,
+ * face exchange fused into J^{-1}) and y = J^{-1} x, with the separable J^{-1};
+ * every kernel widens its loads to FP64, computes in FP64 and rounds its
+ * stores to FP32.  x, y: device, nrhs * N complex64; must not overlap.
+ * Errors: HPS_ERR_ARG (bad arguments, separable J^-1 not built, operator
+ * group), HPS_ERR_OOM, HPS_ERR_DEVICE. */
+int hps_op_left_f32(hps_ctx* c, const void* x, void* y, int nrhs);
+int hps_precond_f32(hps_ctx* c, const void* x, void* y, int nrhs);
 
 /* Kernel timing with HIP events attached to the kernel dispatches themselves
  * (start and end timestamps of the launch) for operator launches (sweep, plus

@@ -573,6 +573,8 @@ void hps_free(hps_ctx* c) {
   hipFree(c->w_g.ptr);
   hipFree(c->w_red.ptr);
   hipFree(c->w_krylov.ptr);
+  hipFree(c->w_krylov32.ptr);
+  hipFree(c->w_ir.ptr);
   hipFree(c->w_small.ptr);
   hipFree(c->w_batch.ptr);
   hipFree(c->w_op.ptr);
@@ -635,8 +637,8 @@ int64_t hps_setup_bytes(int p, const int n_elem[3], int block_precs, int complex
 int hps_trim(hps_ctx* c) {
   if (!c) return fail(HPS_ERR_ARG, "ctx is NULL");
   HPS_TRY_HIP(hipStreamSynchronize(c->stream));
-  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_small, &c->w_batch, &c->w_op, &c->w_b,
-                     &c->w_iti};
+  Workspace* ws[] = {&c->w_g, &c->w_red, &c->w_krylov, &c->w_krylov32, &c->w_ir, &c->w_small,
+                     &c->w_batch, &c->w_op, &c->w_b, &c->w_iti};
   for (Workspace* w : ws) {
     if (w->ptr) {
       HPS_TRY_HIP(hipFree(w->ptr));
@@ -708,6 +710,21 @@ int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec) {
 
 int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
   return hps_precond_prec(c, x, y, nrhs, HPS_PREC_FP64);
+}
+
+int hps_op_left_f32(hps_ctx* c, const void* x, void* y, int nrhs) {
+  if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_op_left_f32");
+  if (c->nop > 1) return fail(HPS_ERR_ARG, "hps_op_left_f32: operator groups are not supported");
+  int rc = ws_reserve(c, &c->w_op, sizeof(float2) * (size_t)c->N * nrhs);
+  if (rc) return rc;
+  return launch_op_left(c, static_cast<const float2*>(x), static_cast<float2*>(c->w_op.ptr),
+                        static_cast<float2*>(y), nrhs);
+}
+
+int hps_precond_f32(hps_ctx* c, const void* x, void* y, int nrhs) {
+  if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_precond_f32");
+  if (c->nop > 1) return fail(HPS_ERR_ARG, "hps_precond_f32: operator groups are not supported");
+  return launch_precond(c, static_cast<const float2*>(x), static_cast<float2*>(y), nrhs);
 }
 
 int hps_op_left(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {

@@ -78,6 +78,16 @@ int job_precond(hps_ctx* c, const Job& job, const double2* x, double2* y, int nb
 int job_op_left(hps_ctx* c, const Job& job, const double2* x, double2* tmp, double2* y, int nb) {
   return job.face ? launch_iti_apply(c, x, y, nb) : launch_op_left(c, x, tmp, y, nb, job.prec);
 }
+// vectors in FP32 (the inner solve of iterative refinement): A and the separable J^{-1}
+int job_apply(hps_ctx* c, const Job&, const float2* x, float2* y, int nb) {
+  return launch_apply(c, x, y, nb);
+}
+int job_precond(hps_ctx* c, const Job&, const float2* x, float2* y, int nb) {
+  return launch_precond(c, x, y, nb);
+}
+int job_op_left(hps_ctx* c, const Job&, const float2* x, float2* tmp, float2* y, int nb) {
+  return launch_op_left(c, x, tmp, y, nb);
+}
 
 // Algorithmic bytes of the timed apply and preconditioner launches of a solve.
 // Left preconditioning with fewer than kBatchedMinRhs right-hand sides fuses
@@ -314,25 +324,29 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
 // (F)GMRES(m) with the delayed-reorthogonalization Arnoldi process (two passes
 // over the basis per step, see hps_krylov.h); m <= kMaxDcgs.  Same stopping
 // rules, restart policy and pipelined residual checks as run_gmres.
-int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m, int maxit,
+// VT: storage of the vectors (complex FP64, or complex FP32 for the inner solve
+// of iterative refinement, whose basis lives in its own workspace).
+template <typename VT>
+int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, int maxit,
              int use_x0, int check_every, hps_stats* st) {
   const int64_t N = job.n;
   const int nb = job.nrhs;
   const int64_t NB = N * nb;
-  const size_t vec_bytes = sizeof(double2) * NB;
+  const size_t vec_bytes = sizeof(VT) * NB;
   // V (m), candidate U, operator image W, TMP, Z' (m, flexible)
   const size_t need = vec_bytes * ((size_t)m + 3 + (job.flexible ? m : 0));
-  int rc = ws_reserve(c, &c->w_krylov, need);
+  Workspace* wk = sizeof(VT) == sizeof(double2) ? &c->w_krylov : &c->w_krylov32;
+  int rc = ws_reserve(c, wk, need);
   if (rc) return rc;
   rc = ws_reserve(c, &c->w_small, sizeof(DcgsState) * nb + 6 * sizeof(double) * nb);
   if (rc) return rc;
   RedBuf rb;
   if ((rc = red_buf(c, kMaxDcgs + 1, nb, &rb))) return rc;
-  double2* V = static_cast<double2*>(c->w_krylov.ptr);
-  double2* U = V + (size_t)m * NB;
-  double2* W = U + NB;
-  double2* TMP = W + NB;
-  double2* Z = job.flexible ? TMP + NB : nullptr;
+  VT* V = static_cast<VT*>(wk->ptr);
+  VT* U = V + (size_t)m * NB;
+  VT* W = U + NB;
+  VT* TMP = W + NB;
+  VT* Z = job.flexible ? TMP + NB : nullptr;
   DcgsState* S = static_cast<DcgsState*>(c->w_small.ptr);
   double* d_res = reinterpret_cast<double*>(S + nb);   // 4 doubles per rhs (last column)
   double* d_nrm = d_res + 4 * nb;                        // norms^2 per rhs
@@ -447,8 +461,8 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
       if (!job.flexible) {
         if ((rc = job_op_left(c, job, U, TMP, W, nb))) return rc;
       } else {
-        if ((rc = launch_precond(c, U, Zj(j), nb, job.prec))) return rc;
-        if ((rc = launch_apply(c, Zj(j), W, nb))) return rc;
+        if ((rc = job_precond(c, job, U, Zj(j), nb))) return rc;
+        if ((rc = job_apply(c, job, Zj(j), W, nb))) return rc;
       }
       if ((rc = launch_dcgs_reduce(c, V, NB, N, j, U, N, W, N, N, S, nb, rb))) return rc;
       const int slot = j & 1;
@@ -481,8 +495,8 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
     if ((rc = launch_dcgs_reduce(c, V, NB, N, written, U, N, nullptr, 0, N, S, nb, rb))) return rc;
     if ((rc = launch_dcgs_small(c, S, nb, written, job.flexible ? 1 : 0, 1, d_res, 0))) return rc;
     if ((rc = launch_dcgs_trisolve(c, S, nb, written, job.flexible ? 1 : 0))) return rc;
-    if ((rc = launch_mupdate_b(c, job.flexible ? Z : V, NB, N, written, S[0].y, sst, 1.0, x, N, N,
-                               nullptr, 0, nb, rb)))
+    if ((rc = launch_mupdate_b(c, (const VT*)(job.flexible ? Z : V), NB, N, written, S[0].y, sst, 1.0,
+                               x, N, N, nullptr, 0, nb, rb)))
       return rc;
     ++restarts;
     if ((rc = residual(false))) return rc;
@@ -514,6 +528,94 @@ int run_dcgs(hps_ctx* c, const Job& job, const double2* b, double2* x, double to
   return all_done() ? HPS_OK : HPS_NOT_CONVERGED;
 }
 
+// Iterative refinement (one right-hand side): an FP64 outer loop on the true
+// residual r = b - A x (FP64 apply), each correction from an inner left-
+// preconditioned GMRES(m) with the delayed-reorthogonalization Arnoldi whose
+// vectors (basis, candidate, operator image) are stored in complex FP32, with
+// the FP32-storage A and the separable J^{-1}, started from 0 on r / ||r||
+// and stopped at the preconditioned residual reduction inner_tol; then
+// x += ||r|| d in FP64.  Stops when ||b - A x|| <= tol ||b||, when the
+// residual stops decreasing, or after maxit inner steps.
+int run_ir(hps_ctx* c, const double2* b, double2* x, double tol, int m, int maxit, int use_x0,
+           int check_every, double inner_tol, double* rhs_res, hps_stats* st) {
+  const int64_t N = c->N;
+  int rc = ws_reserve(c, &c->w_ir, sizeof(double2) * N + 2 * sizeof(float2) * N + 64);
+  if (rc) return rc;
+  double2* r = static_cast<double2*>(c->w_ir.ptr);
+  float2* r32 = reinterpret_cast<float2*>(r + N);
+  float2* d32 = r32 + N;
+  double* d_nrm = reinterpret_cast<double*>(d32 + N);
+  RedBuf rb;
+  if ((rc = red_buf(c, kMaxDcgs + 1, 1, &rb))) return rc;
+  void* hp = nullptr;
+  if ((rc = pinned(c, &hp))) return rc;
+  double* hn = static_cast<double*>(hp) + 4096;   // past the inner solve's records
+  auto norm = [&](const double2* v, double* out) -> int {
+    int e = launch_norm2_b(c, v, N, N, d_nrm, 1, 1, rb);
+    if (e) return e;
+    HPS_TRY_HIP(hipMemcpyAsync(hn, d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HPS_TRY_HIP(hipStreamSynchronize(c->stream));
+    *out = std::sqrt(*hn);
+    if (!std::isfinite(*out)) return fail(HPS_ERR_NUMERIC, "non-finite residual norm (NaN or Inf in the data)");
+    return HPS_OK;
+  };
+  auto residual = [&]() -> int {   // r = b - A x
+    int e = launch_apply(c, x, r, 1);
+    if (e) return e;
+    return launch_sub_from(c, b, r, N);
+  };
+  const double t0 = now();
+  double bn = 0.0, rn = 0.0;
+  if ((rc = norm(b, &bn))) return rc;
+  if (use_x0) {
+    if ((rc = residual())) return rc;
+  } else {
+    HPS_TRY_HIP(hipMemsetAsync(x, 0, sizeof(double2) * N, c->stream));
+    HPS_TRY_HIP(hipMemcpyAsync(r, b, sizeof(double2) * N, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if ((rc = norm(r, &rn))) return rc;
+  Job job;
+  job.flexible = false;
+  job.prec = kFP64;
+  job.n = N;
+  job.nrhs = 1;
+  int its = 0, outer = 0;
+  double prev = HUGE_VAL;
+  bool done = bn == 0.0 || rn <= tol * bn;
+  while (!done && its < maxit && rn < prev) {
+    if ((rc = launch_demote_scaled(c, r, 1.0 / rn, r32, N))) return rc;
+    hps_stats one{};
+    const int inner_max = std::max(m, std::min(maxit - its, 40 * m));
+    const int r1 = run_dcgs<float2>(c, job, r32, d32, inner_tol, m, inner_max, 0, check_every, &one);
+    if (r1 < 0) return r1;
+    its += one.iters;
+    ++outer;
+    if ((rc = launch_axpy_promote(c, rn, d32, x, N))) return rc;
+    if ((rc = residual())) return rc;
+    prev = rn;
+    if ((rc = norm(r, &rn))) return rc;
+    done = rn <= tol * bn;
+  }
+  const double rel = bn > 0.0 ? rn / bn : 0.0;
+  if (rhs_res) *rhs_res = rel;
+  if (st) {
+    st->iters = its;
+    st->restarts = outer;
+    st->converged = done ? 1 : 0;
+    st->lambda_shifted = c->n_shifted;
+    st->t_setup = c->t_setup;
+    st->rel_res = rel;
+    st->true_rel_res = rel;
+    st->t_solve = now() - t0;
+    // the inner step's launches: the sweep (x in and y out in FP32, C, the FP32
+    // face buffer written) and J^{-1} (y in and out in FP32, the face buffer read)
+    const double face = 8.0 * c->nl * (double)c->nb;
+    st->bytes_apply = 16.0 * N + (c->c_complex ? 16.0 : 8.0) * c->nl * c->ni + face;
+    st->bytes_precond = 16.0 * N + face;
+  }
+  return done ? HPS_OK : HPS_NOT_CONVERGED;
+}
+
 int run_solver(hps_ctx* c, const Job& job, const double2* b, double2* x, double tol, int m,
                int maxit, int use_x0, int check_every, int orth, hps_stats* st) {
   if (orth == 0 && m <= kMaxDcgs)
@@ -536,6 +638,14 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
     int64_t bytes = vf * (restart + 3) + 2 * vf + iti_ws_bytes(c, 1) + vf;
     bytes += (int64_t)sizeof(GmresState) + 32 + (int64_t)kPartSlots * kRedBlocks * 16;
     bytes += 16 * c->N * nrhs;
+    return bytes;
+  }
+  if (o.solver == HPS_SOLVER_IR) {
+    // FP64 residual, FP32 residual and correction; the inner FP32 basis, U, W
+    // and TMP; the FP64 face buffer; the small state, the reduction partials, b
+    int64_t bytes = 16 * c->N + 2 * 8 * c->N + 64 + 8 * c->N * (int64_t)(restart + 3);
+    bytes += 16 * c->nl * (int64_t)c->nb + (int64_t)sizeof(DcgsState) + 6 * 8 + 8;
+    bytes += (int64_t)kPartSlots * kRedBlocks * 16 + 16 * c->N * nrhs;
     return bytes;
   }
   const bool fp64_pc = o.precond_prec == 0 || o.precond_prec == HPS_PREC_FP64 ||
@@ -581,7 +691,16 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     return fail(HPS_ERR_ARG, "unknown precond_prec");
   if (!c->blk[prec].data && !(prec == kFP64 && c->sep))
     return fail(HPS_ERR_ARG, "precond_prec blocks were not built at setup");
-  if (o.solver < 0 || o.solver > 4) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver < 0 || o.solver > 5) return fail(HPS_ERR_ARG, "unknown solver");
+  if (o.solver == HPS_SOLVER_IR) {
+    if (!c->sep) return fail(HPS_ERR_ARG, "iterative refinement needs the separable J^-1 (HPS_PREC_SEPARABLE)");
+    if (c->nop > 1) return fail(HPS_ERR_UNSUPPORTED, "iterative refinement: operator groups are not supported");
+    if (o.precond_prec != 0 && o.precond_prec != HPS_PREC_FP64 && o.precond_prec != HPS_PREC_SEPARABLE)
+      return fail(HPS_ERR_ARG, "iterative refinement runs the separable J^-1 (precond_prec must be 0)");
+    if (o.inner_tol < 0.0 || !(o.inner_tol < 1.0))
+      return fail(HPS_ERR_ARG, "inner_tol must lie in [0, 1)");
+    if (restart > kMaxDcgs) return fail(HPS_ERR_ARG, "iterative refinement: restart must be at most 64");
+  }
   if (o.solver == HPS_SOLVER_BGMRES) {
     if (prec != kFP64) return fail(HPS_ERR_ARG, "block GMRES runs the FP64 preconditioner");
     if (c->nop > 1) return fail(HPS_ERR_UNSUPPORTED, "block GMRES: operator groups run lock-step");
@@ -640,6 +759,28 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     acc.converged = rc == HPS_OK;
     acc.lambda_shifted = c->n_shifted;
       acc.t_setup = c->t_setup;
+    if (st) *st = acc;
+  } else if (rc == HPS_OK && o.solver == HPS_SOLVER_IR) {
+    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
+    hps_stats acc{};
+    for (int r = 0; r < nrhs; ++r) {
+      hps_stats one{};
+      const int r1 = run_ir(c, bvec + (size_t)r * c->N, x + (size_t)r * c->N, tol, restart, maxit,
+                            o.use_x0, check_every, itol, o.rhs_rel_res ? o.rhs_rel_res + r : nullptr,
+                            &one);
+      if (r1 < 0) { rc = r1; break; }
+      if (r1 == HPS_NOT_CONVERGED) rc = r1;
+      acc.iters += one.iters;
+      acc.restarts += one.restarts;
+      acc.rel_res = std::max(acc.rel_res, one.rel_res);
+      acc.true_rel_res = std::max(acc.true_rel_res, one.true_rel_res);
+      acc.t_solve += one.t_solve;
+      acc.bytes_apply = one.bytes_apply;
+      acc.bytes_precond = one.bytes_precond;
+    }
+    acc.converged = rc == HPS_OK;
+    acc.lambda_shifted = c->n_shifted;
+    acc.t_setup = c->t_setup;
     if (st) *st = acc;
   } else if (rc == HPS_OK && o.solver == HPS_SOLVER_BGMRES) {
     rc = run_block_gmres(c, prec, bvec, x, nrhs, tol, restart, maxit, o.use_x0 != 0, o.rhs_rel_res, st);

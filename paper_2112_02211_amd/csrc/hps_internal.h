@@ -128,6 +128,8 @@ struct hps_ctx {
   hps::Workspace w_g;               // outgoing impedance buffer
   hps::Workspace w_red;             // reduction partials + counters
   hps::Workspace w_krylov;          // Krylov bases etc.
+  hps::Workspace w_krylov32;        // FP32 Krylov basis of the inner solve of iterative refinement
+  hps::Workspace w_ir;              // iterative refinement: FP64 residual, FP32 residual and correction
   hps::Workspace w_small;           // Hessenberg / Givens state
   hps::Workspace w_batch;           // many-rhs preconditioner: H and U panels
   hps::Workspace w_op;              // A x inside hps_op_left
@@ -212,9 +214,18 @@ int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec)
 // kBatchedMinRhs or more right-hand sides and dense blocks: launch_apply, then
 // launch_precond (the separable form is fused for any nrhs).
 int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int nrhs, int prec);
+// vectors stored in complex FP32 (the inner solve of iterative refinement):
+// A x (sweep and exchange), J^{-1} A x and J^{-1} x with the separable J^{-1};
+// FP64 arithmetic inside the kernels
+int launch_apply(hps_ctx* c, const float2* x, float2* y, int nrhs);
+int launch_op_left(hps_ctx* c, const float2* x, float2* tmp, float2* y, int nrhs);
+int launch_precond(hps_ctx* c, const float2* x, float2* y, int nrhs);
 // the sweep alone: y = A x without the neighbours' outgoing impedance, which
 // goes to g ([rhs][leaf][6][q^2]); e0 / e1 as in launch_k
 int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
+                 hipEvent_t e1);
+// the same with vectors stored in complex FP32 (FP64 arithmetic inside)
+int launch_sweep(hps_ctx* c, const float2* x, float2* y, float2* g, int nrhs, hipEvent_t e0,
                  hipEvent_t e1);
 // J^{-1} (y + exchange(g)) for nrhs < kBatchedMinRhs; g == null: J^{-1} y
 int launch_precond_fused(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
@@ -224,6 +235,8 @@ int run_block_gmres(hps_ctx* c, int prec, const double2* b, double2* x, int k, d
                     int maxit, bool use_x0, double* rhs_res, hps_stats* st);
 // J^{-1} (y + exchange(g)) in the separable form (no blocks; any nrhs); g == null: J^{-1} y
 int launch_precond_sep(hps_ctx* c, const double2* y, const double2* g, double2* z, int nrhs,
+                       hipEvent_t e0, hipEvent_t e1);
+int launch_precond_sep(hps_ctx* c, const float2* y, const float2* g, float2* z, int nrhs,
                        hipEvent_t e0, hipEvent_t e1);
 // many right-hand sides: block product as a GEMM on the matrix cores; with lambda
 // buckets (any nrhs) one GEMM per bucket over all its leaves' columns
@@ -283,5 +296,6 @@ int launch_scale_by(hps_ctx* c, const double2* x, double2* y, int64_t n, const d
                     int inv_sqrt);
 // y = a - y
 int launch_sub_from(hps_ctx* c, const double2* a, double2* y, int64_t n);
+int launch_sub_from(hps_ctx* c, const float2* a, float2* y, int64_t n);
 
 }  // namespace hps

@@ -33,6 +33,15 @@ int launch_mdot_b(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K,
 int launch_mupdate_b(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K,
                      const double2* coef, int64_t cbs, double sign, double2* w, int64_t wbs,
                      int64_t n, double* nrm2, int64_t nstride, int nbatch, const RedBuf& rb);
+// vectors stored in complex FP32: x += sign V coef, and squared norms (FP64 sums)
+int launch_mupdate_b(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K,
+                     const double2* coef, int64_t cbs, double sign, float2* w, int64_t wbs,
+                     int64_t n, double* nrm2, int64_t nstride, int nbatch, const RedBuf& rb);
+int launch_norm2_b(hps_ctx* c, const float2* w, int64_t wbs, int64_t n, double* nrm2, int64_t nbs,
+                   int nbatch, const RedBuf& rb);
+// y = demote(s * x) (complex FP64 to FP32) and y += s * promote(x) (FP32 into FP64)
+int launch_demote_scaled(hps_ctx* c, const double2* x, double s, float2* y, int64_t n);
+int launch_axpy_promote(hps_ctx* c, double s, const float2* x, double2* y, int64_t n);
 int launch_norm2_b(hps_ctx* c, const double2* w, int64_t wbs, int64_t n, double* nrm2, int64_t nbs,
                    int nbatch, const RedBuf& rb);
 int launch_scale_by_b(hps_ctx* c, const double2* x, int64_t xbs, double2* y, int64_t ybs, int64_t n,
@@ -87,6 +96,10 @@ struct DcgsState {
 int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int J,
                        const double2* u, int64_t ubs, const double2* w, int64_t wbs, int64_t n,
                        DcgsState* S, int nbatch, const RedBuf& rb);
+// the same over vectors stored in complex FP32 (sums in FP64)
+int launch_dcgs_reduce(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int J,
+                       const float2* u, int64_t ubs, const float2* w, int64_t wbs, int64_t n,
+                       DcgsState* S, int nbatch, const RedBuf& rb);
 // standalone small step (one workgroup per right-hand side); final_only: only close column j-1
 int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible, int final_only,
                       double* res_out, uint64_t tag);
@@ -97,6 +110,9 @@ int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible,
 // release; res_out may be pinned host memory)
 int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
                        int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
+                       int nbatch, int flexible, double* res_out, uint64_t tag);
+int launch_dcgs_update(hps_ctx* c, float2* V, int64_t ldv, int64_t vbs, int J, float2* u,
+                       int64_t ubs, const float2* w, int64_t wbs, int64_t n, DcgsState* S,
                        int nbatch, int flexible, double* res_out, uint64_t tag);
 int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch);
 // y = R^{-1} gls over the finished columns (at most kmax); flexible: y <- T y

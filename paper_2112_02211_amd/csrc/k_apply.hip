@@ -18,27 +18,51 @@
 // order on both sides, so no permutation is needed.
 #include "hps_internal.h"
 #include "k_common.h"
+#include "k_vec.h"
 
 namespace hps {
 namespace {
 
-// Axis-pass form per order, from measurement (the apply over about 4 million
-// unknowns for every p = 4 ... 16, both forms): line-wise (a thread owns a grid
-// line and SR of its outputs, its p inputs in registers, the table rows uniform
-// across a wavefront and read through the scalar cache, x-lines padded to p + 1
-// in LDS) was 3-19 % faster at p = 8, 9, 12, 13, 14 and 16; element-parallel (a
-// thread owns one output, inputs and table entries from LDS) 1-31 % faster at
-// the other orders.
+// config begin
+// Per order: the axis-pass form, the workgroup size and the waves per SIMD the
+// register budget must leave room for (so that several leaves share a CU and
+// one leaf's loads overlap another's arithmetic).  Forms, from measurement (the
+// apply over about 4 million unknowns for every p = 4 ... 16): line-wise (a
+// thread owns a grid line and SR of its outputs, its p inputs in registers,
+// the table rows uniform across a wavefront and read through the scalar cache,
+// x-lines padded to p + 1 in LDS) was 3-19 % faster at p = 8, 9, 12, 13, 14
+// and 16; element-parallel (a thread owns one output, inputs and table entries
+// from LDS) 1-31 % faster at the other orders; single-pass (one thread per
+// output sums all three axes from the LDS grid, no accumulator tensor) 5 %
+// faster at p = 15.
+enum { kSweepElem = 0, kSweepLine = 1, kSweepSingle = 2 };
 template <int P>
-constexpr bool kSweepLineWise = (P == 8 || P == 9 || P == 12 || P == 13 || P == 14 || P == 16);
+constexpr int kSweepForm = P == 15 ? kSweepSingle
+                         : (P == 8 || P == 9 || P == 12 || P == 13 || P == 14 || P == 16) ? kSweepLine
+                                                                                          : kSweepElem;
+template <int P>
+constexpr int kSweepThreads = kSweepForm<P> == kSweepSingle ? 512
+                            : (P - 2) * (P - 2) * P >= 1024 ? 1024 : ((P - 2) * (P - 2) * P + 63) / 64 * 64;
+template <int P>
+constexpr int kSweepMinWaves = kSweepForm<P> == kSweepSingle ? 4 : 1;
+template <int P>
+constexpr int kSweepOutputs = 2;   // line-wise: outputs of a line per work item
+// p = 12 (16^3 leaves): 512 threads, three outputs per work item (one work item
+// per wavefront and axis) and registers for six waves per SIMD, so that three
+// leaves share a CU; 80 us against 119 us for the apply with 1024 threads (one
+// leaf per CU), the best of six shapes measured
+template <> constexpr int kSweepThreads<12> = 512;
+template <> constexpr int kSweepMinWaves<12> = 6;
+template <> constexpr int kSweepOutputs<12> = 3;
+// config end
 
 template <int P>
 struct Leaf {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
-  static constexpr bool LW = kSweepLineWise<P>;
+  static constexpr bool LW = kSweepForm<P> == kSweepLine;
   static constexpr int P1 = LW ? P + 1 : P;          // LDS length of an x-line
   static constexpr int GS = P * P * P1;               // LDS grid size
-  static constexpr int SR = 2, SG = (P + SR - 1) / SR, SWPG = (L + 63) / 64, SW = SG * SWPG;
+  static constexpr int SR = kSweepOutputs<P>, SG = (P + SR - 1) / SR, SWPG = (L + 63) / 64, SW = SG * SWPG;
   // LDS grid index of grid point (i, j, k)
   __device__ static __forceinline__ int gidx(int i, int j, int k) { return (k * P + j) * P1 + i; }
   // LDS grid index of local node m
@@ -62,13 +86,6 @@ struct Leaf {
   }
 };
 
-// Workgroup size: one thread per (line, output) work item of an axis pass,
-// L lines of P outputs each, at most 1024 threads.
-template <int P>
-constexpr int sweep_threads() {
-  return (P - 2) * (P - 2) * P >= 1024 ? 1024 : ((P - 2) * (P - 2) * P + 63) / 64 * 64;
-}
-
 // One axis pass over the lines of one leaf, AX = 0, 1, 2 (x, y, z).  Work item
 // (line, o) contracts the line's p values with row o of R: o = 0 and o = p-1 are
 // the line's two face outputs (outward normal derivative, the end rows of D),
@@ -78,16 +95,16 @@ constexpr int sweep_threads() {
 // buffer read by the neighbour).
 // Output o of the line through (a, b) along AX, s = row o of R times the line:
 // a face output goes to y and to the face buffer, an interior one into ACC.
-template <int P, int AX>
+template <int P, int AX, typename T>
 __device__ __forceinline__ void axis_out(double2 s, double2 ue, int o, int line, int a, int b,
                                          double2* __restrict__ ACC, double eta,
-                                         double2* __restrict__ yv, double2* __restrict__ gv) {
+                                         T* __restrict__ yv, T* __restrict__ gv) {
   using Lf = Leaf<P>;
   constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI;
   if (o == 0 || o == P - 1) {
     const int f = 2 * AX + (o ? 1 : 0);
-    yv[NI + f * L + line] = make_double2(s.x - eta * ue.y, s.y + eta * ue.x);
-    gv[f * L + line] = make_double2(s.x + eta * ue.y, s.y - eta * ue.x);
+    st2(yv, NI + f * L + line, make_double2(s.x - eta * ue.y, s.y + eta * ue.x));
+    st2(gv, f * L + line, make_double2(s.x + eta * ue.y, s.y - eta * ue.x));
   } else {
     int m;
     if (AX == 0) m = (o - 1) + N1 * (a - 1) + L * (b - 1);
@@ -98,12 +115,12 @@ __device__ __forceinline__ void axis_out(double2 s, double2 ue, int o, int line,
   }
 }
 
-template <int P, int AX>
+template <int P, int AX, typename T>
 __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2* __restrict__ ACC,
                                           const double* __restrict__ R, const double* __restrict__ tab,
-                                          double eta, double2* __restrict__ yv, double2* __restrict__ gv) {
+                                          double eta, T* __restrict__ yv, T* __restrict__ gv) {
   using Lf = Leaf<P>;
-  constexpr int N1 = Lf::N1, L = Lf::L, BD = sweep_threads<P>();
+  constexpr int N1 = Lf::N1, L = Lf::L, BD = kSweepThreads<P>;
   if constexpr (Lf::LW) {
     // line-wise: rows of R (o = 0: -D[0][.], o = p-1: D[p-1][.], else -D2[o][.])
     // straight from the table, at wavefront-uniform addresses
@@ -130,7 +147,7 @@ __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2
         double2 s = make_double2(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < P; ++q) cfma_r(s, sg * row[q], v[q]);
-        axis_out<P, AX>(s, o == 0 ? v[0] : v[P - 1], o, line, a, b, ACC, eta, yv, gv);
+        axis_out<P, AX, T>(s, o == 0 ? v[0] : v[P - 1], o, line, a, b, ACC, eta, yv, gv);
       }
     }
   } else {
@@ -143,56 +160,63 @@ __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2
 #pragma unroll
       for (int q = 0; q < P; ++q) cfma_r(s, R[o * P + q], U[base + q * stride]);
       const double2 ue = (o == 0 || o == P - 1) ? U[base + o * stride] : make_double2(0.0, 0.0);
-      axis_out<P, AX>(s, ue, o, line, a, b, ACC, eta, yv, gv);
+      axis_out<P, AX, T>(s, ue, o, line, a, b, ACC, eta, yv, gv);
     }
   }
 }
 
-template <int P, bool CC>
-__global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
-    const double2* __restrict__ x, double2* __restrict__ y, double2* __restrict__ g,
+// Every load of the leaf is issued before the first LDS store, in rounds of up
+// to eight loads per thread held in named registers (an indexed array would be
+// placed in LDS or scratch by the compiler), then stored to their grid slots.
+template <int P, int BD, int R0, typename T>
+__device__ __forceinline__ void stage_leaf(const T* __restrict__ xv, double2* __restrict__ U) {
+  using Lf = Leaf<P>;
+  constexpr int NN = Lf::NN, NLOAD = (NN + BD - 1) / BD;
+  const int m0 = threadIdx.x + R0 * BD;
+  double2 t0, t1, t2, t3, t4, t5, t6, t7;
+#define HPS_LD(k, t) if constexpr (R0 + k < NLOAD) { if ((R0 + k + 1) * BD <= NN || m0 + k * BD < NN) t = ld2(xv, m0 + k * BD); }
+#define HPS_ST(k, t) if constexpr (R0 + k < NLOAD) { if ((R0 + k + 1) * BD <= NN || m0 + k * BD < NN) U[Lf::grid_of(m0 + k * BD)] = t; }
+  HPS_LD(0, t0) HPS_LD(1, t1) HPS_LD(2, t2) HPS_LD(3, t3)
+  HPS_LD(4, t4) HPS_LD(5, t5) HPS_LD(6, t6) HPS_LD(7, t7)
+  HPS_ST(0, t0) HPS_ST(1, t1) HPS_ST(2, t2) HPS_ST(3, t3)
+  HPS_ST(4, t4) HPS_ST(5, t5) HPS_ST(6, t6) HPS_ST(7, t7)
+#undef HPS_LD
+#undef HPS_ST
+  if constexpr (R0 + 8 < NLOAD) stage_leaf<P, BD, R0 + 8, T>(xv, U);
+}
+
+template <int P, bool CC, typename T>
+__global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_sweep(
+    const T* __restrict__ x, T* __restrict__ y, T* __restrict__ g,
     const void* __restrict__ Cv, const double* __restrict__ tab, double eta, int64_t nl, int64_t N,
     int64_t cs, const double* __restrict__ etas) {
   using Lf = Leaf<P>;
   constexpr int NI = Lf::NI, NN = Lf::NN, NB = Lf::NB;
-  constexpr int BD = sweep_threads<P>();
+  constexpr int BD = kSweepThreads<P>;
   __shared__ double2 U[Lf::GS];
   __shared__ double2 ACC[NI];
   __shared__ double R[P * P];
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
-  const double2* xv = x + rhs * N + tau * NN;
-  double2* yv = y + rhs * N + tau * NN;
-  double2* gv = g + (rhs * nl + tau) * NB;
+  const T* xv = x + rhs * N + tau * NN;
+  T* yv = y + rhs * N + tau * NN;
+  T* gv = g + (rhs * nl + tau) * NB;
   const double* D = tab + tab_off_D(P);
   const double* D2 = tab + tab_off_D2(P);
   // operator groups: right-hand side rhs belongs to operator rhs (its C and eta)
   if (etas) eta = etas[rhs];
   const int64_t cb = rhs * cs + tau * NI;
-  // every load of the leaf is issued before the first LDS store (named
-  // registers, not an array, so that the staging stays in VGPRs)
-  constexpr int NLOAD = (NN + BD - 1) / BD;
-  static_assert(NLOAD <= 4, "leaf larger than four loads per thread");
-  const int m0 = threadIdx.x, m1 = m0 + BD, m2 = m1 + BD, m3 = m2 + BD;
-  double2 t0, t1, t2, t3;
-  if (m0 < NN) t0 = xv[m0];
-  if (NLOAD > 1 && m1 < NN) t1 = xv[m1];
-  if (NLOAD > 2 && m2 < NN) t2 = xv[m2];
-  if (NLOAD > 3 && m3 < NN) t3 = xv[m3];
   for (int k = threadIdx.x; k < P * P; k += BD) {
     const int o = k / P, q = k - o * P;
     R[k] = (o == 0) ? -D[q] : (o == P - 1) ? D[(P - 1) * P + q] : -D2[k];
   }
-  if (m0 < NN) U[Lf::grid_of(m0)] = t0;
-  if (NLOAD > 1 && m1 < NN) U[Lf::grid_of(m1)] = t1;
-  if (NLOAD > 2 && m2 < NN) U[Lf::grid_of(m2)] = t2;
-  if (NLOAD > 3 && m3 < NN) U[Lf::grid_of(m3)] = t3;
+  stage_leaf<P, BD, 0, T>(xv, U);
   __syncthreads();
-  axis_pass<P, 0>(U, ACC, R, tab, eta, yv, gv);
+  axis_pass<P, 0, T>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
-  axis_pass<P, 1>(U, ACC, R, tab, eta, yv, gv);
+  axis_pass<P, 1, T>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
-  axis_pass<P, 2>(U, ACC, R, tab, eta, yv, gv);
+  axis_pass<P, 2, T>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
   // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat))
   for (int m = threadIdx.x; m < NI; m += BD) {
@@ -200,32 +224,28 @@ __global__ __launch_bounds__(sweep_threads<P>()) void k_apply_sweep(
     double2 cu;
     if (CC) cu = cmul(static_cast<const double2*>(Cv)[cb + m], v);
     else cu = cscale(v, static_cast<const double*>(Cv)[cb + m]);
-    yv[m] = make_double2(acc.x - cu.x, acc.y - cu.y);
+    st2(yv, m, make_double2(acc.x - cu.x, acc.y - cu.y));
   }
 }
 
 // Single-pass form: one thread per output computes all three axis sums from the
-// LDS grid at once, so there is no accumulator tensor and two workgroups share
-// a CU at large p (the other forms keep one there).  Measured 5 % faster than
-// element-parallel at p = 15, 5 % slower than line-wise at p = 16.
-template <int P> constexpr bool kSweepFused = (P == 15);
-constexpr int kFusedThreads = 512;
-
-template <int P, bool CC>
-__global__ __launch_bounds__(kFusedThreads, 4) void k_apply_sweep_fe(
-    const double2* __restrict__ x, double2* __restrict__ y, double2* __restrict__ g,
+// LDS grid at once, so there is no accumulator tensor and more workgroups share
+// a CU.
+template <int P, bool CC, typename T>
+__global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_sweep_fe(
+    const T* __restrict__ x, T* __restrict__ y, T* __restrict__ g,
     const void* __restrict__ Cv, const double* __restrict__ tab, double eta, int64_t nl, int64_t N,
     int64_t cs, const double* __restrict__ etas) {
   using Lf = Leaf<P>;
-  constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI, NN = Lf::NN, NB = Lf::NB, BD = kFusedThreads;
+  constexpr int N1 = Lf::N1, L = Lf::L, NI = Lf::NI, NN = Lf::NN, NB = Lf::NB, BD = kSweepThreads<P>;
   constexpr int RP = P + 1;   // padded rows of the table: lanes reading rows i, i + 1 hit other banks
   __shared__ double2 U[Lf::GS];
   __shared__ double R[P * RP];
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
-  const double2* xv = x + rhs * N + tau * NN;
-  double2* yv = y + rhs * N + tau * NN;
-  double2* gv = g + (rhs * nl + tau) * NB;
+  const T* xv = x + rhs * N + tau * NN;
+  T* yv = y + rhs * N + tau * NN;
+  T* gv = g + (rhs * nl + tau) * NB;
   const double* D = tab + tab_off_D(P);
   const double* D2 = tab + tab_off_D2(P);
   if (etas) eta = etas[rhs];
@@ -234,7 +254,7 @@ __global__ __launch_bounds__(kFusedThreads, 4) void k_apply_sweep_fe(
     const int o = k / P, q = k - o * P;
     R[o * RP + q] = (o == 0) ? -D[q] : (o == P - 1) ? D[(P - 1) * P + q] : -D2[k];
   }
-  for (int m = threadIdx.x; m < NN; m += BD) U[Lf::grid_of(m)] = xv[m];
+  stage_leaf<P, BD, 0, T>(xv, U);
   __syncthreads();
   // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat))
   for (int m = threadIdx.x; m < NI; m += BD) {
@@ -250,7 +270,7 @@ __global__ __launch_bounds__(kFusedThreads, 4) void k_apply_sweep_fe(
     double2 cu;
     if (CC) cu = cmul(static_cast<const double2*>(Cv)[cb + m], v);
     else cu = cscale(v, static_cast<const double*>(Cv)[cb + m]);
-    yv[m] = make_double2(s.x - cu.x, s.y - cu.y);
+    st2(yv, m, make_double2(s.x - cu.x, s.y - cu.y));
   }
   // face rows: outward normal derivative along the line (the end rows of D),
   // F v = N v + i eta v_b to y, G v = N v - i eta v_b to the face buffer
@@ -264,12 +284,13 @@ __global__ __launch_bounds__(kFusedThreads, 4) void k_apply_sweep_fe(
 #pragma unroll
     for (int q = 0; q < P; ++q) cfma_r(s, R[o * RP + q], U[base + q * stride]);
     const double2 ue = U[base + o * stride];
-    yv[NI + r] = make_double2(s.x - eta * ue.y, s.y + eta * ue.x);
-    gv[r] = make_double2(s.x + eta * ue.y, s.y - eta * ue.x);
+    st2(yv, NI + r, make_double2(s.x - eta * ue.y, s.y + eta * ue.x));
+    st2(gv, r, make_double2(s.x + eta * ue.y, s.y - eta * ue.x));
   }
 }
 
-__global__ void k_apply_exchange(double2* __restrict__ y, const double2* __restrict__ g,
+template <typename T>
+__global__ void k_apply_exchange(T* __restrict__ y, const T* __restrict__ g,
                                  const int* __restrict__ nbr, int ni, int nb, int L, int64_t nl,
                                  int64_t N) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -281,42 +302,42 @@ __global__ void k_apply_exchange(double2* __restrict__ y, const double2* __restr
   const int t2 = nbr[tau * 6 + f];
   if (t2 < 0) return;
   const int64_t iy = rhs * N + tau * (ni + nb) + ni + rr;
-  const double2 gv = g[(rhs * nl + t2) * nb + (f ^ 1) * L + pos];
-  const double2 v = y[iy];
-  y[iy] = make_double2(v.x + gv.x, v.y + gv.y);
+  const double2 gv = ld2(g, (rhs * nl + t2) * nb + (f ^ 1) * L + pos);
+  const double2 v = ld2(y, iy);
+  st2(y, iy, make_double2(v.x + gv.x, v.y + gv.y));
 }
 
-template <int P>
-int sweep_launch(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
-                 hipEvent_t e1) {
+template <int P, typename T>
+int sweep_launch(hps_ctx* c, const T* x, T* y, T* g, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   dim3 grid((unsigned)c->nl, (unsigned)nrhs);
-  const dim3 block(sweep_threads<P>());
+  const dim3 block(kSweepThreads<P>);
   hipError_t e;
   const int64_t cs = c->nop > 1 ? c->nl * c->ni : 0;
   const double* etas = c->nop > 1 ? c->d_eta : nullptr;
-  if constexpr (kSweepFused<P>) {
-    const dim3 fblock(kFusedThreads);
+  if constexpr (kSweepForm<P> == kSweepSingle) {
     if (c->c_complex)
-      e = launch_k(c, e0, e1, k_apply_sweep_fe<P, true>, grid, fblock, x, y, g, (const void*)c->d_C,
+      e = launch_k(c, e0, e1, k_apply_sweep_fe<P, true, T>, grid, block, x, y, g, (const void*)c->d_C,
                    (const double*)c->d_tab, c->eta, c->nl, c->N, cs, etas);
     else
-      e = launch_k(c, e0, e1, k_apply_sweep_fe<P, false>, grid, fblock, x, y, g, (const void*)c->d_C,
+      e = launch_k(c, e0, e1, k_apply_sweep_fe<P, false, T>, grid, block, x, y, g, (const void*)c->d_C,
                    (const double*)c->d_tab, c->eta, c->nl, c->N, cs, etas);
     return check_hip(e, "k_apply_sweep_fe");
   }
   if (c->c_complex)
-    e = launch_k(c, e0, e1, k_apply_sweep<P, true>, grid, block, x, y, g, (const void*)c->d_C,
+    e = launch_k(c, e0, e1, k_apply_sweep<P, true, T>, grid, block, x, y, g, (const void*)c->d_C,
                  (const double*)c->d_tab, c->eta, c->nl, c->N, cs, etas);
   else
-    e = launch_k(c, e0, e1, k_apply_sweep<P, false>, grid, block, x, y, g, (const void*)c->d_C,
+    e = launch_k(c, e0, e1, k_apply_sweep<P, false, T>, grid, block, x, y, g, (const void*)c->d_C,
                  (const double*)c->d_tab, c->eta, c->nl, c->N, cs, etas);
   return check_hip(e, "k_apply_sweep");
 }
 
 }  // namespace
 
-int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
-                 hipEvent_t e1) {
+namespace {
+
+template <typename T>
+int sweep_dispatch(hps_ctx* c, const T* x, T* y, T* g, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   // an operator group's kernels read operator rhs's C and eta for right-hand side rhs
   if (c->nop > 1 && nrhs != c->nop) return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator");
   switch (c->p) {
@@ -337,6 +358,36 @@ int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs,
   }
 }
 
+}  // namespace
+
+int launch_sweep(hps_ctx* c, const double2* x, double2* y, double2* g, int nrhs, hipEvent_t e0,
+                 hipEvent_t e1) {
+  return sweep_dispatch(c, x, y, g, nrhs, e0, e1);
+}
+
+int launch_sweep(hps_ctx* c, const float2* x, float2* y, float2* g, int nrhs, hipEvent_t e0,
+                 hipEvent_t e1) {
+  return sweep_dispatch(c, x, y, g, nrhs, e0, e1);
+}
+
+namespace {
+
+// sweep, then the exchange, with the face buffer g; timed when tp is given
+template <typename T>
+int apply_with(hps_ctx* c, const T* x, T* y, T* g, int nrhs, TimedPair* tp) {
+  int rc = launch_sweep(c, x, y, g, nrhs, tp ? tp->start : nullptr, nullptr);
+  if (rc) return rc;
+  const int64_t total = c->nl * c->nb;
+  const int threads = 256;
+  const hipError_t e = launch_k(c, nullptr, tp ? tp->stop : nullptr, k_apply_exchange<T>,
+                                dim3((unsigned)((total + threads - 1) / threads), nrhs), dim3(threads),
+                                y, (const T*)g, (const int*)c->d_nbr, c->ni, c->nb, c->n1 * c->n1,
+                                c->nl, c->N);
+  return check_hip(e, "k_apply_exchange");
+}
+
+}  // namespace
+
 int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs) {
   const size_t gbytes = (size_t)nrhs * c->nl * c->nb * sizeof(double2);
   int rc = ws_reserve(c, &c->w_g, gbytes);
@@ -344,21 +395,18 @@ int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs) {
   double2* g = static_cast<double2*>(c->w_g.ptr);
   TimedPair tp;
   if ((rc = timing_pair(c, 0, &tp))) return rc;
-  if ((rc = launch_sweep(c, x, y, g, nrhs, tp.start, nullptr))) {
-    timing_drop(c, tp);
-    return rc;
-  }
-  const int64_t total = c->nl * c->nb;
-  const int threads = 256;
-  const hipError_t e = launch_k(c, nullptr, tp.stop, k_apply_exchange,
-                                dim3((unsigned)((total + threads - 1) / threads), nrhs), dim3(threads),
-                                y, (const double2*)g, (const int*)c->d_nbr, c->ni, c->nb, c->n1 * c->n1,
-                                c->nl, c->N);
-  if ((rc = check_hip(e, "k_apply_exchange"))) {
+  if ((rc = apply_with(c, x, y, g, nrhs, &tp))) {
     timing_drop(c, tp);
     return rc;
   }
   return timing_commit(c, 0, tp);
+}
+
+int launch_apply(hps_ctx* c, const float2* x, float2* y, int nrhs) {
+  const size_t gbytes = (size_t)nrhs * c->nl * c->nb * sizeof(float2);
+  int rc = ws_reserve(c, &c->w_g, gbytes);
+  if (rc) return rc;
+  return apply_with(c, x, y, static_cast<float2*>(c->w_g.ptr), nrhs, nullptr);
 }
 
 }  // namespace hps

@@ -7,6 +7,7 @@
 #include "hps_internal.h"
 #include "hps_krylov.h"
 #include "k_common.h"
+#include "k_vec.h"
 
 namespace hps {
 namespace {
@@ -24,10 +25,10 @@ constexpr int64_t kLongVector = 1 << 22; // ... of at least this many entries sp
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
 // tile; wavefront 0 also accumulates c and d.
-template <int KC, bool HASW>
-__global__ __launch_bounds__(DT) void k_dcgs_reduce(const double2* __restrict__ V, int64_t ldv,
-                                                    int64_t vbs, int J, const double2* __restrict__ u,
-                                                    int64_t ubs, const double2* __restrict__ w,
+template <int KC, bool HASW, typename VT>
+__global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, int64_t ldv,
+                                                    int64_t vbs, int J, const VT* __restrict__ u,
+                                                    int64_t ubs, const VT* __restrict__ w,
                                                     int64_t wbs, int64_t n,
                                                     double2* __restrict__ part) {
   const int bz = blockIdx.z;
@@ -47,12 +48,12 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const double2* __restrict__ 
   for (int64_t t0 = (int64_t)blockIdx.x * 64; t0 < n; t0 += (int64_t)nblk * 64) {
     const int64_t i = t0 + lane;
     const bool ok = i < n;
-    const double2 uv = ok ? u[i] : make_double2(0.0, 0.0);
-    const double2 wv = (HASW && ok) ? w[i] : make_double2(0.0, 0.0);
+    const double2 uv = ok ? ld2(u, i) : make_double2(0.0, 0.0);
+    const double2 wv = (HASW && ok) ? ld2(w, i) : make_double2(0.0, 0.0);
     double2 vr[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
-      vr[kk] = (kk < kn && ok) ? V[(int64_t)(k0 + kk) * ldv + i] : make_double2(0.0, 0.0);
+      vr[kk] = (kk < kn && ok) ? ld2(V, (int64_t)(k0 + kk) * ldv + i) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       aa[kk].x = fma(vr[kk].x, uv.x, fma(vr[kk].y, uv.y, aa[kk].x));
@@ -98,10 +99,10 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const double2* __restrict__ 
 // basis entries, u and w of its tile once (the split over basis vectors has
 // every wavefront read u and w, and leaves wavefronts idle when J < DW).  The
 // DW wavefront sums are added in a fixed order through LDS.
-template <int JM, bool HASW>
-__global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const double2* __restrict__ V, int64_t ldv,
-                                                       int64_t vbs, int J, const double2* __restrict__ u,
-                                                       int64_t ubs, const double2* __restrict__ w,
+template <int JM, bool HASW, typename VT>
+__global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const VT* __restrict__ V, int64_t ldv,
+                                                       int64_t vbs, int J, const VT* __restrict__ u,
+                                                       int64_t ubs, const VT* __restrict__ w,
                                                        int64_t wbs, int64_t n,
                                                        double2* __restrict__ part) {
   const int bz = blockIdx.z;
@@ -118,12 +119,12 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const double2* __restrict
   for (int64_t t0 = ((int64_t)blockIdx.x * DW + ky) * 64; t0 < n; t0 += (int64_t)nblk * DW * 64) {
     const int64_t i = t0 + lane;
     const bool ok = i < n;
-    const double2 uv = ok ? u[i] : make_double2(0.0, 0.0);
-    const double2 wv = (HASW && ok) ? w[i] : make_double2(0.0, 0.0);
+    const double2 uv = ok ? ld2(u, i) : make_double2(0.0, 0.0);
+    const double2 wv = (HASW && ok) ? ld2(w, i) : make_double2(0.0, 0.0);
     double2 vr[JM];
 #pragma unroll
     for (int k = 0; k < JM; ++k)
-      vr[k] = (k < J && ok) ? V[(int64_t)k * ldv + i] : make_double2(0.0, 0.0);
+      vr[k] = (k < J && ok) ? ld2(V, (int64_t)k * ldv + i) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < JM; ++k) {
       aa[k].x = fma(vr[k].x, uv.x, fma(vr[k].y, uv.y, aa[k].x));
@@ -433,9 +434,10 @@ __global__ __launch_bounds__(UT) void k_dcgs_small(DcgsState* __restrict__ S, in
 
 // Update pass of step J, with the small step in workgroup 0 of each right-hand side:
 // V[J] = (u - V_{0..J-1} a) / beta;  u <- (w - V_{0..J-1} b - V[J] vjw) / beta.
-__global__ __launch_bounds__(UT) void k_dcgs_update(double2* __restrict__ V, int64_t ldv, int64_t vbs,
-                                                    int J, double2* __restrict__ u, int64_t ubs,
-                                                    const double2* __restrict__ w, int64_t wbs,
+template <typename VT>
+__global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t ldv, int64_t vbs,
+                                                    int J, VT* __restrict__ u, int64_t ubs,
+                                                    const VT* __restrict__ w, int64_t wbs,
                                                     int64_t n, DcgsState* __restrict__ S,
                                                     int flexible, double* __restrict__ res_out,
                                                     unsigned long long tag, double tiny) {
@@ -461,7 +463,7 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(double2* __restrict__ V, int
       double2 v[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        v[q] = (l + q < J) ? V[(int64_t)(l + q) * ldv + i] : make_double2(0.0, 0.0);
+        v[q] = (l + q < J) ? ld2(V, (int64_t)(l + q) * ldv + i) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double2 x = ca[l + q], y = cb[l + q];
@@ -471,11 +473,11 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(double2* __restrict__ V, int
         sb.y = fma(v[q].x, y.y, fma(v[q].y, y.x, sb.y));
       }
     }
-    const double2 uv = u[i], wv = w[i];
+    const double2 uv = ld2(u, i), wv = ld2(w, i);
     const double2 vj = make_double2((uv.x - sa.x) * inv, (uv.y - sa.y) * inv);
     const double2 t = cmul(vj, cj);
-    V[(int64_t)J * ldv + i] = vj;
-    u[i] = make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv);
+    st2(V, (int64_t)J * ldv + i, vj);
+    st2(u, i, make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv));
   }
 }
 
@@ -517,9 +519,11 @@ __global__ __launch_bounds__(64) void k_dcgs_trisolve(DcgsState* __restrict__ S,
 
 }  // namespace
 
-int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int J,
-                       const double2* u, int64_t ubs, const double2* w, int64_t wbs, int64_t n,
-                       DcgsState* S, int nbatch, const RedBuf& rb) {
+namespace {
+
+template <typename VT>
+int dcgs_reduce(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int J, const VT* u, int64_t ubs,
+                const VT* w, int64_t wbs, int64_t n, DcgsState* S, int nbatch, const RedBuf& rb) {
   if (J > kMaxDcgs || nbatch > rb.nbatch) return fail(HPS_ERR_ARG, "reduction too large");
   const int64_t tiles = (n + 63) / 64;
   const int kc = (J + DW - 1) / DW;
@@ -533,10 +537,10 @@ int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, i
 #define HPS_DR(KC)                                                                              \
   do {                                                                                          \
     if (hw)                                                                                     \
-      hipLaunchKernelGGL((k_dcgs_reduce<KC, true>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, u, \
+      hipLaunchKernelGGL((k_dcgs_reduce<KC, true, VT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, u, \
                          ubs, w, wbs, n, rb.part);                                              \
     else                                                                                        \
-      hipLaunchKernelGGL((k_dcgs_reduce<KC, false>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, \
+      hipLaunchKernelGGL((k_dcgs_reduce<KC, false, VT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, \
                          u, ubs, w, wbs, n, rb.part);                                           \
   } while (0)
   // short bases on long vectors: tiles split over the wavefronts (measured:
@@ -544,10 +548,10 @@ int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, i
   // vectors, where half the wavefronts idle and all re-read u and w)
   if (J <= kShortBasis && n >= kLongVector) {
     if (hw)
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true>), grid, dim3(DT), 0, c->stream, V, ldv,
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT>), grid, dim3(DT), 0, c->stream, V, ldv,
                          vbs, J, u, ubs, w, wbs, n, rb.part);
     else
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false>), grid, dim3(DT), 0, c->stream, V, ldv,
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT>), grid, dim3(DT), 0, c->stream, V, ldv,
                          vbs, J, u, ubs, w, wbs, n, rb.part);
   } else if (kc <= 2) HPS_DR(2); else if (kc <= 4) HPS_DR(4); else HPS_DR(8);
 #undef HPS_DR
@@ -559,6 +563,20 @@ int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, i
   return check_hip(hipGetLastError(), "k_dcgs_finish");
 }
 
+}  // namespace
+
+int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int J,
+                       const double2* u, int64_t ubs, const double2* w, int64_t wbs, int64_t n,
+                       DcgsState* S, int nbatch, const RedBuf& rb) {
+  return dcgs_reduce(c, V, ldv, vbs, J, u, ubs, w, wbs, n, S, nbatch, rb);
+}
+
+int launch_dcgs_reduce(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int J,
+                       const float2* u, int64_t ubs, const float2* w, int64_t wbs, int64_t n,
+                       DcgsState* S, int nbatch, const RedBuf& rb) {
+  return dcgs_reduce(c, V, ldv, vbs, J, u, ubs, w, wbs, n, S, nbatch, rb);
+}
+
 int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible, int final_only,
                       double* res_out, uint64_t tag) {
   if (j < 0 || j > kMaxDcgs) return fail(HPS_ERR_ARG, "small step beyond the restart limit");
@@ -567,9 +585,12 @@ int launch_dcgs_small(hps_ctx* c, DcgsState* S, int nbatch, int j, int flexible,
   return check_hip(hipGetLastError(), "k_dcgs_small");
 }
 
-int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
-                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
-                       int nbatch, int flexible, double* res_out, uint64_t tag) {
+namespace {
+
+template <typename VT>
+int dcgs_update(hps_ctx* c, VT* V, int64_t ldv, int64_t vbs, int J, VT* u, int64_t ubs, const VT* w,
+                int64_t wbs, int64_t n, DcgsState* S, int nbatch, int flexible, double* res_out,
+                uint64_t tag) {
   if (J < 0 || J >= kMaxDcgs) return fail(HPS_ERR_ARG, "update beyond the restart limit");
   // enough workgroups that a thread makes few passes (each pass waits for its
   // loads); every workgroup recomputes the step coefficients, a few KB from L2
@@ -579,7 +600,7 @@ int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, 
   TimedPair tp;
   int rc = timing_pair(c, 4, &tp);
   if (rc) return rc;
-  rc = check_hip(launch_k(c, tp.start, tp.stop, k_dcgs_update, dim3(nblk, 1, nbatch), dim3(UT), V, ldv,
+  rc = check_hip(launch_k(c, tp.start, tp.stop, k_dcgs_update<VT>, dim3(nblk, 1, nbatch), dim3(UT), V, ldv,
                           vbs, J, u, ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag,
                           kBreakdownTol),
                  "k_dcgs_update");
@@ -588,7 +609,21 @@ int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, 
     return rc;
   }
   // algorithmic bytes: V_0..J-1, u and w read, V_J and u written
-  return timing_commit(c, 4, tp, 16.0 * (double)(J + 4) * (double)n * nbatch);
+  return timing_commit(c, 4, tp, (double)sizeof(VT) * (J + 4) * (double)n * nbatch);
+}
+
+}  // namespace
+
+int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
+                       int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
+                       int nbatch, int flexible, double* res_out, uint64_t tag) {
+  return dcgs_update(c, V, ldv, vbs, J, u, ubs, w, wbs, n, S, nbatch, flexible, res_out, tag);
+}
+
+int launch_dcgs_update(hps_ctx* c, float2* V, int64_t ldv, int64_t vbs, int J, float2* u,
+                       int64_t ubs, const float2* w, int64_t wbs, int64_t n, DcgsState* S,
+                       int nbatch, int flexible, double* res_out, uint64_t tag) {
+  return dcgs_update(c, V, ldv, vbs, J, u, ubs, w, wbs, n, S, nbatch, flexible, res_out, tag);
 }
 
 int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch) {

@@ -11,6 +11,7 @@
 #include "hps_internal.h"
 #include "hps_krylov.h"
 #include "k_common.h"
+#include "k_vec.h"
 
 #include <algorithm>
 
@@ -65,9 +66,11 @@ __global__ __launch_bounds__(RT) void k_mdot(const double2* __restrict__ V, int6
 }
 
 // w[i] += sign * sum_k V[k ldv + i] coef[k]; optionally nrm2 = ||w||^2 after the update.
-__global__ __launch_bounds__(RT) void k_mupdate(const double2* __restrict__ V, int64_t ldv,
+// VT: the storage of V and w (complex FP64 or FP32); the sums are FP64.
+template <typename VT>
+__global__ __launch_bounds__(RT) void k_mupdate(const VT* __restrict__ V, int64_t ldv,
                                                 int64_t vbs, int K, const double2* __restrict__ coef,
-                                                int64_t cbs, double sign, double2* __restrict__ w,
+                                                int64_t cbs, double sign, VT* __restrict__ w,
                                                 int64_t wbs, int64_t n, int want_norm,
                                                 double2* __restrict__ part) {
   const int bz = blockIdx.z;
@@ -85,12 +88,12 @@ __global__ __launch_bounds__(RT) void k_mupdate(const double2* __restrict__ V, i
   const unsigned nblk = gridDim.x;
   double sq = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)nblk * RT) {
-    double2 a = w[i];
+    double2 a = ld2(w, i);
     for (int k = 0; k < K; k += 8) {
       double2 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        v[u] = (k + u < K) ? V[(int64_t)(k + u) * ldv + i] : make_double2(0.0, 0.0);
+        v[u] = (k + u < K) ? ld2(V, (int64_t)(k + u) * ldv + i) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const double2 c = cs[k + u];
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(RT) void k_mupdate(const double2* __restrict__ V, i
         a.y = fma(v[u].x, c.y, fma(v[u].y, c.x, a.y));
       }
     }
-    w[i] = a;
+    if (K > 0) st2(w, i, a);
     sq = fma(a.x, a.x, fma(a.y, a.y, sq));
   }
   if (!want_norm) return;
@@ -128,11 +131,29 @@ __global__ void k_scale_by(const double2* __restrict__ x, int64_t xbs, double2* 
   y[bz * ybs + i] = make_double2(a.x * s, a.y * s);
 }
 
-__global__ void k_sub_from(const double2* __restrict__ a, double2* __restrict__ y, int64_t n) {
+__global__ void k_demote_scaled(const double2* __restrict__ x, double s, float2* __restrict__ y,
+                                int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double2 u = a[i], v = y[i];
-  y[i] = make_double2(u.x - v.x, u.y - v.y);
+  const double2 a = x[i];
+  y[i] = make_float2((float)(a.x * s), (float)(a.y * s));
+}
+
+__global__ void k_axpy_promote(double s, const float2* __restrict__ x, double2* __restrict__ y,
+                               int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 a = x[i];
+  const double2 b = y[i];
+  y[i] = make_double2(fma(s, (double)a.x, b.x), fma(s, (double)a.y, b.y));
+}
+
+template <typename VT>
+__global__ void k_sub_from(const VT* __restrict__ a, VT* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 u = ld2(a, i), v = ld2(y, i);
+  st2(y, i, make_double2(u.x - v.x, u.y - v.y));
 }
 
 
@@ -418,18 +439,51 @@ int launch_mdot_b(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K,
   return finish_c(c, rb, K, nblk, out, obs, nbatch);
 }
 
-int launch_mupdate_b(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K,
-                     const double2* coef, int64_t cbs, double sign, double2* w, int64_t wbs,
-                     int64_t n, double* nrm2, int64_t nstride, int nbatch, const RedBuf& rb) {
+template <typename VT>
+static int mupdate_b(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int K, const double2* coef,
+                     int64_t cbs, double sign, VT* w, int64_t wbs, int64_t n, double* nrm2,
+                     int64_t nstride, int nbatch, const RedBuf& rb) {
   if (K > kMaxRestart + 1 || nbatch > rb.nbatch) return fail(HPS_ERR_ARG, "update too large");
   const int nblk = nblocks_for(n, rb.nblk);
   dim3 grid(nblk, 1, nbatch);
-  hipLaunchKernelGGL(k_mupdate, grid, dim3(RT), 0, c->stream, V, ldv, vbs, K, coef, cbs, sign, w,
+  hipLaunchKernelGGL(k_mupdate<VT>, grid, dim3(RT), 0, c->stream, V, ldv, vbs, K, coef, cbs, sign, w,
                      wbs, n, nrm2 ? 1 : 0, rb.part);
   int rc = check_hip(hipGetLastError(), "k_mupdate");
   if (rc || !nrm2) return rc;
   hipLaunchKernelGGL(k_finish_r, dim3(nbatch), dim3(256), 0, c->stream, rb.part, nblk, nrm2, nstride);
   return check_hip(hipGetLastError(), "k_finish_r");
+}
+
+int launch_mupdate_b(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K,
+                     const double2* coef, int64_t cbs, double sign, double2* w, int64_t wbs,
+                     int64_t n, double* nrm2, int64_t nstride, int nbatch, const RedBuf& rb) {
+  return mupdate_b(c, V, ldv, vbs, K, coef, cbs, sign, w, wbs, n, nrm2, nstride, nbatch, rb);
+}
+
+int launch_mupdate_b(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K,
+                     const double2* coef, int64_t cbs, double sign, float2* w, int64_t wbs,
+                     int64_t n, double* nrm2, int64_t nstride, int nbatch, const RedBuf& rb) {
+  return mupdate_b(c, V, ldv, vbs, K, coef, cbs, sign, w, wbs, n, nrm2, nstride, nbatch, rb);
+}
+
+int launch_norm2_b(hps_ctx* c, const float2* w, int64_t wbs, int64_t n, double* nrm2, int64_t nbs,
+                   int nbatch, const RedBuf& rb) {
+  return launch_mupdate_b(c, (const float2*)nullptr, 0, 0, 0, nullptr, 0, 0.0, const_cast<float2*>(w),
+                          wbs, n, nrm2, nbs, nbatch, rb);
+}
+
+int launch_demote_scaled(hps_ctx* c, const double2* x, double s, float2* y, int64_t n) {
+  const int threads = 256;
+  hipLaunchKernelGGL(k_demote_scaled, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
+                     c->stream, x, s, y, n);
+  return check_hip(hipGetLastError(), "k_demote_scaled");
+}
+
+int launch_axpy_promote(hps_ctx* c, double s, const float2* x, double2* y, int64_t n) {
+  const int threads = 256;
+  hipLaunchKernelGGL(k_axpy_promote, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
+                     c->stream, s, x, y, n);
+  return check_hip(hipGetLastError(), "k_axpy_promote");
 }
 
 int launch_mdot(hps_ctx* c, const double2* V, int64_t ldv, int K, const double2* w, int64_t n,
@@ -443,14 +497,14 @@ int launch_mupdate(hps_ctx* c, const double2* V, int64_t ldv, int K, const doubl
 }
 
 int launch_norm2(hps_ctx* c, const double2* w, int64_t n, double* nrm2, const RedBuf& rb) {
-  return launch_mupdate_b(c, nullptr, 0, 0, 0, nullptr, 0, 0.0, const_cast<double2*>(w), 0, n,
-                          nrm2, 0, 1, rb);
+  return launch_mupdate_b(c, (const double2*)nullptr, 0, 0, 0, nullptr, 0, 0.0, const_cast<double2*>(w),
+                          0, n, nrm2, 0, 1, rb);
 }
 
 int launch_norm2_b(hps_ctx* c, const double2* w, int64_t wbs, int64_t n, double* nrm2, int64_t nbs,
                    int nbatch, const RedBuf& rb) {
-  return launch_mupdate_b(c, nullptr, 0, 0, 0, nullptr, 0, 0.0, const_cast<double2*>(w), wbs, n,
-                          nrm2, nbs, nbatch, rb);
+  return launch_mupdate_b(c, (const double2*)nullptr, 0, 0, 0, nullptr, 0, 0.0, const_cast<double2*>(w),
+                          wbs, n, nrm2, nbs, nbatch, rb);
 }
 
 int launch_scale_by(hps_ctx* c, const double2* x, double2* y, int64_t n, const double* s,
@@ -468,8 +522,15 @@ int launch_scale_by_b(hps_ctx* c, const double2* x, int64_t xbs, double2* y, int
 
 int launch_sub_from(hps_ctx* c, const double2* a, double2* y, int64_t n) {
   const int threads = 256;
-  hipLaunchKernelGGL(k_sub_from, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
-                     c->stream, a, y, n);
+  hipLaunchKernelGGL(k_sub_from<double2>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads),
+                     0, c->stream, a, y, n);
+  return check_hip(hipGetLastError(), "k_sub_from");
+}
+
+int launch_sub_from(hps_ctx* c, const float2* a, float2* y, int64_t n) {
+  const int threads = 256;
+  hipLaunchKernelGGL(k_sub_from<float2>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads),
+                     0, c->stream, a, y, n);
   return check_hip(hipGetLastError(), "k_sub_from");
 }
 

@@ -131,4 +131,29 @@ int launch_op_left(hps_ctx* c, const double2* x, double2* tmp, double2* y, int n
   return timing_commit(c, 1, tp);
 }
 
+int launch_op_left(hps_ctx* c, const float2* x, float2* tmp, float2* y, int nrhs) {
+  if (!c->sep) return fail(HPS_ERR_ARG, "vectors in FP32 need the separable J^-1");
+  int rc = ws_reserve(c, &c->w_g, (size_t)nrhs * c->nl * c->nb * sizeof(float2));
+  if (rc) return rc;
+  float2* g = static_cast<float2*>(c->w_g.ptr);
+  TimedPair ta, tp;
+  if ((rc = timing_pair(c, 0, &ta))) return rc;
+  if ((rc = launch_sweep(c, x, tmp, g, nrhs, ta.start, ta.stop))) {
+    timing_drop(c, ta);
+    return rc;
+  }
+  if ((rc = timing_commit(c, 0, ta))) return rc;
+  if ((rc = timing_pair(c, 1, &tp))) return rc;
+  if ((rc = launch_precond_sep(c, tmp, g, y, nrhs, tp.start, tp.stop))) {
+    timing_drop(c, tp);
+    return rc;
+  }
+  return timing_commit(c, 1, tp);
+}
+
+int launch_precond(hps_ctx* c, const float2* x, float2* y, int nrhs) {
+  if (!c->sep) return fail(HPS_ERR_ARG, "vectors in FP32 need the separable J^-1");
+  return launch_precond_sep(c, x, static_cast<const float2*>(nullptr), y, nrhs, nullptr, nullptr);
+}
+
 }  // namespace hps

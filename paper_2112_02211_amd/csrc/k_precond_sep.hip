@@ -27,42 +27,60 @@
 // per unknown), where the dense form also streams the n_b x n_b block.  The
 // tables (Wc, Vc, Ec, Fi per operator) are built on the host at setup.
 #include "hps_internal.h"
+#include "k_vec.h"
 
 namespace hps {
 namespace {
 
-// Mode-product form per order, from measurement (J^-1 over about 4 million
-// unknowns for every p = 4 ... 16, both forms): line-wise (a thread owns a grid
-// line and two of its outputs, the n1 inputs in registers, the matrix rows
-// uniform across a wavefront and read through the scalar cache) was 3-32 %
-// faster at p = 8, 10, 11 and 13-16, element-parallel (a thread owns one
-// output; inputs and matrix entries from LDS) 5-30 % faster at p = 4-7 and 9
-// and equal at 12.
-template <int P> constexpr bool kLineWise = (P == 8 || P == 10 || P == 11 || P >= 13);
-// p >= 13: line-wise in place (a thread owns a whole line and all its outputs,
-// written back over its inputs), so no second LDS tensor is needed and two
-// workgroups fit on a CU (measured: 28 % faster at p = 16 on 32^3 leaves, 8 %
-// at p = 15, 2-3 % at p = 13, 14; 4-8 % slower at p = 12)
-template <int P> constexpr bool kInPlace = (P >= 13);
+// config begin
+// Per order: the mode-product form, the workgroup size, the waves per SIMD the
+// register budget must leave room for, and (line-wise) the outputs of a line
+// per work item.  Forms, from measurement (J^-1 over about 4 million unknowns
+// for every p = 4 ... 16): line-wise (a thread owns a grid line and R of its
+// outputs, the n1 inputs in registers, the matrix rows uniform across a
+// wavefront and read through the scalar cache) was 3-32 % faster at p = 8, 10,
+// 11 and 13-16, element-parallel (a thread owns one output; inputs and matrix
+// entries from LDS) 5-30 % faster at p = 4-7 and 9 and equal at 12; in place
+// (a thread owns a whole line and all its outputs, written back over its
+// inputs, so no second LDS tensor is needed and two workgroups fit on a CU)
+// 28 % faster at p = 16 on 32^3 leaves, 8 % at p = 15, 2-3 % at p = 13, 14.
+enum { kSepElem = 0, kSepLine = 1, kSepInPlace = 2 };
+template <int P>
+constexpr int kSepForm = P >= 13 ? kSepInPlace : (P == 8 || P == 10 || P == 11) ? kSepLine : kSepElem;
+template <int P>
+constexpr int kSepThreads = kSepForm<P> == kSepInPlace ? 512
+                          : ((P - 2) * (P - 2) * (P - 2) + 63) / 64 * 64 < 64 ? 64
+                          : ((P - 2) * (P - 2) * (P - 2) + 63) / 64 * 64 > 1024 ? 1024
+                          : ((P - 2) * (P - 2) * (P - 2) + 63) / 64 * 64;
+template <int P>
+constexpr int kSepMinWaves = kSepForm<P> == kSepInPlace ? 4 : 1;
+template <int P>
+constexpr int kSepOutputs = 2;
+// p = 12 (16^3 leaves): line-wise with five outputs per work item on 256
+// threads (two items per wavefront and mode product), three leaves per CU;
+// 95 us against 118 us element-parallel on 1024 threads, the best of six
+// shapes measured
+template <> constexpr int kSepForm<12> = kSepLine;
+template <> constexpr int kSepThreads<12> = 256;
+template <> constexpr int kSepMinWaves<12> = 8;
+template <> constexpr int kSepOutputs<12> = 5;
+// config end
 
 template <int P>
 struct SL {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
-  static constexpr bool LW = kLineWise<P>, IP = kInPlace<P>;
-  static constexpr int BD0 = (NI + 63) / 64 * 64;
-  // in place: 512 threads and at most 128 VGPRs (four waves per SIMD), so that
-  // two workgroups share a CU
-  static constexpr int BD = IP ? 512 : (BD0 < 64 ? 64 : (BD0 > 1024 ? 1024 : BD0));
-  static constexpr int MINW = IP ? 4 : 1;
+  static constexpr bool LW = kSepForm<P> == kSepLine, IP = kSepForm<P> == kSepInPlace;
+  static constexpr int BD = kSepThreads<P>;
+  static constexpr int MINW = kSepMinWaves<P>;
   static constexpr int ST = sep_table_size(P);
   // line-wise: the LDS tensors pad each x-line to n1 + 1 entries, so the
   // threads of a wavefront that walk neighbouring x-lines read 16-byte words in
   // different banks
-  static constexpr int P1 = LW ? N1 + 1 : N1, SZ = P1 * L, SZX = IP ? 1 : SZ;
+  static constexpr int P1 = (LW || IP) ? N1 + 1 : N1, SZ = P1 * L, SZX = IP ? 1 : SZ;
   // line-wise work items: (output group of R, 64 lines) per wavefront
-  static constexpr int R = 2, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
+  static constexpr int R = kSepOutputs<P>, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
   // tables staged in LDS: Ec | Fi, and for the element-parallel form Wc | Vc before them
-  static constexpr int CTN = LW ? N1 + 4 : ST, CT0 = LW ? 0 : 2 * L;
+  static constexpr int CTN = (LW || IP) ? N1 + 4 : ST, CT0 = (LW || IP) ? 0 : 2 * L;
 };
 
 template <int P>
@@ -206,10 +224,10 @@ __device__ __forceinline__ void cmode(const double2* in, double2* out, const dou
 // (x_b += the neighbour's outgoing impedance on the partner face), as in the
 // dense-block kernel.  Operator groups: right-hand side rhs belongs to
 // operator rhs (os = nl: lambda of [rhs][leaf], table of operator rhs).
-template <int P>
+template <int P, typename VT>
 __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
-    const double2* __restrict__ x, const double2* __restrict__ g, const int* __restrict__ nbr,
-    double2* __restrict__ y, const double2* __restrict__ lam, const double2* __restrict__ sep,
+    const VT* __restrict__ x, const VT* __restrict__ g, const int* __restrict__ nbr,
+    VT* __restrict__ y, const double2* __restrict__ lam, const double2* __restrict__ sep,
     const double* __restrict__ tab, int64_t nl, int64_t N, int64_t os) {
   using S = SL<P>;
   constexpr int N1 = S::N1, L = S::L, NI = S::NI, NB = S::NB, NN = S::NN, BD = S::BD;
@@ -220,8 +238,8 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   __shared__ double RT[4 * N1];     // Dlo | Dhi | C0 | C1
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
-  const double2* xv = x + rhs * N + tau * NN;
-  double2* yv = y + rhs * N + tau * NN;
+  const VT* xv = x + rhs * N + tau * NN;
+  VT* yv = y + rhs * N + tau * NN;
   const double2 lm = lam[tau + rhs * os];
   const double2* st = sep + (os ? (int64_t)rhs * S::ST : 0);
   const double2* Wc = st;          // global: read at wavefront-uniform addresses
@@ -238,15 +256,15 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   }
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
-    T[lidx<P>(i, j, k)] = xv[m];
+    T[lidx<P>(i, j, k)] = ld2(xv, m);
   }
   for (int m = threadIdx.x; m < NB; m += BD) {
-    double2 v = xv[NI + m];
+    double2 v = ld2(xv, NI + m);
     if (g) {
       const int f = m / L, pos = m - f * L;
       const int t2 = nbr[tau * 6 + f];
       if (t2 >= 0) {
-        const double2 gv = g[(rhs * nl + t2) * NB + (f ^ 1) * L + pos];
+        const double2 gv = ld2(g, (rhs * nl + t2) * NB + (f ^ 1) * L + pos);
         v = make_double2(v.x + gv.x, v.y + gv.y);
       }
     }
@@ -305,7 +323,7 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   __syncthreads();
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
-    yv[m] = T[lidx<P>(i, j, k)];
+    st2(yv, m, T[lidx<P>(i, j, k)]);
   }
   // u_b = g - Fi Fbi1 u_line,  Fbi1 u_line = [-sum Dlo u, sum Dhi u]
   for (int ln = threadIdx.x; ln < 3 * L; ln += BD) {
@@ -325,26 +343,27 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
     cfma(fa, F1, shi);
     cfma(fb, F2, slo);
     cfma(fb, F3, shi);
-    yv[NI + 2 * ax * L + pos] = csub(a, fa);
-    yv[NI + (2 * ax + 1) * L + pos] = csub(b, fb);
+    st2(yv, NI + 2 * ax * L + pos, csub(a, fa));
+    st2(yv, NI + (2 * ax + 1) * L + pos, csub(b, fb));
   }
 }
 
-template <int P>
-int sep_launch(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs, hipEvent_t e0,
-               hipEvent_t e1) {
+template <int P, typename VT>
+int sep_launch(hps_ctx* c, const VT* x, const VT* g, VT* y, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid((unsigned)c->nl, (unsigned)nrhs);
   const dim3 block(SL<P>::BD);
   const int64_t os = c->nop > 1 ? c->nl : 0;
-  const hipError_t e = launch_k(c, e0, e1, k_precond_sep<P>, grid, block, x, g, c->d_nbr, y,
+  const hipError_t e = launch_k(c, e0, e1, k_precond_sep<P, VT>, grid, block, x, g, c->d_nbr, y,
                                 c->d_lambda, c->d_sep, c->d_tab, c->nl, c->N, os);
   return check_hip(e, "k_precond_sep");
 }
 
 }  // namespace
 
-int launch_precond_sep(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs,
-                       hipEvent_t e0, hipEvent_t e1) {
+namespace {
+
+template <typename VT>
+int sep_dispatch(hps_ctx* c, const VT* x, const VT* g, VT* y, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   if (!c->sep || !c->d_sep) return fail(HPS_ERR_ARG, "the separable J^-1 was not built at setup");
   if (c->nop > 1 && nrhs != c->nop) return fail(HPS_ERR_ARG, "operator group: one right-hand side per operator");
   if (nrhs > 65535) return fail(HPS_ERR_ARG, "at most 65535 right-hand sides per call");
@@ -364,6 +383,18 @@ int launch_precond_sep(hps_ctx* c, const double2* x, const double2* g, double2* 
     case 16: return sep_launch<16>(c, x, g, y, nrhs, e0, e1);
     default: return fail(HPS_ERR_UNSUPPORTED, "p out of range");
   }
+}
+
+}  // namespace
+
+int launch_precond_sep(hps_ctx* c, const double2* x, const double2* g, double2* y, int nrhs,
+                       hipEvent_t e0, hipEvent_t e1) {
+  return sep_dispatch(c, x, g, y, nrhs, e0, e1);
+}
+
+int launch_precond_sep(hps_ctx* c, const float2* x, const float2* g, float2* y, int nrhs,
+                       hipEvent_t e0, hipEvent_t e1) {
+  return sep_dispatch(c, x, g, y, nrhs, e0, e1);
 }
 
 }  // namespace hps

@@ -22,7 +22,7 @@ HPS_ERR_ARG, HPS_ERR_UNSUPPORTED, HPS_ERR_OOM = -1, -2, -3
 HPS_ERR_DEVICE, HPS_ERR_BREAKDOWN, HPS_ERR_NUMERIC = -4, -5, -6
 ERRORS = {-1: "ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BREAKDOWN", -6: "NUMERIC"}
 PREC = {"fp64": 1, "fp32": 2, "bf16": 4, "separable": 8}
-SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2, "iti": 3, "block_gmres": 4}
+SOLVER = {"gmres": 0, "fgmres": 1, "batched": 2, "iti": 3, "block_gmres": 4, "ir": 5}
 ORTH = {"dcgs": 0, "cgs2": 1}
 MEDIUM_ZERO, MEDIUM_NODAL, MEDIUM_BUMPS = 0, 1, 2
 
@@ -55,7 +55,7 @@ class _Opts(ctypes.Structure):
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("max_iters", ctypes.c_int), ("use_x0", ctypes.c_int),
                 ("precond_prec", ctypes.c_int), ("check_every", ctypes.c_int), ("orth", ctypes.c_int),
-                ("rhs_rel_res", ctypes.POINTER(ctypes.c_double))]
+                ("rhs_rel_res", ctypes.POINTER(ctypes.c_double)), ("inner_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -86,6 +86,8 @@ SIGNATURES = {
     "hps_lambdas": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Z)]),
     "hps_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "hps_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_op_left_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_precond_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_op_left": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -162,6 +164,15 @@ def _stream_ptr():
 def _dev_opt(t, name: str):
     """_dev, or NULL for None (optional arguments such as zero boundary data)."""
     return None if t is None else _dev(t, name)
+
+
+def _dev32(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be a complex64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _dev(t, name: str):
@@ -342,6 +353,22 @@ class Context:
         _check(lib().hps_apply(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x)))
         return y
 
+    def op_left_f32(self, x, y=None):
+        """y = J^{-1} A x on complex64 vectors (the inner operator of iterative refinement)."""
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        self._sync_stream()
+        _check(lib().hps_op_left_f32(self._h, _dev32(x, "x"), _dev32(y, "y"), self._nrhs(x)))
+        return y
+
+    def precond_f32(self, x, y=None):
+        """y = J^{-1} x on complex64 vectors (separable form)."""
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        self._sync_stream()
+        _check(lib().hps_precond_f32(self._h, _dev32(x, "x"), _dev32(y, "y"), self._nrhs(x)))
+        return y
+
     def precond(self, x, y=None, prec: str = "fp64"):
         """y = J^{-1} x with the blocks stored in ``prec``."""
         torch = _torch()
@@ -414,18 +441,22 @@ class Context:
 
     def gmres(self, s, t, tol: float = 1e-10, restart: int = 30, u=None, solver: str = "gmres",
               precond_prec: str = "fp64", max_iters: int = 0, check_every: int = 1,
-              use_x0: bool = False, raise_on_nc: bool = False, orth: str = "dcgs"):
+              use_x0: bool = False, raise_on_nc: bool = False, orth: str = "dcgs",
+              inner_tol: float = 0.0):
         """Solve A u = b(s, t); returns (u, stats dict, converged flag).
         t may be None: zero boundary data.
 
         orth: "dcgs" (delayed reorthogonalization, two passes per step; restart
-        <= 64) or "cgs2" (classical Gram-Schmidt twice, three passes)."""
+        <= 64) or "cgs2" (classical Gram-Schmidt twice, three passes).
+        solver "ir": iterative refinement with FP32 inner solves stopped at
+        inner_tol (0: the library's default)."""
         torch = _torch()
         u = torch.zeros_like(s) if u is None else u
         nrhs = self._nrhs(s)
         res = (ctypes.c_double * nrhs)()
-        so = _SolveOpts(SOLVER[solver], int(max_iters), 1 if use_x0 else 0, PREC[precond_prec],
-                        int(check_every), ORTH[orth], ctypes.cast(res, ctypes.POINTER(ctypes.c_double)))
+        so = _SolveOpts(SOLVER[solver], int(max_iters), 1 if use_x0 else 0,
+                        0 if solver == "ir" else PREC[precond_prec], int(check_every), ORTH[orth],
+                        ctypes.cast(res, ctypes.POINTER(ctypes.c_double)), float(inner_tol))
         st = Stats()
         self._sync_stream()
         rc = lib().hps_gmres(self._h, _dev(s, "s"), _dev_opt(t, "t"), float(tol), int(restart),

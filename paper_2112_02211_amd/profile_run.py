@@ -49,7 +49,7 @@ CSRC = os.path.join(ROOT, "paper_2112_02211_amd", "csrc")
 # every source the preconditioner kernel is compiled from
 PRECOND_SOURCES = ("k_precond_fused.h", "k_leaf.h", "k_common.h")
 # the Arnoldi kernels and their launchers
-ARNOLDI_SOURCES = ("k_dcgs.hip", "k_common.h")
+ARNOLDI_SOURCES = ("k_dcgs.hip", "k_common.h", "k_vec.h")
 KERNEL_SOURCES = {"k_precond_fused": PRECOND_SOURCES, "k_dcgs_update": ARNOLDI_SOURCES}
 COPY_MIB = 1024
 
