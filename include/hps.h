@@ -240,6 +240,23 @@ int hps_set_stream(hps_ctx* c, void* stream);
  * must not overlap. */
 int hps_apply(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
 
+/* hps_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, but the face buffer between
+ * the sweep and the exchange (nrhs * #leaves * 6 (p-2)^2 complex values) lives
+ * in a static device array of HPS_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each GPU until the process ends, instead of a context workspace.  The call
+ * allocates nothing, records no timing events, and needs no clearing of the
+ * array (the sweep writes every entry the exchange reads).  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads, other contexts) race and must be ordered by the caller.
+ * x, y: device, nrhs * N complex; must not overlap.
+ * Errors: HPS_ERR_ARG (bad arguments, or a face buffer larger than
+ * HPS_NOALLOC_SCRATCH_BYTES: at most 65536 face nodes' worth of leaves times
+ * right-hand sides per MiB), HPS_ERR_DEVICE. */
+#define HPS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hps_apply_noalloc(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);
+
 /* y = J^{-1} x (Sec. 4, Algorithm 4, eq. (block_pc)) with the FP64 blocks.
  * x, y: device, nrhs * N complex; must not overlap. */
 int hps_precond(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs);

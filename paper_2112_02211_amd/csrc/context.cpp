@@ -386,8 +386,10 @@ int setup_impl(const hps_domain* d, int nop, const double* kappas, const double*
     for (int j = 0; j < n1; ++j)
       for (int i = 0; i < n1; ++i)
         tab[tab_off_ed3(p) + i + n1 * (j + n1 * k)] = c->tab.E[i] + c->tab.E[j] + c->tab.E[k];
-  int rc = dev_alloc(c, (void**)&c->d_tab, sizeof(double) * tab.size());
+  // the static face buffer of hps_apply_noalloc on this device
+  int rc = scratch_address(&c->d_scratch);
   if (rc) return bail(rc);
+  if ((rc = dev_alloc(c, (void**)&c->d_tab, sizeof(double) * tab.size()))) return bail(rc);
   if ((rc = check_hip(hipMemcpyAsync(c->d_tab, tab.data(), sizeof(double) * tab.size(),
                                      hipMemcpyHostToDevice, c->stream), "upload tables")))
     return bail(rc);
@@ -699,6 +701,11 @@ int hps_lambdas(const hps_ctx* c, hps_z* lam) {
 int hps_apply(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
   if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_apply");
   return launch_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nrhs);
+}
+
+int hps_apply_noalloc(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs) {
+  if (!c || !x || !y || nrhs < 1) return fail(HPS_ERR_ARG, "bad arguments to hps_apply_noalloc");
+  return launch_apply_noalloc(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nrhs);
 }
 
 int hps_precond_prec(hps_ctx* c, const hps_z* x, hps_z* y, int nrhs, int prec) {

@@ -113,6 +113,9 @@ struct hps_ctx {
   int group_leaves = 1;             // leaves in the largest group
   int n_shifted = 0;
   double t_setup = 0.0;  // seconds of hps_setup (host wall clock, device synchronized)
+  // device address of the static face buffer of hps_apply_noalloc on the
+  // context's device (from hipGetSymbolAddress at setup)
+  double2* d_scratch = nullptr;
   hps::Blocks blk[3];
   // separable form of the FP64 J^-1 (block_precs has HPS_PREC_SEPARABLE): no
   // FP64 blocks; one complex table per operator
@@ -208,6 +211,11 @@ inline hipError_t launch_k_lds(hps_ctx* c, hipEvent_t e0, hipEvent_t e1, void (*
 
 // hot path
 int launch_apply(hps_ctx* c, const double2* x, double2* y, int nrhs);
+// launch_apply with the face buffer in the library's static device array
+// (no allocation); scratch_address looks up that array's address on the
+// current device (once per device, cached)
+int launch_apply_noalloc(hps_ctx* c, const double2* x, double2* y, int nrhs);
+int scratch_address(double2** out);
 int launch_precond(hps_ctx* c, const double2* x, double2* y, int nrhs, int prec);
 // y = J^{-1} A x with the face exchange of A fused into the preconditioner's
 // load (one leaf per workgroup); tmp receives A x without the exchange.  With

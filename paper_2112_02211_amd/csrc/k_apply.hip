@@ -16,9 +16,17 @@
 // face row of leaf tau on an interior face j adds the neighbour's outgoing
 // impedance on the partner face j'; shared faces list their nodes in the same
 // order on both sides, so no permutation is needed.
+#include <mutex>
+
 #include "hps_internal.h"
 #include "k_common.h"
 #include "k_vec.h"
+
+// Face buffer of the allocation-free apply (hps_apply_noalloc): a file-scope
+// device array, one copy per GPU, held until the process ends.  Host code uses
+// only the address hipGetSymbolAddress returns for it on each device (the
+// array's name on the host is not a device address).
+__device__ __align__(256) double2 scratch[HPS_NOALLOC_SCRATCH_BYTES / sizeof(double2)];
 
 namespace hps {
 namespace {
@@ -407,6 +415,37 @@ int launch_apply(hps_ctx* c, const float2* x, float2* y, int nrhs) {
   int rc = ws_reserve(c, &c->w_g, gbytes);
   if (rc) return rc;
   return apply_with(c, x, y, static_cast<float2*>(c->w_g.ptr), nrhs, nullptr);
+}
+
+int scratch_address(double2** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  if (check_hip(hipGetDevice(&dev), "hipGetDevice")) return HPS_ERR_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return fail(HPS_ERR_DEVICE, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(HPS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    addr[dev] = p;
+  }
+  *out = static_cast<double2*>(addr[dev]);
+  return HPS_OK;
+}
+
+int launch_apply_noalloc(hps_ctx* c, const double2* x, double2* y, int nrhs) {
+  const size_t gbytes = (size_t)nrhs * c->nl * c->nb * sizeof(double2);
+  if (gbytes > (size_t)HPS_NOALLOC_SCRATCH_BYTES)
+    return fail(HPS_ERR_ARG, "hps_apply_noalloc: the face buffer needs " + std::to_string(gbytes) +
+                                 " bytes, more than the static scratch of " +
+                                 std::to_string((size_t)HPS_NOALLOC_SCRATCH_BYTES) + " bytes");
+  if (!c->d_scratch) return fail(HPS_ERR_DEVICE, "hps_apply_noalloc: no scratch address for this context");
+  return apply_with(c, x, y, c->d_scratch, nrhs, nullptr);
 }
 
 }  // namespace hps

@@ -86,6 +86,7 @@ SIGNATURES = {
     "hps_lambdas": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Z)]),
     "hps_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "hps_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hps_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_op_left_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_precond_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "hps_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
@@ -367,6 +368,13 @@ class Context:
         y = torch.empty_like(x) if y is None else y
         self._sync_stream()
         _check(lib().hps_precond_f32(self._h, _dev32(x, "x"), _dev32(y, "y"), self._nrhs(x)))
+        return y
+
+    def apply_noalloc(self, x, y):
+        """y = A x with the face buffer in the library's static device array:
+        the call allocates no device memory (y must be given)."""
+        self._sync_stream()
+        _check(lib().hps_apply_noalloc(self._h, _dev(x, "x"), _dev(y, "y"), self._nrhs(x)))
         return y
 
     def precond(self, x, y=None, prec: str = "fp64"):
