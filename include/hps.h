@@ -167,7 +167,7 @@ typedef struct {
   double* rhs_rel_res; /* NULL, or host array of nrhs: on return the final relative residual of
                           each right-hand side, in the norm its stopping test uses */
   double inner_tol;    /* HPS_SOLVER_IR: relative tolerance of each inner FP32 solve (its
-                          preconditioned residual reduction); 0 = 1e-5 */
+                          preconditioned residual reduction); 0 = 1e-3 */
 } hps_solve_opts;
 
 typedef struct {

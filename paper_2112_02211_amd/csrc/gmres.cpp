@@ -761,7 +761,7 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
       acc.t_setup = c->t_setup;
     if (st) *st = acc;
   } else if (rc == HPS_OK && o.solver == HPS_SOLVER_IR) {
-    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
+    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
     hps_stats acc{};
     for (int r = 0; r < nrhs; ++r) {
       hps_stats one{};

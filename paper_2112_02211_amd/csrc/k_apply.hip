@@ -17,6 +17,7 @@
 // impedance on the partner face j'; shared faces list their nodes in the same
 // order on both sides, so no permutation is needed.
 #include <mutex>
+#include <type_traits>
 
 #include "hps_internal.h"
 #include "k_common.h"
@@ -181,11 +182,15 @@ __device__ __forceinline__ void stage_leaf(const T* __restrict__ xv, double2* __
   using Lf = Leaf<P>;
   constexpr int NN = Lf::NN, NLOAD = (NN + BD - 1) / BD;
   const int m0 = threadIdx.x + R0 * BD;
-  double2 t0, t1, t2, t3, t4, t5, t6, t7;
-#define HPS_LD(k, t) if constexpr (R0 + k < NLOAD) { if ((R0 + k + 1) * BD <= NN || m0 + k * BD < NN) t = ld2(xv, m0 + k * BD); }
-#define HPS_ST(k, t) if constexpr (R0 + k < NLOAD) { if ((R0 + k + 1) * BD <= NN || m0 + k * BD < NN) U[Lf::grid_of(m0 + k * BD)] = t; }
+  // storage-type registers (FP32 values are widened only at the LDS store, so
+  // that no conversion sits between one load and the next); a lane past the
+  // leaf's last value loads that value again and does not store it
+  T t0, t1, t2, t3, t4, t5, t6, t7;
+#define HPS_LD(k, t) if constexpr (R0 + k < NLOAD) { t = xv[min(m0 + k * BD, NN - 1)]; }
+#define HPS_ST(k, t) if constexpr (R0 + k < NLOAD) { if ((R0 + k + 1) * BD <= NN || m0 + k * BD < NN) U[Lf::grid_of(m0 + k * BD)] = widen(t, true); }
   HPS_LD(0, t0) HPS_LD(1, t1) HPS_LD(2, t2) HPS_LD(3, t3)
   HPS_LD(4, t4) HPS_LD(5, t5) HPS_LD(6, t6) HPS_LD(7, t7)
+  __builtin_amdgcn_sched_barrier(0);   // every load issued before the first store
   HPS_ST(0, t0) HPS_ST(1, t1) HPS_ST(2, t2) HPS_ST(3, t3)
   HPS_ST(4, t4) HPS_ST(5, t5) HPS_ST(6, t6) HPS_ST(7, t7)
 #undef HPS_LD
@@ -214,6 +219,15 @@ __global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_s
   // operator groups: right-hand side rhs belongs to operator rhs (its C and eta)
   if (etas) eta = etas[rhs];
   const int64_t cb = rhs * cs + tau * NI;
+  // C at this thread's interior rows, loaded with the leaf (used in the last phase)
+  using CT = std::conditional_t<CC, double2, double>;
+  constexpr int NLC = (NI + BD - 1) / BD;
+  const CT* Cp = static_cast<const CT*>(Cv) + cb;
+  CT c0{}, c1{}, c2{}, c3{};
+  c0 = Cp[min((int)threadIdx.x, NI - 1)];
+  if constexpr (NLC > 1) c1 = Cp[min((int)threadIdx.x + BD, NI - 1)];
+  if constexpr (NLC > 2) c2 = Cp[min((int)threadIdx.x + 2 * BD, NI - 1)];
+  if constexpr (NLC > 3) c3 = Cp[min((int)threadIdx.x + 3 * BD, NI - 1)];
   for (int k = threadIdx.x; k < P * P; k += BD) {
     const int o = k / P, q = k - o * P;
     R[k] = (o == 0) ? -D[q] : (o == P - 1) ? D[(P - 1) * P + q] : -D2[k];
@@ -226,12 +240,26 @@ __global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_s
   __syncthreads();
   axis_pass<P, 2, T>(U, ACC, R, tab, eta, yv, gv);
   __syncthreads();
-  // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat))
-  for (int m = threadIdx.x; m < NI; m += BD) {
+  // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat)); C was loaded
+  // into registers with the leaf, so this phase waits for no memory
+#define HPS_CO(k, c)                                                            \
+  if constexpr (k < NLC) {                                                      \
+    const int m = threadIdx.x + k * BD;                                         \
+    if ((k + 1) * BD <= NI || m < NI) {                                         \
+      const double2 v = U[Lf::grid_of(m)], acc = ACC[m];                        \
+      double2 cu;                                                               \
+      if constexpr (CC) cu = cmul(c, v);                                        \
+      else cu = cscale(v, c);                                                   \
+      st2(yv, m, make_double2(acc.x - cu.x, acc.y - cu.y));                     \
+    }                                                                           \
+  }
+  HPS_CO(0, c0) HPS_CO(1, c1) HPS_CO(2, c2) HPS_CO(3, c3)
+#undef HPS_CO
+  for (int m = threadIdx.x + 4 * BD; m < NI; m += BD) {   // rows past four per thread
     const double2 v = U[Lf::grid_of(m)], acc = ACC[m];
     double2 cu;
-    if (CC) cu = cmul(static_cast<const double2*>(Cv)[cb + m], v);
-    else cu = cscale(v, static_cast<const double*>(Cv)[cb + m]);
+    if constexpr (CC) cu = cmul(Cp[m], v);
+    else cu = cscale(v, Cp[m]);
     st2(yv, m, make_double2(acc.x - cu.x, acc.y - cu.y));
   }
 }

@@ -48,12 +48,21 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, in
   for (int64_t t0 = (int64_t)blockIdx.x * 64; t0 < n; t0 += (int64_t)nblk * 64) {
     const int64_t i = t0 + lane;
     const bool ok = i < n;
-    const double2 uv = ok ? ld2(u, i) : make_double2(0.0, 0.0);
-    const double2 wv = (HASW && ok) ? ld2(w, i) : make_double2(0.0, 0.0);
+    const int64_t is = ok ? i : n - 1;   // in-bounds entry for unconditional FP32 loads
+    const VT ur = ld_tile(u, i, is, ok);
+    const VT wr = ld_tile(w, HASW ? i : 0, HASW ? is : 0, HASW && ok);
+    VT rr[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const bool c = kk < kn && ok;
+      const int ks = k0 + kk < J ? k0 + kk : 0;
+      rr[kk] = ld_tile(V, (int64_t)(k0 + kk) * ldv + i, (int64_t)ks * ldv + is, c);
+    }
+    const double2 uv = widen(ur, ok);
+    const double2 wv = widen(wr, HASW && ok);
     double2 vr[KC];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk)
-      vr[kk] = (kk < kn && ok) ? ld2(V, (int64_t)(k0 + kk) * ldv + i) : make_double2(0.0, 0.0);
+    for (int kk = 0; kk < KC; ++kk) vr[kk] = widen(rr[kk], kk < kn && ok);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       aa[kk].x = fma(vr[kk].x, uv.x, fma(vr[kk].y, uv.y, aa[kk].x));
@@ -119,12 +128,18 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const VT* __restrict__ V,
   for (int64_t t0 = ((int64_t)blockIdx.x * DW + ky) * 64; t0 < n; t0 += (int64_t)nblk * DW * 64) {
     const int64_t i = t0 + lane;
     const bool ok = i < n;
-    const double2 uv = ok ? ld2(u, i) : make_double2(0.0, 0.0);
-    const double2 wv = (HASW && ok) ? ld2(w, i) : make_double2(0.0, 0.0);
-    double2 vr[JM];
+    const int64_t is = ok ? i : n - 1;
+    const VT ur = ld_tile(u, i, is, ok);
+    const VT wr = ld_tile(w, HASW ? i : 0, HASW ? is : 0, HASW && ok);
+    VT rr[JM];
 #pragma unroll
     for (int k = 0; k < JM; ++k)
-      vr[k] = (k < J && ok) ? ld2(V, (int64_t)k * ldv + i) : make_double2(0.0, 0.0);
+      rr[k] = ld_tile(V, (int64_t)k * ldv + i, (int64_t)(k < J ? k : 0) * ldv + is, k < J && ok);
+    const double2 uv = widen(ur, ok);
+    const double2 wv = widen(wr, HASW && ok);
+    double2 vr[JM];
+#pragma unroll
+    for (int k = 0; k < JM; ++k) vr[k] = widen(rr[k], k < J && ok);
 #pragma unroll
     for (int k = 0; k < JM; ++k) {
       aa[k].x = fma(vr[k].x, uv.x, fma(vr[k].y, uv.y, aa[k].x));
@@ -460,10 +475,13 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t 
     // eight basis vectors per round, the last round predicated (its loads still
     // issue together; coefficients beyond J are zero and so are skipped loads)
     for (int l = 0; l < J; l += 8) {
-      double2 v[8];
+      VT r[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        v[q] = (l + q < J) ? ld2(V, (int64_t)(l + q) * ldv + i) : make_double2(0.0, 0.0);
+        r[q] = ld_tile(V, (int64_t)(l + q) * ldv + i, (int64_t)l * ldv + i, l + q < J);
+      double2 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = widen(r[q], l + q < J);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double2 x = ca[l + q], y = cb[l + q];

@@ -90,10 +90,13 @@ __global__ __launch_bounds__(RT) void k_mupdate(const VT* __restrict__ V, int64_
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)nblk * RT) {
     double2 a = ld2(w, i);
     for (int k = 0; k < K; k += 8) {
-      double2 v[8];
+      VT r[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        v[u] = (k + u < K) ? ld2(V, (int64_t)(k + u) * ldv + i) : make_double2(0.0, 0.0);
+        r[u] = ld_tile(V, (int64_t)(k + u) * ldv + i, (int64_t)k * ldv + i, k + u < K);
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = widen(r[u], k + u < K);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const double2 c = cs[k + u];

@@ -220,6 +220,67 @@ __device__ __forceinline__ void cmode(const double2* in, double2* out, const dou
   else cmode_el<P, AX, SCALE>(in, out, Ml, Ec, lm);
 }
 
+// The leaf's loads are issued before any of them is used: up to eight interior
+// and four face values per thread (plus, with the exchange, the neighbour's
+// outgoing impedance on the partner face) in named registers of the storage
+// type (an indexed array would go to LDS or scratch), all issued before the
+// first LDS store (a scheduling barrier keeps the compiler from interleaving
+// them), then widened and stored: interior values to the padded tensor T, face
+// values to G.  A lane past the end loads an in-bounds value again and stores
+// nothing.  Larger leaves stage the remaining values in plain loops.
+template <int P, typename VT, bool HASG>
+__device__ __forceinline__ void stage_leaf(const VT* __restrict__ xv, const VT* __restrict__ gb,
+                                           const int* nb6, int64_t tau, double2* __restrict__ T,
+                                           double2* __restrict__ G) {
+  using S = SL<P>;
+  constexpr int N1 = S::N1, L = S::L, NI = S::NI, NB = S::NB, BD = S::BD;
+  constexpr int NLI = (NI + BD - 1) / BD, NLB = (NB + BD - 1) / BD;
+  const int t = threadIdx.x;
+  VT a0, a1, a2, a3, a4, a5, a6, a7, x0, x1, x2, x3, g0, g1, g2, g3;
+#define HPS_LI(k, r) if constexpr (k < NLI) { r = xv[min(t + k * BD, NI - 1)]; }
+#define HPS_LB(k, xr, gr)                                                      \
+  if constexpr (k < NLB) {                                                     \
+    const int m = min(t + k * BD, NB - 1), f = m / L, pos = m - f * L;         \
+    xr = xv[NI + m];                                                            \
+    if constexpr (HASG) {                                                       \
+      const int t2 = nb6[f];                                                    \
+      gr = gb[(t2 >= 0 ? (int64_t)t2 : tau) * NB + (f ^ 1) * L + pos];         \
+    }                                                                           \
+  }
+#define HPS_SI(k, r)                                                                     \
+  if constexpr (k < NLI) {                                                               \
+    const int m = t + k * BD;                                                            \
+    if ((k + 1) * BD <= NI || m < NI) T[lidx<P>(m % N1, (m / N1) % N1, m / L)] = widen(r, true); \
+  }
+#define HPS_SB(k, xr, gr)                                                      \
+  if constexpr (k < NLB) {                                                     \
+    const int m = t + k * BD;                                                  \
+    if ((k + 1) * BD <= NB || m < NB) {                                        \
+      double2 v = widen(xr, true);                                             \
+      if (HASG && nb6[m / L] >= 0) v = cadd(v, widen(gr, true));               \
+      G[m] = v;                                                                \
+    }                                                                          \
+  }
+  HPS_LI(0, a0) HPS_LI(1, a1) HPS_LI(2, a2) HPS_LI(3, a3)
+  HPS_LI(4, a4) HPS_LI(5, a5) HPS_LI(6, a6) HPS_LI(7, a7)
+  HPS_LB(0, x0, g0) HPS_LB(1, x1, g1) HPS_LB(2, x2, g2) HPS_LB(3, x3, g3)
+  __builtin_amdgcn_sched_barrier(0);
+  HPS_SI(0, a0) HPS_SI(1, a1) HPS_SI(2, a2) HPS_SI(3, a3)
+  HPS_SI(4, a4) HPS_SI(5, a5) HPS_SI(6, a6) HPS_SI(7, a7)
+  HPS_SB(0, x0, g0) HPS_SB(1, x1, g1) HPS_SB(2, x2, g2) HPS_SB(3, x3, g3)
+#undef HPS_LI
+#undef HPS_LB
+#undef HPS_SI
+#undef HPS_SB
+  for (int m = t + 8 * BD; m < NI; m += BD) T[lidx<P>(m % N1, (m / N1) % N1, m / L)] = widen(xv[m], true);
+  for (int m = t + 4 * BD; m < NB; m += BD) {
+    double2 v = widen(xv[NI + m], true);
+    const int f = m / L;
+    if (HASG && nb6[f] >= 0) v = cadd(v, widen(gb[(int64_t)nb6[f] * NB + (f ^ 1) * L + (m - f * L)], true));
+    G[m] = v;
+  }
+}
+
 // g != null: x is A v without the face exchange, added here while loading
 // (x_b += the neighbour's outgoing impedance on the partner face), as in the
 // dense-block kernel.  Operator groups: right-hand side rhs belongs to
@@ -244,31 +305,29 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   const double2* st = sep + (os ? (int64_t)rhs * S::ST : 0);
   const double2* Wc = st;          // global: read at wavefront-uniform addresses
   const double2* Vc = st + L;
-  for (int k = threadIdx.x; k < S::CTN; k += BD) CT[k] = st[2 * L - S::CT0 + k];
-  for (int k = threadIdx.x; k < 4 * N1; k += BD) {
-    const int t = k % N1, w = k / N1;
-    double v;
-    if (w == 0) v = tab[tab_off_D(P) + 1 + t];                      // D[0][1 + t]
-    else if (w == 1) v = tab[tab_off_D(P) + (P - 1) * P + 1 + t];   // D[p-1][1 + t]
-    else if (w == 2) v = tab[tab_off_D2(P) + (t + 1) * P];          // D2[1 + t][0]
-    else v = tab[tab_off_D2(P) + (t + 1) * P + P - 1];              // D2[1 + t][p-1]
-    RT[k] = v;
-  }
-  for (int m = threadIdx.x; m < NI; m += BD) {
-    const int i = m % N1, j = (m / N1) % N1, k = m / L;
-    T[lidx<P>(i, j, k)] = ld2(xv, m);
-  }
-  for (int m = threadIdx.x; m < NB; m += BD) {
-    double2 v = ld2(xv, NI + m);
-    if (g) {
-      const int f = m / L, pos = m - f * L;
-      const int t2 = nbr[tau * 6 + f];
-      if (t2 >= 0) {
-        const double2 gv = ld2(g, (rhs * nl + t2) * NB + (f ^ 1) * L + pos);
-        v = make_double2(v.x + gv.x, v.y + gv.y);
-      }
-    }
-    G[m] = v;
+  // table entries: thread k loads entry k of Ec | Fi (| Wc | Vc) and of
+  // Dlo | Dhi | C0 | C1 from in-bounds (clamped) addresses without a branch, so
+  // that these loads and the leaf's are all in flight together; they are
+  // stored to LDS after the leaf's values
+  static_assert(4 * N1 <= BD, "table rows per thread");
+  const int kr = min((int)threadIdx.x, 4 * N1 - 1), tr = kr % N1, wr = kr / N1;
+  const int toff = wr == 0 ? tab_off_D(P) + 1 + tr                  // D[0][1 + t]
+                 : wr == 1 ? tab_off_D(P) + (P - 1) * P + 1 + tr    // D[p-1][1 + t]
+                 : wr == 2 ? tab_off_D2(P) + (tr + 1) * P           // D2[1 + t][0]
+                           : tab_off_D2(P) + (tr + 1) * P + P - 1;  // D2[1 + t][p-1]
+  const double rt = tab[toff];
+  double2 ct = make_double2(0.0, 0.0);
+  if constexpr (S::CTN <= BD) ct = st[2 * L - S::CT0 + min((int)threadIdx.x, S::CTN - 1)];
+  int nb6[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) nb6[f] = g ? nbr[tau * 6 + f] : -1;
+  if (g) stage_leaf<P, VT, true>(xv, g + (int64_t)rhs * nl * NB, nb6, tau, T, G);
+  else stage_leaf<P, VT, false>(xv, nullptr, nb6, tau, T, G);
+  if ((int)threadIdx.x < 4 * N1) RT[threadIdx.x] = rt;
+  if constexpr (S::CTN <= BD) {
+    if ((int)threadIdx.x < S::CTN) CT[threadIdx.x] = ct;
+  } else {
+    for (int k = threadIdx.x; k < S::CTN; k += BD) CT[k] = st[2 * L - S::CT0 + k];
   }
   __syncthreads();
   const double2* Ec = CT + S::CT0;
