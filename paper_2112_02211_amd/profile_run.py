@@ -104,6 +104,84 @@ def run(a):
     print(f"copy bytes read = written = {n * 4}")
 
 
+def sep(a):
+    """The kernels of one step of the separable solve, --launches times each
+    after one warm-up: the left operator J^-1 A (sweep, then the separable J^-1
+    with the exchange fused into its load) on complex FP64 vectors and on
+    complex FP32 vectors (the inner step of iterative refinement)."""
+    import numpy as np
+    import torch
+    from paper_2112_02211_amd import hps, problems as P
+
+    prob = P.workload(a.workload)
+    ctx = hps.Context.from_problem(prob, block_precs=("separable",))
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal(ctx.N) + 1j * rng.standard_normal(ctx.N)).cuda()
+    y = torch.empty_like(x)
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for name, fn in (("op_left_fp64", lambda: ctx.op_left(x, y)),
+                     ("op_left_fp32", lambda: ctx.op_left_f32(x32, y32))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.launches):
+            fn()
+        torch.cuda.synchronize()
+        print(f"{name}: {(time.perf_counter() - t0) / a.launches * 1e3:.4f} ms per launch", flush=True)
+
+
+SQ_DOC = {
+    "SQ_WAVES": "waves launched",
+    "SQ_WAVE_CYCLES": "wave-cycles resident (summed over waves)",
+    "SQ_BUSY_CYCLES": "cycles the sequencers were busy",
+    "SQ_INSTS_VALU": "vector ALU instructions",
+    "SQ_ACTIVE_INST_VALU": "cycles a wave issued VALU work (summed over waves)",
+    "SQ_INSTS_LDS": "LDS instructions",
+    "SQ_LDS_BANK_CONFLICT": "cycles stalled on LDS bank conflicts",
+    "SQ_INSTS_VMEM_RD": "vector memory read instructions",
+    "GRBM_GUI_ACTIVE": "GPU busy cycles",
+}
+
+
+def sq_summary(a):
+    """Per-kernel sequencer counters (one --pmc run, csv in --pmc-dir) of the
+    kernels whose names contain the --kernels substrings: averages per
+    dispatch, and the derived occupancy (resident waves per CU), VALU-active
+    and LDS-conflict fractions."""
+    path = os.path.join(a.pmc_dir, "run_counter_collection.csv")
+    rows = list(csv.DictReader(open(path)))
+    by = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        by[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    L = [f"# {a.title}", "#", "# command (R = repository root):", "#   cd /tmp && export TMPDIR=/tmp",
+         f"#   {a.cmd}", "#"]
+    for k, name in SQ_DOC.items():
+        L.append(f"# {k}: {name}")
+    L.append("#")
+    for kern, ctrs in sorted(by.items()):
+        if not any(s in kern for s in a.kernels.split(",")):
+            continue
+        n = max(len(v) for v in ctrs.values())
+        avg = {c: statistics.mean(v) for c, v in ctrs.items()}
+        L.append(f"kernel: {kern[:160]}")
+        L.append(f"  dispatches: {n}")
+        for c in SQ_DOC:
+            if c in avg:
+                L.append(f"  {c}: {avg[c]:.0f}")
+        # ratios of counters accumulated the same way (the absolute units of the
+        # cycle counters are the hardware's; only the ratios are read here)
+        if "SQ_ACTIVE_INST_VALU" in avg and "SQ_WAVE_CYCLES" in avg and avg["SQ_WAVE_CYCLES"] > 0:
+            L.append(f"  VALU-issue cycles per resident wave-cycle: {avg['SQ_ACTIVE_INST_VALU'] / avg['SQ_WAVE_CYCLES']:.3f}")
+        if "SQ_LDS_BANK_CONFLICT" in avg and "SQ_INSTS_LDS" in avg and avg["SQ_INSTS_LDS"] > 0:
+            L.append(f"  LDS bank-conflict cycles per LDS instruction: {avg['SQ_LDS_BANK_CONFLICT'] / avg['SQ_INSTS_LDS']:.3f}")
+        if "SQ_INSTS_VALU" in avg and "SQ_WAVES" in avg and avg["SQ_WAVES"] > 0:
+            L.append(f"  VALU instructions per wave: {avg['SQ_INSTS_VALU'] / avg['SQ_WAVES']:.0f}")
+    with open(a.out, "w") as f:
+        f.write("\n".join(L) + "\n")
+    print("\n".join(L))
+
+
 def _copy_phase(a):
     import torch
     n = a.copy_mib * (1 << 20) // 4
@@ -372,7 +450,7 @@ def trace_summary(a):
          f"{'max_us':>9s} {'pct':>6s}"]
     for r in rows[:a.rows]:
         name = r["Name"].replace("hps::(anonymous namespace)::", "").replace(
-            "HIP_vector_type<double, 2u>", "double2")[:70]
+            "HIP_vector_type<double, 2u>", "double2").replace("HIP_vector_type<float, 2u>", "float2")[:70]
         L.append(f"  {name:70s} {r['Calls']:>6s} {float(r['TotalDurationNs']) / 1e6:10.2f} "
                  f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:9.2f} "
                  f"{float(r['MaxNs']) / 1e3:9.2f} {100 * float(r['TotalDurationNs']) / tot:6.2f}")
@@ -385,7 +463,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", nargs="?", default="run",
                     choices=("run", "pmc-summary", "trace-summary", "arnoldi", "arnoldi-summary", "gemm",
-                             "gemm-summary"))
+                             "gemm-summary", "sep", "sq-summary"))
     ap.add_argument("--workload", default="bumps_8x8x8_p10")
     ap.add_argument("--launches", type=int, default=4)
     ap.add_argument("--iti", action="store_true",
@@ -403,9 +481,12 @@ def main():
     ap.add_argument("--cmd", default="")
     ap.add_argument("--title", default="rocprofv3 kernel statistics")
     ap.add_argument("--rows", type=int, default=24)
+    ap.add_argument("--kernels", default="k_apply_sweep,k_precond_sep",
+                    help="sq-summary: comma-separated kernel name substrings")
     a = ap.parse_args()
     {"run": run, "pmc-summary": pmc_summary, "trace-summary": trace_summary, "arnoldi": arnoldi,
-     "arnoldi-summary": arnoldi_summary, "gemm": gemm, "gemm-summary": gemm_summary}[a.mode](a)
+     "arnoldi-summary": arnoldi_summary, "gemm": gemm, "gemm-summary": gemm_summary, "sep": sep,
+     "sq-summary": sq_summary}[a.mode](a)
 
 
 if __name__ == "__main__":

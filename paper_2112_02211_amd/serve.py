@@ -161,7 +161,9 @@ class ServeConfig:
     precond_prec: str = "fp64"
     restart: int = 50                # Krylov dimension of a cycle = one tick
     tol: float = 1e-8
-    solver: str = "gmres"            # single right-hand side: "gmres" (left, FP64 J^-1) or "fgmres"
+    solver: str = "gmres"            # single right-hand side: "gmres" (left, FP64 J^-1), "fgmres",
+                                     # or "ir" (iterative refinement with FP32 inner solves; needs
+                                     # block_prec "separable"; a tick is one inner cycle)
     max_batch: int = 64
     max_iters: int = 20000           # per request; beyond it the request is returned unconverged
     keep_solution_on_host: bool = True

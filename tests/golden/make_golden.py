@@ -8,14 +8,17 @@ iteration count:
 
     python tests/golden/make_golden.py bumps_8x8x8_p10
     python tests/golden/make_golden.py bumps_16x16x16_p12 --bucket 1e-2 --nsamp 8192
-    python tests/golden/make_golden.py bumps_16x16x16_p10_64rhs --bucket 1e-2 --rhs 0,21,42,63
+    python tests/golden/make_golden.py bumps_16x16x16_p10_64rhs --bucket 1e-2 --rhs 0,31,63 --restart 50
+    python tests/golden/make_golden.py request_stream --request 39 --bucket 1e-2
 
 --bucket delta shares one LU factorization among the leaves whose homogenized
 lambda round to the same point of a grid of spacing delta kappa^2 (the oracle's
 lambda buckets).  That changes only the preconditioner, so GMRES converges to
 the same u = A^{-1} b; it keeps the factorizations of 4096 leaves of 1600
 unknowns within host memory.  With several --rhs indices (sources of the
-workload) the file holds one row of samples per source.
+workload) the file holds one row of samples per source.  --request RID takes
+request RID of the serving stream (problems.request_stream, seed 5) instead
+of a named workload and writes request_stream_r<RID>_oracle.npz.
 """
 import argparse
 import os
@@ -54,8 +57,12 @@ def solve_one(prob, op, M, which, tol, restart, t0):
 
 
 def main(name: str, tol: float = 1e-13, nsamp: int = 4096, bucket: float = 0.0,
-         rhs=(0,), restart=None):
-    prob = P.workload(name)
+         rhs=(0,), restart=None, request=None):
+    if request is not None:
+        prob = P.request_stream(request + 1, rate=1.0, seed=5)[request].prob
+        name = f"request_stream_r{request}"
+    else:
+        prob = P.workload(name)
     t0 = time.time()
     op = O.build(prob)
     print(f"{name}: N={op.d.N} nnz={op.A.nnz} built {time.time() - t0:.0f}s", flush=True)
@@ -91,5 +98,6 @@ if __name__ == "__main__":
     ap.add_argument("--bucket", type=float, default=0.0)
     ap.add_argument("--rhs", default="0")
     ap.add_argument("--restart", type=int, default=None)
+    ap.add_argument("--request", type=int, default=None)
     a = ap.parse_args()
-    main(a.name, a.tol, a.nsamp, a.bucket, tuple(int(v) for v in a.rhs.split(",")), a.restart)
+    main(a.name, a.tol, a.nsamp, a.bucket, tuple(int(v) for v in a.rhs.split(",")), a.restart, a.request)
