@@ -12,6 +12,15 @@
 namespace hps {
 namespace {
 
+// Non-temporal hints (template flag NT) for long vectors: the basis loads of
+// both passes and the update pass's stores of V[J] and u go around the caches,
+// which a basis of more than a few hundred MB leaves before it is read again.
+// Measured on 6.5M-entry vectors (16^3 leaves, p = 12): update pass 5.27 ->
+// 6.01 TB/s, solve 332 -> 321 ms; on 0.46M-entry ones (8^3, p = 10), whose
+// vectors live in the last-level cache, 7 % slower, hence the threshold.
+// Non-temporal loads of u and w as well were slower in both.
+constexpr int64_t kNtVector = int64_t(1) << 21;
+
 constexpr int DW = 8;          // wavefronts of the reduction workgroup (split over k)
 constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
 constexpr int UT = 256;        // update-pass (and small-step) workgroup
@@ -25,7 +34,7 @@ constexpr int64_t kLongVector = 1 << 22; // ... of at least this many entries sp
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
 // tile; wavefront 0 also accumulates c and d.
-template <int KC, bool HASW, typename VT>
+template <int KC, bool HASW, typename VT, bool NT>
 __global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, int64_t ldv,
                                                     int64_t vbs, int J, const VT* __restrict__ u,
                                                     int64_t ubs, const VT* __restrict__ w,
@@ -56,7 +65,7 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, in
     for (int kk = 0; kk < KC; ++kk) {
       const bool c = kk < kn && ok;
       const int ks = k0 + kk < J ? k0 + kk : 0;
-      rr[kk] = ld_tile(V, (int64_t)(k0 + kk) * ldv + i, (int64_t)ks * ldv + is, c);
+      rr[kk] = ld_tile_h<NT>(V, (int64_t)(k0 + kk) * ldv + i, (int64_t)ks * ldv + is, c);
     }
     const double2 uv = widen(ur, ok);
     const double2 wv = widen(wr, HASW && ok);
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, in
 // basis entries, u and w of its tile once (the split over basis vectors has
 // every wavefront read u and w, and leaves wavefronts idle when J < DW).  The
 // DW wavefront sums are added in a fixed order through LDS.
-template <int JM, bool HASW, typename VT>
+template <int JM, bool HASW, typename VT, bool NT>
 __global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const VT* __restrict__ V, int64_t ldv,
                                                        int64_t vbs, int J, const VT* __restrict__ u,
                                                        int64_t ubs, const VT* __restrict__ w,
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const VT* __restrict__ V,
     VT rr[JM];
 #pragma unroll
     for (int k = 0; k < JM; ++k)
-      rr[k] = ld_tile(V, (int64_t)k * ldv + i, (int64_t)(k < J ? k : 0) * ldv + is, k < J && ok);
+      rr[k] = ld_tile_h<NT>(V, (int64_t)k * ldv + i, (int64_t)(k < J ? k : 0) * ldv + is, k < J && ok);
     const double2 uv = widen(ur, ok);
     const double2 wv = widen(wr, HASW && ok);
     double2 vr[JM];
@@ -449,7 +458,7 @@ __global__ __launch_bounds__(UT) void k_dcgs_small(DcgsState* __restrict__ S, in
 
 // Update pass of step J, with the small step in workgroup 0 of each right-hand side:
 // V[J] = (u - V_{0..J-1} a) / beta;  u <- (w - V_{0..J-1} b - V[J] vjw) / beta.
-template <typename VT>
+template <typename VT, bool NT>
 __global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t ldv, int64_t vbs,
                                                     int J, VT* __restrict__ u, int64_t ubs,
                                                     const VT* __restrict__ w, int64_t wbs,
@@ -478,7 +487,7 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t 
       VT r[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        r[q] = ld_tile(V, (int64_t)(l + q) * ldv + i, (int64_t)l * ldv + i, l + q < J);
+        r[q] = ld_tile_h<NT>(V, (int64_t)(l + q) * ldv + i, (int64_t)l * ldv + i, l + q < J);
       double2 v[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = widen(r[q], l + q < J);
@@ -491,11 +500,12 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t 
         sb.y = fma(v[q].x, y.y, fma(v[q].y, y.x, sb.y));
       }
     }
-    const double2 uv = ld2(u, i), wv = ld2(w, i);
+    const double2 uv = widen(ld_tile(u, i, i, true), true);
+    const double2 wv = widen(ld_tile(w, i, i, true), true);
     const double2 vj = make_double2((uv.x - sa.x) * inv, (uv.y - sa.y) * inv);
     const double2 t = cmul(vj, cj);
-    st2(V, (int64_t)J * ldv + i, vj);
-    st2(u, i, make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv));
+    st2_h<NT>(V, (int64_t)J * ldv + i, vj);
+    st2_h<NT>(u, i, make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv));
   }
 }
 
@@ -552,27 +562,36 @@ int dcgs_reduce(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int J, const 
   const int nblk = (int)std::min<int64_t>(tiles, kc <= 2 ? (mid ? 512 : 1024) : (mid ? 256 : 512));
   dim3 grid(nblk, 1, nbatch);
   const bool hw = w != nullptr;
-#define HPS_DR(KC)                                                                              \
+  const bool nt = n >= kNtVector;
+#define HPS_DR1(KC, NT)                                                                       \
   do {                                                                                          \
     if (hw)                                                                                     \
-      hipLaunchKernelGGL((k_dcgs_reduce<KC, true, VT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, u, \
-                         ubs, w, wbs, n, rb.part);                                              \
+      hipLaunchKernelGGL((k_dcgs_reduce<KC, true, VT, NT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, \
+                         J, u, ubs, w, wbs, n, rb.part);                                        \
     else                                                                                        \
-      hipLaunchKernelGGL((k_dcgs_reduce<KC, false, VT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, \
-                         u, ubs, w, wbs, n, rb.part);                                           \
+      hipLaunchKernelGGL((k_dcgs_reduce<KC, false, VT, NT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, \
+                         J, u, ubs, w, wbs, n, rb.part);                                        \
   } while (0)
+#define HPS_DR(KC) do { if (nt) HPS_DR1(KC, true); else HPS_DR1(KC, false); } while (0)
   // short bases on long vectors: tiles split over the wavefronts (measured:
   // the split over basis vectors reached about 2.5 TB/s for J <= 8 on 1e9-entry
   // vectors, where half the wavefronts idle and all re-read u and w)
   if (J <= kShortBasis && n >= kLongVector) {
-    if (hw)
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT>), grid, dim3(DT), 0, c->stream, V, ldv,
-                         vbs, J, u, ubs, w, wbs, n, rb.part);
+    if (hw && nt)
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT, true>), grid, dim3(DT), 0, c->stream, V,
+                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
+    else if (hw)
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT, false>), grid, dim3(DT), 0, c->stream, V,
+                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
+    else if (nt)
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT, true>), grid, dim3(DT), 0, c->stream, V,
+                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
     else
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT>), grid, dim3(DT), 0, c->stream, V, ldv,
-                         vbs, J, u, ubs, w, wbs, n, rb.part);
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT, false>), grid, dim3(DT), 0, c->stream, V,
+                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
   } else if (kc <= 2) HPS_DR(2); else if (kc <= 4) HPS_DR(4); else HPS_DR(8);
 #undef HPS_DR
+#undef HPS_DR1
   int rc = check_hip(hipGetLastError(), "k_dcgs_reduce");
   if (rc) return rc;
   const int nslots = (hw ? 2 * J : J) + (hw ? 2 : 1);
@@ -618,9 +637,13 @@ int dcgs_update(hps_ctx* c, VT* V, int64_t ldv, int64_t vbs, int J, VT* u, int64
   TimedPair tp;
   int rc = timing_pair(c, 4, &tp);
   if (rc) return rc;
-  rc = check_hip(launch_k(c, tp.start, tp.stop, k_dcgs_update<VT>, dim3(nblk, 1, nbatch), dim3(UT), V, ldv,
-                          vbs, J, u, ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag,
-                          kBreakdownTol),
+  rc = check_hip(n >= kNtVector
+                     ? launch_k(c, tp.start, tp.stop, k_dcgs_update<VT, true>, dim3(nblk, 1, nbatch),
+                                dim3(UT), V, ldv, vbs, J, u, ubs, w, wbs, n, S, flexible, res_out,
+                                (unsigned long long)tag, kBreakdownTol)
+                     : launch_k(c, tp.start, tp.stop, k_dcgs_update<VT, false>, dim3(nblk, 1, nbatch),
+                                dim3(UT), V, ldv, vbs, J, u, ubs, w, wbs, n, S, flexible, res_out,
+                                (unsigned long long)tag, kBreakdownTol),
                  "k_dcgs_update");
   if (rc) {
     timing_drop(c, tp);

@@ -33,6 +33,45 @@ __device__ __forceinline__ float2 ld_tile(const float2* p, int64_t i, int64_t i_
   return p[c ? i : i_safe];
 }
 __device__ __forceinline__ double2 widen(double2 v, bool) { return v; }
+// Non-temporal forms (streamed data that is not read again soon: the Krylov
+// basis of a long vector): the same loads and stores with the non-temporal hint.
+typedef double vnt_d2 __attribute__((ext_vector_type(2)));
+typedef float vnt_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt2(const double2* p) {
+  const vnt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const vnt_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_nt2(const float2* p) {
+  const vnt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const vnt_f2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt2(double2* p, double2 v) {
+  vnt_d2 t;
+  t.x = v.x;
+  t.y = v.y;
+  __builtin_nontemporal_store(t, reinterpret_cast<vnt_d2*>(p));
+}
+__device__ __forceinline__ void st_nt2(float2* p, double2 v) {
+  vnt_f2 t;
+  t.x = (float)v.x;
+  t.y = (float)v.y;
+  __builtin_nontemporal_store(t, reinterpret_cast<vnt_f2*>(p));
+}
+template <bool NT>
+__device__ __forceinline__ double2 ld_tile_h(const double2* p, int64_t i, int64_t i_safe, bool c) {
+  if constexpr (NT) return c ? ld_nt2(p + i) : make_double2(0.0, 0.0);
+  else return ld_tile(p, i, i_safe, c);
+}
+template <bool NT>
+__device__ __forceinline__ float2 ld_tile_h(const float2* p, int64_t i, int64_t i_safe, bool c) {
+  if constexpr (NT) return ld_nt2(p + (c ? i : i_safe));
+  else return ld_tile(p, i, i_safe, c);
+}
+template <bool NT, typename VT>
+__device__ __forceinline__ void st2_h(VT* p, int64_t i, double2 v) {
+  if constexpr (NT) st_nt2(p + i, v);
+  else st2(p, i, v);
+}
 __device__ __forceinline__ double2 widen(float2 v, bool c) {
   return c ? make_double2((double)v.x, (double)v.y) : make_double2(0.0, 0.0);
 }
