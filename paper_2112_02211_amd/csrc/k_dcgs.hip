@@ -12,14 +12,21 @@
 namespace hps {
 namespace {
 
-// Non-temporal hints (template flag NT) for long vectors: the basis loads of
-// both passes and the update pass's stores of V[J] and u go around the caches,
-// which a basis of more than a few hundred MB leaves before it is read again.
-// Measured on 6.5M-entry vectors (16^3 leaves, p = 12): update pass 5.27 ->
-// 6.01 TB/s, solve 332 -> 321 ms; on 0.46M-entry ones (8^3, p = 10), whose
-// vectors live in the last-level cache, 7 % slower, hence the threshold.
-// Non-temporal loads of u and w as well were slower in both.
+// Non-temporal hints (template flag NT) for long vectors: the update pass's
+// basis loads and its stores of V[J] and u, and the basis loads of the
+// short-basis reduction, go around the caches, which a basis of more than a few
+// hundred MB leaves before it is read again.  Measured on 6.5M-entry vectors
+// (16^3 leaves, p = 12): update pass 551 -> 483 us, short-basis reduction
+// 133 -> 112 us; on 0.46M-entry ones (8^3, p = 10), whose vectors live in the
+// last-level cache, the solve was 7 % slower, hence the threshold.  The hint
+// slowed the other reductions (2-10 %: there eight wavefronts share u and w
+// through the cache) and non-temporal loads of u and w slowed every pass.
 constexpr int64_t kNtVector = int64_t(1) << 21;
+// Tiles per pass of the split-over-basis reduction (all their loads issued
+// before the first use): two for FP32-stored vectors, whose 8-byte loads keep
+// half as many bytes in flight (inner solve of iterative refinement on 6.5M
+// entries: 236 -> 228 ms), one for FP64 (two: 1.3 % slower).
+template <typename VT> constexpr int red_tiles() { return sizeof(VT) == 8 ? 2 : 1; }
 
 constexpr int DW = 8;          // wavefronts of the reduction workgroup (split over k)
 constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
@@ -34,7 +41,7 @@ constexpr int64_t kLongVector = 1 << 22; // ... of at least this many entries sp
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
 // tile; wavefront 0 also accumulates c and d.
-template <int KC, bool HASW, typename VT, bool NT>
+template <int KC, bool HASW, typename VT>
 __global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, int64_t ldv,
                                                     int64_t vbs, int J, const VT* __restrict__ u,
                                                     int64_t ubs, const VT* __restrict__ w,
@@ -54,38 +61,47 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce(const VT* __restrict__ V, in
   double cc = 0.0;
   double2 dd = make_double2(0.0, 0.0);
   const unsigned nblk = gridDim.x;
-  for (int64_t t0 = (int64_t)blockIdx.x * 64; t0 < n; t0 += (int64_t)nblk * 64) {
-    const int64_t i = t0 + lane;
-    const bool ok = i < n;
-    const int64_t is = ok ? i : n - 1;   // in-bounds entry for unconditional FP32 loads
-    const VT ur = ld_tile(u, i, is, ok);
-    const VT wr = ld_tile(w, HASW ? i : 0, HASW ? is : 0, HASW && ok);
-    VT rr[KC];
+  constexpr int RT = red_tiles<VT>();
+  for (int64_t t0 = (int64_t)blockIdx.x * 64 * RT; t0 < n; t0 += (int64_t)nblk * 64 * RT) {
+    VT ur[RT], wr[RT], rr[RT][KC];
+    bool okt[RT];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const bool c = kk < kn && ok;
-      const int ks = k0 + kk < J ? k0 + kk : 0;
-      rr[kk] = ld_tile_h<NT>(V, (int64_t)(k0 + kk) * ldv + i, (int64_t)ks * ldv + is, c);
-    }
-    const double2 uv = widen(ur, ok);
-    const double2 wv = widen(wr, HASW && ok);
-    double2 vr[KC];
+    for (int s = 0; s < RT; ++s) {
+      const int64_t i = t0 + s * 64 + lane;
+      const bool ok = i < n;
+      const int64_t is = ok ? i : n - 1;   // in-bounds entry for unconditional FP32 loads
+      okt[s] = ok;
+      ur[s] = ld_tile(u, i, is, ok);
+      wr[s] = VT{};   // no load at all without w (w is null then)
+      if constexpr (HASW) wr[s] = ld_tile(w, i, is, ok);
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) vr[kk] = widen(rr[kk], kk < kn && ok);
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      aa[kk].x = fma(vr[kk].x, uv.x, fma(vr[kk].y, uv.y, aa[kk].x));
-      aa[kk].y = fma(vr[kk].x, uv.y, fma(-vr[kk].y, uv.x, aa[kk].y));
-      if (HASW) {
-        ab[kk].x = fma(vr[kk].x, wv.x, fma(vr[kk].y, wv.y, ab[kk].x));
-        ab[kk].y = fma(vr[kk].x, wv.y, fma(-vr[kk].y, wv.x, ab[kk].y));
+      for (int kk = 0; kk < KC; ++kk) {
+        const bool c = kk < kn && ok;
+        const int ks = k0 + kk < J ? k0 + kk : 0;
+        rr[s][kk] = ld_tile(V, (int64_t)(k0 + kk) * ldv + i, (int64_t)ks * ldv + is, c);
       }
     }
-    if (ky == 0) {
-      cc = fma(uv.x, uv.x, fma(uv.y, uv.y, cc));
-      if (HASW) {
-        dd.x = fma(uv.x, wv.x, fma(uv.y, wv.y, dd.x));
-        dd.y = fma(uv.x, wv.y, fma(-uv.y, wv.x, dd.y));
+#pragma unroll
+    for (int s = 0; s < RT; ++s) {
+      const bool ok = okt[s];
+      const double2 uv = widen(ur[s], ok);
+      const double2 wv = widen(wr[s], HASW && ok);
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const double2 vr = widen(rr[s][kk], kk < kn && ok);
+        aa[kk].x = fma(vr.x, uv.x, fma(vr.y, uv.y, aa[kk].x));
+        aa[kk].y = fma(vr.x, uv.y, fma(-vr.y, uv.x, aa[kk].y));
+        if (HASW) {
+          ab[kk].x = fma(vr.x, wv.x, fma(vr.y, wv.y, ab[kk].x));
+          ab[kk].y = fma(vr.x, wv.y, fma(-vr.y, wv.x, ab[kk].y));
+        }
+      }
+      if (ky == 0) {
+        cc = fma(uv.x, uv.x, fma(uv.y, uv.y, cc));
+        if (HASW) {
+          dd.x = fma(uv.x, wv.x, fma(uv.y, wv.y, dd.x));
+          dd.y = fma(uv.x, wv.y, fma(-uv.y, wv.x, dd.y));
+        }
       }
     }
   }
@@ -139,7 +155,8 @@ __global__ __launch_bounds__(DT) void k_dcgs_reduce_es(const VT* __restrict__ V,
     const bool ok = i < n;
     const int64_t is = ok ? i : n - 1;
     const VT ur = ld_tile(u, i, is, ok);
-    const VT wr = ld_tile(w, HASW ? i : 0, HASW ? is : 0, HASW && ok);
+    VT wr{};   // no load at all without w (w is null then)
+    if constexpr (HASW) wr = ld_tile(w, i, is, ok);
     VT rr[JM];
 #pragma unroll
     for (int k = 0; k < JM; ++k)
@@ -562,36 +579,28 @@ int dcgs_reduce(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int J, const 
   const int nblk = (int)std::min<int64_t>(tiles, kc <= 2 ? (mid ? 512 : 1024) : (mid ? 256 : 512));
   dim3 grid(nblk, 1, nbatch);
   const bool hw = w != nullptr;
-  const bool nt = n >= kNtVector;
-#define HPS_DR1(KC, NT)                                                                       \
+#define HPS_DR(KC)                                                                            \
   do {                                                                                          \
     if (hw)                                                                                     \
-      hipLaunchKernelGGL((k_dcgs_reduce<KC, true, VT, NT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, \
-                         J, u, ubs, w, wbs, n, rb.part);                                        \
+      hipLaunchKernelGGL((k_dcgs_reduce<KC, true, VT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, u, \
+                         ubs, w, wbs, n, rb.part);                                              \
     else                                                                                        \
-      hipLaunchKernelGGL((k_dcgs_reduce<KC, false, VT, NT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, \
-                         J, u, ubs, w, wbs, n, rb.part);                                        \
+      hipLaunchKernelGGL((k_dcgs_reduce<KC, false, VT>), grid, dim3(DT), 0, c->stream, V, ldv, vbs, J, u, \
+                         ubs, w, wbs, n, rb.part);                                              \
   } while (0)
-#define HPS_DR(KC) do { if (nt) HPS_DR1(KC, true); else HPS_DR1(KC, false); } while (0)
   // short bases on long vectors: tiles split over the wavefronts (measured:
   // the split over basis vectors reached about 2.5 TB/s for J <= 8 on 1e9-entry
   // vectors, where half the wavefronts idle and all re-read u and w)
   if (J <= kShortBasis && n >= kLongVector) {
-    if (hw && nt)
+    static_assert(kLongVector >= kNtVector, "the split reduction takes the non-temporal form");
+    if (hw)
       hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT, true>), grid, dim3(DT), 0, c->stream, V,
                          ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
-    else if (hw)
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT, false>), grid, dim3(DT), 0, c->stream, V,
-                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
-    else if (nt)
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT, true>), grid, dim3(DT), 0, c->stream, V,
-                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
     else
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT, false>), grid, dim3(DT), 0, c->stream, V,
+      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT, true>), grid, dim3(DT), 0, c->stream, V,
                          ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
   } else if (kc <= 2) HPS_DR(2); else if (kc <= 4) HPS_DR(4); else HPS_DR(8);
 #undef HPS_DR
-#undef HPS_DR1
   int rc = check_hip(hipGetLastError(), "k_dcgs_reduce");
   if (rc) return rc;
   const int nslots = (hw ? 2 * J : J) + (hw ? 2 : 1);

@@ -45,6 +45,11 @@ CASES = [
     ((2, 1, 1), 16, 25.0, 2, 16),
     ((1, 1, 5), 9, 12.0, 3, 17),
     ((1, 2, 1), 15, 24.0, 2, 18),
+    ((2, 2, 1), 5, 6.0, 3, 19),
+    ((1, 2, 3), 6, 8.0, 3, 20),
+    ((2, 1, 2), 11, 22.0, 4, 21),
+    ((1, 1, 2), 13, 26.0, 2, 22),
+    ((2, 1, 1), 14, 28.0, 3, 23),
 ]
 
 
