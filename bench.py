@@ -31,6 +31,7 @@ The JSON line also carries:
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -46,7 +47,9 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 MIXED_TOL = 1e-10
 BATCHED_TOL = 1e-10  # many right-hand sides: tight enough for 1e-8 error against the oracle
 IR_INNER_TOL = 1e-3  # inner (FP32) relative tolerance of iterative refinement
-TIMING_EVERY = 8     # launches per timed launch inside the timed region
+TIMING_EVERY = 7     # launches per timed launch inside the timed region: a prime, so that
+                     # with a restart that is not a multiple of it the timed launches visit
+                     # every step of a cycle (every basis length) equally often
 BUCKET_DELTAS = (1e-3, 1e-2)   # lambda grid spacings (times kappa^2) of the bucketed runs
 METRIC = "HPS operator applies/s (Munknowns/s) + time-to-1e-8 solve; served p50/p99"
 
@@ -118,10 +121,11 @@ def cpu_baseline(prob) -> dict:
     t0 = time.perf_counter()
     M.apply_elems(y, sample)
     t_p = (time.perf_counter() - t0) * (op.d.nl / len(sample))
-    # classical Arnoldi step at the middle of a restart-50 cycle: 25 MGS projections
-    # against 25 distinct basis vectors (each a full N-vector in its own memory,
+    # classical Arnoldi step at the middle of a restart cycle: m/2 MGS projections
+    # against m/2 distinct basis vectors (each a full N-vector in its own memory,
     # as in a real cycle; not a few vectors that stay in cache)
-    V = [x / np.linalg.norm(x)] + [np.roll(x, 7919 * (i + 1)) for i in range(24)]
+    nproj = max(1, prob.restart // 2)
+    V = [x / np.linalg.norm(x)] + [np.roll(x, 7919 * (i + 1)) for i in range(nproj - 1)]
     t0 = time.perf_counter()
     w = y.copy()
     for v in V:
@@ -134,7 +138,8 @@ def cpu_baseline(prob) -> dict:
             "sample": (f"one oracle GMRES step (one right-hand side) on the same workload: {a_desc} "
                        f"({t_a * 1e3:.1f} ms), J^-1 by dense-LU leaf solves on "
                        f"{len(sample)} of {op.d.nl} leaves scaled to all ({t_p * 1e3:.0f} ms), "
-                       f"25 MGS projections against 25 distinct basis vectors ({t_o * 1e3:.0f} ms)")}
+                       f"{nproj} MGS projections against {nproj} distinct basis vectors "
+                       f"({t_o * 1e3:.0f} ms)")}
 
 
 def oracle_check_rhs(name: str, U, N: int):
@@ -183,6 +188,10 @@ def main():
                     help="requests of the serving workload (request_stream)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving leg of the default line")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="GMRES restart of the default workload's solves (0: the workload's)")
+    ap.add_argument("--serve-restart", type=int, default=10,
+                    help="GMRES restart (one cycle per tick) of the serving runs")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="block precision of the many-right-hand-side workload")
     ap.add_argument("--precond", default="blocks", choices=["blocks", "separable"],
@@ -205,6 +214,8 @@ def main():
     if prob.lambda_bucket > 0:
         return run_bucketed(a, prob)
     full = a.workload != DEFAULT_WORKLOAD
+    if a.restart > 0:
+        prob = dataclasses.replace(prob, restart=a.restart)
     line = solve_line(a, prob, a.steps, a.warmup, extensions=full)
     if not full and not a.no_secondary:
         progress(f"secondary workload {SECONDARY_WORKLOAD}")
@@ -213,7 +224,7 @@ def main():
             sec.pop(k, None)
         line["secondary"] = {SECONDARY_WORKLOAD: sec}
         progress(f"serving leg ({a.serve_requests} requests)")
-        line["serving"] = serving_leg(a.serve_requests)
+        line["serving"] = serving_leg(a.serve_requests, a.serve_restart)
         line["served_p50_ms"] = line["serving"]["fp64"]["served_p50_ms"]
         line["served_p99_ms"] = line["serving"]["fp64"]["served_p99_ms"]
     if not a.no_cpu_baseline:
@@ -488,7 +499,7 @@ def extension_solves(a, ctx, prob, s, t) -> dict:
     return {"lambda_buckets": buckets, "iti_face_system": iti}
 
 
-def serving_leg(n_requests: int) -> dict:
+def serving_leg(n_requests: int, restart: int = 10) -> dict:
     """A bounded run of the serving pattern: the first n_requests of the mixed
     request stream (meshes 4^3 ... 16^3, p in {8, 10}, 8-12 points per
     wavelength, 5-20 bumps, one source each), Poisson arrivals at 75 % of the
@@ -508,7 +519,7 @@ def serving_leg(n_requests: int) -> dict:
     for label, solver in (("fp64", "fgmres"), ("ir_fp32_inner", "ir")):
         progress(f"serving leg: {label}")
         cfg = ServeConfig(slots=4, block_prec="separable", precond_prec="fp64", solver=solver,
-                          restart=50, tol=1e-8)
+                          restart=restart, tol=1e-8)
         probe = P.request_stream(max(4, n_requests // 4), rate=1.0, seed=5)
         srv = Server(cfg)
         res = srv.run(fresh(probe), closed_loop=True)
@@ -531,8 +542,8 @@ def serving_leg(n_requests: int) -> dict:
             "max_true_rel_res": max(r.true_rel_res for r in res),
             "operator_applies_munknowns_per_s": round(st["operator_applies_munknowns_per_s"], 1)}
     out["config"] = {"meshes": [4, 8, 12, 16], "orders": [8, 10], "ppw": [8, 12], "tol": 1e-8,
-                     "solvers": {"fp64": "FGMRES(50), separable FP64 J^-1",
-                                 "ir_fp32_inner": "iterative refinement, FP32-vector inner GMRES(50)"},
+                     "solvers": {"fp64": f"FGMRES({restart}), separable FP64 J^-1",
+                                 "ir_fp32_inner": f"iterative refinement, FP32-vector inner GMRES({restart})"},
                      "slots": 4, "arrivals": "Poisson at 75 % of each path's measured capacity",
                      "seed": 5}
     out["capacity_ratio_ir_over_fp64"] = round(out["ir_fp32_inner"]["capacity_solves_per_s"] /
@@ -830,7 +841,8 @@ def run_serving(a):
             ("fp64_separable", "separable", 0.0, 0.0, 0, "fgmres"),
             ("ir_fp32_inner_separable", "separable", 0.0, 0.0, 0, "ir")):
         cfg = ServeConfig(slots=4, block_prec=prec, precond_prec="fp64" if prec == "separable" else prec,
-                          solver=solver, restart=50, tol=1e-8, lambda_bucket=bucket, group_ops=groups)
+                          solver=solver, restart=a.serve_restart, tol=1e-8, lambda_bucket=bucket,
+                          group_ops=groups)
         # service capacity: the first requests back to back
         probe = P.request_stream(a.requests // 4, rate=1.0, seed=5, share=share)
         srv = Server(cfg)
