@@ -456,6 +456,9 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
       }
       return all ? 1 : 0;
     };
+    bool stopped = false;   // the step records said every right-hand side is done or stuck
+    int last_step = -1;     // the last step's record, read after the closing work is queued
+    uint64_t last_tag = 0;
     for (int j = 0; j < m && its < maxit; ++j) {
       // operator image of the candidate: left J^-1 A u, flexible A M^-1 u (z'_j kept)
       if (!job.flexible) {
@@ -478,11 +481,14 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
         const int cv = converged_at(pending, pending_tag);
         pending = -1;
         if (cv < 0) return cv;
-        if (cv) break;
+        if (cv) {
+          stopped = true;
+          break;
+        }
       }
       if (last) {
-        const int cv = converged_at(j, tag);
-        if (cv < 0) return cv;
+        last_step = j;
+        last_tag = tag;
         break;
       }
       if (want) {
@@ -495,10 +501,30 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
     if ((rc = launch_dcgs_reduce(c, V, NB, N, written, U, N, nullptr, 0, N, S, nb, rb))) return rc;
     if ((rc = launch_dcgs_small(c, S, nb, written, job.flexible ? 1 : 0, 1, d_res, 0))) return rc;
     if ((rc = launch_dcgs_trisolve(c, S, nb, written, job.flexible ? 1 : 0))) return rc;
-    if ((rc = launch_mupdate_b(c, (const VT*)(job.flexible ? Z : V), NB, N, written, S[0].y, sst, 1.0,
-                               x, N, N, nullptr, 0, nb, rb)))
+    // left GMRES on FP64 vectors: x += V y and the next residual from the
+    // Arnoldi relation in one pass (no operator application, no host round
+    // trip).  Flexible GMRES takes the iterate from Z; FP32-stored iterates
+    // (inner solves of iterative refinement) keep the recomputed residual
+    // below, because the recursion does not see the rounding of x to FP32
+    // (with it the inner solves took 20 % more steps).
+    const bool implicit = !job.flexible && sizeof(VT) == sizeof(double2);
+    if (implicit) {
+      if ((rc = launch_dcgs_restart_coef(c, S, nb, written))) return rc;
+      if ((rc = launch_dcgs_restart(c, (const VT*)V, NB, N, written, U, N, x, N, N, S, nb))) return rc;
+    } else if ((rc = launch_mupdate_b(c, (const VT*)(job.flexible ? Z : V), NB, N, written, S[0].y, sst,
+                                      1.0, x, N, N, nullptr, 0, nb, rb))) {
       return rc;
+    }
     ++restarts;
+    if (last_step >= 0) {   // read while the closing work runs
+      const int cv = converged_at(last_step, last_tag);
+      if (cv < 0) return cv;
+      stopped = cv != 0;
+    }
+    // the next cycle starts from the implicit residual unless the records say
+    // the solve may be over (then the true residual decides) or the step
+    // budget is spent
+    if (implicit && !stopped && its < maxit) continue;
     if ((rc = residual(false))) return rc;
     if ((rc = read_norms(beta2))) return rc;
     for (int r = 0; r < nb; ++r) {

@@ -86,10 +86,13 @@ struct DcgsState {
   double2 gls[kDcgsLd];             // right-hand side of the small least-squares problem
   double2 gprev[kDcgsLd];           // projection of the last operator image (next column)
   double2 y[kMaxDcgs];
+  double2 rc[kDcgsLd];              // restart: the new residual's coefficients over V
+  double2 rsig;                     // ... and over the last candidate u
   double beta0;
   double res;
   int flag;                         // nonzero: the candidate fell into the basis (stop the cycle)
   int ncols;                        // finished Hessenberg columns
+  int rk;                           // restart: basis vectors the new residual combines
 };
 
 // reduction pass: partials of a, b (j basis vectors), c, d, finished into S[b].red
@@ -117,5 +120,18 @@ int launch_dcgs_update(hps_ctx* c, float2* V, int64_t ldv, int64_t vbs, int J, f
 int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch);
 // y = R^{-1} gls over the finished columns (at most kmax); flexible: y <- T y
 int launch_dcgs_trisolve(hps_ctx* c, DcgsState* S, int nbatch, int kmax, int flexible);
+// Restart of left GMRES without applying the operator: after trisolve, with k
+// finished columns and K written basis vectors, the residual of the updated
+// iterate is r' = r - Op V_k y = V_{k+1} (beta0 e_0 - Hbar_k y) (Arnoldi
+// relation).  When the last column was closed (k = K), v_K = (u - V_K a)/beta
+// is not stored and r' = V_K (beta0 e_0 - H_K y + a y_{k-1}) - y_{k-1} u; after
+// an early stop (k < K) v_k is V[k].  The coefficients go to S.rc / S.rsig.
+int launch_dcgs_restart_coef(hps_ctx* c, DcgsState* S, int nbatch, int K);
+// One pass over V[0..K-1]: x += V y and u <- V rc + rsig u (the next cycle's
+// first candidate), per right-hand side.
+int launch_dcgs_restart(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K, double2* u,
+                        int64_t ubs, double2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch);
+int launch_dcgs_restart(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K, float2* u,
+                        int64_t ubs, float2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch);
 
 }  // namespace hps

@@ -562,6 +562,86 @@ __global__ __launch_bounds__(64) void k_dcgs_trisolve(DcgsState* __restrict__ S,
   }
 }
 
+// Restart coefficients (one wavefront per right-hand side), after trisolve:
+// t = beta0 e_0 - Hbar_k y over rows 0 .. k (column l of Hbar holds rows
+// 0 .. l + 1).  Closed last column (k = K): v_K = (u - V_K a) / beta is not
+// stored, so its term t_K v_K = -y_{k-1} (u - V_K a) goes to rsig = -y_{k-1}
+// and a y_{k-1} is added to the first K coefficients; otherwise (the cycle
+// stopped after k columns) v_k is V[k] and t is the whole combination.
+__global__ __launch_bounds__(64) void k_dcgs_restart_coef(DcgsState* __restrict__ S, int K) {
+  DcgsState& s = S[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int k = min(K, s.ncols);
+  const bool closed = k == K;
+  const double2 z2 = make_double2(0.0, 0.0);
+  const double2 ylast = k > 0 ? s.y[k - 1] : z2;
+  constexpr int ld = kDcgsLd;
+  for (int i = lane; i < kDcgsLd; i += 64) {
+    double2 t = make_double2(i == 0 ? s.beta0 : 0.0, 0.0);
+    for (int l = max(0, i - 1); l < k; ++l) t = csub(t, cmul(s.H[i + ld * l], s.y[l]));
+    if (closed) t = i < k ? cadd(t, cmul(s.red[i], ylast)) : z2;
+    else if (i > k) t = z2;
+    s.rc[i] = t;
+  }
+  if (lane == 0) {
+    s.rsig = closed ? make_double2(-ylast.x, -ylast.y) : z2;
+    s.rk = closed ? k : k + 1;
+  }
+}
+
+// x += V y and u <- V rc + rsig u in one pass over the first rk basis vectors
+// of each right-hand side (x's sum in the order of the plain multi-axpy: x
+// first, then V[0], V[1], ...).
+template <typename VT, bool NT>
+__global__ __launch_bounds__(UT) void k_dcgs_restart(const VT* __restrict__ V, int64_t ldv, int64_t vbs,
+                                                     int K, VT* __restrict__ u, int64_t ubs,
+                                                     VT* __restrict__ x, int64_t xbs, int64_t n,
+                                                     const DcgsState* __restrict__ S) {
+  const int bz = blockIdx.z;
+  const DcgsState& s = S[bz];
+  __shared__ double2 cy[kMaxDcgs + 8], cr[kMaxDcgs + 8];
+  const int rk = min(s.rk, K);
+  const int k8 = (rk + 7) / 8 * 8;
+  for (int l = threadIdx.x; l < k8; l += UT) {
+    cy[l] = l < rk ? s.y[l] : make_double2(0.0, 0.0);
+    cr[l] = l < rk ? s.rc[l] : make_double2(0.0, 0.0);
+  }
+  const double2 sg = s.rsig;
+  const bool use_u = sg.x != 0.0 || sg.y != 0.0;
+  __syncthreads();
+  V += bz * vbs;
+  u += bz * ubs;
+  x += bz * xbs;
+  for (int64_t i = (int64_t)blockIdx.x * UT + threadIdx.x; i < n; i += (int64_t)gridDim.x * UT) {
+    double2 sx = widen(ld_tile(x, i, i, true), true);
+    double2 su = make_double2(0.0, 0.0);
+    for (int l = 0; l < rk; l += 8) {
+      VT r[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        r[q] = ld_tile_h<NT>(V, (int64_t)(l + q) * ldv + i, (int64_t)l * ldv + i, l + q < rk);
+      double2 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = widen(r[q], l + q < rk);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double2 a = cy[l + q], b = cr[l + q];
+        sx.x = fma(v[q].x, a.x, fma(-v[q].y, a.y, sx.x));
+        sx.y = fma(v[q].x, a.y, fma(v[q].y, a.x, sx.y));
+        su.x = fma(v[q].x, b.x, fma(-v[q].y, b.y, su.x));
+        su.y = fma(v[q].x, b.y, fma(v[q].y, b.x, su.y));
+      }
+    }
+    if (use_u) {
+      const double2 uv = widen(ld_tile(u, i, i, true), true);
+      su.x = fma(sg.x, uv.x, fma(-sg.y, uv.y, su.x));
+      su.y = fma(sg.x, uv.y, fma(sg.y, uv.x, su.y));
+    }
+    st2(x, i, sx);
+    st2(u, i, su);
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -684,6 +764,41 @@ int launch_dcgs_start(hps_ctx* c, DcgsState* S, int nbatch) {
 int launch_dcgs_trisolve(hps_ctx* c, DcgsState* S, int nbatch, int kmax, int flexible) {
   hipLaunchKernelGGL(k_dcgs_trisolve, dim3(nbatch), dim3(64), 0, c->stream, S, kmax, flexible);
   return check_hip(hipGetLastError(), "k_dcgs_trisolve");
+}
+
+int launch_dcgs_restart_coef(hps_ctx* c, DcgsState* S, int nbatch, int K) {
+  if (K < 1 || K > kMaxDcgs) return fail(HPS_ERR_ARG, "restart after 1 .. 64 basis vectors");
+  hipLaunchKernelGGL(k_dcgs_restart_coef, dim3(nbatch), dim3(64), 0, c->stream, S, K);
+  return check_hip(hipGetLastError(), "k_dcgs_restart_coef");
+}
+
+namespace {
+
+template <typename VT>
+int dcgs_restart(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int K, VT* u, int64_t ubs, VT* x,
+                 int64_t xbs, int64_t n, DcgsState* S, int nbatch) {
+  if (K < 1 || K > kMaxDcgs) return fail(HPS_ERR_ARG, "restart after 1 .. 64 basis vectors");
+  const int nblk = (int)std::min<int64_t>((n + UT - 1) / UT, 32768);
+  const dim3 grid(nblk, 1, nbatch);
+  if (n >= kNtVector)
+    hipLaunchKernelGGL((k_dcgs_restart<VT, true>), grid, dim3(UT), 0, c->stream, V, ldv, vbs, K, u, ubs,
+                       x, xbs, n, S);
+  else
+    hipLaunchKernelGGL((k_dcgs_restart<VT, false>), grid, dim3(UT), 0, c->stream, V, ldv, vbs, K, u, ubs,
+                       x, xbs, n, S);
+  return check_hip(hipGetLastError(), "k_dcgs_restart");
+}
+
+}  // namespace
+
+int launch_dcgs_restart(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int K, double2* u,
+                        int64_t ubs, double2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch) {
+  return dcgs_restart(c, V, ldv, vbs, K, u, ubs, x, xbs, n, S, nbatch);
+}
+
+int launch_dcgs_restart(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K, float2* u,
+                        int64_t ubs, float2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch) {
+  return dcgs_restart(c, V, ldv, vbs, K, u, ubs, x, xbs, n, S, nbatch);
 }
 
 }  // namespace hps
