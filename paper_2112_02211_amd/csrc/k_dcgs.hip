@@ -34,9 +34,10 @@ constexpr int UT = 256;        // update-pass (and small-step) workgroup
 constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
 constexpr int64_t kMidVector = 1 << 24;  // reduction grid sizes below / from here
 constexpr int kShortBasis = 8;           // reductions over at most this many basis vectors ...
-constexpr int64_t kLongVector = 1 << 22; // ... of at least this many entries split tiles over wavefronts
+constexpr int64_t kLongVector = 1 << 21; // ... of at least this many entries split tiles over wavefronts
                                          // (measured: 3 % slower on 0.46M-entry vectors, where u and w
-                                         // re-reads hit in cache; faster from 6.5M entries on)
+                                         // re-reads hit in cache; faster from 3.67M entries on: the
+                                         // 64-vector lock-step solve of those took 9.87 -> 9.46 s)
 
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
