@@ -253,6 +253,7 @@ __global__ void k_dcgs_start(DcgsState* __restrict__ S, int nb) {
   s.flag = 0;
   s.ncols = 0;
   s.res = 0.0;
+  s.beta0 = 0.0;   // set by step 0 unless the cycle's first candidate breaks down
   for (int i = 0; i < kDcgsLd; ++i) s.gls[i] = make_double2(0.0, 0.0);
 }
 
@@ -568,7 +569,9 @@ __global__ __launch_bounds__(64) void k_dcgs_trisolve(DcgsState* __restrict__ S,
 // 0 .. l + 1).  Closed last column (k = K): v_K = (u - V_K a) / beta is not
 // stored, so its term t_K v_K = -y_{k-1} (u - V_K a) goes to rsig = -y_{k-1}
 // and a y_{k-1} is added to the first K coefficients; otherwise (the cycle
-// stopped after k columns) v_k is V[k] and t is the whole combination.
+// stopped after k columns) v_k is V[k] and t is the whole combination.  If
+// the cycle's first candidate broke down (no V[0] written, beta0 still 0:
+// a zero or non-finite residual) the residual stays u.
 __global__ __launch_bounds__(64) void k_dcgs_restart_coef(DcgsState* __restrict__ S, int K) {
   DcgsState& s = S[blockIdx.x];
   const int lane = threadIdx.x;
@@ -584,9 +587,12 @@ __global__ __launch_bounds__(64) void k_dcgs_restart_coef(DcgsState* __restrict_
     else if (i > k) t = z2;
     s.rc[i] = t;
   }
+  const bool none = k == 0 && s.beta0 == 0.0;
+  if (none)
+    for (int i = lane; i < kDcgsLd; i += 64) s.rc[i] = z2;
   if (lane == 0) {
-    s.rsig = closed ? make_double2(-ylast.x, -ylast.y) : z2;
-    s.rk = closed ? k : k + 1;
+    s.rsig = closed ? make_double2(-ylast.x, -ylast.y) : (none ? make_double2(1.0, 0.0) : z2);
+    s.rk = closed ? k : (none ? 0 : k + 1);
   }
 }
 

@@ -160,7 +160,8 @@ class ServeConfig:
     block_prec: str = "fp64"         # "separable": the FP64 J^-1 without stored blocks
     precond_prec: str = "fp64"
     restart: int = 10                # Krylov dimension of a cycle = one tick (10: the fastest
-                                     # of 10/20/50 on the mixed stream, 67 vs 60 vs 41 solves/s)
+                                     # of 10/20/50 on the mixed stream, 67 vs 60 vs 41 solves/s;
+                                     # BF16 blocks need about 50: at 10 some requests stalled)
     tol: float = 1e-8
     solver: str = "gmres"            # single right-hand side: "gmres" (left, FP64 J^-1), "fgmres",
                                      # or "ir" (iterative refinement with FP32 inner solves; needs

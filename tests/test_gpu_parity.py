@@ -268,6 +268,41 @@ def test_zero_right_hand_side_returns_zero(hps_mod, solver):
     assert torch.count_nonzero(u).item() == 0
 
 
+def test_zero_right_hand_side_in_a_lock_step_batch(hps_mod):
+    # restarts of left GMRES form the next residual from the Arnoldi relation;
+    # a right-hand side whose cycle breaks down at its first step (here a zero
+    # one) must keep its zero residual and zero solution through every cycle,
+    # whatever an earlier solve left in the solver state
+    prob = P.bump_problem("zb", (2, 2, 2), 8, 14.0, 4, 3, 36, 4, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob)
+    op = O.build(prob)
+    xyz = ctx.nodes()
+    N = ctx.N
+    S = np.concatenate([P.rhs_data(prob, xyz, r)[0] for r in range(3)])
+    ctx.gmres(dev(S), dev(np.zeros_like(S)), tol=1e-11, restart=4, solver="batched")
+    S[N:2 * N] = 0.0
+    u, st, ok = ctx.gmres(dev(S), dev(np.zeros_like(S)), tol=1e-11, restart=4, solver="batched")
+    assert ok and st["restarts"] >= 3
+    U = host(u).reshape(3, N)
+    assert np.count_nonzero(U[1]) == 0
+    for r in (0, 2):
+        ud = O.solve_direct(op, O.assemble_rhs(op.d, S[r * N:(r + 1) * N], np.zeros(N)))
+        assert rel(U[r], ud) < 1e-9, r
+
+
+def test_short_restarts_reach_the_direct_solution(hps_mod):
+    # many restart cycles (GMRES(3)), each starting from the residual given by
+    # the Arnoldi relation; the final residual is the recomputed true one
+    prob = P.bump_problem("sr", (2, 2, 1), 8, 10.0, 3, 1, 37, 3, 1e-11)
+    ctx = hps_mod.Context.from_problem(prob)
+    op = O.build(prob)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-11, restart=3)
+    assert ok and st["restarts"] >= 5
+    assert st["true_rel_res"] <= 1e-11
+    assert rel(host(u), O.solve_direct(op)) < 1e-9
+
+
 @pytest.mark.parametrize("solver", ["gmres", "fgmres"])
 def test_invariant_krylov_space_breakdown(hps_mod, solver):
     # one leaf, constant medium: J^-1 A = I, so left GMRES meets an invariant
