@@ -54,11 +54,6 @@ KERNEL_SOURCES = {"k_precond_fused": PRECOND_SOURCES, "k_dcgs_update": ARNOLDI_S
 COPY_MIB = 1024
 
 
-def _rel(path):
-    """An output folder as the profiled command named it: relative to the repository root."""
-    return os.path.relpath(os.path.abspath(path), os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-
-
 def kernel_source_hash(kernel: str = "k_precond_fused") -> str:
     """Hash of a profiled kernel's sources: counters taken on other sources
     describe another kernel."""
@@ -239,8 +234,8 @@ def arnoldi_summary(a):
          "#",
          "# commands (R = repository root; one counter per run):",
          "#   cd /tmp && export TMPDIR=/tmp",
-         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/{_rel(a.fetch)} -o run -- {cmd}",
-         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/{_rel(a.write)} -o run -- {cmd}",
+         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {cmd}",
+         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {cmd}",
          f"#   python -m paper_2112_02211_amd.profile_run arnoldi-summary --workload {a.workload} "
          f"--launches {a.launches} --fetch <fetch dir> --write <write dir> --run-log <stdout of a run> --out <this file>",
          "#",
@@ -316,7 +311,7 @@ def gemm_summary(a):
          "# command (R = repository root):",
          "#   cd /tmp && export TMPDIR=/tmp",
          f"#   rocprofv3 --pmc MfmaUtil MfmaFlopsF64 MfmaFlopsF32 MfmaFlopsBF16 --output-format csv "
-         f"-d $R/{_rel(a.pmc_dir)} -o run -- python "
+         f"-d <dir> -o run -- python "
          f"$R/paper_2112_02211_amd/profile_run.py gemm --workload {a.workload} --rhs {a.rhs} --launches {a.launches}",
          f"#   python -m paper_2112_02211_amd.profile_run gemm-summary --workload {a.workload} --rhs {a.rhs} "
          f"--launches {a.launches} --pmc-dir <that dir> --out <this file>",
@@ -385,10 +380,10 @@ def pmc_summary(a):
          "#",
          "# commands (R = repository root; one counter per run):",
          "#   cd /tmp && export TMPDIR=/tmp",
-         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/{_rel(a.fetch)} "
+         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> "
          f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}"
          f"{' --iti' if a.iti else ''}",
-         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/{_rel(a.write)} "
+         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> "
          f"-o run -- python $R/paper_2112_02211_amd/profile_run.py --workload {a.workload} --launches {a.launches}"
          f"{' --iti' if a.iti else ''}",
          f"#   python -m paper_2112_02211_amd.profile_run pmc-summary --workload {a.workload} "
