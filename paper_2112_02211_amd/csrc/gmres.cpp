@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "hps_internal.h"
@@ -325,14 +326,20 @@ int run_gmres(hps_ctx* c, const Job& job, const double2* b, double2* x, double t
 // over the basis per step, see hps_krylov.h); m <= kMaxDcgs.  Same stopping
 // rules, restart policy and pipelined residual checks as run_gmres.
 // VT: storage of the vectors (complex FP64, or complex FP32 for the inner solve
-// of iterative refinement, whose basis lives in its own workspace).
-template <typename VT>
-int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, int maxit,
+// of iterative refinement, whose basis lives in its own workspace); XT: storage
+// of the iterate x (FP64 over an FP32 basis for that inner solve, one
+// right-hand side).
+template <typename VT, typename XT = VT>
+int run_dcgs(hps_ctx* c, const Job& job, const VT* b, XT* x, double tol, int m, int maxit,
              int use_x0, int check_every, hps_stats* st) {
+  constexpr bool kMixed = !std::is_same<VT, XT>::value;
+  static_assert(!kMixed || (std::is_same<VT, float2>::value && std::is_same<XT, double2>::value),
+                "the only mixed storage is an FP64 iterate over an FP32 basis");
   const int64_t N = job.n;
   const int nb = job.nrhs;
   const int64_t NB = N * nb;
   const size_t vec_bytes = sizeof(VT) * NB;
+  if (kMixed && (nb != 1 || job.flexible)) return fail(HPS_ERR_ARG, "FP64 iterate: one right-hand side, left GMRES");
   // V (m), candidate U, operator image W, TMP, Z' (m, flexible)
   const size_t need = vec_bytes * ((size_t)m + 3 + (job.flexible ? m : 0));
   Workspace* wk = sizeof(VT) == sizeof(double2) ? &c->w_krylov : &c->w_krylov32;
@@ -398,7 +405,12 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
     if (x_zero) {
       HPS_TRY_HIP(hipMemcpyAsync(TMP, b, vec_bytes, hipMemcpyDeviceToDevice, c->stream));
     } else {
-      if ((e = job_apply(c, job, x, TMP, nb))) return e;
+      if constexpr (kMixed) {   // the FP32 operator on x rounded to FP32 (W is free here)
+        if ((e = launch_demote_scaled(c, x, 1.0, W, N))) return e;
+        if ((e = job_apply(c, job, W, TMP, nb))) return e;
+      } else {
+        if ((e = job_apply(c, job, x, TMP, nb))) return e;
+      }
       if ((e = launch_sub_from(c, b, TMP, NB))) return e;
     }
     if (!job.flexible) {
@@ -419,7 +431,7 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
     if ((rc = residual(false))) return rc;
     if ((rc = read_norms(beta2))) return rc;
   } else {
-    HPS_TRY_HIP(hipMemsetAsync(x, 0, vec_bytes, c->stream));
+    HPS_TRY_HIP(hipMemsetAsync(x, 0, sizeof(XT) * NB, c->stream));
     beta2 = bn2;
   }
   for (int r = 0; r < nb; ++r)
@@ -503,17 +515,18 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
     if ((rc = launch_dcgs_trisolve(c, S, nb, written, job.flexible ? 1 : 0))) return rc;
     // left GMRES on FP64 vectors: x += V y and the next residual from the
     // Arnoldi relation in one pass (no operator application, no host round
-    // trip).  Flexible GMRES takes the iterate from Z; FP32-stored iterates
-    // (inner solves of iterative refinement) keep the recomputed residual
-    // below, because the recursion does not see the rounding of x to FP32
-    // (with it the inner solves took 20 % more steps).
-    const bool implicit = !job.flexible && sizeof(VT) == sizeof(double2);
+    // trip).  Flexible GMRES takes the iterate from Z; an FP32-stored iterate
+    // keeps the recomputed residual below, because the recursion does not see
+    // x's rounding to FP32 (with it inner solves took 20 % more steps), so the
+    // inner solves of iterative refinement keep x in FP64.
+    const bool implicit = !job.flexible && sizeof(XT) == sizeof(double2);
     if (implicit) {
       if ((rc = launch_dcgs_restart_coef(c, S, nb, written))) return rc;
       if ((rc = launch_dcgs_restart(c, (const VT*)V, NB, N, written, U, N, x, N, N, S, nb))) return rc;
-    } else if ((rc = launch_mupdate_b(c, (const VT*)(job.flexible ? Z : V), NB, N, written, S[0].y, sst,
-                                      1.0, x, N, N, nullptr, 0, nb, rb))) {
-      return rc;
+    } else if constexpr (!kMixed) {
+      if ((rc = launch_mupdate_b(c, (const VT*)(job.flexible ? Z : V), NB, N, written, S[0].y, sst, 1.0,
+                                 x, N, N, nullptr, 0, nb, rb)))
+        return rc;
     }
     ++restarts;
     if (last_step >= 0) {   // read while the closing work runs
@@ -560,17 +573,18 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, VT* x, double tol, int m, 
 // vectors (basis, candidate, operator image) are stored in complex FP32, with
 // the FP32-storage A and the separable J^{-1}, started from 0 on r / ||r||
 // and stopped at the preconditioned residual reduction inner_tol; then
-// x += ||r|| d in FP64.  Stops when ||b - A x|| <= tol ||b||, when the
+// x += ||r|| d in FP64.  The inner iterate d is kept in FP64, so the inner
+// restarts take the residual from the Arnoldi relation.  Stops when ||b - A x|| <= tol ||b||, when the
 // residual stops decreasing, or after maxit inner steps.
 int run_ir(hps_ctx* c, const double2* b, double2* x, double tol, int m, int maxit, int use_x0,
            int check_every, double inner_tol, double* rhs_res, hps_stats* st) {
   const int64_t N = c->N;
-  int rc = ws_reserve(c, &c->w_ir, sizeof(double2) * N + 2 * sizeof(float2) * N + 64);
+  int rc = ws_reserve(c, &c->w_ir, 2 * sizeof(double2) * N + sizeof(float2) * N + 64);
   if (rc) return rc;
   double2* r = static_cast<double2*>(c->w_ir.ptr);
-  float2* r32 = reinterpret_cast<float2*>(r + N);
-  float2* d32 = r32 + N;
-  double* d_nrm = reinterpret_cast<double*>(d32 + N);
+  double2* d64 = r + N;   // the inner correction, kept in FP64 (see run_dcgs)
+  float2* r32 = reinterpret_cast<float2*>(d64 + N);
+  double* d_nrm = reinterpret_cast<double*>(r32 + N);
   RedBuf rb;
   if ((rc = red_buf(c, kMaxDcgs + 1, 1, &rb))) return rc;
   void* hp = nullptr;
@@ -612,11 +626,11 @@ int run_ir(hps_ctx* c, const double2* b, double2* x, double tol, int m, int maxi
     if ((rc = launch_demote_scaled(c, r, 1.0 / rn, r32, N))) return rc;
     hps_stats one{};
     const int inner_max = std::max(m, std::min(maxit - its, 40 * m));
-    const int r1 = run_dcgs<float2>(c, job, r32, d32, inner_tol, m, inner_max, 0, check_every, &one);
+    const int r1 = run_dcgs<float2, double2>(c, job, r32, d64, inner_tol, m, inner_max, 0, check_every, &one);
     if (r1 < 0) return r1;
     its += one.iters;
     ++outer;
-    if ((rc = launch_axpy_promote(c, rn, d32, x, N))) return rc;
+    if ((rc = launch_axpy_promote(c, rn, d64, x, N))) return rc;
     if ((rc = residual())) return rc;
     prev = rn;
     if ((rc = norm(r, &rn))) return rc;
@@ -667,9 +681,9 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
     return bytes;
   }
   if (o.solver == HPS_SOLVER_IR) {
-    // FP64 residual, FP32 residual and correction; the inner FP32 basis, U, W
+    // FP64 residual and correction, FP32 residual; the inner FP32 basis, U, W
     // and TMP; the FP64 face buffer; the small state, the reduction partials, b
-    int64_t bytes = 16 * c->N + 2 * 8 * c->N + 64 + 8 * c->N * (int64_t)(restart + 3);
+    int64_t bytes = 2 * 16 * c->N + 8 * c->N + 64 + 8 * c->N * (int64_t)(restart + 3);
     bytes += 16 * c->nl * (int64_t)c->nb + (int64_t)sizeof(DcgsState) + 6 * 8 + 8;
     bytes += (int64_t)kPartSlots * kRedBlocks * 16 + 16 * c->N * nrhs;
     return bytes;

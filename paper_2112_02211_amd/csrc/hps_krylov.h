@@ -42,6 +42,7 @@ int launch_norm2_b(hps_ctx* c, const float2* w, int64_t wbs, int64_t n, double* 
 // y = demote(s * x) (complex FP64 to FP32) and y += s * promote(x) (FP32 into FP64)
 int launch_demote_scaled(hps_ctx* c, const double2* x, double s, float2* y, int64_t n);
 int launch_axpy_promote(hps_ctx* c, double s, const float2* x, double2* y, int64_t n);
+int launch_axpy_promote(hps_ctx* c, double s, const double2* x, double2* y, int64_t n);
 int launch_norm2_b(hps_ctx* c, const double2* w, int64_t wbs, int64_t n, double* nrm2, int64_t nbs,
                    int nbatch, const RedBuf& rb);
 int launch_scale_by_b(hps_ctx* c, const double2* x, int64_t xbs, double2* y, int64_t ybs, int64_t n,
@@ -133,5 +134,8 @@ int launch_dcgs_restart(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, 
                         int64_t ubs, double2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch);
 int launch_dcgs_restart(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K, float2* u,
                         int64_t ubs, float2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch);
+// the same with the iterate x in FP64 over an FP32 basis
+int launch_dcgs_restart(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K, float2* u,
+                        int64_t ubs, double2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch);
 
 }  // namespace hps

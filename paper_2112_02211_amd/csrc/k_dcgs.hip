@@ -598,11 +598,11 @@ __global__ __launch_bounds__(64) void k_dcgs_restart_coef(DcgsState* __restrict_
 
 // x += V y and u <- V rc + rsig u in one pass over the first rk basis vectors
 // of each right-hand side (x's sum in the order of the plain multi-axpy: x
-// first, then V[0], V[1], ...).
-template <typename VT, bool NT>
+// first, then V[0], V[1], ...).  x may be stored in FP64 over an FP32 basis.
+template <typename VT, typename XT, bool NT>
 __global__ __launch_bounds__(UT) void k_dcgs_restart(const VT* __restrict__ V, int64_t ldv, int64_t vbs,
                                                      int K, VT* __restrict__ u, int64_t ubs,
-                                                     VT* __restrict__ x, int64_t xbs, int64_t n,
+                                                     XT* __restrict__ x, int64_t xbs, int64_t n,
                                                      const DcgsState* __restrict__ S) {
   const int bz = blockIdx.z;
   const DcgsState& s = S[bz];
@@ -781,18 +781,18 @@ int launch_dcgs_restart_coef(hps_ctx* c, DcgsState* S, int nbatch, int K) {
 
 namespace {
 
-template <typename VT>
-int dcgs_restart(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int K, VT* u, int64_t ubs, VT* x,
+template <typename VT, typename XT>
+int dcgs_restart(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int K, VT* u, int64_t ubs, XT* x,
                  int64_t xbs, int64_t n, DcgsState* S, int nbatch) {
   if (K < 1 || K > kMaxDcgs) return fail(HPS_ERR_ARG, "restart after 1 .. 64 basis vectors");
   const int nblk = (int)std::min<int64_t>((n + UT - 1) / UT, 32768);
   const dim3 grid(nblk, 1, nbatch);
   if (n >= kNtVector)
-    hipLaunchKernelGGL((k_dcgs_restart<VT, true>), grid, dim3(UT), 0, c->stream, V, ldv, vbs, K, u, ubs,
-                       x, xbs, n, S);
+    hipLaunchKernelGGL((k_dcgs_restart<VT, XT, true>), grid, dim3(UT), 0, c->stream, V, ldv, vbs, K, u,
+                       ubs, x, xbs, n, S);
   else
-    hipLaunchKernelGGL((k_dcgs_restart<VT, false>), grid, dim3(UT), 0, c->stream, V, ldv, vbs, K, u, ubs,
-                       x, xbs, n, S);
+    hipLaunchKernelGGL((k_dcgs_restart<VT, XT, false>), grid, dim3(UT), 0, c->stream, V, ldv, vbs, K, u,
+                       ubs, x, xbs, n, S);
   return check_hip(hipGetLastError(), "k_dcgs_restart");
 }
 
@@ -805,6 +805,11 @@ int launch_dcgs_restart(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, 
 
 int launch_dcgs_restart(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K, float2* u,
                         int64_t ubs, float2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch) {
+  return dcgs_restart(c, V, ldv, vbs, K, u, ubs, x, xbs, n, S, nbatch);
+}
+
+int launch_dcgs_restart(hps_ctx* c, const float2* V, int64_t ldv, int64_t vbs, int K, float2* u,
+                        int64_t ubs, double2* x, int64_t xbs, int64_t n, DcgsState* S, int nbatch) {
   return dcgs_restart(c, V, ldv, vbs, K, u, ubs, x, xbs, n, S, nbatch);
 }
 

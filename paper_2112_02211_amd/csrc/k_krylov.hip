@@ -142,11 +142,11 @@ __global__ void k_demote_scaled(const double2* __restrict__ x, double s, float2*
   y[i] = make_float2((float)(a.x * s), (float)(a.y * s));
 }
 
-__global__ void k_axpy_promote(double s, const float2* __restrict__ x, double2* __restrict__ y,
-                               int64_t n) {
+template <typename XT>
+__global__ void k_axpy_promote(double s, const XT* __restrict__ x, double2* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float2 a = x[i];
+  const XT a = x[i];
   const double2 b = y[i];
   y[i] = make_double2(fma(s, (double)a.x, b.x), fma(s, (double)a.y, b.y));
 }
@@ -484,8 +484,15 @@ int launch_demote_scaled(hps_ctx* c, const double2* x, double s, float2* y, int6
 
 int launch_axpy_promote(hps_ctx* c, double s, const float2* x, double2* y, int64_t n) {
   const int threads = 256;
-  hipLaunchKernelGGL(k_axpy_promote, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
+  hipLaunchKernelGGL(k_axpy_promote<float2>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
                      c->stream, s, x, y, n);
+  return check_hip(hipGetLastError(), "k_axpy_promote");
+}
+
+int launch_axpy_promote(hps_ctx* c, double s, const double2* x, double2* y, int64_t n) {
+  const int threads = 256;
+  hipLaunchKernelGGL(k_axpy_promote<double2>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads),
+                     0, c->stream, s, x, y, n);
   return check_hip(hipGetLastError(), "k_axpy_promote");
 }
 
