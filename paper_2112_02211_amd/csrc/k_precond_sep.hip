@@ -64,6 +64,11 @@ template <> constexpr int kSepForm<12> = kSepLine;
 template <> constexpr int kSepThreads<12> = 256;
 template <> constexpr int kSepMinWaves<12> = 8;
 template <> constexpr int kSepOutputs<12> = 5;
+// Face values in the second tensor's space (where it holds them): at p = 12 it
+// takes the leaf from 45.3 to 35.7 KB of LDS, four leaves per CU instead of
+// three; at p = 10 the registers it adds would cost a wavefront per SIMD.
+template <int P>
+constexpr bool kSepAliasG = P == 12;
 // config end
 
 template <int P>
@@ -292,9 +297,15 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
     const double* __restrict__ tab, int64_t nl, int64_t N, int64_t os) {
   using S = SL<P>;
   constexpr int N1 = S::N1, L = S::L, NI = S::NI, NB = S::NB, NN = S::NN, BD = S::BD;
+  // The face values G are last read by the interior correction, before the
+  // first mode product writes X, so G can live in X's space (kSepAliasG); the
+  // face recovery then takes g from registers.
+  constexpr bool GX = kSepAliasG<P> && S::SZX >= NB;
+  constexpr int NGL = (3 * L + BD - 1) / BD;   // grid lines per thread in the face phases
   __shared__ double2 T[S::SZ];
   __shared__ double2 X[S::SZX];
-  __shared__ double2 G[NB];
+  __shared__ double2 Gs[GX ? 1 : NB];
+  double2* const G = GX ? X : Gs;
   __shared__ double2 CT[S::CTN];    // (Wc | Vc |) Ec | Fi
   __shared__ double RT[4 * N1];     // Dlo | Dhi | C0 | C1
   const int64_t tau = blockIdx.x;
@@ -338,17 +349,27 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   const double* Dhi = RT + N1;
   const double* C0 = RT + 2 * N1;
   const double* C1 = RT + 3 * N1;
-  // g = Fi [x_lo, x_hi] on every line, in place
-  for (int ln = threadIdx.x; ln < 3 * L; ln += BD) {
-    const int ax = ln / L, pos = ln - ax * L;
-    const double2 lo = G[2 * ax * L + pos], hi = G[(2 * ax + 1) * L + pos];
-    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    cfma(a, F0, lo);
-    cfma(a, F1, hi);
-    cfma(b, F2, lo);
-    cfma(b, F3, hi);
-    G[2 * ax * L + pos] = a;
-    G[(2 * ax + 1) * L + pos] = b;
+  // g = Fi [x_lo, x_hi] on every line, in place (and kept in registers when G
+  // shares X's space)
+  double2 ga[GX ? NGL : 1], gb[GX ? NGL : 1];
+#pragma unroll
+  for (int k = 0; k < NGL; ++k) {
+    const int ln = threadIdx.x + k * BD;
+    if (ln < 3 * L) {
+      const int ax = ln / L, pos = ln - ax * L;
+      const double2 lo = G[2 * ax * L + pos], hi = G[(2 * ax + 1) * L + pos];
+      double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+      cfma(a, F0, lo);
+      cfma(a, F1, hi);
+      cfma(b, F2, lo);
+      cfma(b, F3, hi);
+      G[2 * ax * L + pos] = a;
+      G[(2 * ax + 1) * L + pos] = b;
+      if constexpr (GX) {
+        ga[k] = a;
+        gb[k] = b;
+      }
+    }
   }
   __syncthreads();
   // r_i = x_i - A_ib g  (A_ib: -D2[1 + i][{0, p-1}] towards the two ends of each line)
@@ -385,7 +406,10 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
     st2(yv, m, T[lidx<P>(i, j, k)]);
   }
   // u_b = g - Fi Fbi1 u_line,  Fbi1 u_line = [-sum Dlo u, sum Dhi u]
-  for (int ln = threadIdx.x; ln < 3 * L; ln += BD) {
+#pragma unroll
+  for (int k = 0; k < NGL; ++k) {
+    const int ln = threadIdx.x + k * BD;
+    if (ln >= 3 * L) break;
     const int ax = ln / L, pos = ln - ax * L;
     int base, stride;
     line_of<P>(ax, pos % N1, pos / N1, base, stride);
@@ -396,7 +420,14 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
       cfma_r(slo, -Dlo[t], u);
       cfma_r(shi, Dhi[t], u);
     }
-    double2 a = G[2 * ax * L + pos], b = G[(2 * ax + 1) * L + pos];
+    double2 a, b;
+    if constexpr (GX) {
+      a = ga[k];
+      b = gb[k];
+    } else {
+      a = G[2 * ax * L + pos];
+      b = G[(2 * ax + 1) * L + pos];
+    }
     double2 fa = make_double2(0.0, 0.0), fb = make_double2(0.0, 0.0);
     cfma(fa, F0, slo);
     cfma(fa, F1, shi);
