@@ -125,7 +125,10 @@ typedef struct {
 
 /* Solvers for hps_gmres. */
 #define HPS_SOLVER_GMRES 0   /* left preconditioned GMRES(m) on J^-1 A x = J^-1 b (eq. (globalsystem)), FP64 */
-#define HPS_SOLVER_FGMRES 1  /* right preconditioned flexible GMRES(m), FP64 outer; J^-1 in precond_prec */
+#define HPS_SOLVER_FGMRES 1  /* right preconditioned flexible GMRES(m), FP64 outer; J^-1 in precond_prec;
+                                several right-hand sides advance in lock step as with
+                                HPS_SOLVER_BLOCK (one Krylov space each, stopped on its own true
+                                residual; "iters" is then the largest count) */
 #define HPS_SOLVER_BLOCK 2   /* lock-step GMRES(m): one Krylov space per right-hand side, up to 64
                                 advanced together (J^-1 of 4 or more as a GEMM on the matrix
                                 cores); left preconditioned with FP64 blocks, flexible otherwise */

@@ -701,7 +701,8 @@ extern "C" int64_t hps_solve_bytes(const hps_ctx* c, int restart, int nrhs, cons
     return bytes;
   }
   const bool flexible = o.solver == HPS_SOLVER_FGMRES || !fp64_pc;
-  const int64_t nbat = (o.solver == HPS_SOLVER_BLOCK || c->nop > 1) ? std::min(nrhs, kMaxBatch) : 1;
+  const bool lock = o.solver == HPS_SOLVER_BLOCK || c->nop > 1 || (o.solver == HPS_SOLVER_FGMRES && nrhs > 1);
+  const int64_t nbat = lock ? std::min(nrhs, kMaxBatch) : 1;
   const int64_t vec = 16 * c->N * nbat;
   int64_t bytes = vec * ((restart + 1) + (flexible ? restart : 0) + 1);  // basis (+Z) + tmp
   bytes += (int64_t)sizeof(GmresState) * nbat + 32 * nbat;               // Hessenberg state
@@ -837,8 +838,10 @@ extern "C" int hps_gmres(hps_ctx* c, const hps_z* s, const hps_z* t, double tol,
     job.flexible = (o.solver == HPS_SOLVER_FGMRES) || prec != kFP64;
     job.prec = prec;
     job.n = c->N;
-    // operator groups always run their right-hand sides in lock step (one per operator)
-    if (o.solver == HPS_SOLVER_BLOCK || c->nop > 1) {
+    // operator groups always run their right-hand sides in lock step (one per
+    // operator), and so does flexible GMRES on several right-hand sides (the
+    // same iterations as one at a time)
+    if (o.solver == HPS_SOLVER_BLOCK || c->nop > 1 || (o.solver == HPS_SOLVER_FGMRES && nrhs > 1)) {
       hps_stats acc{};
       for (int r0 = 0; r0 < nrhs && (rc == HPS_OK || rc == HPS_NOT_CONVERGED); r0 += kMaxBatch) {
         job.nrhs = std::min(kMaxBatch, nrhs - r0);

@@ -377,7 +377,9 @@ class Server:
                     S = torch.cat([a.s for a in active]) if k > 1 else active[0].s
                     T = torch.cat([a.t for a in active]) if k > 1 else active[0].t
                     U = torch.cat([a.u for a in active]) if k > 1 else active[0].u
-                    solver = "batched" if k > 1 else single
+                    # flexible GMRES runs a batch in lock step itself (true-residual stops
+                    # for every request); left GMRES batches as "batched"
+                    solver = single if single == "fgmres" or k == 1 else "batched"
                     _, st, _ = ctx.gmres(S, T, tol=cfg.tol, restart=cfg.restart, u=U, solver=solver,
                                          precond_prec=cfg.precond_prec, max_iters=cfg.restart,
                                          use_x0=True)
