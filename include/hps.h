@@ -153,7 +153,9 @@ typedef struct {
                                 preconditioned GMRES(m) whose vectors are stored in complex FP32
                                 (basis, operator and J^-1 kernels read and write FP32, arithmetic
                                 FP64 inside), started from 0 on r / ||r|| and stopped at the
-                                preconditioned residual reduction inner_tol; x += ||r|| d in FP64.
+                                preconditioned residual reduction inner_tol, or at a tenth of the
+                                reduction the outer tolerance still needs when that is larger (the
+                                last refinement is short); x += ||r|| d in FP64.
                                 Stops when ||r|| <= tol ||b||.  Needs the separable J^-1
                                 (HPS_PREC_SEPARABLE; no operator groups); "iters" counts inner
                                 steps, "restarts" refinement steps; bytes_apply / bytes_precond
