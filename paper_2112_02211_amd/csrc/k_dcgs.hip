@@ -12,11 +12,11 @@
 namespace hps {
 namespace {
 
-// Non-temporal hints (template flag NT) for long vectors: the update pass's
-// basis loads and its stores of V[J] and u, and the basis loads of the
-// short-basis reduction, go around the caches, which a basis of more than a few
-// hundred MB leaves before it is read again.  Measured on 6.5M-entry vectors
-// (16^3 leaves, p = 12): update pass 551 -> 483 us, short-basis reduction
+// Non-temporal basis loads (template flag NT) for long vectors, in the update
+// pass and the short-basis reduction: a basis of more than a few hundred MB
+// leaves the caches before it is read again (all vector stores carry the hint,
+// see st2).  Measured on 6.5M-entry vectors (16^3 leaves, p = 12), together with
+// the update pass's stores: update pass 551 -> 483 us, short-basis reduction
 // 133 -> 112 us; on 0.46M-entry ones (8^3, p = 10), whose vectors live in the
 // last-level cache, the solve was 7 % slower, hence the threshold.  The hint
 // slowed the other reductions (2-10 %: there eight wavefronts share u and w
@@ -523,8 +523,8 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t 
     const double2 wv = widen(ld_tile(w, i, i, true), true);
     const double2 vj = make_double2((uv.x - sa.x) * inv, (uv.y - sa.y) * inv);
     const double2 t = cmul(vj, cj);
-    st2_h<NT>(V, (int64_t)J * ldv + i, vj);
-    st2_h<NT>(u, i, make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv));
+    st2(V, (int64_t)J * ldv + i, vj);
+    st2(u, i, make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv));
   }
 }
 
