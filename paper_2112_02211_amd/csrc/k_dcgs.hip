@@ -33,11 +33,17 @@ constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
 constexpr int UT = 256;        // update-pass (and small-step) workgroup
 constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
 constexpr int64_t kMidVector = 1 << 24;  // reduction grid sizes below / from here
-constexpr int kShortBasis = 8;           // reductions over at most this many basis vectors ...
+constexpr int kShortBasis = 12;          // reductions over at most this many basis vectors ...
 constexpr int64_t kLongVector = 1 << 21; // ... of at least this many entries split tiles over wavefronts
                                          // (measured: 3 % slower on 0.46M-entry vectors, where u and w
                                          // re-reads hit in cache; faster from 3.67M entries on: the
-                                         // 64-vector lock-step solve of those took 9.87 -> 9.46 s)
+                                         // 64-vector lock-step solve of those took 9.87 -> 9.46 s).
+                                         // Twelve, with one instantiation per basis size, covers every
+                                         // reduction of GMRES(10) (the closing one included): on 6.5M
+                                         // entries the FP64 solve took 128.6 -> 127.6 ms and iterative
+                                         // refinement 124.9 -> 118.2 ms against eight with one
+                                         // eight-vector instantiation (sixteen: no further change;
+                                         // 1024 workgroups instead of 512: 1 % slower)
 
 // Partials of a_k = sum conj(V_k) u, b_k = sum conj(V_k) w (k < J), c = sum |u|^2,
 // d = sum conj(u) w.  Wavefront ky owns basis vectors ky*kc .. ky*kc+kc-1 of the
@@ -653,6 +659,19 @@ __global__ __launch_bounds__(UT) void k_dcgs_restart(const VT* __restrict__ V, i
 
 namespace {
 
+// The split reduction instantiated for JM = max(J, 1): registers for the basis
+// vectors in use only (25-98 VGPRs for one to twelve vectors without w, 36-166
+// with w; eight waves per SIMD up to four or five vectors).
+template <bool HASW, typename VT, int JM = 1>
+void launch_reduce_es(int J, dim3 grid, hipStream_t st, const VT* V, int64_t ldv, int64_t vbs,
+                      const VT* u, int64_t ubs, const VT* w, int64_t wbs, int64_t n, double2* part) {
+  if constexpr (JM < kShortBasis) {
+    if (J > JM) return launch_reduce_es<HASW, VT, JM + 1>(J, grid, st, V, ldv, vbs, u, ubs, w, wbs, n, part);
+  }
+  hipLaunchKernelGGL((k_dcgs_reduce_es<JM, HASW, VT, true>), grid, dim3(DT), 0, st, V, ldv, vbs, J, u, ubs,
+                     w, wbs, n, part);
+}
+
 template <typename VT>
 int dcgs_reduce(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int J, const VT* u, int64_t ubs,
                 const VT* w, int64_t wbs, int64_t n, DcgsState* S, int nbatch, const RedBuf& rb) {
@@ -680,12 +699,8 @@ int dcgs_reduce(hps_ctx* c, const VT* V, int64_t ldv, int64_t vbs, int J, const 
   // vectors, where half the wavefronts idle and all re-read u and w)
   if (J <= kShortBasis && n >= kLongVector) {
     static_assert(kLongVector >= kNtVector, "the split reduction takes the non-temporal form");
-    if (hw)
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, true, VT, true>), grid, dim3(DT), 0, c->stream, V,
-                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
-    else
-      hipLaunchKernelGGL((k_dcgs_reduce_es<kShortBasis, false, VT, true>), grid, dim3(DT), 0, c->stream, V,
-                         ldv, vbs, J, u, ubs, w, wbs, n, rb.part);
+    if (hw) launch_reduce_es<true, VT>(J, grid, c->stream, V, ldv, vbs, u, ubs, w, wbs, n, rb.part);
+    else launch_reduce_es<false, VT>(J, grid, c->stream, V, ldv, vbs, u, ubs, w, wbs, n, rb.part);
   } else if (kc <= 2) HPS_DR(2); else if (kc <= 4) HPS_DR(4); else HPS_DR(8);
 #undef HPS_DR
   int rc = check_hip(hipGetLastError(), "k_dcgs_reduce");
