@@ -104,8 +104,13 @@ typedef struct {
  * entries with real and imaginary parts interleaved: Wc = Vc^{-1} (n1 x n1,
  * row major), Vc (the eigenvectors of the line operator Lt as columns, row
  * major), Ec (its n1 eigenvalues), Fi (the inverse 2 x 2 face system of a line,
- * row major: rows lo, hi).  HPS_ERR_NUMERIC if the eigendecomposition fails its
- * reconstruction check. */
+ * row major: rows lo, hi).  For even n1 the modes come in two halves: first
+ * those whose eigenvectors are even under the flip i <-> n1-1-i of a line
+ * (Lt commutes with it: the two faces of a line mirror each other), then the
+ * odd ones, each half sorted by real, then imaginary part, and the parity of
+ * the columns of Vc and the rows of Wc is exact; for odd n1 all n1 are sorted
+ * that way.  HPS_ERR_NUMERIC if the eigendecomposition fails its
+ * reconstruction check (or, for even n1, Lt is not symmetric under the flip). */
 int hps_separable_table(int p, double h, double eta, double* out);
 
 typedef struct {

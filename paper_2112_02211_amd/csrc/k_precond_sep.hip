@@ -22,7 +22,8 @@
 //   u_b   = g - Fi Fbi1 u_line                    on every grid line
 //
 // One workgroup per (leaf, right-hand side), the leaf in LDS, six complex mode
-// products (two forms, chosen per order: kLineWise).  Cost per leaf O(n1^4);
+// products (three forms, chosen per order: kSepForm; at p = 10 and 12 in even /
+// odd halves, kSepSplit).  Cost per leaf O(n1^4);
 // the kernel reads x and writes y once (32 bytes
 // per unknown), where the dense form also streams the n_b x n_b block.  The
 // tables (Wc, Vc, Ec, Fi per operator) are built on the host at setup.
@@ -69,6 +70,14 @@ template <> constexpr int kSepOutputs<12> = 5;
 // three; at p = 10 the registers it adds would cost a wavefront per SIMD.
 template <int P>
 constexpr bool kSepAliasG = P == 12;
+// Even / odd mode products (the table's modes split by parity under the flip
+// of a line, even n1 only; a work item's output group must hold modes of one
+// parity): each product takes half the multiplications.  Measured on 16^3
+// leaves: J^-1 at p = 12 80 -> 66 us in the solve (the solve 128.4 -> 124.1
+// ms), at p = 10 41.5 -> 39.8 us (64 right-hand sides 2.55 -> 2.40 ms); at
+// p = 8 (n1 = 6: one or three outputs per item instead of two) 4-15 % slower.
+template <int P>
+constexpr bool kSepSplit = P == 12 || P == 10;
 // config end
 
 template <int P>
@@ -112,7 +121,7 @@ __device__ __forceinline__ void line_of(int ax, int a, int b, int& base, int& st
 // major).  SCALE: the output element (i, j, k) is multiplied by
 // 1 / (-(Ec_i + Ec_j + Ec_k) - lambda) (the last forward product).
 // Line-wise form: M in global memory, read at wavefront-uniform addresses.
-template <int P, int AX, bool SCALE>
+template <int P, int AX, bool SCALE, bool INV>
 __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2* __restrict__ out,
                                          const double2* __restrict__ M, const double2* __restrict__ Ec,
                                          double2 lm) {
@@ -127,6 +136,47 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
     const int a = line % N1, b = line / N1;
     int base, stride;
     line_of<P>(AX, a, b, base, stride);
+    if constexpr (kSepSplit<P>) {
+      // Modes 0 .. H-1 are even, H .. n1-1 odd (H = n1 / 2): an even row of
+      // Wc is symmetric (Wc[o][n1-1-i] = Wc[o][i]), an odd row antisymmetric,
+      // and the even / odd columns of Vc likewise.  Forward: fold the line
+      // (v_i +/- v_{n1-1-i}, i < H) and take H terms per output.  Inverse:
+      // the even group writes A_i = sum_e Vc[i][e] z_e at position i, the odd
+      // group B_i = sum_o Vc[i][H + o] z_{H + o} at n1-1-i; the butterflies
+      // (A + B, A - B) along all three axes follow the last product.
+      static_assert(N1 % 2 == 0 && (N1 / 2) % R == 0, "groups of one parity");
+      constexpr int H = N1 / 2;
+      const bool odd = og * R >= H;   // uniform across the wavefront
+      double2 f[H];
+      if constexpr (!INV) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          const double2 lo = in[base + i * stride], hi = in[base + (N1 - 1 - i) * stride];
+          f[i] = odd ? csub(lo, hi) : cadd(lo, hi);
+        }
+      } else {
+        const int h0 = odd ? H : 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) f[q] = in[base + (h0 + q) * stride];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int o = og * R + r;
+        const double2* Mr = INV ? M + (odd ? (o - H) * N1 + H : o * N1) : M + o * N1;
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < H; ++q) cfma(s, Mr[q], f[q]);
+        if (SCALE) {   // AX == 2: output element (a, b, o)
+          const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
+          const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
+          const double den = 1.0 / (ar * ar + ai * ai);
+          s = cmul(s, make_double2(ar * den, -ai * den));
+        }
+        const int pos = (INV && odd) ? N1 - 1 - (o - H) : o;
+        out[base + pos * stride] = s;
+      }
+      continue;
+    }
     double2 v[N1];
 #pragma unroll
     for (int i = 0; i < N1; ++i) v[i] = in[base + i * stride];
@@ -215,14 +265,44 @@ __device__ __forceinline__ void cmode_ip(double2* __restrict__ T, const double2*
   }
 }
 
-// One mode product in the order's form; in place, out is in (the result is in T).
-template <int P, int AX, bool SCALE>
+// One mode product in the order's form (INV: a product with Vc); in place, out
+// is in (the result is in T).
+template <int P, int AX, bool SCALE, bool INV>
 __device__ __forceinline__ void cmode(const double2* in, double2* out, const double2* __restrict__ Mg,
                                       const double2* __restrict__ Ml, const double2* __restrict__ Ec,
                                       double2 lm) {
+  static_assert(!kSepSplit<P> || SL<P>::LW, "even / odd products in the line-wise form only");
   if constexpr (SL<P>::IP) cmode_ip<P, AX, SCALE>(const_cast<double2*>(in), Mg, Ec, lm);
-  else if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE>(in, out, Mg, Ec, lm);
+  else if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE, INV>(in, out, Mg, Ec, lm);
   else cmode_el<P, AX, SCALE>(in, out, Ml, Ec, lm);
+}
+
+// The butterflies the even / odd inverse products leave: per axis, the pair
+// (A at i, B at n1-1-i) of every line becomes (A + B, A - B); one thread per
+// group of eight mirror images.
+template <int P>
+__device__ __forceinline__ void split_butterflies(double2* __restrict__ T) {
+  using S = SL<P>;
+  constexpr int N1 = S::N1, H = N1 / 2, BD = S::BD;
+  for (int g = threadIdx.x; g < H * H * H; g += BD) {
+    const int i = g % H, j = (g / H) % H, k = g / (H * H);
+    const int ii[2] = {i, N1 - 1 - i}, jj[2] = {j, N1 - 1 - j}, kk[2] = {k, N1 - 1 - k};
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = T[lidx<P>(ii[q & 1], jj[(q >> 1) & 1], kk[q >> 2])];
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q & bit) continue;
+        const double2 x = v[q], y = v[q | bit];
+        v[q] = cadd(x, y);
+        v[q | bit] = csub(x, y);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) T[lidx<P>(ii[q & 1], jj[(q >> 1) & 1], kk[q >> 2])] = v[q];
+  }
 }
 
 // The leaf's loads are issued before any of them is used: up to eight interior
@@ -389,18 +469,22 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   // u_i = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
   // (ping-pong T -> X -> T ..., ending in T; in place: all in T)
   double2* const X1 = S::IP ? T : X;
-  cmode<P, 0, false>(T, X1, Wc, Wl, Ec, lm);
+  cmode<P, 0, false, false>(T, X1, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 1, false>(X1, T, Wc, Wl, Ec, lm);
+  cmode<P, 1, false, false>(X1, T, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 2, true>(T, X1, Wc, Wl, Ec, lm);
+  cmode<P, 2, true, false>(T, X1, Wc, Wl, Ec, lm);
   __syncthreads();
-  cmode<P, 0, false>(X1, T, Vc, Vl, Ec, lm);
+  cmode<P, 0, false, true>(X1, T, Vc, Vl, Ec, lm);
   __syncthreads();
-  cmode<P, 1, false>(T, X1, Vc, Vl, Ec, lm);
+  cmode<P, 1, false, true>(T, X1, Vc, Vl, Ec, lm);
   __syncthreads();
-  cmode<P, 2, false>(X1, T, Vc, Vl, Ec, lm);
+  cmode<P, 2, false, true>(X1, T, Vc, Vl, Ec, lm);
   __syncthreads();
+  if constexpr (kSepSplit<P>) {
+    split_butterflies<P>(T);
+    __syncthreads();
+  }
   for (int m = threadIdx.x; m < NI; m += BD) {
     const int i = m % N1, j = (m / N1) % N1, k = m / L;
     st2(yv, m, T[lidx<P>(i, j, k)]);

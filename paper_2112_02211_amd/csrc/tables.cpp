@@ -455,7 +455,8 @@ void build_face_operators(const HostTables& t, std::vector<double>* Fbi, std::ve
 // with Lt = D2[1:e, 1:e] - D2[1:e, {0, e}] Fi Fbi1, a complex n1 x n1 matrix.
 // With Lt = Vc diag(Ec) Vc^{-1} the interior solve is a fast diagonalization
 // as in Algorithm 3, now with complex factors.  Packed table (complex, row
-// major): [Wc = Vc^{-1} | Vc | Ec | Fi].
+// major): [Wc = Vc^{-1} | Vc | Ec | Fi]; for even n1 the modes are split into
+// even and odd ones under the flip of a line (below).
 std::string build_sep_table(const HostTables& t, double eta, std::vector<double>* out) {
   const int p = t.p, n1 = t.n1, e = p - 1;
   const std::vector<double>& D = t.D;
@@ -475,53 +476,104 @@ std::string build_sep_table(const HostTables& t, double eta, std::vector<double>
     }
   double lnorm = 0.0;
   for (const cd& v : Lt) lnorm = std::max(lnorm, std::abs(v));
-  std::vector<cd> ev;
-  if (!complex_eigenvalues(Lt, n1, ev)) return "eigenvalues of the line operator did not converge";
-  std::sort(ev.begin(), ev.end(), [](const cd& a, const cd& b) {
-    return a.real() != b.real() ? a.real() < b.real() : a.imag() < b.imag();
-  });
-  // eigenvectors by inverse iteration with a slightly perturbed shift
-  CMat V(n1 * n1, 0.0);
-  for (int k = 0; k < n1; ++k) {
-    const cd lam = ev[k];
-    const cd shift = lam + 1e-10 * std::max(std::abs(lam), 1.0);
-    CMat M = Lt;
-    for (int i = 0; i < n1; ++i) M[i * n1 + i] -= shift;
+  // eigenpairs of an n x n complex matrix: eigenvalues sorted by real, then
+  // imaginary part; eigenvectors (columns of X, row major) by inverse
+  // iteration with a slightly perturbed shift, unit norm, largest component
+  // real and positive
+  auto eig = [&](const CMat& A, int n, std::vector<cd>& ev, CMat& X) -> std::string {
+    if (!complex_eigenvalues(A, n, ev)) return "eigenvalues of the line operator did not converge";
+    std::sort(ev.begin(), ev.end(), [](const cd& a, const cd& b) {
+      return a.real() != b.real() ? a.real() < b.real() : a.imag() < b.imag();
+    });
+    X.assign((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+      const cd lam = ev[k];
+      const cd shift = lam + 1e-10 * std::max(std::abs(lam), 1.0);
+      CMat M = A;
+      for (int i = 0; i < n; ++i) M[i * n + i] -= shift;
+      std::vector<int> piv;
+      if (!clu_factor(M, piv, n)) return "inverse iteration: singular shift";
+      std::vector<cd> x(n);
+      for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.1 * std::sin(1.7 * i + 0.3 * k);
+      for (int it = 0; it < 4; ++it) {
+        clu_solve(M, piv, n, x);
+        double nrm = 0.0;
+        for (const cd& v : x) nrm += std::norm(v);
+        nrm = std::sqrt(nrm);
+        for (cd& v : x) v /= nrm;
+      }
+      int im = 0;
+      for (int i = 1; i < n; ++i)
+        if (std::abs(x[i]) > std::abs(x[im])) im = i;
+      const cd ph = std::abs(x[im]) / x[im];
+      for (cd& v : x) v *= ph;
+      double r = 0.0;
+      for (int i = 0; i < n; ++i) {
+        cd s = -lam * x[i];
+        for (int j = 0; j < n; ++j) s += A[i * n + j] * x[j];
+        r = std::max(r, std::abs(s));
+      }
+      if (r > 1e-9 * lnorm) return "line operator: eigenvector residual too large";
+      for (int i = 0; i < n; ++i) X[i * n + k] = x[i];
+    }
+    return std::string();
+  };
+  auto inverse = [&](const CMat& A, int n, CMat& Ai) -> bool {
+    CMat LU = A;
     std::vector<int> piv;
-    if (!clu_factor(M, piv, n1)) return "inverse iteration: singular shift";
-    std::vector<cd> x(n1);
-    for (int i = 0; i < n1; ++i) x[i] = 1.0 + 0.1 * std::sin(1.7 * i + 0.3 * k);
-    for (int it = 0; it < 4; ++it) {
-      clu_solve(M, piv, n1, x);
-      double nrm = 0.0;
-      for (const cd& v : x) nrm += std::norm(v);
-      nrm = std::sqrt(nrm);
-      for (cd& v : x) v /= nrm;
+    if (!clu_factor(LU, piv, n)) return false;
+    Ai.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+      std::vector<cd> col(n, 0.0);
+      col[j] = 1.0;
+      clu_solve(LU, piv, n, col);
+      for (int i = 0; i < n; ++i) Ai[i * n + j] = col[i];
     }
-    // phase convention: largest component real and positive
-    int im = 0;
-    for (int i = 1; i < n1; ++i)
-      if (std::abs(x[i]) > std::abs(x[im])) im = i;
-    const cd ph = std::abs(x[im]) / x[im];
-    for (cd& v : x) v *= ph;
-    double r = 0.0;
-    for (int i = 0; i < n1; ++i) {
-      cd s = -lam * x[i];
-      for (int j = 0; j < n1; ++j) s += Lt[i * n1 + j] * x[j];
-      r = std::max(r, std::abs(s));
+    return true;
+  };
+  std::vector<cd> ev(n1);
+  CMat V(n1 * n1, 0.0), W(n1 * n1, 0.0);
+  if (n1 % 2 == 0) {
+    // Lt commutes with the flip J (i <-> n1-1-i: the two faces of a line mirror
+    // each other), so its eigenvectors are even ([y; J y]) or odd ([y; -J y]),
+    // with y an eigenvector of Le = L11 + L12 J or Lo = L11 - L12 J (h x h,
+    // h = n1 / 2).  Even modes come first, then odd ones; with
+    // Ye = [y_e / sqrt 2], Yo likewise, Vc = [[Ye, Yo], [J Ye, -J Yo]] and
+    // Wc = Vc^{-1} = [[Ye^{-1}, Ye^{-1} J], [Yo^{-1}, -Yo^{-1} J]] / 2 hold
+    // the structure exactly, which the p = 12 kernel uses (each mode product
+    // then takes half the multiplications).
+    const int h = n1 / 2;
+    double asym = 0.0;
+    for (int i = 0; i < n1; ++i)
+      for (int j = 0; j < n1; ++j)
+        asym = std::max(asym, std::abs(Lt[i * n1 + j] - Lt[(n1 - 1 - i) * n1 + (n1 - 1 - j)]));
+    if (asym > 1e-12 * lnorm) return "line operator: not symmetric under the flip of a line";
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      const double s = sgn == 0 ? 1.0 : -1.0;
+      CMat Lh((size_t)h * h);
+      for (int i = 0; i < h; ++i)
+        for (int j = 0; j < h; ++j) Lh[i * h + j] = Lt[i * n1 + j] + s * Lt[i * n1 + (n1 - 1 - j)];
+      std::vector<cd> eh;
+      CMat Y, Yi;
+      std::string err = eig(Lh, h, eh, Y);
+      if (!err.empty()) return err;
+      for (cd& v : Y) v *= std::sqrt(0.5);
+      if (!inverse(Y, h, Yi)) return "line operator: eigenvector matrix singular";
+      for (int k = 0; k < h; ++k) {
+        const int col = sgn * h + k;
+        ev[col] = eh[k];
+        for (int i = 0; i < h; ++i) {
+          V[i * n1 + col] = Y[i * h + k];
+          V[(n1 - 1 - i) * n1 + col] = s * Y[i * h + k];
+          W[col * n1 + i] = 0.5 * Yi[k * h + i];
+          W[col * n1 + (n1 - 1 - i)] = 0.5 * s * Yi[k * h + i];
+        }
+      }
     }
-    if (r > 1e-9 * lnorm) return "line operator: eigenvector residual too large";
-    for (int i = 0; i < n1; ++i) V[i * n1 + k] = x[i];
-  }
-  CMat LU = V;
-  std::vector<int> piv;
-  if (!clu_factor(LU, piv, n1)) return "line operator: eigenvector matrix singular";
-  CMat W(n1 * n1);
-  for (int j = 0; j < n1; ++j) {
-    std::vector<cd> col(n1, 0.0);
-    col[j] = 1.0;
-    clu_solve(LU, piv, n1, col);
-    for (int i = 0; i < n1; ++i) W[i * n1 + j] = col[i];
+  } else {
+    std::string err = eig(Lt, n1, ev, V);
+    if (!err.empty()) return err;
+    if (!inverse(V, n1, W)) return "line operator: eigenvector matrix singular";
   }
   double rec = 0.0;
   for (int i = 0; i < n1; ++i)

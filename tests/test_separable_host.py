@@ -32,7 +32,7 @@ def _line_operator(d):
     return Lt, Fi
 
 
-def _separable_solve(d, lam, x, table):
+def _separable_solve(d, lam, x, table, split=False):
     """The kernel's steps: g = Fi [x_lo, x_hi] per line; r = x_i - A_ib g;
     u_i = (Vc x Vc x Vc) diag(1 / (-Ec_sum - lambda)) (Wc x Wc x Wc) r;
     u_b = g - Fi Fbi1 u_line.  Leaf layout [interior, x fastest | faces 1..6]."""
@@ -58,7 +58,10 @@ def _separable_solve(d, lam, x, table):
         return np.einsum("ok,kji->oji", M, A)
 
     Es = Ec[:, None, None] + Ec[None, :, None] + Ec[None, None, :]
-    U = modes(Vc, modes(Wc, T) / (-Es - lam))
+    if split:
+        U = _split_modes(Vc, _split_modes(Wc, T, False) / (-Es - lam), True)
+    else:
+        U = modes(Vc, modes(Wc, T) / (-Es - lam))
     out = np.zeros(d.n, dtype=complex)
     out[:NI] = U.reshape(-1)
     # lines along x through (j, k): U[k, j, :]; along y through (i, k): U[k, :, i]; along z: U[:, j, i]
@@ -68,6 +71,66 @@ def _separable_solve(d, lam, x, table):
         out[NI + 2 * ax * L:NI + (2 * ax + 1) * L] = (G[2 * ax] - (Fi[0, 0] * slo + Fi[0, 1] * shi)).reshape(-1)
         out[NI + (2 * ax + 1) * L:NI + (2 * ax + 2) * L] = (G[2 * ax + 1] - (Fi[1, 0] * slo + Fi[1, 1] * shi)).reshape(-1)
     return out
+
+
+def _split_modes(M, A, inverse):
+    """The even / odd mode products of the p = 12 kernel along the three axes
+    of A ([k][j][i]), with modes 0 .. H-1 even and H .. n1-1 odd.  Forward
+    (M = Wc): fold each line, v_i + v_{n1-1-i} for the even modes and v_i -
+    v_{n1-1-i} for the odd ones, and take H terms per output.  Inverse (M = Vc):
+    A_i from the even modes at position i, B_i from the odd modes at n1-1-i,
+    then the butterflies (A + B, A - B) along all three axes."""
+    n1 = M.shape[0]
+    H = n1 // 2
+    for ax in (2, 1, 0):       # x, y, z in turn (A is [k][j][i])
+        X = np.moveaxis(A, ax, -1)
+        out = np.empty_like(X)
+        if not inverse:
+            lo, hi = X[..., :H], X[..., ::-1][..., :H]
+            out[..., :H] = (lo + hi) @ M[:H, :H].T
+            out[..., H:] = (lo - hi) @ M[H:, :H].T
+        else:
+            out[..., :H] = X[..., :H] @ M[:H, :H].T
+            out[..., ::-1][..., :H] = X[..., H:] @ M[:H, H:].T
+        A = np.moveaxis(out, -1, ax)
+    if inverse:
+        for ax in range(3):
+            X = np.moveaxis(A, ax, -1)
+            a, b = X[..., :H].copy(), X[..., ::-1][..., :H].copy()
+            X[..., :H] = a + b
+            X[..., ::-1][..., :H] = a - b
+    return A
+
+
+@pytest.mark.parametrize("p", [4, 6, 8, 10, 12, 14, 16])
+def test_even_odd_mode_products_equal_the_full_ones(p):
+    # the kernel's even / odd form (fold, half products, deferred butterflies)
+    # against the plain fast diagonalization on the same table, and with it
+    # against the oracle's dense LU of the leaf matrix
+    rng = np.random.default_rng(100 + p)
+    kappa, h = 40.0, 0.125
+    d = O.make_disc((1, 1, 1), p, kappa, kappa, (0, 0, 0), (h, h, h))
+    Wc, Vc, Ec, Fi = hps.separable_table(p, h, kappa)
+    n1 = p - 2
+    r = rng.standard_normal((n1, n1, n1)) + 1j * rng.standard_normal((n1, n1, n1))
+    lam = kappa ** 2 * (0.7 + 0.05j)
+    Es = Ec[:, None, None] + Ec[None, :, None] + Ec[None, None, :]
+
+    def full(M, A):
+        A = np.einsum("oi,kji->kjo", M, A)
+        A = np.einsum("oj,kji->koi", M, A)
+        return np.einsum("ok,kji->oji", M, A)
+
+    want = full(Vc, full(Wc, r) / (-Es - lam))
+    got = _split_modes(Vc, _split_modes(Wc, r, False) / (-Es - lam), True)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-13
+    # and the whole leaf solve with it
+    ops = O.local_ops(d)
+    A, _ = O.leaf_matrices(d, np.full(d.ni, lam), ops)
+    x = rng.standard_normal(d.n) + 1j * rng.standard_normal(d.n)
+    sol = np.linalg.solve(A, x)
+    out = _separable_solve(d, lam, x, (Wc, Vc, Ec, Fi), split=True)
+    assert np.linalg.norm(out - sol) / np.linalg.norm(sol) < 1e-12
 
 
 @pytest.mark.parametrize("p", list(range(4, 17)))
@@ -80,10 +143,22 @@ def test_table_is_an_eigendecomposition_of_the_line_operator(p):
     assert np.max(np.abs(Wc @ Vc - np.eye(n1))) < 1e-12
     assert np.max(np.abs(Vc @ np.diag(Ec) @ Wc - Lt)) < 1e-11 * np.max(np.abs(Lt))
     assert np.max(np.abs(Fi - Fi_o)) < 1e-13 * np.max(np.abs(Fi_o))
-    # the spectrum is that of Lt (sorted by real part, then imaginary part)
+    # the spectrum is that of Lt
     ev = np.linalg.eigvals(Lt)
     ev = ev[np.lexsort((ev.imag, ev.real))]
-    assert np.max(np.abs(Ec - ev)) < 1e-10 * np.max(np.abs(ev))
+    got = Ec[np.lexsort((Ec.imag, Ec.real))]
+    assert np.max(np.abs(got - ev)) < 1e-10 * np.max(np.abs(ev))
+    if n1 % 2 == 0:
+        # Lt commutes with the flip of a line (its two faces mirror each other):
+        # modes 0 .. n1/2-1 are even, the rest odd, exactly (the p = 12 kernel
+        # takes half the terms of each mode product from this)
+        H, J = n1 // 2, np.eye(n1)[::-1]
+        assert np.max(np.abs(J @ Lt @ J - Lt)) < 1e-13 * np.max(np.abs(Lt))
+        par = np.r_[np.ones(H), -np.ones(H)]
+        assert np.array_equal(J @ Vc, Vc * par)
+        assert np.array_equal(Wc @ J, par[:, None] * Wc)
+    else:
+        assert np.array_equal(Ec, Ec[np.lexsort((Ec.imag, Ec.real))])
 
 
 @pytest.mark.parametrize("p", list(range(4, 17)))
