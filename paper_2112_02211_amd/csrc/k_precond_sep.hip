@@ -66,8 +66,9 @@ template <> constexpr int kSepThreads<12> = 256;
 template <> constexpr int kSepMinWaves<12> = 8;
 template <> constexpr int kSepOutputs<12> = 5;
 // Face values in the second tensor's space (where it holds them): at p = 12 it
-// takes the leaf from 45.3 to 35.7 KB of LDS, four leaves per CU instead of
-// three; at p = 10 the registers it adds would cost a wavefront per SIMD.
+// took the leaf from 45.3 to 35.7 KB of LDS, four leaves per CU instead of
+// three (before the in-place even / odd products removed that tensor); at
+// p = 10 the registers it adds would cost a wavefront per SIMD.
 template <int P>
 constexpr bool kSepAliasG = P == 12;
 // Even / odd mode products (the table's modes split by parity under the flip
@@ -78,6 +79,14 @@ constexpr bool kSepAliasG = P == 12;
 // p = 8 (n1 = 6: one or three outputs per item instead of two) 4-15 % slower.
 template <int P>
 constexpr bool kSepSplit = P == 12 || P == 10;
+// Even / odd products in place: every work item holds its line's inputs in
+// registers, so after a barrier it can write its outputs over them and the
+// second LDS tensor goes (one work item per wavefront and product).  At
+// p = 12: 27.7 KB of LDS per leaf instead of 35.7 (five leaves per CU instead
+// of four), J^-1 64.5 -> 62.8 us, the 16^3 solve 124.1 -> 122.9 ms; p = 10 is
+// held to three workgroups per CU by its registers either way.
+template <int P>
+constexpr bool kSepSplitInPlace = P == 12;
 // config end
 
 template <int P>
@@ -90,7 +99,8 @@ struct SL {
   // line-wise: the LDS tensors pad each x-line to n1 + 1 entries, so the
   // threads of a wavefront that walk neighbouring x-lines read 16-byte words in
   // different banks
-  static constexpr int P1 = (LW || IP) ? N1 + 1 : N1, SZ = P1 * L, SZX = IP ? 1 : SZ;
+  static constexpr bool SIP = kSepSplitInPlace<P>;
+  static constexpr int P1 = (LW || IP) ? N1 + 1 : N1, SZ = P1 * L, SZX = (IP || SIP) ? 1 : SZ;
   // line-wise work items: (output group of R, 64 lines) per wavefront
   static constexpr int R = kSepOutputs<P>, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
   // tables staged in LDS: Ec | Fi, and for the element-parallel form Wc | Vc before them
@@ -129,6 +139,53 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
   constexpr int N1 = S::N1, L = S::L, R = S::R, WPG = S::WPG, NW = S::BD / 64;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  if constexpr (S::SIP) {
+    // in place (in == out): every item's inputs to registers, a barrier, then
+    // every item's outputs (the barrier is outside any branch)
+    static_assert(kSepSplit<P> && S::W <= NW, "one work item per wavefront");
+    constexpr int H = N1 / 2;
+    const int og = wave / WPG;
+    const int line = (wave - og * WPG) * 64 + lane;
+    const bool act = wave < S::W && line < L;
+    const int a = act ? line % N1 : 0, b = act ? line / N1 : 0;
+    int base, stride;
+    line_of<P>(AX, a, b, base, stride);
+    const bool odd = og * R >= H;
+    double2 f[H];
+    if (act) {
+      if constexpr (!INV) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          const double2 lo = in[base + i * stride], hi = in[base + (N1 - 1 - i) * stride];
+          f[i] = odd ? csub(lo, hi) : cadd(lo, hi);
+        }
+      } else {
+        const int h0 = odd ? H : 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) f[q] = in[base + (h0 + q) * stride];
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int o = og * R + r;
+        const double2* Mr = INV ? M + (odd ? (o - H) * N1 + H : o * N1) : M + o * N1;
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < H; ++q) cfma(s, Mr[q], f[q]);
+        if (SCALE) {
+          const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
+          const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
+          const double den = 1.0 / (ar * ar + ai * ai);
+          s = cmul(s, make_double2(ar * den, -ai * den));
+        }
+        const int pos = (INV && odd) ? N1 - 1 - (o - H) : o;
+        out[base + pos * stride] = s;
+      }
+    }
+    return;
+  }
   for (int w = wave; w < S::W; w += NW) {
     const int og = w / WPG;
     const int line = (w - og * WPG) * 64 + lane;
@@ -468,7 +525,7 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   __syncthreads();
   // u_i = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
   // (ping-pong T -> X -> T ..., ending in T; in place: all in T)
-  double2* const X1 = S::IP ? T : X;
+  double2* const X1 = (S::IP || S::SIP) ? T : X;
   cmode<P, 0, false, false>(T, X1, Wc, Wl, Ec, lm);
   __syncthreads();
   cmode<P, 1, false, false>(X1, T, Wc, Wl, Ec, lm);
