@@ -363,7 +363,9 @@ int hps_kernel_times(hps_ctx* c, double out[8], int reset);
 
 /* The Arnoldi update pass (one launch per Arnoldi step, the basis read once;
  * with the dense blocks replaced by the separable J^-1 it is the largest
- * kernel of a solve), timed like the kinds above: out[0] = milliseconds of the
+ * kernel of a solve; on long vectors the last one of a restart cycle also makes
+ * the cycle's closing reduction from the values it holds), timed like the
+ * kinds above: out[0] = milliseconds of the
  * timed launches, out[1] = their number, out[2] = their algorithmic HBM bytes
  * (per right-hand side and step j: basis vectors 0..j-1 and two vectors read,
  * two written, 16 N (j + 4) bytes).  Synchronizes the stream; reset != 0

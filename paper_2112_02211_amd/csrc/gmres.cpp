@@ -469,6 +469,7 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, XT* x, double tol, int m, 
       return all ? 1 : 0;
     };
     bool stopped = false;   // the step records said every right-hand side is done or stuck
+    bool closed = false;    // the last update pass made the closing reduction
     int last_step = -1;     // the last step's record, read after the closing work is queued
     uint64_t last_tag = 0;
     for (int j = 0; j < m && its < maxit; ++j) {
@@ -483,11 +484,15 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, XT* x, double tol, int m, 
       const int slot = j & 1;
       ++its;
       const uint64_t tag = epoch | (uint64_t)its;
-      if ((rc = launch_dcgs_update(c, V, NB, N, j, U, N, W, N, N, S, nb, job.flexible ? 1 : 0,
-                                   drec + 4 * slot * nb, tag)))
+      const bool last = (j == m - 1) || its >= maxit;
+      // the last update pass of a cycle also makes the closing reduction
+      closed = last && dcgs_can_close(j, N);
+      if ((rc = closed ? launch_dcgs_update_close(c, V, NB, N, j, U, N, W, N, N, S, nb,
+                                                  job.flexible ? 1 : 0, drec + 4 * slot * nb, tag, rb)
+                       : launch_dcgs_update(c, V, NB, N, j, U, N, W, N, N, S, nb, job.flexible ? 1 : 0,
+                                            drec + 4 * slot * nb, tag)))
         return rc;
       written = j + 1;
-      const bool last = (j == m - 1) || its >= maxit;
       const bool want = (its % check_every == 0) || last;
       if (pending >= 0) {
         const int cv = converged_at(pending, pending_tag);
@@ -509,8 +514,10 @@ int run_dcgs(hps_ctx* c, const Job& job, const VT* b, XT* x, double tol, int m, 
       }
     }
     // close the last column: reduction of the current candidate against the
-    // basis (a no-op for right-hand sides whose cycle already stopped)
-    if ((rc = launch_dcgs_reduce(c, V, NB, N, written, U, N, nullptr, 0, N, S, nb, rb))) return rc;
+    // basis (a no-op for right-hand sides whose cycle already stopped), unless
+    // the last update pass made it
+    if (!closed && (rc = launch_dcgs_reduce(c, V, NB, N, written, U, N, nullptr, 0, N, S, nb, rb)))
+      return rc;
     if ((rc = launch_dcgs_small(c, S, nb, written, job.flexible ? 1 : 0, 1, d_res, 0))) return rc;
     if ((rc = launch_dcgs_trisolve(c, S, nb, written, job.flexible ? 1 : 0))) return rc;
     // left GMRES on FP64 vectors: x += V y and the next residual from the

@@ -96,6 +96,17 @@ struct DcgsState {
   int rk;                           // restart: basis vectors the new residual combines
 };
 
+// The update pass of the last step J of a cycle (long vectors, J <= 12: see
+// dcgs_can_close) with the cycle's closing reduction folded in: S[b].red gets
+// a_k (k <= J) and c of the new candidate, as launch_dcgs_reduce over the
+// J + 1 basis vectors and u without w would give them.
+bool dcgs_can_close(int J, int64_t n);
+int launch_dcgs_update_close(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
+                             int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
+                             int nbatch, int flexible, double* res_out, uint64_t tag, const RedBuf& rb);
+int launch_dcgs_update_close(hps_ctx* c, float2* V, int64_t ldv, int64_t vbs, int J, float2* u,
+                             int64_t ubs, const float2* w, int64_t wbs, int64_t n, DcgsState* S,
+                             int nbatch, int flexible, double* res_out, uint64_t tag, const RedBuf& rb);
 // reduction pass: partials of a, b (j basis vectors), c, d, finished into S[b].red
 int launch_dcgs_reduce(hps_ctx* c, const double2* V, int64_t ldv, int64_t vbs, int J,
                        const double2* u, int64_t ubs, const double2* w, int64_t wbs, int64_t n,

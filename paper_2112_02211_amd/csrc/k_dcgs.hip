@@ -33,6 +33,7 @@ constexpr int DT = 64 * DW;    // its threads; one tile = 64 vector entries
 constexpr int UT = 256;        // update-pass (and small-step) workgroup
 constexpr double kBreakdownTol = 1e-14;  // beta^2 <= tol * ||u||^2: the candidate is in the span
 constexpr int64_t kMidVector = 1 << 24;  // reduction grid sizes below / from here
+constexpr int kCloseMaxJ = 12;           // last steps whose update pass takes the closing reduction
 constexpr int kShortBasis = 12;          // reductions over at most this many basis vectors ...
 constexpr int64_t kLongVector = 1 << 21; // ... of at least this many entries split tiles over wavefronts
                                          // (measured: 3 % slower on 0.46M-entry vectors, where u and w
@@ -534,6 +535,111 @@ __global__ __launch_bounds__(UT) void k_dcgs_update(VT* __restrict__ V, int64_t 
   }
 }
 
+// The update pass of the last step J of a cycle with the cycle's closing
+// reduction folded in: besides V[J] and the new candidate u it writes, per
+// workgroup, the partials of a_k = sum conj(V_k) u (k <= J, V_J included) and
+// c = sum |u|^2 of that new candidate (the reduction k_dcgs_reduce would
+// otherwise make over the J + 1 basis vectors and u without w).  Every basis
+// entry is already in registers, so the reduction costs no HBM traffic.  The
+// grid is at most kRedBlocks workgroups, each thread taking entries with a
+// grid stride; one instantiation per J (JM = J: the loads carry no predicate).  When the step breaks down
+// (or the cycle already stopped) the partials are zero and unused: the
+// closing small step then sees the cycle's stop flag.
+template <typename VT, bool NT, int JM>
+__global__ __launch_bounds__(UT) void k_dcgs_update_close(VT* __restrict__ V, int64_t ldv, int64_t vbs,
+                                                          int J, VT* __restrict__ u, int64_t ubs,
+                                                          const VT* __restrict__ w, int64_t wbs,
+                                                          int64_t n, DcgsState* __restrict__ S,
+                                                          int flexible, double* __restrict__ res_out,
+                                                          unsigned long long tag, double tiny,
+                                                          double2* __restrict__ part) {
+  const int bz = blockIdx.z;
+  DcgsState& s = S[bz];
+  constexpr int JA = JM > 0 ? JM : 1;   // array sizes
+  __shared__ SmallSmem sm;
+  __shared__ double2 red[UT / 64][JM + 2];
+  const int flag = s.flag;
+  const Coef cf = dcgs_coeffs(s, JM, true, sm, tiny);
+  if (blockIdx.x == 0) dcgs_small_step(s, JM, flexible, 0, res_out + 4 * bz, tag, sm, cf, flag);
+  (void)J;
+  const unsigned nblk = gridDim.x;
+  double2* pz = part + (int64_t)bz * kPartSlots * nblk;
+  if (flag || !cf.ok) {
+    if ((int)threadIdx.x <= JM) pz[(int64_t)threadIdx.x * nblk + blockIdx.x] = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0) pz[(int64_t)kSlotC * nblk + blockIdx.x] = make_double2(0.0, 0.0);
+    return;
+  }
+  V += bz * vbs;
+  u += bz * ubs;
+  w += bz * wbs;
+  const double inv = cf.inv;
+  const double2 cj = cf.vjw;
+  const double2* ca = sm.a;
+  const double2* cb = sm.b;
+  double2 acc[JM + 1];
+#pragma unroll
+  for (int q = 0; q <= JM; ++q) acc[q] = make_double2(0.0, 0.0);
+  double cc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * UT + threadIdx.x; i < n; i += (int64_t)nblk * UT) {
+    // the step coefficients are read from LDS again on every pass (held in
+    // registers they took 8 VGPRs per basis vector: 182 instead of 124 at
+    // J = 9, two waves per SIMD instead of four)
+    asm volatile("" ::: "memory");
+    VT r[JA];
+#pragma unroll
+    for (int q = 0; q < JM; ++q) r[q] = NT ? ld_nt2(V + (int64_t)q * ldv + i) : V[(int64_t)q * ldv + i];
+    const double2 uv = widen(ld_tile(u, i, i, true), true);
+    const double2 wv = widen(ld_tile(w, i, i, true), true);
+    double2 v[JA];
+#pragma unroll
+    for (int q = 0; q < JM; ++q) v[q] = widen(r[q], true);
+    double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) {
+      const double2 x = ca[q], y = cb[q];
+      sa.x = fma(v[q].x, x.x, fma(-v[q].y, x.y, sa.x));
+      sa.y = fma(v[q].x, x.y, fma(v[q].y, x.x, sa.y));
+      sb.x = fma(v[q].x, y.x, fma(-v[q].y, y.y, sb.x));
+      sb.y = fma(v[q].x, y.y, fma(v[q].y, y.x, sb.y));
+    }
+    const double2 vj = make_double2((uv.x - sa.x) * inv, (uv.y - sa.y) * inv);
+    const double2 t = cmul(vj, cj);
+    const double2 un = make_double2((wv.x - sb.x - t.x) * inv, (wv.y - sb.y - t.y) * inv);
+    st2(V, (int64_t)JM * ldv + i, vj);
+    st2(u, i, un);
+    // the closing sums over the values as stored
+    const double2 vs = as_stored(vj, V), us = as_stored(un, u);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) {
+      acc[q].x = fma(v[q].x, us.x, fma(v[q].y, us.y, acc[q].x));
+      acc[q].y = fma(v[q].x, us.y, fma(-v[q].y, us.x, acc[q].y));
+    }
+    acc[JM].x = fma(vs.x, us.x, fma(vs.y, us.y, acc[JM].x));
+    acc[JM].y = fma(vs.x, us.y, fma(-vs.y, us.x, acc[JM].y));
+    cc = fma(us.x, us.x, fma(us.y, us.y, cc));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q <= JM; ++q) {
+    const double ar = wave_sum(acc[q].x), ai = wave_sum(acc[q].y);
+    if (lane == 0) red[wv][q] = make_double2(ar, ai);
+  }
+  {
+    const double cs = wave_sum(cc);
+    if (lane == 0) red[wv][JM + 1] = make_double2(cs, 0.0);
+  }
+  __syncthreads();
+  // slots 0 .. J: a_k (V_J included); slot C: c
+  const int t = threadIdx.x;
+  if (t <= JM + 1) {
+    double2 v = red[0][t];
+#pragma unroll
+    for (int q = 1; q < UT / 64; ++q) v = cadd(v, red[q][t]);
+    const int slot = t <= JM ? t : kSlotC;
+    pz[(int64_t)slot * nblk + blockIdx.x] = v;
+  }
+}
+
 // y = R^{-1} gls over k = min(kmax, ncols) columns (y zero beyond); flexible: y <- T y.
 __global__ __launch_bounds__(64) void k_dcgs_trisolve(DcgsState* __restrict__ S, int kmax,
                                                       int flexible) {
@@ -764,7 +870,61 @@ int dcgs_update(hps_ctx* c, VT* V, int64_t ldv, int64_t vbs, int J, VT* u, int64
   return timing_commit(c, 4, tp, (double)sizeof(VT) * (J + 4) * (double)n * nbatch);
 }
 
+// the last update pass of a cycle with its closing reduction (long vectors)
+template <typename VT, int JM = 0>
+int dcgs_update_close_j(hps_ctx* c, dim3 grid, hipEvent_t e0, hipEvent_t e1, VT* V, int64_t ldv,
+                        int64_t vbs, int J, VT* u, int64_t ubs, const VT* w, int64_t wbs, int64_t n,
+                        DcgsState* S, int flexible, double* res_out, uint64_t tag, double2* part) {
+  if constexpr (JM < kCloseMaxJ) {
+    if (J > JM)
+      return dcgs_update_close_j<VT, JM + 1>(c, grid, e0, e1, V, ldv, vbs, J, u, ubs, w, wbs, n, S,
+                                             flexible, res_out, tag, part);
+  }
+  return check_hip(launch_k(c, e0, e1, k_dcgs_update_close<VT, true, JM>, grid, dim3(UT), V, ldv, vbs, J,
+                            u, ubs, w, wbs, n, S, flexible, res_out, (unsigned long long)tag,
+                            kBreakdownTol, part),
+                   "k_dcgs_update_close");
+}
+
+template <typename VT>
+int dcgs_update_close(hps_ctx* c, VT* V, int64_t ldv, int64_t vbs, int J, VT* u, int64_t ubs,
+                      const VT* w, int64_t wbs, int64_t n, DcgsState* S, int nbatch, int flexible,
+                      double* res_out, uint64_t tag, const RedBuf& rb) {
+  if (J < 0 || J > kCloseMaxJ || n < kNtVector || nbatch > rb.nbatch)
+    return fail(HPS_ERR_ARG, "closing update: basis too long or vector too short");
+  const int64_t tiles = (n + UT - 1) / UT;
+  const int nblk = (int)std::min<int64_t>(tiles, kRedBlocks);
+  TimedPair tp;
+  int rc = timing_pair(c, 4, &tp);
+  if (rc) return rc;
+  rc = dcgs_update_close_j<VT>(c, dim3(nblk, 1, nbatch), tp.start, tp.stop, V, ldv, vbs, J, u, ubs, w,
+                               wbs, n, S, flexible, res_out, tag, rb.part);
+  if (rc) {
+    timing_drop(c, tp);
+    return rc;
+  }
+  if ((rc = timing_commit(c, 4, tp, (double)sizeof(VT) * (J + 4) * (double)n * nbatch))) return rc;
+  // finish a_0 .. a_J and c, as the reduction without w over J + 1 vectors does
+  const int nslots = J + 2;
+  hipLaunchKernelGGL(k_dcgs_finish, dim3((nslots + 3) / 4, nbatch), dim3(256), 0, c->stream, rb.part, J + 1,
+                     0, nblk, S);
+  return check_hip(hipGetLastError(), "k_dcgs_finish");
+}
+
 }  // namespace
+
+bool dcgs_can_close(int J, int64_t n) { return J >= 0 && J <= kCloseMaxJ && n >= kNtVector; }
+
+int launch_dcgs_update_close(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
+                             int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,
+                             int nbatch, int flexible, double* res_out, uint64_t tag, const RedBuf& rb) {
+  return dcgs_update_close(c, V, ldv, vbs, J, u, ubs, w, wbs, n, S, nbatch, flexible, res_out, tag, rb);
+}
+int launch_dcgs_update_close(hps_ctx* c, float2* V, int64_t ldv, int64_t vbs, int J, float2* u,
+                             int64_t ubs, const float2* w, int64_t wbs, int64_t n, DcgsState* S,
+                             int nbatch, int flexible, double* res_out, uint64_t tag, const RedBuf& rb) {
+  return dcgs_update_close(c, V, ldv, vbs, J, u, ubs, w, wbs, n, S, nbatch, flexible, res_out, tag, rb);
+}
 
 int launch_dcgs_update(hps_ctx* c, double2* V, int64_t ldv, int64_t vbs, int J, double2* u,
                        int64_t ubs, const double2* w, int64_t wbs, int64_t n, DcgsState* S,

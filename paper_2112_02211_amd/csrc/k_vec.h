@@ -70,6 +70,11 @@ __device__ __forceinline__ float2 ld_tile_h(const float2* p, int64_t i, int64_t 
   if constexpr (NT) return ld_nt2(p + (c ? i : i_safe));
   else return ld_tile(p, i, i_safe, c);
 }
+// The value a store of v to storage of the pointer's type keeps, widened again.
+__device__ __forceinline__ double2 as_stored(double2 v, const double2*) { return v; }
+__device__ __forceinline__ double2 as_stored(double2 v, const float2*) {
+  return make_double2((double)(float)v.x, (double)(float)v.y);
+}
 __device__ __forceinline__ double2 widen(float2 v, bool c) {
   return c ? make_double2((double)v.x, (double)v.y) : make_double2(0.0, 0.0);
 }

@@ -220,7 +220,8 @@ def arnoldi_summary(a):
     alg = info["arnoldi_update_algorithmic_bytes"]
     F = _counters(os.path.join(a.fetch, "run_counter_collection.csv"), "FETCH_SIZE")
     W = _counters(os.path.join(a.write, "run_counter_collection.csv"), "WRITE_SIZE")
-    fu, wu = _find(F, "k_dcgs_update"), _find(W, "k_dcgs_update")
+    fu = _counters_of(os.path.join(a.fetch, "run_counter_collection.csv"), "FETCH_SIZE", "k_dcgs_update")
+    wu = _counters_of(os.path.join(a.write, "run_counter_collection.csv"), "WRITE_SIZE", "k_dcgs_update")
     if len(fu) != 2 * K or len(wu) != 2 * K:
         raise ValueError(f"expected {2 * K} update dispatches, got {len(fu)}, {len(wu)}")
     med = lambda v: statistics.median(v[1:])
@@ -345,6 +346,15 @@ def _counters(path, counter):
     for r in rows:
         d[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return d
+
+
+def _counters_of(path, counter, key):
+    """Values of one counter, in dispatch order, over every kernel whose name
+    contains key (the update pass has two kernels: the plain one and the one
+    that ends a cycle with its closing reduction)."""
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter and key in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in rows]
 
 
 def _find(d, key):

@@ -242,3 +242,28 @@ def test_mid_size_reductions_match_cgs2(hps_mod):
             out[orth] = (host(u), st["true_rel_res"])
         assert rel(out["dcgs"][0], out["cgs2"][0]) < 1e-9, (restart, steps)
         assert abs(out["dcgs"][1] - out["cgs2"][1]) < 1e-8 * out["cgs2"][1]
+
+
+@pytest.mark.parametrize("solver", ["batched", "fgmres"])
+def test_lock_step_cycles_closed_by_the_update_pass(hps_mod, solver):
+    # Three right-hand sides of 5.2 million entries in lock step, restart 6:
+    # every cycle ends on an update pass that also makes the cycle's closing
+    # reduction (one set of partials per right-hand side).  After the same 18
+    # steps each iterate is the same vector as a single-right-hand-side solve
+    # with classical Gram-Schmidt twice, which has no such pass.
+    prob = P.bump_problem("mid", (18, 18, 18), 10, 30.0, 6, 3, 47, 30, 1e-10)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    N = ctx.N
+    assert N > (1 << 21)
+    xyz = ctx.nodes()
+    srcs = [P.gaussian_source(prob, xyz, r) for r in range(3)]
+    S = dev(np.concatenate(srcs))
+    U, st, ok = ctx.gmres(S, None, tol=1e-14, restart=6, max_iters=18, solver=solver)
+    assert st["iters"] == 18
+    Uh = host(U)
+    for r, s in enumerate(srcs):
+        one = "gmres" if solver == "batched" else "fgmres"
+        u1, st1, _ = ctx.gmres(dev(s), None, tol=1e-14, restart=6, max_iters=18, solver=one, orth="cgs2")
+        assert st1["iters"] == 18
+        assert rel(Uh[r * N:(r + 1) * N], host(u1)) < 1e-9, (solver, r)
+    ctx.free()
