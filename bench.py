@@ -76,11 +76,13 @@ BUCKET_DELTAS = (1e-3, 1e-2)   # lambda grid spacings (times kappa^2) of the buc
 METRIC = "HPS operator applies/s (Munknowns/s) + time-to-1e-8 solve; served p50/p99"
 
 
-def read_traffic(workload: str, kernel: str = "k_precond_fused"):
+def read_traffic(workload: str, kernel: str = "k_precond_fused", alg_bytes: float = 0.0):
     """HBM bytes per launch of `kernel` (k_precond_fused: the FP64 J^-1 with the
     fused exchange; k_dcgs_update: the Arnoldi update pass, averaged over the
     launches of one solve) from the committed PMC summary, if it was taken on
-    the current kernel source; else None."""
+    the current kernel source and, given alg_bytes (this run's algorithmic
+    bytes per launch), on launches of the same mean size (within 2 %: the
+    update pass's mean depends on the restart); else None."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -94,6 +96,8 @@ def read_traffic(workload: str, kernel: str = "k_precond_fused"):
     if vals.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
+        if alg_bytes > 0 and abs(float(vals["algorithmic_bytes_per_launch"]) / alg_bytes - 1.0) > 0.02:
+            return None
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -318,7 +322,7 @@ def solve_line(a, prob, steps: int, warmup: int, extensions: bool) -> dict:
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(name, "k_dcgs_update"),
+                "traffic": read_traffic(name, "k_dcgs_update", upd_bytes),
                 "kernel": "k_dcgs_update (Arnoldi update pass)",
                 "avg_launch_ms": round(upd_ms, 5),
                 "algorithmic_bytes_per_launch": round(upd_bytes)}
@@ -351,17 +355,19 @@ def solve_line(a, prob, steps: int, warmup: int, extensions: bool) -> dict:
     # with FP32 and BF16 stored blocks, all stopped by the same true-residual
     # tolerance (equal accuracy: the error against the oracle is reported next
     # to the time).
-    mixed = {"tol_true_residual": MIXED_TOL,
+    # (flexible GMRES and iterative refinement at the workload's restart for
+    # them: right-preconditioned GMRES stalls at small restarts on some media)
+    mixed = {"tol_true_residual": MIXED_TOL, "restart": prob.flex_restart,
              "j_inverse_form": {"fp64": "separable", "fp32": "stored blocks", "bf16": "stored blocks"}}
     for pr in ("fp64", "fp32", "bf16"):
         progress(f"{name}: FGMRES, {pr} J^-1")
         uu = torch.zeros_like(s)
-        ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="fgmres",
+        ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.flex_restart, u=uu, solver="fgmres",
                   precond_prec=pr, check_every=a.check_every)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(reps):
-            _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="fgmres",
+            _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.flex_restart, u=uu, solver="fgmres",
                                     precond_prec=pr, check_every=a.check_every)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / reps
@@ -374,7 +380,7 @@ def solve_line(a, prob, steps: int, warmup: int, extensions: bool) -> dict:
     # vectors and basis, separable J^-1), stopped at the same true residual
     progress(f"{name}: iterative refinement, FP32 inner solves")
     uu = torch.zeros_like(s)
-    ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="ir", inner_tol=IR_INNER_TOL,
+    ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.flex_restart, u=uu, solver="ir", inner_tol=IR_INNER_TOL,
               check_every=a.check_every)
     ctx.set_timing(True, every=TIMING_EVERY)
     ctx.kernel_times(reset=True)
@@ -382,7 +388,7 @@ def solve_line(a, prob, steps: int, warmup: int, extensions: bool) -> dict:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(reps):
-        _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.restart, u=uu, solver="ir",
+        _, st2, ok2 = ctx.gmres(s, t, tol=MIXED_TOL, restart=prob.flex_restart, u=uu, solver="ir",
                                 inner_tol=IR_INNER_TOL, check_every=a.check_every)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t1) / reps
@@ -411,11 +417,11 @@ def solve_line(a, prob, steps: int, warmup: int, extensions: bool) -> dict:
                       ("ir_fp32_inner", dict(solver="ir", inner_tol=IR_INNER_TOL))):
         progress(f"{name}: {label} to true residual 1e-8")
         uu = torch.zeros_like(s)
-        ctx.gmres(s, t, tol=1e-8, restart=prob.restart, u=uu, check_every=a.check_every, **kw)
+        ctx.gmres(s, t, tol=1e-8, restart=prob.flex_restart, u=uu, check_every=a.check_every, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(reps):
-            _, st3, ok3 = ctx.gmres(s, t, tol=1e-8, restart=prob.restart, u=uu, check_every=a.check_every,
+            _, st3, ok3 = ctx.gmres(s, t, tol=1e-8, restart=prob.flex_restart, u=uu, check_every=a.check_every,
                                     **kw)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / reps
@@ -834,10 +840,10 @@ def run_batched(a, prob):
     # the same J^-1 in lock-step flexible GMRES: the headline's stopping rule
     # (true residual), so the comparison with the FP32 blocks is step for step
     Uf = torch.zeros_like(S)
-    sctx.gmres(S, T, tol=tol, restart=prob.restart, u=Uf, solver="fgmres", check_every=a.check_every)
+    sctx.gmres(S, T, tol=tol, restart=prob.flex_restart, u=Uf, solver="fgmres", check_every=a.check_every)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    _, stf, okf = sctx.gmres(S, T, tol=tol, restart=prob.restart, u=Uf, solver="fgmres",
+    _, stf, okf = sctx.gmres(S, T, tol=tol, restart=prob.flex_restart, u=Uf, solver="fgmres",
                              check_every=a.check_every)
     torch.cuda.synchronize()
     f_el = time.perf_counter() - t1

@@ -38,12 +38,13 @@ def c3():
     s, t = P.rhs_data(prob, xyz)
     sd, td = torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda()
     for solver, tol in (("gmres", 1e-10), ("fgmres", 1e-10)):
-        u, st, ok = sep.gmres(sd, td, tol=tol, restart=prob.restart, solver=solver)
+        m = prob.restart if solver == "gmres" else prob.flex_restart
+        u, st, ok = sep.gmres(sd, td, tol=tol, restart=m, solver=solver)
         sols[f"separable_{solver}"] = (u.cpu().numpy(), st, ok)
     sep.free()
     ctx = hps.Context.from_problem(prob, block_precs=("fp64", "fp32", "bf16"))
     for prec in ("fp64", "fp32", "bf16"):
-        u, st, ok = ctx.gmres(sd, td, tol=1e-10, restart=prob.restart, solver="fgmres",
+        u, st, ok = ctx.gmres(sd, td, tol=1e-10, restart=prob.flex_restart, solver="fgmres",
                               precond_prec=prec)
         sols[prec] = (u.cpu().numpy(), st, ok)
     yield prob, ctx, d, xyz, s, t, sols
