@@ -755,8 +755,11 @@ def run_batched(a, prob):
 
     tol = BATCHED_TOL
 
+    # reduced-precision blocks make the lock-step solve flexible
+    m = prob.flex_restart if prec != "fp64" else prob.restart
+
     def step():
-        return ctx.gmres(S, T, tol=tol, restart=prob.restart, u=U, solver="batched",
+        return ctx.gmres(S, T, tol=tol, restart=m, u=U, solver="batched",
                          precond_prec=prec, check_every=a.check_every)
 
     # tile shape of the block GEMM for this order, precision and batch (autotuner)
@@ -878,7 +881,7 @@ def run_batched(a, prob):
         "config": {"workload": a.workload, "n_elem": list(prob.n_elem), "p": prob.p, "q": prob.q,
                    "kappa": prob.kappa, "unknowns_per_rhs": N, "rhs": k,
                    "solver": f"lock-step FGMRES, FP64 Krylov, {prec} blocks",
-                   "restart": prob.restart, "tol": tol},
+                   "restart": m, "tol": tol},
         "iters_per_solve": its / a.steps, "converged": bool(ok), "true_rel_res": st["true_rel_res"],
         "err_vs_oracle": errs, "setup_s": round(t_setup, 3),
         "precond_batched_ms": round(prec_ms, 4), "apply_ms_all_rhs": round(app_ms, 4),
