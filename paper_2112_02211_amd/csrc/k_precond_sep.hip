@@ -112,6 +112,18 @@ __device__ __forceinline__ int lidx(int i, int j, int k) {
   return i + SL<P>::P1 * (j + SL<P>::N1 * k);
 }
 
+// 1 / x by the hardware reciprocal estimate refined with two Newton-Raphson
+// steps (r <- r + r (1 - x r)); x > 0 and finite here (the squared modulus of
+// a diagonal entry of the diagonalized leaf operator).  Against the IEEE
+// division: J^-1 at p = 12 on 16^3 leaves 65.2 -> 63.7 us, results within the
+// parity bounds of the division (the error of each step squares).
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 __device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
   acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
   acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
@@ -177,7 +189,7 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
         if (SCALE) {
           const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
           const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
-          const double den = 1.0 / (ar * ar + ai * ai);
+          const double den = recip_nr(ar * ar + ai * ai);
           s = cmul(s, make_double2(ar * den, -ai * den));
         }
         const int pos = (INV && odd) ? N1 - 1 - (o - H) : o;
@@ -226,7 +238,7 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
         if (SCALE) {   // AX == 2: output element (a, b, o)
           const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
           const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
-          const double den = 1.0 / (ar * ar + ai * ai);
+          const double den = recip_nr(ar * ar + ai * ai);
           s = cmul(s, make_double2(ar * den, -ai * den));
         }
         const int pos = (INV && odd) ? N1 - 1 - (o - H) : o;
@@ -247,7 +259,7 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
       if (SCALE) {   // AX == 2: output element (a, b, o)
         const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
         const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
-        const double den = 1.0 / (ar * ar + ai * ai);
+        const double den = recip_nr(ar * ar + ai * ai);
         s = cmul(s, make_double2(ar * den, -ai * den));
       }
       out[base + o * stride] = s;
@@ -273,7 +285,7 @@ __device__ __forceinline__ void cmode_el(const double2* __restrict__ in, double2
       const int i = m % N1, j = (m / N1) % N1, k = m / L;
       const double ar = -(Ec[i].x + Ec[j].x + Ec[k].x) - lm.x;
       const double ai = -(Ec[i].y + Ec[j].y + Ec[k].y) - lm.y;
-      const double den = 1.0 / (ar * ar + ai * ai);
+      const double den = recip_nr(ar * ar + ai * ai);
       s = cmul(s, make_double2(ar * den, -ai * den));
     }
     out[m] = s;
@@ -313,7 +325,7 @@ __device__ __forceinline__ void cmode_ip(double2* __restrict__ T, const double2*
         if (SCALE) {
           const double ar = -(Ec[a].x + Ec[b].x + Ec[o].x) - lm.x;
           const double ai = -(Ec[a].y + Ec[b].y + Ec[o].y) - lm.y;
-          const double den = 1.0 / (ar * ar + ai * ai);
+          const double den = recip_nr(ar * ar + ai * ai);
           r = cmul(r, make_double2(ar * den, -ai * den));
         }
         T[base + o * stride] = r;
