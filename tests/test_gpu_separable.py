@@ -267,3 +267,27 @@ def test_lock_step_cycles_closed_by_the_update_pass(hps_mod, solver):
         assert st1["iters"] == 18
         assert rel(Uh[r * N:(r + 1) * N], host(u1)) < 1e-9, (solver, r)
     ctx.free()
+
+
+def test_refinement_cycles_closed_by_the_fp32_update_pass(hps_mod):
+    # Iterative refinement with inner GMRES(6) on the 16^3-leaf, p = 12
+    # workload (6.5 million entries): every inner cycle ends on the FP32-vector
+    # update pass that also makes the closing reduction (over values as stored
+    # in FP32).  Refinement stops on the FP64 true residual, so a wrong closing
+    # reduction would show as no convergence; the solution is checked against
+    # the oracle's converged solution at its sampled nodes.  (Small restarts
+    # need a medium on which they converge: on the 18^3, p = 10 medium above,
+    # left GMRES(6 ... 10) stalls near a relative residual of 0.45 with either
+    # orthogonalization, and refinement with it.)
+    import os
+    name = "bumps_16x16x16_p12"
+    prob = P.workload(name)
+    ctx = hps_mod.Context.from_problem(prob, block_precs=("separable",))
+    assert ctx.N > (1 << 21)
+    s, t = P.rhs_data(prob, ctx.nodes())
+    u, st, ok = ctx.gmres(dev(s), dev(t), tol=1e-10, restart=6, solver="ir")
+    assert ok and st["true_rel_res"] <= 1e-10 and st["restarts"] >= 2
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_oracle.npz"))
+    err = rel(host(u)[g["idx"]], g["u"])
+    assert err < 1e-8, err
+    ctx.free()
