@@ -87,6 +87,14 @@ constexpr bool kSepSplit = P == 12 || P == 10;
 // held to three workgroups per CU by its registers either way.
 template <int P>
 constexpr bool kSepSplitInPlace = P == 12;
+// In-place tensor padded by one entry per xy-plane instead of one per x-line
+// (1010 entries instead of 1100 at p = 12: 25.7 KB of LDS per leaf, six
+// leaves per CU instead of five); the x-axis products then give neighbouring
+// lanes neighbouring planes (stride L + 1) rather than neighbouring rows.
+// On 16^3 leaves: J^-1 62.3-63.2 -> 59.0-59.7 us, the solve 101.65 -> 100.8 ms,
+// iterative refinement (inner restart 10) 107.35 -> 106.45 ms.
+template <int P>
+constexpr bool kSepPlanePad = P == 12;
 // config end
 
 template <int P>
@@ -100,7 +108,12 @@ struct SL {
   // threads of a wavefront that walk neighbouring x-lines read 16-byte words in
   // different banks
   static constexpr bool SIP = kSepSplitInPlace<P>;
-  static constexpr int P1 = (LW || IP) ? N1 + 1 : N1, SZ = P1 * L, SZX = (IP || SIP) ? 1 : SZ;
+  static constexpr int P1 = (LW || IP) ? N1 + 1 : N1;
+  // plane padding (in-place line-wise form only): entry (i, j, k) at
+  // i + n1 j + (L + 1) k
+  static constexpr bool PP = SIP && kSepPlanePad<P>;
+  static constexpr int JS = PP ? N1 : P1, KS = PP ? L + 1 : P1 * N1;   // strides of j and k
+  static constexpr int SZ = KS * N1, SZX = (IP || SIP) ? 1 : SZ;
   // line-wise work items: (output group of R, 64 lines) per wavefront
   static constexpr int R = kSepOutputs<P>, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
   // tables staged in LDS: Ec | Fi, and for the element-parallel form Wc | Vc before them
@@ -109,7 +122,7 @@ struct SL {
 
 template <int P>
 __device__ __forceinline__ int lidx(int i, int j, int k) {
-  return i + SL<P>::P1 * (j + SL<P>::N1 * k);
+  return i + SL<P>::JS * j + SL<P>::KS * k;
 }
 
 // 1 / x by the hardware reciprocal estimate refined with two Newton-Raphson
@@ -134,9 +147,9 @@ __device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
 template <int P>
 __device__ __forceinline__ void line_of(int ax, int a, int b, int& base, int& stride) {
   using S = SL<P>;
-  if (ax == 0) { base = S::P1 * (a + S::N1 * b); stride = 1; }
-  else if (ax == 1) { base = a + S::P1 * S::N1 * b; stride = S::P1; }
-  else { base = a + S::P1 * b; stride = S::P1 * S::N1; }
+  if (ax == 0) { base = S::JS * a + S::KS * b; stride = 1; }
+  else if (ax == 1) { base = a + S::KS * b; stride = S::JS; }
+  else { base = a + S::JS * b; stride = S::KS; }
 }
 
 // out[.., o, ..] = sum_i M[o][i] in[.., i, ..] along axis AX (M complex, row
@@ -159,7 +172,9 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
     const int og = wave / WPG;
     const int line = (wave - og * WPG) * 64 + lane;
     const bool act = wave < S::W && line < L;
-    const int a = act ? line % N1 : 0, b = act ? line / N1 : 0;
+    // plane padding: x-lines in k-major order across the lanes
+    constexpr bool KM = S::PP && AX == 0;
+    const int a = act ? (KM ? line / N1 : line % N1) : 0, b = act ? (KM ? line % N1 : line / N1) : 0;
     int base, stride;
     line_of<P>(AX, a, b, base, stride);
     const bool odd = og * R >= H;
