@@ -63,6 +63,27 @@ constexpr int kSweepOutputs = 2;   // line-wise: outputs of a line per work item
 template <> constexpr int kSweepThreads<12> = 512;
 template <> constexpr int kSweepMinWaves<12> = 6;
 template <> constexpr int kSweepOutputs<12> = 3;
+// Bank-spread lanes (line-wise form): each axis pass hands its lines to the
+// lanes by the residue mod 16 of the line's first LDS index (SweepLanes), so
+// that the 16-byte reads of a quarter wavefront fall in different bank groups,
+// and the accumulator's strides are congruent mod 16 to the grid's, so that the
+// same assignment serves its read-modify-writes.  Grid strides (1, p + 1, SK),
+// accumulator strides (1, AJ, AK); at p = 12 (1, 13, 165) and (1, 13, 133) leave
+// one residue collision in the three passes (a 10 x 10 block of lines under the
+// unpadded k-stride 156 and the packed accumulator had 18), at 52.7 KB of LDS per
+// leaf (three leaves per CU as before).  On 16^3 leaves: the solve 100.8 ->
+// 99.7 ms, iterative refinement 108.8 -> 107.3 ms (alternating runs).
+template <int P>
+constexpr bool kSweepBankPerm = P == 12;
+template <int P>
+constexpr int kSweepGridK = 0;
+template <int P>
+constexpr int kSweepAccJ = 0;
+template <int P>
+constexpr int kSweepAccK = 0;
+template <> constexpr int kSweepGridK<12> = 165;
+template <> constexpr int kSweepAccJ<12> = 13;
+template <> constexpr int kSweepAccK<12> = 133;
 // config end
 
 template <int P>
@@ -70,10 +91,22 @@ struct Leaf {
   static constexpr int N1 = P - 2, L = N1 * N1, NI = N1 * L, NB = 6 * L, NN = NI + NB;
   static constexpr bool LW = kSweepForm<P> == kSweepLine;
   static constexpr int P1 = LW ? P + 1 : P;          // LDS length of an x-line
-  static constexpr int GS = P * P * P1;               // LDS grid size
+  static constexpr bool BP = LW && kSweepBankPerm<P>;
+  // grid strides (1, P1, SK) and accumulator strides (1, AJ, AK)
+  static constexpr int SK = BP ? kSweepGridK<P> : P * P1;
+  static constexpr int AJ = BP ? kSweepAccJ<P> : N1, AK = BP ? kSweepAccK<P> : L;
+  static_assert(SK >= P * P1 && AJ >= N1 && AK >= N1 * AJ, "strides cover the grid");
+  static constexpr int GS = BP ? (P - 1) * (1 + P1 + SK) + 1 : P * P * P1;   // LDS grid size
+  static constexpr int AS = BP ? (N1 - 1) * (1 + AJ + AK) + 1 : NI;         // accumulator size
   static constexpr int SR = kSweepOutputs<P>, SG = (P + SR - 1) / SR, SWPG = (L + 63) / 64, SW = SG * SWPG;
   // LDS grid index of grid point (i, j, k)
-  __device__ static __forceinline__ int gidx(int i, int j, int k) { return (k * P + j) * P1 + i; }
+  __device__ static __forceinline__ int gidx(int i, int j, int k) { return i + P1 * j + SK * k; }
+  // accumulator index of interior node (i, j, k), 0-based
+  __device__ static __forceinline__ int aidx(int i, int j, int k) { return i + AJ * j + AK * k; }
+  __device__ static __forceinline__ int acc_of(int m) {
+    if constexpr (BP) return aidx(m % N1, (m / N1) % N1, m / L);
+    else return m;
+  }
   // LDS grid index of local node m
   __device__ static __forceinline__ int grid_of(int m) {
     if (m < NI) {
@@ -91,9 +124,63 @@ struct Leaf {
   __device__ static __forceinline__ void line(int ax, int a, int b, int& base, int& stride) {
     if (ax == 0) { base = gidx(0, a, b); stride = 1; }
     else if (ax == 1) { base = gidx(a, 0, b); stride = P1; }
-    else { base = gidx(a, b, 0); stride = P * P1; }
+    else { base = gidx(a, b, 0); stride = SK; }
   }
 };
+
+// Lane assignment of the bank-spread form: word s holds, in byte AX, the line
+// that slot s (= 64 * (wavefront mod lines-per-group) + lane) takes in axis
+// pass AX; slots past the last line hold L.  Built at compile time: each group
+// of 16 slots takes lines of as many different residues (mod 16, of the line's
+// first grid index) as remain, the most plentiful residues first, in residue
+// order, so a quarter wavefront reads 16 different bank groups.
+struct SweepLanes {
+  unsigned int w[128];
+};
+template <int P>
+constexpr SweepLanes make_sweep_lanes() {
+  using Lf = Leaf<P>;
+  constexpr int N1 = Lf::N1, L = Lf::L;
+  static_assert(Lf::SWPG * 64 <= 128, "two wavefronts of lines per output group at most");
+  SweepLanes t{};
+  for (int s = 0; s < 128; ++s) t.w[s] = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    int res[128] = {};
+    int cnt[16] = {};
+    bool used[128] = {};
+    for (int l = 0; l < L; ++l) {
+      const int a = l % N1 + 1, b = l / N1 + 1;
+      const int e = ax == 0 ? Lf::P1 * a + Lf::SK * b : ax == 1 ? a + Lf::SK * b : a + Lf::P1 * b;
+      res[l] = e % 16;
+      ++cnt[res[l]];
+    }
+    int slot = 0;
+    while (slot < L) {
+      const int g = L - slot < 16 ? L - slot : 16;
+      int took[16] = {};
+      for (int k = 0; k < g; ++k) {
+        int best = -1;
+        for (int r = 0; r < 16; ++r) {
+          if (cnt[r] == 0) continue;
+          if (best < 0 || took[r] < took[best] || (took[r] == took[best] && cnt[r] > cnt[best])) best = r;
+        }
+        ++took[best];
+        --cnt[best];
+      }
+      for (int r = 0; r < 16; ++r)
+        for (int k = 0; k < took[r]; ++k) {
+          int l = 0;
+          while (used[l] || res[l] != r) ++l;
+          used[l] = true;
+          t.w[slot++] |= (unsigned)l << (8 * ax);
+        }
+    }
+    for (int s = L; s < 128; ++s) t.w[s] |= (unsigned)L << (8 * ax);
+  }
+  return t;
+}
+static_assert(!Leaf<12>::BP || Leaf<12>::L < 256, "line indices fit a byte");
+__constant__ SweepLanes kSweepLanes12 = make_sweep_lanes<12>();
 
 // One axis pass over the lines of one leaf, AX = 0, 1, 2 (x, y, z).  Work item
 // (line, o) contracts the line's p values with row o of R: o = 0 and o = p-1 are
@@ -116,9 +203,9 @@ __device__ __forceinline__ void axis_out(double2 s, double2 ue, int o, int line,
     st2(gv, f * L + line, make_double2(s.x + eta * ue.y, s.y - eta * ue.x));
   } else {
     int m;
-    if (AX == 0) m = (o - 1) + N1 * (a - 1) + L * (b - 1);
-    else if (AX == 1) m = (a - 1) + N1 * (o - 1) + L * (b - 1);
-    else m = (a - 1) + N1 * (b - 1) + L * (o - 1);
+    if (AX == 0) m = Lf::aidx(o - 1, a - 1, b - 1);
+    else if (AX == 1) m = Lf::aidx(a - 1, o - 1, b - 1);
+    else m = Lf::aidx(a - 1, b - 1, o - 1);
     if (AX == 0) ACC[m] = s;
     else ACC[m] = make_double2(ACC[m].x + s.x, ACC[m].y + s.y);
   }
@@ -127,9 +214,11 @@ __device__ __forceinline__ void axis_out(double2 s, double2 ue, int o, int line,
 template <int P, int AX, typename T>
 __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2* __restrict__ ACC,
                                           const double* __restrict__ R, const double* __restrict__ tab,
-                                          double eta, T* __restrict__ yv, T* __restrict__ gv) {
+                                          double eta, T* __restrict__ yv, T* __restrict__ gv,
+                                          unsigned int lanes) {
   using Lf = Leaf<P>;
   constexpr int N1 = Lf::N1, L = Lf::L, BD = kSweepThreads<P>;
+  static_assert(!Lf::BP || Lf::SW == BD / 64, "bank-spread lanes: one work item per wavefront and pass");
   if constexpr (Lf::LW) {
     // line-wise: rows of R (o = 0: -D[0][.], o = p-1: D[p-1][.], else -D2[o][.])
     // straight from the table, at wavefront-uniform addresses
@@ -139,7 +228,7 @@ __device__ __forceinline__ void axis_pass(const double2* __restrict__ U, double2
     const int lane = threadIdx.x & 63;
     for (int w = wave; w < Lf::SW; w += BD / 64) {
       const int og = w / Lf::SWPG;
-      const int line = (w - og * Lf::SWPG) * 64 + lane;
+      const int line = Lf::BP ? (int)((lanes >> (8 * AX)) & 0xffu) : (w - og * Lf::SWPG) * 64 + lane;
       if (line >= L) continue;
       const int a = line % N1 + 1, b = line / N1 + 1;
       int base, stride;
@@ -207,7 +296,7 @@ __global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_s
   constexpr int NI = Lf::NI, NN = Lf::NN, NB = Lf::NB;
   constexpr int BD = kSweepThreads<P>;
   __shared__ double2 U[Lf::GS];
-  __shared__ double2 ACC[NI];
+  __shared__ double2 ACC[Lf::AS];
   __shared__ double R[P * P];
   const int64_t tau = blockIdx.x;
   const int rhs = blockIdx.y;
@@ -232,13 +321,19 @@ __global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_s
     const int o = k / P, q = k - o * P;
     R[k] = (o == 0) ? -D[q] : (o == P - 1) ? D[(P - 1) * P + q] : -D2[k];
   }
+  // this thread's lines in the three axis passes (bank-spread form)
+  unsigned int lanes = 0;
+  if constexpr (Lf::BP) {
+    static_assert(P == 12, "lane table built for p = 12");
+    lanes = kSweepLanes12.w[((int)(threadIdx.x >> 6) % Lf::SWPG) * 64 + (int)(threadIdx.x & 63)];
+  }
   stage_leaf<P, BD, 0, T>(xv, U);
   __syncthreads();
-  axis_pass<P, 0, T>(U, ACC, R, tab, eta, yv, gv);
+  axis_pass<P, 0, T>(U, ACC, R, tab, eta, yv, gv, lanes);
   __syncthreads();
-  axis_pass<P, 1, T>(U, ACC, R, tab, eta, yv, gv);
+  axis_pass<P, 1, T>(U, ACC, R, tab, eta, yv, gv, lanes);
   __syncthreads();
-  axis_pass<P, 2, T>(U, ACC, R, tab, eta, yv, gv);
+  axis_pass<P, 2, T>(U, ACC, R, tab, eta, yv, gv, lanes);
   __syncthreads();
   // interior rows: -(Dx^2 + Dy^2 + Dz^2) v - C v (eq. (leafmat)); C was loaded
   // into registers with the leaf, so this phase waits for no memory
@@ -246,7 +341,7 @@ __global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_s
   if constexpr (k < NLC) {                                                      \
     const int m = threadIdx.x + k * BD;                                         \
     if ((k + 1) * BD <= NI || m < NI) {                                         \
-      const double2 v = U[Lf::grid_of(m)], acc = ACC[m];                        \
+      const double2 v = U[Lf::grid_of(m)], acc = ACC[Lf::acc_of(m)];            \
       double2 cu;                                                               \
       if constexpr (CC) cu = cmul(c, v);                                        \
       else cu = cscale(v, c);                                                   \
@@ -256,7 +351,7 @@ __global__ __launch_bounds__(kSweepThreads<P>, kSweepMinWaves<P>) void k_apply_s
   HPS_CO(0, c0) HPS_CO(1, c1) HPS_CO(2, c2) HPS_CO(3, c3)
 #undef HPS_CO
   for (int m = threadIdx.x + 4 * BD; m < NI; m += BD) {   // rows past four per thread
-    const double2 v = U[Lf::grid_of(m)], acc = ACC[m];
+    const double2 v = U[Lf::grid_of(m)], acc = ACC[Lf::acc_of(m)];
     double2 cu;
     if constexpr (CC) cu = cmul(Cp[m], v);
     else cu = cscale(v, Cp[m]);
