@@ -22,6 +22,7 @@
 #include "hps_internal.h"
 #include "k_common.h"
 #include "k_vec.h"
+#include "k_lanes.h"
 
 // Face buffer of the allocation-free apply (hps_apply_noalloc): a file-scope
 // device array, one copy per GPU, held until the process ends.  Host code uses
@@ -128,59 +129,19 @@ struct Leaf {
   }
 };
 
-// Lane assignment of the bank-spread form: word s holds, in byte AX, the line
-// that slot s (= 64 * (wavefront mod lines-per-group) + lane) takes in axis
-// pass AX; slots past the last line hold L.  Built at compile time: each group
-// of 16 slots takes lines of as many different residues (mod 16, of the line's
-// first grid index) as remain, the most plentiful residues first, in residue
-// order, so a quarter wavefront reads 16 different bank groups.
-struct SweepLanes {
-  unsigned int w[128];
-};
+// Lane assignment of the bank-spread form (k_lanes.h): byte AX of word s is
+// the line that slot s (= 64 * (wavefront mod lines-per-group) + lane) takes in
+// axis pass AX, ordered by the residue mod 16 of the line's first grid index.
 template <int P>
-constexpr SweepLanes make_sweep_lanes() {
+constexpr LaneTable make_sweep_lanes() {
   using Lf = Leaf<P>;
-  constexpr int N1 = Lf::N1, L = Lf::L;
-  static_assert(Lf::SWPG * 64 <= 128, "two wavefronts of lines per output group at most");
-  SweepLanes t{};
-  for (int s = 0; s < 128; ++s) t.w[s] = 0;
-  for (int ax = 0; ax < 3; ++ax) {
-    int res[128] = {};
-    int cnt[16] = {};
-    bool used[128] = {};
-    for (int l = 0; l < L; ++l) {
-      const int a = l % N1 + 1, b = l / N1 + 1;
-      const int e = ax == 0 ? Lf::P1 * a + Lf::SK * b : ax == 1 ? a + Lf::SK * b : a + Lf::P1 * b;
-      res[l] = e % 16;
-      ++cnt[res[l]];
-    }
-    int slot = 0;
-    while (slot < L) {
-      const int g = L - slot < 16 ? L - slot : 16;
-      int took[16] = {};
-      for (int k = 0; k < g; ++k) {
-        int best = -1;
-        for (int r = 0; r < 16; ++r) {
-          if (cnt[r] == 0) continue;
-          if (best < 0 || took[r] < took[best] || (took[r] == took[best] && cnt[r] > cnt[best])) best = r;
-        }
-        ++took[best];
-        --cnt[best];
-      }
-      for (int r = 0; r < 16; ++r)
-        for (int k = 0; k < took[r]; ++k) {
-          int l = 0;
-          while (used[l] || res[l] != r) ++l;
-          used[l] = true;
-          t.w[slot++] |= (unsigned)l << (8 * ax);
-        }
-    }
-    for (int s = L; s < 128; ++s) t.w[s] |= (unsigned)L << (8 * ax);
-  }
-  return t;
+  static_assert(Lf::SWPG * 64 <= 128 && Lf::L < 256, "two wavefronts of lines, byte line indices");
+  return bank_spread_lanes(Lf::L, [](int ax, int l) {
+    const int a = l % Lf::N1 + 1, b = l / Lf::N1 + 1;
+    return ax == 0 ? Lf::P1 * a + Lf::SK * b : ax == 1 ? a + Lf::SK * b : a + Lf::P1 * b;
+  });
 }
-static_assert(!Leaf<12>::BP || Leaf<12>::L < 256, "line indices fit a byte");
-__constant__ SweepLanes kSweepLanes12 = make_sweep_lanes<12>();
+__constant__ LaneTable kSweepLanes12 = make_sweep_lanes<12>();
 
 // One axis pass over the lines of one leaf, AX = 0, 1, 2 (x, y, z).  Work item
 // (line, o) contracts the line's p values with row o of R: o = 0 and o = p-1 are

@@ -29,6 +29,7 @@
 // tables (Wc, Vc, Ec, Fi per operator) are built on the host at setup.
 #include "hps_internal.h"
 #include "k_vec.h"
+#include "k_lanes.h"
 
 namespace hps {
 namespace {
@@ -95,6 +96,14 @@ constexpr bool kSepSplitInPlace = P == 12;
 // iterative refinement (inner restart 10) 107.35 -> 106.45 ms.
 template <int P>
 constexpr bool kSepPlanePad = P == 12;
+// With plane padding, the in-place products hand each axis pass's lines to the
+// lanes by the residue mod 16 of the line's first LDS index (k_lanes.h), so that
+// the 16-byte accesses of a quarter wavefront fall in different bank groups
+// (at p = 12 one collision left over the three axes, against 12 with x-lines
+// in k-major order and the other axes in natural order).  On 16^3 leaves: J^-1
+// 62.5 -> 61.7 us in the solve (profiler), the solve 99.7 -> 99.4 ms.
+template <int P>
+constexpr bool kSepBankPerm = P == 12;
 // config end
 
 template <int P>
@@ -114,6 +123,7 @@ struct SL {
   static constexpr bool PP = SIP && kSepPlanePad<P>;
   static constexpr int JS = PP ? N1 : P1, KS = PP ? L + 1 : P1 * N1;   // strides of j and k
   static constexpr int SZ = KS * N1, SZX = (IP || SIP) ? 1 : SZ;
+  static constexpr bool BPL = PP && kSepBankPerm<P>;   // lanes from a bank-spread table
   // line-wise work items: (output group of R, 64 lines) per wavefront
   static constexpr int R = kSepOutputs<P>, G = (N1 + R - 1) / R, WPG = (L + 63) / 64, W = G * WPG;
   // tables staged in LDS: Ec | Fi, and for the element-parallel form Wc | Vc before them
@@ -152,6 +162,20 @@ __device__ __forceinline__ void line_of(int ax, int a, int b, int& base, int& st
   else { base = a + S::JS * b; stride = S::KS; }
 }
 
+// Bank-spread lane table of the in-place products: byte AX of word s is the
+// line (a + n1 b) that slot s (= 64 * (wavefront mod lines-per-group) + lane)
+// takes in the products along axis AX.
+template <int P>
+constexpr LaneTable make_sep_lanes() {
+  using S = SL<P>;
+  static_assert(S::WPG * 64 <= 128 && S::L < 256, "two wavefronts of lines, byte line indices");
+  return bank_spread_lanes(S::L, [](int ax, int l) {
+    const int a = l % S::N1, b = l / S::N1;
+    return ax == 0 ? S::JS * a + S::KS * b : ax == 1 ? a + S::KS * b : a + S::JS * b;
+  });
+}
+__constant__ LaneTable kSepLanes12 = make_sep_lanes<12>();
+
 // out[.., o, ..] = sum_i M[o][i] in[.., i, ..] along axis AX (M complex, row
 // major).  SCALE: the output element (i, j, k) is multiplied by
 // 1 / (-(Ec_i + Ec_j + Ec_k) - lambda) (the last forward product).
@@ -159,7 +183,7 @@ __device__ __forceinline__ void line_of(int ax, int a, int b, int& base, int& st
 template <int P, int AX, bool SCALE, bool INV>
 __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2* __restrict__ out,
                                          const double2* __restrict__ M, const double2* __restrict__ Ec,
-                                         double2 lm) {
+                                         double2 lm, unsigned int lanes) {
   using S = SL<P>;
   constexpr int N1 = S::N1, L = S::L, R = S::R, WPG = S::WPG, NW = S::BD / 64;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -170,10 +194,10 @@ __device__ __forceinline__ void cmode_lw(const double2* __restrict__ in, double2
     static_assert(kSepSplit<P> && S::W <= NW, "one work item per wavefront");
     constexpr int H = N1 / 2;
     const int og = wave / WPG;
-    const int line = (wave - og * WPG) * 64 + lane;
+    const int line = S::BPL ? (int)((lanes >> (8 * AX)) & 0xffu) : (wave - og * WPG) * 64 + lane;
     const bool act = wave < S::W && line < L;
-    // plane padding: x-lines in k-major order across the lanes
-    constexpr bool KM = S::PP && AX == 0;
+    // plane padding without the lane table: x-lines in k-major order across the lanes
+    constexpr bool KM = S::PP && !S::BPL && AX == 0;
     const int a = act ? (KM ? line / N1 : line % N1) : 0, b = act ? (KM ? line % N1 : line / N1) : 0;
     int base, stride;
     line_of<P>(AX, a, b, base, stride);
@@ -354,10 +378,10 @@ __device__ __forceinline__ void cmode_ip(double2* __restrict__ T, const double2*
 template <int P, int AX, bool SCALE, bool INV>
 __device__ __forceinline__ void cmode(const double2* in, double2* out, const double2* __restrict__ Mg,
                                       const double2* __restrict__ Ml, const double2* __restrict__ Ec,
-                                      double2 lm) {
+                                      double2 lm, unsigned int lanes) {
   static_assert(!kSepSplit<P> || SL<P>::LW, "even / odd products in the line-wise form only");
   if constexpr (SL<P>::IP) cmode_ip<P, AX, SCALE>(const_cast<double2*>(in), Mg, Ec, lm);
-  else if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE, INV>(in, out, Mg, Ec, lm);
+  else if constexpr (SL<P>::LW) cmode_lw<P, AX, SCALE, INV>(in, out, Mg, Ec, lm, lanes);
   else cmode_el<P, AX, SCALE>(in, out, Ml, Ec, lm);
 }
 
@@ -480,6 +504,13 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   const double2* st = sep + (os ? (int64_t)rhs * S::ST : 0);
   const double2* Wc = st;          // global: read at wavefront-uniform addresses
   const double2* Vc = st + L;
+  // this thread's lines in the three axes' products (bank-spread lanes),
+  // loaded with the leaf
+  unsigned int lanes = 0;
+  if constexpr (S::BPL) {
+    static_assert(P == 12, "lane table built for p = 12");
+    lanes = kSepLanes12.w[((int)(threadIdx.x >> 6) % S::WPG) * 64 + (int)(threadIdx.x & 63)];
+  }
   // table entries: thread k loads entry k of Ec | Fi (| Wc | Vc) and of
   // Dlo | Dhi | C0 | C1 from in-bounds (clamped) addresses without a branch, so
   // that these loads and the leaf's are all in flight together; they are
@@ -553,17 +584,17 @@ __global__ __launch_bounds__(SL<P>::BD, SL<P>::MINW) void k_precond_sep(
   // u_i = (Vc x Vc x Vc) diag(1 / (-Ec_Delta - lambda)) (Wc x Wc x Wc) r_i
   // (ping-pong T -> X -> T ..., ending in T; in place: all in T)
   double2* const X1 = (S::IP || S::SIP) ? T : X;
-  cmode<P, 0, false, false>(T, X1, Wc, Wl, Ec, lm);
+  cmode<P, 0, false, false>(T, X1, Wc, Wl, Ec, lm, lanes);
   __syncthreads();
-  cmode<P, 1, false, false>(X1, T, Wc, Wl, Ec, lm);
+  cmode<P, 1, false, false>(X1, T, Wc, Wl, Ec, lm, lanes);
   __syncthreads();
-  cmode<P, 2, true, false>(T, X1, Wc, Wl, Ec, lm);
+  cmode<P, 2, true, false>(T, X1, Wc, Wl, Ec, lm, lanes);
   __syncthreads();
-  cmode<P, 0, false, true>(X1, T, Vc, Vl, Ec, lm);
+  cmode<P, 0, false, true>(X1, T, Vc, Vl, Ec, lm, lanes);
   __syncthreads();
-  cmode<P, 1, false, true>(T, X1, Vc, Vl, Ec, lm);
+  cmode<P, 1, false, true>(T, X1, Vc, Vl, Ec, lm, lanes);
   __syncthreads();
-  cmode<P, 2, false, true>(X1, T, Vc, Vl, Ec, lm);
+  cmode<P, 2, false, true>(X1, T, Vc, Vl, Ec, lm, lanes);
   __syncthreads();
   if constexpr (kSepSplit<P>) {
     split_butterflies<P>(T);
