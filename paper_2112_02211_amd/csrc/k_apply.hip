@@ -44,10 +44,12 @@ namespace {
 // and 16; element-parallel (a thread owns one output, inputs and table entries
 // from LDS) 1-31 % faster at the other orders; single-pass (one thread per
 // output sums all three axes from the LDS grid, no accumulator tensor) 5 %
-// faster at p = 15.
+// faster at p = 15, and at p = 10 once every leaf load was issued before the
+// first LDS store: J^-1 A on 16^3 leaves 94-95 -> 83 us, with 64 right-hand
+// sides 5.65-5.72 -> 4.42-4.49 ms (8^3 leaves: the solve 14.71 -> 14.66 ms).
 enum { kSweepElem = 0, kSweepLine = 1, kSweepSingle = 2 };
 template <int P>
-constexpr int kSweepForm = P == 15 ? kSweepSingle
+constexpr int kSweepForm = (P == 15 || P == 10) ? kSweepSingle
                          : (P == 8 || P == 9 || P == 12 || P == 13 || P == 14 || P == 16) ? kSweepLine
                                                                                           : kSweepElem;
 template <int P>
