@@ -2,9 +2,10 @@
 //
 // A kernel that gives each lane one grid line of a leaf and walks the lines'
 // entries at a common stride reads, at each step, one 16-byte entry per lane
-// at (first index of the lane's line) + step * stride.  Sixteen lanes can be
-// served together when their first indices differ mod 16 (16 entries of 16 B
-// cover the 64 four-byte banks).  The table assigns the lines of each axis pass
+// at (first index of the lane's line) + step * stride.  With 64 four-byte
+// banks, 16 entries of 16 B whose indices differ mod 16 touch disjoint banks
+// (and 8 whose indices differ mod 8 cover 32 of them), which is what the bank
+// conflict counters rewarded when measured.  The table assigns the lines of each axis pass
 // to the slots of up to two wavefronts (slot = 64 * wavefront + lane) so that
 // each group of 16 slots takes lines of as many different residues mod 16 as
 // remain, the most plentiful residues first, in residue order (so each half
