@@ -66,6 +66,13 @@ template <> constexpr int kSepForm<12> = kSepLine;
 template <> constexpr int kSepThreads<12> = 256;
 template <> constexpr int kSepMinWaves<12> = 8;
 template <> constexpr int kSepOutputs<12> = 5;
+// p = 10: 256 threads (two outputs per work item: one work item per wavefront
+// in each product instead of half the wavefronts idle on 512), registers for
+// six waves per SIMD, so six leaves share a CU instead of three: J^-1 on 16^3
+// leaves 39.1 -> 33.0 us, with 64 right-hand sides 2.37 -> 1.98 ms (on 8^3
+// leaves, two per CU, the solve 14.65 -> 14.70 ms).
+template <> constexpr int kSepThreads<10> = 256;
+template <> constexpr int kSepMinWaves<10> = 6;
 // Face values in the second tensor's space (where it holds them): at p = 12 it
 // took the leaf from 45.3 to 35.7 KB of LDS, four leaves per CU instead of
 // three (before the in-place even / odd products removed that tensor); at
@@ -84,8 +91,9 @@ constexpr bool kSepSplit = P == 12 || P == 10;
 // registers, so after a barrier it can write its outputs over them and the
 // second LDS tensor goes (one work item per wavefront and product).  At
 // p = 12: 27.7 KB of LDS per leaf instead of 35.7 (five leaves per CU instead
-// of four), J^-1 64.5 -> 62.8 us, the 16^3 solve 124.1 -> 122.9 ms; p = 10 is
-// held to three workgroups per CU by its registers either way.
+// of four), J^-1 64.5 -> 62.8 us, the 16^3 solve 124.1 -> 122.9 ms.  At p = 10
+// registers, not LDS, set the leaves per CU: in place there was 1-2 % slower on
+// 16^3 leaves with 256 threads (and equal with 512).
 template <int P>
 constexpr bool kSepSplitInPlace = P == 12;
 // In-place tensor padded by one entry per xy-plane instead of one per x-line
